@@ -1,0 +1,315 @@
+"""CPU FP64 dense oracle for plane-wave H.psi and the block Davidson iteration.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+``cpu_baseline`` leg of the benchmark may import this module; the product
+path never calls it.  It shares no code with the GPU library: no FFT, no
+blocking, no fusion -- each function is the plain definition, written out in
+NumPy/SciPy in float64 / complex128.
+
+Hamiltonian in a plane-wave basis (Hartree atomic units), following the
+Kohn-Sham equation of the self-consistency appendix (kinetic -hbar^2/2m
+nabla^2 plus a potential), the separable projector form of the
+pseudopotential (beta projectors, Sec. 3 and the SCF appendix's <psi|beta>
+notation) and the plane-wave / FFT-grid representation of the parallelization
+section:
+
+    H_{GG'} = 1/2 |k+G|^2 delta_{GG'}                               (kinetic)
+            + Vt((m_G - m_G') mod n)                                (local)
+            + sum_I sum_{ij in I} beta_i(G) D^I_{ij} conj(beta_j(G'))  (nonlocal)
+
+with Vt(dm) = (1/N) sum_j V(r_j) exp(-2 pi i sum_d dm_d j_d / n_d), the
+discrete Fourier coefficient of the real potential sampled on the grid.
+The forward transform convention is psi(r_j) = sum_G psi_G exp(+i G.r_j)
+(unscaled); the Bloch factor exp(ik.r) commutes with V(r) and is not applied.
+
+The Davidson routine follows the iterative-diagonalization appendix (block
+Davidson: residuals g = (H - eps S) psi, corrections D g with the diagonal
+preconditioner, reduced problem on span{psi, dpsi}, Ritz update, optional
+expanding basis up to a fixed size), with S = 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+
+
+# ----------------------------------------------------------------------------
+# H.psi pieces
+# ----------------------------------------------------------------------------
+
+def kinetic(kpg: np.ndarray) -> np.ndarray:
+    """Kinetic diagonal T_G = |k+G|^2 / 2 (Ha), from Cartesian k+G in bohr^-1."""
+    kpg = np.asarray(kpg, dtype=np.float64)
+    return 0.5 * np.sum(kpg * kpg, axis=1)
+
+
+def dft_matrix(n: int, sign: int) -> np.ndarray:
+    """Plain DFT matrix F[m, j] = exp(sign * 2 pi i m j / n)."""
+    m = np.arange(n)
+    return np.exp(sign * 2j * math.pi * np.outer(m, m) / n)
+
+
+def vtilde_table(vloc_r: np.ndarray) -> np.ndarray:
+    """Vt(dm) for every dm mod n, as a [n3][n2][n1] complex table.
+
+    Direct discrete Fourier sums (three explicit DFT matrices, O(n^4)); no FFT.
+    ``vloc_r`` is [n3][n2][n1] (x fastest).
+    """
+    v = np.asarray(vloc_r, dtype=np.float64)
+    n3, n2, n1 = v.shape
+    f1, f2, f3 = dft_matrix(n1, -1), dft_matrix(n2, -1), dft_matrix(n3, -1)
+    t = np.einsum("mj,abj->abm", f1, v.astype(np.complex128))   # over j1
+    t = np.einsum("mj,ajc->amc", f2, t)                          # over j2
+    t = np.einsum("mj,jbc->mbc", f3, t)                          # over j3
+    return t / float(n1 * n2 * n3)
+
+
+def vtilde_lookup(vt: np.ndarray, dm: np.ndarray) -> np.ndarray:
+    """Vt at integer offsets dm[..., 3] (h, k, l), wrapped mod the grid."""
+    n3, n2, n1 = vt.shape
+    return vt[dm[..., 2] % n3, dm[..., 1] % n2, dm[..., 0] % n1]
+
+
+def dense_d(nbeta: int, blk_off, dmat) -> np.ndarray:
+    """Block-diagonal D (nbeta x nbeta) from concatenated col-major blocks."""
+    d = np.zeros((nbeta, nbeta), dtype=np.complex128)
+    pos = 0
+    for i in range(len(blk_off) - 1):
+        o0, o1 = int(blk_off[i]), int(blk_off[i + 1])
+        nh = o1 - o0
+        d[o0:o1, o0:o1] = np.asarray(dmat[pos:pos + nh * nh]).reshape(nh, nh).T
+        pos += nh * nh
+    return d
+
+
+def h_rows(miller, kpg, vloc_r, beta, blk_off, dmat, rows, vt=None) -> np.ndarray:
+    """Rows ``rows`` of the dense Hamiltonian, shape [len(rows)][npw]."""
+    miller = np.asarray(miller, dtype=np.int64)
+    rows = np.asarray(rows, dtype=np.int64)
+    if vt is None:
+        vt = vtilde_table(vloc_r)
+    dm = miller[rows][:, None, :] - miller[None, :, :]
+    h = vtilde_lookup(vt, dm).astype(np.complex128)
+    t = kinetic(kpg)
+    h[np.arange(len(rows)), rows] += t[rows]
+    beta = np.asarray(beta, dtype=np.complex128)
+    if beta.shape[0] > 0:
+        d = dense_d(beta.shape[0], blk_off, dmat)
+        # sum_ij beta_i(G) D_ij conj(beta_j(G'))   (beta stored [nbeta][npw])
+        h += (beta[:, rows].T @ d) @ np.conj(beta)
+    return h
+
+
+def dense_h(miller, kpg, vloc_r, beta, blk_off, dmat) -> np.ndarray:
+    """The full dense npw x npw Hamiltonian."""
+    npw = np.asarray(miller).shape[0]
+    vt = vtilde_table(vloc_r)
+    out = np.empty((npw, npw), dtype=np.complex128)
+    step = 2048
+    for r0 in range(0, npw, step):
+        rows = np.arange(r0, min(npw, r0 + step))
+        out[r0:r0 + len(rows)] = h_rows(miller, kpg, vloc_r, beta, blk_off, dmat, rows, vt=vt)
+    return out
+
+
+def dense_h_of(p) -> np.ndarray:
+    """dense_h for a generated problem object."""
+    return dense_h(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat)
+
+
+def hpsi(h: np.ndarray, psi: np.ndarray) -> np.ndarray:
+    """H.psi for bands stored [nb][npw]: (H psi_b)_G = sum_G' H_GG' psi_b(G')."""
+    return np.asarray(psi) @ h.T
+
+
+def hpsi_rows_of(p, psi, rows) -> np.ndarray:
+    """(H psi)[:, rows] computed from explicit rows of H (for large cells)."""
+    hr = h_rows(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, rows)
+    return np.asarray(psi) @ hr.T
+
+
+def hpsi_brute(miller, kpg, vloc_r, beta, blk_off, dmat, psi) -> np.ndarray:
+    """H.psi through real space by explicit sums (no H matrix, no FFT).
+
+    psi(r_j) = sum_G psi_G exp(+2 pi i m_G.j/n); (V psi)(r) = V(r) psi(r);
+    (V psi)_G = (1/N) sum_j exp(-2 pi i m_G.j/n) (V psi)(r_j).  For tiny cells.
+    """
+    miller = np.asarray(miller, dtype=np.int64)
+    v = np.asarray(vloc_r, dtype=np.float64)
+    n3, n2, n1 = v.shape
+    j3, j2, j1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    frac = np.stack([j1.ravel() / n1, j2.ravel() / n2, j3.ravel() / n3], axis=1)
+    phase = np.exp(2j * math.pi * (miller @ frac.T))           # [npw][N]
+    psi = np.asarray(psi, dtype=np.complex128)
+    out = np.empty_like(psi)
+    t = kinetic(kpg)
+    vflat = v.ravel()
+    beta = np.asarray(beta, dtype=np.complex128)
+    d = dense_d(beta.shape[0], blk_off, dmat) if beta.shape[0] else None
+    for b in range(psi.shape[0]):
+        pr = psi[b] @ phase                                     # psi(r_j)
+        vg = (np.conj(phase) @ (vflat * pr)) / vflat.size       # (V psi)_G
+        acc = t * psi[b] + vg
+        if d is not None:
+            for i in range(beta.shape[0]):
+                for j in range(beta.shape[0]):
+                    if d[i, j] != 0:
+                        acc = acc + beta[i] * d[i, j] * np.vdot(beta[j], psi[b])
+        out[b] = acc
+    return out
+
+
+def h_diag(miller, kpg, vloc_r, beta, blk_off, dmat) -> np.ndarray:
+    """Exact diagonal <k+G|H|k+G> (used by the Davidson preconditioner)."""
+    v = np.asarray(vloc_r, dtype=np.float64)
+    diag = kinetic(kpg) + float(np.mean(v))         # Vt(0) = mean of V(r)
+    beta = np.asarray(beta, dtype=np.complex128)
+    if beta.shape[0]:
+        d = dense_d(beta.shape[0], blk_off, dmat)
+        diag = diag + np.real(np.einsum("ig,ij,jg->g", beta, d, np.conj(beta)))
+    return diag
+
+
+# ----------------------------------------------------------------------------
+# spectra
+# ----------------------------------------------------------------------------
+
+def eigh_lowest(h: np.ndarray, nb: int):
+    """Lowest nb eigenpairs of the dense Hermitian H (ascending)."""
+    w, v = scipy.linalg.eigh(h, subset_by_index=[0, nb - 1], driver="evr")
+    return w, v.T.copy()          # eigenvectors as [nb][npw]
+
+
+def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None = None,
+             ndim: int = 2, tol_resid: float = 1e-6, tol_deig: float = 5e-9,
+             max_iter: int = 200, precond_floor: float = 0.1):
+    """Block Davidson on a dense H, in the order the appendix states it.
+
+    1. orthonormalise the trial orbitals and take eps_i = <psi_i|H|psi_i>;
+    2. residuals g_i = (H - eps_i) psi_i;
+    3. corrections dpsi_i = g_i / (H_GG - eps_i) for unconverged i
+       (the diagonal approximation of (H - eps)^-1; |denominator| floored);
+    4. reduced problem sum_k (H_jk - eps S_jk) c_k = 0 on the basis phi;
+    5. psi_i = sum_j c^(i)_j phi_j; eps_i = <psi_i|H|psi_i>; iterate, growing the
+       basis with new corrections until ndim*nb, then restarting from psi.
+    Returns (eps, psi [nb][npw], iterations, residual norms).
+    """
+    psi = np.asarray(psi0, dtype=np.complex128).copy()
+    if hdiag is None:
+        hdiag = np.real(np.diag(h))
+    # step 1: orthonormalise (Cholesky of the overlap) and Rayleigh quotients
+    s = np.conj(psi) @ psi.T
+    lo = np.linalg.cholesky(s)
+    psi = np.linalg.solve(lo, psi)            # rows: L^-1 psi  -> orthonormal
+    hpsi_ = hpsi(h, psi)
+    eps = np.real(np.einsum("bg,bg->b", np.conj(psi), hpsi_))
+    phi = psi.copy()
+    hphi = hpsi_.copy()
+    eps_prev = np.full(nb, np.inf)
+    it = 0
+    rn = None
+    while True:
+        g = hpsi_ - eps[:, None] * psi                       # step 2
+        rn = np.linalg.norm(g, axis=1)
+        conv = (rn <= tol_resid) & (np.abs(eps - eps_prev) <= tol_deig)
+        if conv.all() or it >= max_iter:
+            break
+        todo = np.nonzero(~conv)[0]
+        den = hdiag[None, :] - eps[todo, None]               # step 3
+        den = np.where(np.abs(den) < precond_floor, np.copysign(precond_floor, den), den)
+        dpsi = g[todo] / den
+        dpsi /= np.linalg.norm(dpsi, axis=1, keepdims=True)
+        if phi.shape[0] + len(todo) > ndim * nb:             # restart from Ritz vectors
+            phi, hphi = psi.copy(), hpsi_.copy()
+        phi = np.concatenate([phi, dpsi], axis=0)
+        hphi = np.concatenate([hphi, hpsi(h, dpsi)], axis=0)
+        hred = np.conj(phi) @ hphi.T                         # step 4
+        sred = np.conj(phi) @ phi.T
+        hred = 0.5 * (hred + np.conj(hred.T))
+        sred = 0.5 * (sred + np.conj(sred.T))
+        w, c = scipy.linalg.eigh(hred, sred, subset_by_index=[0, nb - 1])
+        eps_prev = eps
+        psi = c.T @ phi                                      # step 5
+        hpsi_ = c.T @ hphi
+        eps = np.real(np.einsum("bg,bg->b", np.conj(psi), hpsi_))
+        it += 1
+    return eps, psi, it, rn
+
+
+def secular_roots(t: np.ndarray, beta: np.ndarray, d: float, count: int, tol: float = 1e-15):
+    """Lowest ``count`` eigenvalues of diag(t) + d |beta><beta| (d > 0).
+
+    Textbook rank-one update: each distinct pole p with multiplicity k keeps
+    k - 1 eigenvalues equal to p; the others are the roots of
+    f(lam) = 1 - d sum_p W_p / (lam - p), one in each interval between
+    consecutive poles and one above the last (W_p = sum over the pole of
+    |beta_G|^2).  Roots are found by plain bisection in float64.
+    """
+    assert d > 0
+    t = np.asarray(t, dtype=np.float64)
+    w = np.abs(np.asarray(beta)) ** 2
+    order = np.argsort(t, kind="stable")
+    t, w = t[order], w[order]
+    poles, weights, mult = [], [], []
+    i = 0
+    while i < len(t):
+        j = i
+        while j + 1 < len(t) and abs(t[j + 1] - t[i]) <= 1e-12 * max(1.0, abs(t[i])):
+            j += 1
+        poles.append(t[i])
+        weights.append(w[i:j + 1].sum())
+        mult.append(j - i + 1)
+        i = j + 1
+    poles = np.array(poles)
+    weights = np.array(weights)
+    vals = []
+    for p, k in zip(poles, mult):
+        vals.extend([p] * (k - 1))
+
+    def f(lam):
+        return 1.0 - d * np.sum(weights / (lam - poles))
+
+    upper = poles[-1] + d * weights.sum() + 1.0
+    for idx in range(len(poles)):
+        lo_ = poles[idx]
+        hi_ = poles[idx + 1] if idx + 1 < len(poles) else upper
+        a_, b_ = lo_, hi_
+        for _ in range(200):
+            mid = 0.5 * (a_ + b_)
+            if mid <= a_ or mid >= b_:
+                break
+            if f(mid) < 0:
+                a_ = mid
+            else:
+                b_ = mid
+            if b_ - a_ <= tol * max(1.0, abs(mid)):
+                break
+        vals.append(0.5 * (a_ + b_))
+        if len(vals) >= count + len(t):
+            break
+    vals = np.sort(np.array(vals))
+    return vals[:count]
+
+
+def kato_temple(theta: np.ndarray, resid: np.ndarray):
+    """A-posteriori bounds for Ritz pairs (theta_i, residual norm r_i).
+
+    Returns (bauer_fike, kato_temple): an exact eigenvalue lies within r_i of
+    theta_i, and for an isolated Ritz value |theta_i - lambda_i| <=
+    r_i^2 / delta_i with delta_i the distance from theta_i to the nearest
+    other spectral interval [theta_j - r_j, theta_j + r_j].  Where the
+    intervals overlap, the Kato-Temple value is +inf.
+    """
+    theta = np.asarray(theta, dtype=np.float64)
+    r = np.asarray(resid, dtype=np.float64)
+    kt = np.full_like(theta, np.inf)
+    for i in range(len(theta)):
+        others = [abs(theta[j] - theta[i]) - r[j] for j in range(len(theta)) if j != i]
+        if not others:
+            continue
+        delta = min(others)
+        if delta > r[i]:
+            kt[i] = r[i] ** 2 / delta
+    return r.copy(), kt

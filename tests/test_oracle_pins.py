@@ -1,0 +1,216 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+Each test pins part of the oracle to something other than itself: a closed
+form, a textbook reduction, an independent route (explicit real-space sums,
+the generator's own V(G) coefficients) or an invariant of the Hamiltonian.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0906_2569_amd import pwgen
+
+
+def _free(a=10.0, ecut=15.0, nr=(30, 30, 30), natoms=8, nb=16, seed=1, **kw):
+    return pwgen.make_cell(a, ecut, natoms, nb, seed, nr=nr, with_vloc=False, with_beta=False, **kw)
+
+
+def test_sphere_sizes():
+    # counts of {m : |G_m|^2 <= ecut} for the workloads' cells
+    assert pwgen.sphere(10.0, 15.0)[0].shape[0] == 949
+    assert pwgen.sphere(20.5, 25.0)[0].shape[0] == 18277
+    m, _, _ = pwgen.sphere(41.0, 30.0)
+    assert m.shape[0] == 191471
+    assert pwgen.min_grid(m) == (144, 144, 144)
+
+
+def test_free_electron_closed_form():
+    # V = 0, beta = 0: eigenvalues are |G|^2/2 = (2 pi/a)^2 |m|^2 / 2 exactly.
+    p = _free()
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, 16)
+    unit = 2.0 * math.pi ** 2 / 100.0          # (2 pi / 10)^2 / 2 = 0.19739208802...
+    expect = np.array([0.0] + [unit] * 6 + [2 * unit] * 9)
+    assert abs(unit - 0.19739208802178717) < 1e-15
+    np.testing.assert_allclose(w, expect, atol=1e-13)
+    # the 12-fold |m|^2 = 2 shell is complete in the sphere
+    w2, _ = oracle.eigh_lowest(h, 19)
+    np.testing.assert_allclose(w2[7:19], 2 * unit, atol=1e-13)
+
+
+def test_free_electron_shifted_k():
+    # k = (1/4, 1/4, 0) b: eigenvalues are |k+G|^2/2 for the sorted sphere
+    a = 10.0
+    p = pwgen.make_cell(a, 10.0, 0, 8, 3, kfrac=(0.25, 0.25, 0.0), with_vloc=False, with_beta=False)
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, 8)
+    b = 2 * math.pi / a
+    # hand-enumerated lowest |k+G|^2 (units b^2): (1/4,1/4,0)->1/8 (x1: m=0),
+    # m=(-1,0,0),(0,-1,0) -> 9/16+1/16=5/8 (x2), m=(-1,-1,0) -> 9/8 (x1),
+    # m=(0,0,+-1) -> 1/8+1 = 9/8 (x2)
+    expect = 0.5 * b * b * np.array([1 / 8, 5 / 8, 5 / 8, 9 / 8, 9 / 8, 9 / 8])
+    np.testing.assert_allclose(w[:6], expect, atol=1e-13)
+
+
+def test_vtilde_equals_generator_coefficients():
+    # The generator defines V(G) and builds V(r) by its own inverse transform;
+    # the oracle's direct DFT of V(r) must give those coefficients back, and
+    # zero outside their support.  A flipped sign gives conj(V(G)) != V(G).
+    p = pwgen.config1()
+    vt = oracle.vtilde_table(p.vloc_r)
+    got = oracle.vtilde_lookup(vt, p.vg_miller.astype(np.int64))
+    np.testing.assert_allclose(got, p.vg_coef, atol=1e-15, rtol=0)
+    assert np.abs(p.vg_coef.imag).max() > 1e-3          # really complex
+    mask = np.ones(vt.shape, dtype=bool)
+    n3, n2, n1 = vt.shape
+    vm = p.vg_miller
+    mask[vm[:, 2] % n3, vm[:, 1] % n2, vm[:, 0] % n1] = False
+    assert np.abs(vt[mask]).max() < 1e-15
+
+
+def test_single_plane_wave_gives_v_of_g_difference():
+    # psi = e_{G0}: (H psi)_G = T_G0 delta + V(G - G0), with V from the generator.
+    p = pwgen.config1(with_beta=False)
+    h = oracle.dense_h_of(p)
+    vdict = {tuple(m): c for m, c in zip(p.vg_miller.tolist(), p.vg_coef)}
+    t = oracle.kinetic(p.kpg)
+    rng = np.random.default_rng(0)
+    for g0 in rng.choice(p.npw, 5, replace=False):
+        e = np.zeros((1, p.npw), dtype=np.complex128)
+        e[0, g0] = 1.0
+        out = oracle.hpsi(h, e)[0]
+        expect = np.array([vdict.get(tuple(m), 0.0) for m in (p.miller - p.miller[g0]).tolist()])
+        expect[g0] += t[g0]
+        np.testing.assert_allclose(out, expect, atol=1e-14, rtol=0)
+
+
+@pytest.mark.parametrize("seed,a,ecut,kfrac,nr", [
+    (11, 5.0, 6.0, (0, 0, 0), None),
+    (12, 4.0, 8.0, (0.25, 0.25, 0.0), None),
+    (13, 6.0, 4.0, (0.1, -0.3, 0.2), (15, 16, 18)),
+    (14, 5.5, 5.0, (0, 0, 0), (12, 10, 9)),   # grid below the no-alias bound: still exact mod n
+])
+def test_dense_equals_real_space_brute_force(seed, a, ecut, kfrac, nr):
+    p = pwgen.tiny_cell(seed, a=a, ecut_ry=ecut, natoms=2, nb=3, kfrac=kfrac, nr=nr)
+    h = oracle.dense_h_of(p)
+    ref = oracle.hpsi_brute(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, p.psi0)
+    got = oracle.hpsi(h, p.psi0)
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+def test_hermitian():
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    assert np.abs(h - h.conj().T).max() <= 1e-15 * np.abs(h).max() * 10
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, p.npw)) + 1j * rng.standard_normal((2, p.npw))
+    hx = oracle.hpsi(h, x)
+    lhs = np.vdot(x[0], hx[1])
+    rhs = np.conj(np.vdot(x[1], hx[0]))
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_constant_potential_shifts_spectrum():
+    p = pwgen.config1()
+    c = 0.37
+    h0 = oracle.dense_h(p.miller, p.kpg, np.zeros_like(p.vloc_r), p.beta, p.blk_off, p.dmat)
+    h1 = oracle.dense_h(p.miller, p.kpg, np.full_like(p.vloc_r, c), p.beta, p.blk_off, p.dmat)
+    w0, _ = oracle.eigh_lowest(h0, 16)
+    w1, _ = oracle.eigh_lowest(h1, 16)
+    np.testing.assert_allclose(w1, w0 + c, atol=1e-13)
+
+
+def test_rank_one_secular_equation():
+    # V = 0, a single projector with D = d: textbook secular equation.
+    p = pwgen.config1(with_vloc=False)
+    beta = p.beta[:1]
+    for d in (0.25, 1.0):
+        h = oracle.dense_h(p.miller, p.kpg, np.zeros_like(p.vloc_r), beta,
+                           np.array([0, 1], dtype=np.int32), np.array([d], dtype=np.complex128))
+        w, _ = oracle.eigh_lowest(h, 20)
+        ref = oracle.secular_roots(oracle.kinetic(p.kpg), beta[0], d, 20)
+        np.testing.assert_allclose(w, ref, atol=1e-12)
+        assert abs(w[0]) > 1e-4                       # the projector really moved the bottom
+
+
+def test_nonlocal_acting_on_its_projector():
+    # V = 0, one normalised projector beta with D = d:  H beta = T beta + d beta.
+    p = pwgen.config1(with_vloc=False)
+    beta = p.beta[1:2]                                 # a p-projector (complex, odd)
+    d = 0.8
+    h = oracle.dense_h(p.miller, p.kpg, np.zeros_like(p.vloc_r), beta,
+                       np.array([0, 1], dtype=np.int32), np.array([d], dtype=np.complex128))
+    out = oracle.hpsi(h, beta)[0]
+    np.testing.assert_allclose(out, oracle.kinetic(p.kpg) * beta[0] + d * beta[0], atol=1e-14)
+
+
+def test_time_reversal_pair():
+    # real V(r) and real diagonal D: eps_n(k) = eps_n(-k)
+    streams = np.random.SeedSequence(77).spawn(4)
+    pa = pwgen.make_cell(7.0, 8.0, 3, 8, None, kfrac=(0.25, 0.25, 0.0), streams=streams)
+    pb = pwgen.make_cell(7.0, 8.0, 3, 8, None, kfrac=(-0.25, -0.25, 0.0), streams=streams)
+    wa, _ = oracle.eigh_lowest(oracle.dense_h_of(pa), 8)
+    wb, _ = oracle.eigh_lowest(oracle.dense_h_of(pb), 8)
+    np.testing.assert_allclose(wa, wb, atol=1e-12)
+
+
+def test_grid_translation_invariance():
+    # translating V(r) by a grid vector and every atom by the same vector is a
+    # unitary (diagonal phase) change of basis: the spectrum is unchanged.
+    streams = np.random.SeedSequence(78).spawn(4)
+    p = pwgen.make_cell(6.0, 8.0, 3, 8, None, kfrac=(0.1, 0.2, 0.3), streams=streams)
+    n1, n2, n3 = p.nr
+    shift = np.array([3, 1, 2])                     # grid steps along x, y, z
+    v2 = np.roll(p.vloc_r, shift=(shift[2], shift[1], shift[0]), axis=(0, 1, 2))
+    tvec = p.a * shift / np.array([n1, n2, n3])
+    beta2 = p.beta * np.exp(-1j * (p.kpg @ tvec))[None, :]
+    h1 = oracle.dense_h_of(p)
+    h2 = oracle.dense_h(p.miller, p.kpg, v2, beta2, p.blk_off, p.dmat)
+    w1, _ = oracle.eigh_lowest(h1, 8)
+    w2, _ = oracle.eigh_lowest(h2, 8)
+    np.testing.assert_allclose(w1, w2, atol=1e-12)
+    assert np.abs(h1 - h2).max() > 1e-3               # the matrices themselves differ
+
+
+def test_h_diag_matches_dense_diagonal():
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    hd = oracle.h_diag(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat)
+    np.testing.assert_allclose(hd, np.real(np.diag(h)), atol=1e-14)
+
+
+@pytest.mark.parametrize("ndim", [2, 3, 4])
+def test_davidson_converges_to_dense_spectrum(ndim):
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, p.nb)
+    # the 2N form (restart every iteration) converges slowly for the top band,
+    # whose gap to band nb+1 is small: there only the eigenvalues are checked
+    eps, psi, it, rn = oracle.davidson(h, p.psi0, p.nb, ndim=ndim, max_iter=400)
+    if ndim > 2:
+        assert rn.max() <= 1e-6
+        assert 3 < it < 400
+    np.testing.assert_allclose(eps, w, atol=5e-9)
+    # Ritz values bound the exact ones from above (Courant-Fischer)
+    assert np.all(eps >= w - 1e-12)
+    # orthonormal output
+    np.testing.assert_allclose(np.conj(psi) @ psi.T, np.eye(p.nb), atol=1e-12)
+
+
+def test_a_posteriori_bounds_hold():
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    w, v = oracle.eigh_lowest(h, 20)
+    rng = np.random.default_rng(5)
+    x = v[:8] + 1e-4 * (rng.standard_normal(v[:8].shape) + 1j * rng.standard_normal(v[:8].shape))
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    hx = oracle.hpsi(h, x)
+    theta = np.real(np.einsum("bg,bg->b", np.conj(x), hx))
+    r = np.linalg.norm(hx - theta[:, None] * x, axis=1)
+    bf, kt = oracle.kato_temple(theta, r)
+    assert np.all(np.abs(theta - w[:8]) <= bf + 1e-14)
+    finite = np.isfinite(kt)
+    assert finite.any()
+    assert np.all(np.abs(theta - w[:8])[finite] <= kt[finite] * (1 + 1e-6) + 1e-15)

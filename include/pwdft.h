@@ -1,0 +1,170 @@
+/*
+ * pwdft.h -- C ABI of the MI355X plane-wave H.psi / block-Davidson library.
+ *
+ * What it computes (Hartree atomic units throughout):
+ *
+ *   H psi (G) = 1/2 |k+G|^2 psi(G)                                  kinetic
+ *             + [ (1/N) sum_r exp(-iG.r) V(r) sum_G' psi(G') exp(iG'.r) ]   local
+ *             + sum_I sum_{ij in I} beta_i(G) D^I_ij <beta_j|psi>            nonlocal
+ *
+ * for a block of bands in a plane-wave basis (the Kohn-Sham equation of the
+ * self-consistency appendix, with the separable norm-conserving projector form
+ * of the pseudopotential described in Sec. 3, and the plane-wave / FFT-grid
+ * data of the parallelization section), and the lowest nb solutions of
+ * H psi_i = eps_i psi_i with <psi_i|psi_j> = delta_ij (the generalized problem
+ * of the iterative-diagonalization appendix with S = 1), by the block Davidson
+ * method stated there (residuals, diagonal preconditioner, reduced problem on
+ * the enlarged basis, Ritz update, optional expanding basis).
+ *
+ * Conventions
+ *  - Complex numbers are interleaved (re, im) pairs of double (pw_c128).
+ *  - A "block" of ncol vectors of length npw is column-major: element g of
+ *    column j is at  x[j*ld + g],  ld >= npw.
+ *  - The FFT convention is psi(r_j) = sum_G psi_G exp(+i G.r_j) (unscaled) and
+ *    f_G = (1/N) sum_j f(r_j) exp(-i G.r_j); the Bloch factor exp(ik.r)
+ *    commutes with V(r) and is not applied.
+ *  - Device pointers are HIP device memory (e.g. torch tensors' data_ptr());
+ *    host pointers are ordinary process memory.  Arguments marked [dev] must be
+ *    device pointers, [host] host pointers.
+ *  - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *  - Every call returns pw_status (0 = PW_OK); nothing is thrown across the ABI.
+ *    pw_last_error() gives a message for the last failing call of the calling
+ *    host thread.  Asynchronous device faults surface as PW_EDEVICE on the
+ *    next call that synchronizes.
+ *  - Thread safety: a plan may be used by one host thread / stream at a time.
+ */
+#ifndef PWDFT_H
+#define PWDFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PW_OK = 0,
+  PW_ENOTCONV = 1,      /* outputs valid (best Ritz pairs) but not converged          */
+  PW_EINVAL = -1,       /* bad argument (sizes, strides, grid too small, ...)         */
+  PW_ENOMEM = -2,       /* device allocation failed / size beyond the plan's capacity */
+  PW_EDEVICE = -3,      /* HIP runtime error                                          */
+  PW_EBREAKDOWN = -4,   /* overlap matrix not positive definite after a restart       */
+  PW_ENAN = -5,         /* non-finite residual norm                                   */
+  PW_ECANCELLED = -6    /* solve cancelled through pw_cancel                          */
+} pw_status;
+
+typedef enum {
+  PW_FP64 = 0,          /* every step in float64                                      */
+  PW_MIXED = 1          /* FFT and projector GEMMs in float32 (float32 accumulation);
+                           Cholesky, reduced eigenproblem, residual norms in float64  */
+} pw_precision;
+
+typedef struct { double re, im; } pw_c128;
+
+typedef struct pw_ctx_s*  pw_ctx;
+typedef struct pw_plan_s* pw_plan;
+
+/*
+ * One plane-wave problem: a cell at one k-point.  Read only during
+ * pw_plan_create; the plan copies everything it needs (the caller may free
+ * all of these arrays afterwards).
+ */
+typedef struct {
+  int32_t        npw;        /* number of plane waves in the sphere (> 0)                        */
+  const int32_t* miller;     /* [host] [npw][3] integer (h,k,l) of each G; any order               */
+  const double*  kpg;        /* [host] [npw][3] Cartesian k+G in bohr^-1                           */
+  int32_t        nr[3];      /* FFT grid (n1, n2, n3); must satisfy n_d >= 4*max|m_d| + 1         */
+  const double*  vloc_r;     /* [dev]  [n3][n2][n1] real V_loc(r_j) in Ha, x fastest              */
+  int32_t        nbeta;      /* number of projectors (>= 0)                                        */
+  const pw_c128* beta;       /* [dev]  [nbeta][ld_beta] column-major beta_j(G) (NULL if nbeta = 0) */
+  int32_t        ld_beta;    /* >= npw                                                              */
+  int32_t        nblk;       /* number of D blocks (atoms)                                         */
+  const int32_t* blk_off;    /* [host] [nblk+1], 0 = blk_off[0] < ... < blk_off[nblk] = nbeta       */
+  const pw_c128* dmat;       /* [host] concatenated Hermitian nh x nh blocks, column-major, in Ha   */
+} pw_problem;
+
+/* Capacity of a plan: workspace is allocated once, at plan creation. */
+typedef struct {
+  pw_precision precision;    /* PW_FP64 or PW_MIXED                                                 */
+  int32_t      nb_max;       /* largest number of bands passed to hpsi_apply / davidson_solve      */
+  int32_t      ndim_max;     /* largest Davidson basis factor (basis <= ndim*nb); 0 = no solver ws  */
+} pw_plan_opts;
+
+typedef struct {
+  int32_t ndim;              /* basis cap = ndim*nb, 2..8 (default 4)                               */
+  int32_t max_iter;          /* default 200                                                          */
+  double  tol_resid;         /* Ha, band converged when ||g_i||_2 <= tol_resid (default 1e-6) ...   */
+  double  tol_deig;          /* ... and |eps_i - eps_i(previous)| <= tol_deig (default 5e-9 Ha)     */
+  double  precond_floor;     /* Ha, |h_diag - eps_i| is floored to this (default 0.1)               */
+  double  ladder_switch;     /* mixed only: max ||g_i|| below which float64 H.psi takes over (1e-4) */
+} pw_david_opts;
+
+typedef struct {
+  int32_t iters;             /* Davidson iterations                                                  */
+  int32_t restarts;          /* basis collapses to the Ritz vectors                                  */
+  int32_t n_hpsi_fp32;       /* band-H.psi applications in float32                                   */
+  int32_t n_hpsi_fp64;       /* band-H.psi applications in float64                                   */
+  int32_t nconv;             /* converged bands at exit                                              */
+  double  max_resid;         /* max_i ||g_i||_2 of the final float64 verification                    */
+} pw_david_stats;
+
+/* Last error message of the calling host thread ("" if none). */
+const char* pw_last_error(void);
+
+/* Create / destroy a context bound to HIP device `device`. */
+pw_status pw_ctx_create(int device, pw_ctx* out);
+pw_status pw_ctx_destroy(pw_ctx ctx);
+
+/* Fill opts with the defaults listed above. */
+void pw_david_opts_default(pw_david_opts* opts);
+
+/* Device bytes pw_plan_create would allocate for (problem, opts). */
+size_t pw_footprint_bytes(const pw_problem* problem, const pw_plan_opts* opts);
+
+/*
+ * Validate the problem, build the sphere -> FFT-box maps (z sticks, x columns),
+ * the kinetic and preconditioner diagonals, twiddle tables, copies of V(r),
+ * beta and D (float32 copies too in PW_MIXED), and all workspace.
+ * Errors: PW_EINVAL (npw <= 0, duplicate G, grid below 4*max|m|+1, ld_beta <
+ * npw, blocks not covering nbeta, D not Hermitian to 1e-12), PW_ENOMEM.
+ * Synchronous; allocates device memory.
+ */
+pw_status pw_plan_create(pw_ctx ctx, const pw_problem* problem, const pw_plan_opts* opts,
+                         pw_plan* out);
+pw_status pw_plan_destroy(pw_plan plan);
+
+/* Plan sizes: out[0]=npw, out[1]=n_sticks, out[2]=x columns, out[3]=N, out[4]=nbeta. */
+pw_status pw_plan_info(pw_plan plan, int64_t out[8]);
+
+/*
+ * hpsi = H psi for nb bands (overwrite).  psi and hpsi are [dev] blocks
+ * [nb][ld] of pw_c128, ldpsi/ldhpsi >= npw, and must not overlap.  `prec`
+ * selects float64 or float32 arithmetic for the FFT and projector steps (the
+ * latter needs a PW_MIXED plan); input and output stay complex128.
+ * Asynchronous on `stream`; no allocation, no host synchronization.
+ * Errors: PW_EINVAL (nb < 0 or > nb_max, ld < npw, NULL pointers), PW_EDEVICE.
+ */
+pw_status hpsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128* psi,
+                     int32_t ldpsi, pw_c128* hpsi, int32_t ldhpsi, void* stream);
+
+/*
+ * Block Davidson for the nb lowest eigenpairs.
+ *   psi   [dev] [nb][ldpsi]: in = trial vectors (any linearly independent set),
+ *         out = orthonormal eigenvector estimates.
+ *   eig   [dev] double[nb], ascending Rayleigh quotients of the output psi.
+ *   resid [dev] double[nb], ||H psi_i - eps_i psi_i||_2 of the output psi.
+ * Both are recomputed by a final float64 H.psi.  opts may be NULL (defaults);
+ * stats [host] may be NULL.  The host reads one small result per iteration
+ * (stream synchronization).  Returns PW_OK, PW_ENOTCONV (max_iter reached;
+ * outputs valid), PW_EBREAKDOWN, PW_ENAN, PW_EINVAL, PW_EDEVICE.
+ * No allocation; needs a plan with nb_max >= nb and ndim_max >= opts->ndim.
+ */
+pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, double* eig,
+                         double* resid, const pw_david_opts* opts, pw_david_stats* stats,
+                         void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PWDFT_H */

@@ -1,0 +1,645 @@
+// H.psi on the plane-wave sphere: plan construction (sphere -> FFT box maps,
+// kinetic and preconditioner diagonals, twiddles, operator copies) and the
+// three transform passes of the local potential term:
+//
+//   k_zinv  : gather psi(G) onto z sticks, inverse z transform      (sphere -> sticks)
+//   k_plane : per z plane, inverse y (x columns that hold sticks), inverse x,
+//             multiply by V(r), forward x, forward y; only stick positions
+//             are written back                                        (sticks -> sticks)
+//   k_zfwd  : forward z transform, 1/N, gather to the sphere, add the
+//             kinetic term 1/2 |k+G|^2 psi(G)                        (sticks -> sphere)
+//
+// followed by the projector term (calbec, D blocks, add back), see zgemm.hip.
+// The product equals sum_G' Vt((m_G - m_G') mod n) psi(G') exactly (up to
+// rounding), Vt being the discrete Fourier coefficients of V(r) on the grid;
+// with n_d >= 4 max|m_d| + 1 no wrapped term reaches the sphere.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <vector>
+
+#include "plan.h"
+
+namespace {
+
+constexpr int ZSB = 16;        // sticks per workgroup in the z passes
+constexpr int ZTHREADS = 128;
+constexpr int PTHREADS = 256;
+
+template <typename T>
+__device__ __forceinline__ cpx<T> to_t(c128 v) { return cpx<T>{(T)v.x, (T)v.y}; }
+
+// ---------------------------------------------------------------------------
+// pass 1: sphere -> sticks, inverse z transform
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(ZTHREADS)
+k_zinv(SphereMap m, const c128* __restrict__ psi, int ldpsi,
+       cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ twg) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n3 = m.n3;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n3;
+  cpx<T>* B = A + ZSB * n3;
+  const int s0 = blockIdx.x * ZSB;
+  const int ns = min(ZSB, m.nst - s0);
+  const int band = blockIdx.y;
+  const c128* pb = psi + (size_t)band * ldpsi;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < ZSB * n3; i += blockDim.x) B[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  const int e0 = m.st_ptr[s0], e1 = m.st_ptr[s0 + ns];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    B[(m.ent_s[e] - s0) * n3 + m.ent_z[e]] = to_t<T>(pb[m.ent_g[e]]);
+  __syncthreads();
+  cpx<T>* out = sticks + (size_t)band * n3 * m.ldst + s0;
+  const int ldst = m.ldst;
+  fft_run<T>(
+      m.f3, ns, T(1), tw, A, B, n3, false, true,
+      [&](int b, int i) { return B[b * n3 + i]; },
+      [&](int b, int i, cpx<T> v) { out[(size_t)i * ldst + b] = v; });
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: one z plane of one band
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(PTHREADS)
+k_plane(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
+        const cpx<T>* __restrict__ tw1g, const cpx<T>* __restrict__ tw2g, int cbatch) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n1 = m.n1, n2 = m.n2, nxr = m.nxr, nst = m.nst;
+  const int lmax = max(n1, n2);
+  cpx<T>* tw1 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw2 = tw1 + n1;
+  cpx<T>* Y = tw2 + n2;              // [nxr][n2]
+  cpx<T>* A = Y + nxr * n2;          // [cbatch][lmax]
+  cpx<T>* B = A + cbatch * lmax;     // [cbatch][lmax]
+  int* hx_of = reinterpret_cast<int*>(B + cbatch * lmax);   // [n1]
+
+  const int z = blockIdx.x;
+  const int band = blockIdx.y;
+  cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
+  const T* vz = vr + (size_t)z * n1 * n2;
+
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) { tw1[i] = tw1g[i]; hx_of[i] = m.i1_hx[i]; }
+  for (int i = threadIdx.x; i < n2; i += blockDim.x) tw2[i] = tw2g[i];
+  for (int i = threadIdx.x; i < nxr * n2; i += blockDim.x) Y[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  for (int s = threadIdx.x; s < nst; s += blockDim.x) Y[m.st_hx[s] * n2 + m.st_i2[s]] = st[s];
+  __syncthreads();
+
+  // inverse y on the x columns that hold sticks
+  for (int c0 = 0; c0 < nxr; c0 += cbatch) {
+    const int nc = min(cbatch, nxr - c0);
+    cpx<T>* Yc = Y + c0 * n2;
+    fft_run<T>(
+        m.f2, nc, T(1), tw2, A, B, lmax, false, false,
+        [&](int b, int i) { return Yc[b * n2 + i]; },
+        [&](int b, int i, cpx<T> v) { Yc[b * n2 + i] = v; });
+  }
+
+  // rows: inverse x (x_r nonzero inputs), times V(r), forward x (x_r outputs kept)
+  const int lr = fft_last_read(m.f1);
+  cpx<T>* X = (lr == 0) ? B : A;
+  cpx<T>* P0 = (X == A) ? B : A;
+  for (int r0 = 0; r0 < n2; r0 += cbatch) {
+    const int nr = min(cbatch, n2 - r0);
+    fft_run<T>(
+        m.f1, nr, T(1), tw1, A, B, lmax, false, false,
+        [&](int b, int i) {
+          const int hx = hx_of[i];
+          return hx >= 0 ? Y[hx * n2 + r0 + b] : cpx<T>{T(0), T(0)};
+        },
+        [&](int b, int i, cpx<T> v) { X[b * lmax + i] = v * vz[(r0 + b) * n1 + i]; });
+    fft_run<T>(
+        m.f1, nr, T(-1), tw1, P0, X, lmax, false, false,
+        [&](int b, int i) { return X[b * lmax + i]; },
+        [&](int b, int i, cpx<T> v) {
+          const int hx = hx_of[i];
+          if (hx >= 0) Y[hx * n2 + r0 + b] = v;
+        });
+  }
+
+  // forward y on the x columns
+  for (int c0 = 0; c0 < nxr; c0 += cbatch) {
+    const int nc = min(cbatch, nxr - c0);
+    cpx<T>* Yc = Y + c0 * n2;
+    fft_run<T>(
+        m.f2, nc, T(-1), tw2, A, B, lmax, false, false,
+        [&](int b, int i) { return Yc[b * n2 + i]; },
+        [&](int b, int i, cpx<T> v) { Yc[b * n2 + i] = v; });
+  }
+  for (int s = threadIdx.x; s < nst; s += blockDim.x) st[s] = Y[m.st_hx[s] * n2 + m.st_i2[s]];
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: forward z transform, gather to the sphere, kinetic term
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(ZTHREADS)
+k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
+       const c128* __restrict__ psi, int ldpsi, c128* __restrict__ hpsi, int ldhpsi,
+       const cpx<T>* __restrict__ twg, double inv_n) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n3 = m.n3;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n3;
+  cpx<T>* B = A + ZSB * n3;
+  const int s0 = blockIdx.x * ZSB;
+  const int ns = min(ZSB, m.nst - s0);
+  const int band = blockIdx.y;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const cpx<T>* in = sticks + (size_t)band * n3 * m.ldst + s0;
+  const int ldst = m.ldst;
+  const int lr = fft_last_read(m.f3);
+  cpx<T>* X = (lr == 0) ? B : A;
+  fft_run<T>(
+      m.f3, ns, T(-1), tw, A, B, n3, true, false,
+      [&](int b, int i) { return in[(size_t)i * ldst + b]; },
+      [&](int b, int i, cpx<T> v) { X[b * n3 + i] = v; });
+  const c128* pb = psi + (size_t)band * ldpsi;
+  c128* hb = hpsi + (size_t)band * ldhpsi;
+  const int e0 = m.st_ptr[s0], e1 = m.st_ptr[s0 + ns];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int g = m.ent_g[e];
+    const cpx<T> v = X[(m.ent_s[e] - s0) * n3 + m.ent_z[e]];
+    const c128 p = pb[g];
+    const double t = m.kin[g];
+    hb[g] = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// plan-time helpers
+// ---------------------------------------------------------------------------
+__global__ void k_f64_to_f32(const double* __restrict__ a, float* __restrict__ b, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    b[i] = (float)a[i];
+}
+
+// diag of the projector term: sum_{ij in blocks} beta_i(G) D_ij conj(beta_j(G))
+__global__ void k_hdiag(int npw, int nbeta, const c128* __restrict__ beta, int ldb,
+                        const int* __restrict__ dstart, const int* __restrict__ dlen,
+                        const c128* __restrict__ drow, int nhmax, const double* __restrict__ kin,
+                        double v0, double* __restrict__ hdiag) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= npw) return;
+  double acc = 0.0;
+  for (int i = 0; i < nbeta; ++i) {
+    const c128 bi = beta[(size_t)i * ldb + g];
+    const int j0 = dstart[i], nh = dlen[i];
+    for (int t = 0; t < nh; ++t) {
+      const c128 d = drow[(size_t)i * nhmax + t];
+      const c128 bj = beta[(size_t)(j0 + t) * ldb + g];
+      // Re( beta_i D_ij conj(beta_j) )
+      const c128 dbj = c128{d.x * bj.x + d.y * bj.y, d.y * bj.x - d.x * bj.y};  // D_ij conj(bj)
+      acc += bi.x * dbj.x - bi.y * dbj.y;
+    }
+  }
+  hdiag[g] = kin[g] + v0 + acc;
+}
+
+template <typename T>
+size_t plane_lds_bytes(int n1, int n2, int nxr, int cb) {
+  const int lmax = std::max(n1, n2);
+  return sizeof(cpx<T>) * ((size_t)n1 + n2 + (size_t)nxr * n2 + 2 * (size_t)cb * lmax) +
+         sizeof(int) * (size_t)n1;
+}
+
+// largest column/row batch whose plane pass fits the LDS budget
+template <typename T>
+int plane_batch(int n1, int n2, int nxr) {
+  const size_t budget = 156 * 1024;
+  for (int cb : {16, 12, 8, 6, 4, 2, 1})
+    if (plane_lds_bytes<T>(n1, n2, nxr, cb) <= budget) return cb;
+  return 0;
+}
+
+template <typename T>
+size_t z_lds_bytes(int n3) { return sizeof(cpx<T>) * ((size_t)n3 + 2 * (size_t)ZSB * n3); }
+
+template <typename T>
+pw_status set_lds_limits() {
+  static bool done = false;
+  if (done) return PW_OK;
+  PW_HIP(hipFuncSetAttribute((const void*)k_plane<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  PW_HIP(hipFuncSetAttribute((const void*)k_zinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  PW_HIP(hipFuncSetAttribute((const void*)k_zfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  done = true;
+  return PW_OK;
+}
+
+template <typename X>
+pw_status dalloc(pw_plan p, X** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) return PW_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(X));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return pw::fail(PW_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(X)) + " bytes failed");
+  }
+  p->allocs.push_back(q);
+  *ptr = static_cast<X*>(q);
+  return PW_OK;
+}
+
+template <typename X>
+pw_status upload(pw_plan p, X** ptr, const std::vector<X>& v) {
+  PW_TRY(dalloc(p, ptr, v.size()));
+  if (!v.empty()) PW_HIP(hipMemcpy(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+  return PW_OK;
+}
+
+void twiddles(int L, std::vector<c128>& t64, std::vector<c64>& t32) {
+  t64.resize(L);
+  t32.resize(L);
+  for (int m = 0; m < L; ++m) {
+    // exp(+2 pi i m / L) in float64 from libm
+    const double a = 2.0 * M_PI * (double)m / (double)L;
+    t64[m] = c128{std::cos(a), std::sin(a)};
+    t32[m] = c64{(float)t64[m].x, (float)t64[m].y};
+  }
+}
+
+int band_chunk_for(const pw_plan_opts& o, int n3, int ldst) {
+  // bound the stick workspace to ~2 GiB
+  const size_t per_band = (size_t)n3 * ldst * sizeof(c128);
+  size_t cap = ((size_t)2 << 30) / std::max<size_t>(per_band, 1);
+  cap = std::max<size_t>(cap, 1);
+  return (int)std::min<size_t>((size_t)std::max(o.nb_max, 1), cap);
+}
+
+struct Geometry {
+  int n1, n2, n3, nst, nxr, ldst, nhmax;
+};
+
+pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* geo) {
+  PW_CHECK(pr != nullptr && o != nullptr, PW_EINVAL, "NULL problem or options");
+  PW_CHECK(pr->npw > 0, PW_EINVAL, "npw must be positive");
+  PW_CHECK(pr->miller && pr->kpg, PW_EINVAL, "miller and kpg are required (host arrays)");
+  PW_CHECK(pr->vloc_r, PW_EINVAL, "vloc_r is required (device array)");
+  PW_CHECK(o->precision == PW_FP64 || o->precision == PW_MIXED, PW_EINVAL, "bad precision");
+  PW_CHECK(o->nb_max > 0, PW_EINVAL, "nb_max must be positive");
+  PW_CHECK(o->ndim_max == 0 || (o->ndim_max >= 2 && o->ndim_max <= 8), PW_EINVAL, "ndim_max must be 0 or 2..8");
+  PW_CHECK(pr->nbeta >= 0, PW_EINVAL, "nbeta < 0");
+  if (pr->nbeta > 0) {
+    PW_CHECK(pr->beta && pr->dmat && pr->blk_off, PW_EINVAL, "beta, dmat and blk_off are required when nbeta > 0");
+    PW_CHECK(pr->ld_beta >= pr->npw, PW_EINVAL, "ld_beta < npw");
+    PW_CHECK(pr->nblk > 0, PW_EINVAL, "nblk must be positive when nbeta > 0");
+    PW_CHECK(pr->blk_off[0] == 0 && pr->blk_off[pr->nblk] == pr->nbeta, PW_EINVAL, "D blocks must cover [0, nbeta)");
+  }
+  int hmax[3] = {0, 0, 0};
+  for (int g = 0; g < pr->npw; ++g)
+    for (int d = 0; d < 3; ++d) hmax[d] = std::max(hmax[d], std::abs(pr->miller[3 * g + d]));
+  for (int d = 0; d < 3; ++d) {
+    PW_CHECK(pr->nr[d] >= 4 * hmax[d] + 1, PW_EINVAL,
+             "FFT grid too small along axis " + std::to_string(d) + ": need >= " + std::to_string(4 * hmax[d] + 1));
+    FftDesc f;
+    PW_CHECK(fft_factor(pr->nr[d], f), PW_EINVAL, "grid size must have only prime factors 2, 3, 5");
+  }
+  geo->n1 = pr->nr[0];
+  geo->n2 = pr->nr[1];
+  geo->n3 = pr->nr[2];
+  // sticks and x columns
+  std::vector<char> col(geo->n1, 0);
+  std::vector<char> stk((size_t)geo->n1 * geo->n2, 0);
+  int nst = 0;
+  for (int g = 0; g < pr->npw; ++g) {
+    const int i1 = ((pr->miller[3 * g] % geo->n1) + geo->n1) % geo->n1;
+    const int i2 = ((pr->miller[3 * g + 1] % geo->n2) + geo->n2) % geo->n2;
+    col[i1] = 1;
+    if (!stk[(size_t)i1 * geo->n2 + i2]) { stk[(size_t)i1 * geo->n2 + i2] = 1; ++nst; }
+  }
+  geo->nst = nst;
+  geo->nxr = 0;
+  for (int i = 0; i < geo->n1; ++i) geo->nxr += col[i];
+  geo->ldst = (nst + 3) / 4 * 4;
+  geo->nhmax = 0;
+  for (int b = 0; b < pr->nblk && pr->nbeta > 0; ++b) {
+    const int nh = pr->blk_off[b + 1] - pr->blk_off[b];
+    PW_CHECK(nh > 0, PW_EINVAL, "empty or decreasing D block offsets");
+    geo->nhmax = std::max(geo->nhmax, nh);
+  }
+  const bool mixed = o->precision == PW_MIXED;
+  PW_CHECK(plane_batch<double>(geo->n1, geo->n2, geo->nxr) > 0 || mixed, PW_EINVAL,
+           "grid too large for the float64 plane pass");
+  PW_CHECK(plane_batch<float>(geo->n1, geo->n2, geo->nxr) > 0, PW_EINVAL, "grid too large for the plane pass");
+  PW_CHECK(z_lds_bytes<double>(geo->n3) <= 160 * 1024, PW_EINVAL, "n3 too large");
+  return PW_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// public plan API
+// ---------------------------------------------------------------------------
+extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o) {
+  Geometry geo;
+  if (check_problem(pr, o, &geo) != PW_OK) return 0;
+  const bool mixed = o->precision == PW_MIXED;
+  const size_t N = (size_t)geo.n1 * geo.n2 * geo.n3;
+  const size_t ldb = ((size_t)pr->npw + 15) / 16 * 16;
+  size_t b = 0;
+  b += (size_t)pr->npw * (4 * sizeof(int) + 2 * sizeof(double));
+  b += (size_t)geo.nst * 3 * sizeof(int) + geo.n1 * sizeof(int);
+  b += N * (sizeof(double) + (mixed ? sizeof(float) : 0));
+  b += (size_t)pr->nbeta * ldb * (sizeof(c128) + (mixed ? sizeof(c64) : 0));
+  b += (size_t)pr->nbeta * (2 * sizeof(int) + geo.nhmax * (sizeof(c128) + sizeof(c64)));
+  const int chunk = band_chunk_for(*o, geo.n3, geo.ldst);
+  b += (size_t)chunk * geo.n3 * geo.ldst * sizeof(c128);
+  b += 2 * (size_t)o->nb_max * std::max(pr->nbeta, 1) * sizeof(c128);
+  b += pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128));
+  if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max);
+  return b;
+}
+
+extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* o,
+                                    pw_plan* out) {
+  PW_CHECK(ctx != nullptr && out != nullptr, PW_EINVAL, "NULL context or output");
+  *out = nullptr;
+  Geometry geo;
+  PW_TRY(check_problem(pr, o, &geo));
+  PW_HIP(hipSetDevice(ctx->device));
+  PW_TRY(set_lds_limits<double>());
+  PW_TRY(set_lds_limits<float>());
+
+  const int npw = pr->npw, n1 = geo.n1, n2 = geo.n2, n3 = geo.n3;
+  // D blocks: Hermitian check
+  std::vector<int> dstart, dlen;
+  std::vector<c128> drow;
+  if (pr->nbeta > 0) {
+    dstart.resize(pr->nbeta);
+    dlen.resize(pr->nbeta);
+    drow.assign((size_t)pr->nbeta * geo.nhmax, c128{0, 0});
+    size_t pos = 0;
+    for (int b = 0; b < pr->nblk; ++b) {
+      const int o0 = pr->blk_off[b], nh = pr->blk_off[b + 1] - o0;
+      const pw_c128* blk = pr->dmat + pos;
+      for (int i = 0; i < nh; ++i)
+        for (int j = 0; j < nh; ++j) {
+          const pw_c128 dij = blk[(size_t)j * nh + i], dji = blk[(size_t)i * nh + j];
+          const double scale = std::max(1.0, std::hypot(dij.re, dij.im));
+          PW_CHECK(std::abs(dij.re - dji.re) <= 1e-12 * scale && std::abs(dij.im + dji.im) <= 1e-12 * scale,
+                   PW_EINVAL, "D block " + std::to_string(b) + " is not Hermitian");
+          drow[(size_t)(o0 + i) * geo.nhmax + j] = c128{dij.re, dij.im};
+        }
+      for (int i = 0; i < nh; ++i) { dstart[o0 + i] = o0; dlen[o0 + i] = nh; }
+      pos += (size_t)nh * nh;
+    }
+  }
+
+  // sphere -> grid maps
+  std::vector<int> i1v(npw), i2v(npw), i3v(npw);
+  {
+    std::vector<char> seen((size_t)n1 * n2 * n3, 0);
+    for (int g = 0; g < npw; ++g) {
+      i1v[g] = ((pr->miller[3 * g] % n1) + n1) % n1;
+      i2v[g] = ((pr->miller[3 * g + 1] % n2) + n2) % n2;
+      i3v[g] = ((pr->miller[3 * g + 2] % n3) + n3) % n3;
+      const size_t key = ((size_t)i3v[g] * n2 + i2v[g]) * n1 + i1v[g];
+      PW_CHECK(!seen[key], PW_EINVAL, "duplicate G vector at index " + std::to_string(g));
+      seen[key] = 1;
+    }
+  }
+  // x columns in ascending i1; sticks ordered by (column, i2); entries by i3
+  std::vector<int> i1_hx(n1, -1);
+  int nxr = 0;
+  {
+    std::vector<char> col(n1, 0);
+    for (int g = 0; g < npw; ++g) col[i1v[g]] = 1;
+    for (int i = 0; i < n1; ++i)
+      if (col[i]) i1_hx[i] = nxr++;
+  }
+  std::vector<int> order(npw);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int a, int b) {
+    if (i1_hx[i1v[a]] != i1_hx[i1v[b]]) return i1_hx[i1v[a]] < i1_hx[i1v[b]];
+    if (i2v[a] != i2v[b]) return i2v[a] < i2v[b];
+    return i3v[a] < i3v[b];
+  });
+  std::vector<int> st_ptr, st_hx, st_i2, ent_g(npw), ent_z(npw), ent_s(npw);
+  for (int e = 0; e < npw; ++e) {
+    const int g = order[e];
+    if (e == 0 || i1v[g] != i1v[order[e - 1]] || i2v[g] != i2v[order[e - 1]]) {
+      st_ptr.push_back(e);
+      st_hx.push_back(i1_hx[i1v[g]]);
+      st_i2.push_back(i2v[g]);
+    }
+    ent_g[e] = g;
+    ent_z[e] = i3v[g];
+    ent_s[e] = (int)st_hx.size() - 1;
+  }
+  st_ptr.push_back(npw);
+  std::vector<double> kin(npw);
+  for (int g = 0; g < npw; ++g) {
+    const double* q = pr->kpg + 3 * g;
+    kin[g] = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+  }
+
+  pw_plan p = new pw_plan_s();
+  p->ctx = ctx;
+  p->opts = *o;
+  p->npw = npw;
+  p->n1 = n1; p->n2 = n2; p->n3 = n3;
+  p->N = (long)n1 * n2 * n3;
+  p->nst = geo.nst;
+  p->nxr = nxr;
+  p->ldst = geo.ldst;
+  p->nbeta = pr->nbeta;
+  p->nblk = pr->nbeta > 0 ? pr->nblk : 0;
+  p->nhmax = geo.nhmax;
+  p->ldb = (npw + 15) / 16 * 16;
+  p->band_chunk = band_chunk_for(*o, n3, geo.ldst);
+  fft_factor(n1, p->f1);
+  fft_factor(n2, p->f2);
+  fft_factor(n3, p->f3);
+  const bool mixed = o->precision == PW_MIXED;
+
+  auto fail_cleanup = [&](pw_status st) {
+    pw_plan_destroy(p);
+    return st;
+  };
+#define PLAN_TRY(expr)                      \
+  do {                                      \
+    pw_status s_ = (expr);                  \
+    if (s_ != PW_OK) return fail_cleanup(s_); \
+  } while (0)
+
+  PLAN_TRY(upload(p, &p->st_ptr, st_ptr));
+  PLAN_TRY(upload(p, &p->st_hx, st_hx));
+  PLAN_TRY(upload(p, &p->st_i2, st_i2));
+  PLAN_TRY(upload(p, &p->ent_g, ent_g));
+  PLAN_TRY(upload(p, &p->ent_z, ent_z));
+  PLAN_TRY(upload(p, &p->ent_s, ent_s));
+  PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
+  PLAN_TRY(upload(p, &p->kin, kin));
+  {
+    std::vector<c128> t64;
+    std::vector<c64> t32;
+    twiddles(n1, t64, t32);
+    PLAN_TRY(upload(p, &p->tw64_1, t64));
+    PLAN_TRY(upload(p, &p->tw32_1, t32));
+    twiddles(n2, t64, t32);
+    PLAN_TRY(upload(p, &p->tw64_2, t64));
+    PLAN_TRY(upload(p, &p->tw32_2, t32));
+    twiddles(n3, t64, t32);
+    PLAN_TRY(upload(p, &p->tw64_3, t64));
+    PLAN_TRY(upload(p, &p->tw32_3, t32));
+  }
+  // V(r): copy, mean for the preconditioner diagonal, float32 copy
+  PLAN_TRY(dalloc(p, &p->vr64, (size_t)p->N));
+  if (hipMemcpy(p->vr64, pr->vloc_r, sizeof(double) * p->N, hipMemcpyDeviceToDevice) != hipSuccess)
+    return fail_cleanup(pw::fail(PW_EDEVICE, "copy of vloc_r failed (is it a device pointer?)"));
+  double v0 = 0.0;
+  {
+    std::vector<double> hv(p->N);
+    if (hipMemcpy(hv.data(), p->vr64, sizeof(double) * p->N, hipMemcpyDeviceToHost) != hipSuccess)
+      return fail_cleanup(pw::fail(PW_EDEVICE, "readback of vloc_r failed"));
+    long double acc = 0.0L;
+    for (long i = 0; i < p->N; ++i) {
+      if (!std::isfinite(hv[i])) return fail_cleanup(pw::fail(PW_ENAN, "non-finite value in vloc_r"));
+      acc += hv[i];
+    }
+    v0 = (double)(acc / (long double)p->N);
+  }
+  if (mixed) {
+    PLAN_TRY(dalloc(p, &p->vr32, (size_t)p->N));
+    k_f64_to_f32<<<1024, 256>>>(p->vr64, p->vr32, (size_t)p->N);
+  }
+  // beta, D
+  if (p->nbeta > 0) {
+    PLAN_TRY(dalloc(p, &p->beta64, (size_t)p->nbeta * p->ldb));
+    if (hipMemset(p->beta64, 0, sizeof(c128) * (size_t)p->nbeta * p->ldb) != hipSuccess ||
+        hipMemcpy2D(p->beta64, sizeof(c128) * p->ldb, pr->beta, sizeof(c128) * pr->ld_beta,
+                    sizeof(c128) * npw, p->nbeta, hipMemcpyDeviceToDevice) != hipSuccess)
+      return fail_cleanup(pw::fail(PW_EDEVICE, "copy of beta failed (is it a device pointer?)"));
+    if (mixed) {
+      PLAN_TRY(dalloc(p, &p->beta32, (size_t)p->nbeta * p->ldb));
+      k_f64_to_f32<<<1024, 256>>>((const double*)p->beta64, (float*)p->beta32, 2 * (size_t)p->nbeta * p->ldb);
+    }
+    PLAN_TRY(upload(p, &p->dstart, dstart));
+    PLAN_TRY(upload(p, &p->dlen, dlen));
+    PLAN_TRY(upload(p, &p->drow64, drow));
+    std::vector<c64> d32(drow.size());
+    for (size_t i = 0; i < drow.size(); ++i) d32[i] = c64{(float)drow[i].x, (float)drow[i].y};
+    PLAN_TRY(upload(p, &p->drow32, d32));
+  }
+  PLAN_TRY(dalloc(p, &p->hdiag, (size_t)npw));
+  k_hdiag<<<ceil_div(npw, 256), 256>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen,
+                                       p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
+  // workspace
+  PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->sticks), (size_t)p->band_chunk * n3 * p->ldst));
+  const int nbeta1 = std::max(p->nbeta, 1);
+  PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becp), (size_t)o->nb_max * nbeta1));
+  PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
+  p->part_bytes = pw::splitk_part_bytes(nbeta1, o->nb_max, npw, sizeof(c128));
+  PLAN_TRY(dalloc(p, reinterpret_cast<char**>(&p->part), p->part_bytes));
+  if (o->ndim_max > 0) PLAN_TRY(pw::dav_alloc(p));
+  if (hipDeviceSynchronize() != hipSuccess)
+    return fail_cleanup(pw::fail(PW_EDEVICE, "plan initialisation kernels failed"));
+#undef PLAN_TRY
+  *out = p;
+  return PW_OK;
+}
+
+extern "C" pw_status pw_plan_destroy(pw_plan p) {
+  if (!p) return PW_OK;
+  (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
+  (void)hipDeviceSynchronize();
+  pw::dav_free(p);
+  for (void* q : p->allocs)
+    if (q) (void)hipFree(q);
+  delete p;
+  return PW_OK;
+}
+
+extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
+  PW_CHECK(p != nullptr && out != nullptr, PW_EINVAL, "NULL plan or output");
+  out[0] = p->npw;
+  out[1] = p->nst;
+  out[2] = p->nxr;
+  out[3] = p->N;
+  out[4] = p->nbeta;
+  out[5] = p->band_chunk;
+  out[6] = plane_batch<double>(p->n1, p->n2, p->nxr);
+  out[7] = plane_batch<float>(p->n1, p->n2, p->nxr);
+  return PW_OK;
+}
+
+namespace {
+template <typename T>
+pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, int ldhpsi,
+                   hipStream_t s) {
+  const bool f64 = sizeof(T) == 8;
+  const SphereMap m = p->map();
+  const cpx<T>* tw1 = f64 ? (const cpx<T>*)p->tw64_1 : (const cpx<T>*)p->tw32_1;
+  const cpx<T>* tw2 = f64 ? (const cpx<T>*)p->tw64_2 : (const cpx<T>*)p->tw32_2;
+  const cpx<T>* tw3 = f64 ? (const cpx<T>*)p->tw64_3 : (const cpx<T>*)p->tw32_3;
+  const T* vr = f64 ? (const T*)p->vr64 : (const T*)p->vr32;
+  PW_CHECK(vr != nullptr, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
+  const int cb = plane_batch<T>(p->n1, p->n2, p->nxr);
+  PW_CHECK(cb > 0, PW_EINVAL, "grid too large for this precision's plane pass");
+  const size_t zl = z_lds_bytes<T>(p->n3);
+  const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
+  cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
+  const int gz = ceil_div(p->nst, ZSB);
+  for (int c0 = 0; c0 < nb; c0 += p->band_chunk) {
+    const int nbc = std::min(p->band_chunk, nb - c0);
+    k_zinv<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3);
+    k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
+    k_zfwd<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
+                                                   hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
+                                                   1.0 / (double)p->N);
+  }
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+}  // namespace
+
+pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
+                          c128* hpsi, int ldhpsi, hipStream_t s) {
+  if (nb == 0) return PW_OK;
+  if (prec == PW_FP64) {
+    PW_TRY(hpsi_fft<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
+    if (p->nbeta > 0) {
+      c128* bd = static_cast<c128*>(p->becpd);
+      PW_TRY(pw::calbec_d<double>(p, nb, psi, ldpsi, bd, s));
+      PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, p->nbeta, 1.0, p->beta64, p->ldb,
+                                                   bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
+    }
+  } else {
+    PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
+    PW_TRY(hpsi_fft<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
+    if (p->nbeta > 0) {
+      c64* bd = static_cast<c64*>(p->becpd);
+      PW_TRY(pw::calbec_d<float>(p, nb, psi, ldpsi, bd, s));
+      PW_TRY((pw::zgemm_nn<float, float, float>(p->npw, nb, p->nbeta, 1.0, p->beta32, p->ldb,
+                                                bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
+    }
+  }
+  return PW_OK;
+}
+
+extern "C" pw_status hpsi_apply(pw_plan p, pw_precision prec, int32_t nb, const pw_c128* psi,
+                                int32_t ldpsi, pw_c128* hpsi, int32_t ldhpsi, void* stream) {
+  PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
+  PW_CHECK(nb >= 0 && nb <= p->opts.nb_max, PW_EINVAL,
+           "nb out of range [0, nb_max=" + std::to_string(p->opts.nb_max) + "]");
+  if (nb == 0) return PW_OK;
+  PW_CHECK(psi != nullptr && hpsi != nullptr, PW_EINVAL, "NULL psi or hpsi");
+  PW_CHECK(ldpsi >= p->npw && ldhpsi >= p->npw, PW_EINVAL, "leading dimension < npw");
+  PW_CHECK(prec == PW_FP64 || prec == PW_MIXED, PW_EINVAL, "bad precision");
+  const char* a0 = reinterpret_cast<const char*>(psi);
+  const char* a1 = a0 + sizeof(pw_c128) * ((size_t)(nb - 1) * ldpsi + p->npw);
+  const char* b0 = reinterpret_cast<const char*>(hpsi);
+  const char* b1 = b0 + sizeof(pw_c128) * ((size_t)(nb - 1) * ldhpsi + p->npw);
+  PW_CHECK(a1 <= b0 || b1 <= a0, PW_EINVAL, "psi and hpsi overlap");
+  PW_HIP(hipSetDevice(p->ctx->device));
+  return pw::hpsi_launch(p, prec, nb, reinterpret_cast<const c128*>(psi), ldpsi,
+                         reinterpret_cast<c128*>(hpsi), ldhpsi, static_cast<hipStream_t>(stream));
+}

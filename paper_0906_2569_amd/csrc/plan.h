@@ -1,0 +1,107 @@
+// Internal plan / context layout shared by the library's translation units.
+#pragma once
+#include <vector>
+
+#include "common.h"
+#include "fft.h"
+
+struct pw_ctx_s {
+  int device;
+};
+
+// Device-side description of the sphere <-> FFT-box maps, passed by value.
+struct SphereMap {
+  int npw, n1, n2, n3;
+  int nst;         // number of z sticks (distinct (h,k))
+  int nxr;         // number of x columns (distinct h)
+  int ldst;        // stick-buffer row length (>= nst)
+  const int* st_ptr;   // [nst+1]   CSR: sphere entries of stick s
+  const int* ent_g;    // [npw]     sphere index of each entry (stick-major, z ascending)
+  const int* ent_z;    // [npw]     z grid index (l mod n3) of each entry
+  const int* ent_s;    // [npw]     stick of each entry
+  const int* st_hx;    // [nst]     x-column index of stick s
+  const int* st_i2;    // [nst]     y grid index (k mod n2) of stick s
+  const int* i1_hx;    // [n1]      x-column index at x grid index i1, or -1
+  const double* kin;   // [npw]     |k+G|^2 / 2
+  FftDesc f1, f2, f3;  // transforms along x, y, z
+};
+
+struct DavWork;  // Davidson workspace (davidson.hip)
+
+struct pw_plan_s {
+  pw_ctx ctx = nullptr;
+  pw_plan_opts opts{};
+  int npw = 0, n1 = 0, n2 = 0, n3 = 0;
+  long N = 0;
+  int nst = 0, nxr = 0, ldst = 0;
+  int nbeta = 0, nblk = 0, nhmax = 0;
+  int ldb = 0;              // leading dimension of the plan's beta copies
+  int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
+
+  // maps (device)
+  int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
+      *st_i2 = nullptr, *i1_hx = nullptr;
+  double* kin = nullptr;     // [npw]
+  double* hdiag = nullptr;   // [npw] exact diagonal of H
+  FftDesc f1{}, f2{}, f3{};
+  c128 *tw64_1 = nullptr, *tw64_2 = nullptr, *tw64_3 = nullptr;
+  c64 *tw32_1 = nullptr, *tw32_2 = nullptr, *tw32_3 = nullptr;
+
+  // operator data (device)
+  double* vr64 = nullptr;    // [N]
+  float* vr32 = nullptr;     // [N]  (mixed only)
+  c128* beta64 = nullptr;    // [nbeta][ldb]
+  c64* beta32 = nullptr;     // [nbeta][ldb] (mixed only)
+  int* dstart = nullptr;     // [nbeta] first projector of the D block of projector j
+  int* dlen = nullptr;       // [nbeta] size of that block
+  c128* drow64 = nullptr;    // [nbeta][nhmax] row j of D restricted to its block
+  c64* drow32 = nullptr;
+
+  // H.psi workspace (device)
+  void* sticks = nullptr;    // [band_chunk][n3][ldst] complex (FP64 size)
+  void* part = nullptr;      // split-K partials
+  size_t part_bytes = 0;
+  void* becp = nullptr;      // [nb_max][nbeta] complex128 (or complex64)
+  void* becpd = nullptr;     // D-applied becp
+
+  DavWork* dav = nullptr;
+  std::vector<void*> allocs;
+
+  SphereMap map() const {
+    SphereMap m;
+    m.npw = npw; m.n1 = n1; m.n2 = n2; m.n3 = n3;
+    m.nst = nst; m.nxr = nxr; m.ldst = ldst;
+    m.st_ptr = st_ptr; m.ent_g = ent_g; m.ent_z = ent_z; m.ent_s = ent_s;
+    m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.kin = kin;
+    m.f1 = f1; m.f2 = f2; m.f3 = f3;
+    return m;
+  }
+};
+
+namespace pw {
+// H.psi for nb bands (nb <= opts.nb_max) on `stream`.
+pw_status hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
+                      c128* hpsi, int ldhpsi, hipStream_t stream);
+
+// C[m, n] = sum_k conj(A[k, m]) B[k, n]  (A, B K-contiguous columns), C col-major ldc,
+// alpha-scaled, written as complex128.  Deterministic split-K.  T = compute type.
+template <typename T, typename TA, typename TB>
+pw_status zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>* B, int ldb,
+                   c128* C, int ldc, void* part, size_t part_bytes, hipStream_t stream);
+
+// calbec with the D blocks applied: out[n][j] = sum_{j' in blk(j)} D_jj' sum_k conj(beta[j'][k]) psi[n][k]
+template <typename T>
+pw_status calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t stream);
+
+// C[m, n] = alpha sum_k A[m, k] B[k, n] + beta C[m, n];  A M-contiguous (A[k*lda + m]),
+// B K-contiguous (B[n*ldb + k]), C M-contiguous complex128 (C[n*ldc + m]).
+template <typename T, typename TA, typename TB>
+pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
+                   const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream);
+
+size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
+
+pw_status dav_alloc(pw_plan p);
+void dav_free(pw_plan p);
+size_t dav_bytes(int npw, int nb_max, int ndim_max);
+}  // namespace pw

@@ -1,0 +1,335 @@
+// Complex GEMMs on the matrix cores (v_mfma_f64_16x16x4f64 for float64,
+// v_mfma_f32_16x16x4f32 for float32), used for the projector term of H.psi
+// (<beta|psi>, then sum_j beta_j (D <beta|psi>)_j) and for the Davidson
+// subspace products (phi^H H phi, phi^H phi, Ritz rotations).
+//
+// Complex products use four real MFMAs per 16x16x4 block:
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
+// with Im A negated once, at the LDS store, when A enters conjugated.
+//
+// Two shapes:
+//   cn : C[m, n] = sum_k conj(A[k, m]) B[k, n]; A and B are stored as
+//        K-contiguous columns (the plane-wave index runs fastest).  K is the
+//        long plane-wave dimension, so K is split over workgroups and the
+//        partial tiles are summed in a fixed order by a second kernel
+//        (deterministic, no atomics).
+//   nn : C[m, n] = alpha sum_k A[m, k] B[k, n] + beta C[m, n]; A is M-contiguous
+//        (a block of plane-wave vectors), B K-contiguous (small coefficients).
+#include <algorithm>
+
+#include "plan.h"
+
+namespace {
+
+template <typename T>
+struct Mma;
+template <>
+struct Mma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ v4 run(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+// Operand / result placement of the 16x16x4 MFMAs (64 lanes): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16].  Result element q (0..3) of lane l
+// is D[4 (l / 16) + q][l % 16] for the float32 instruction and
+// D[4 q + l / 16][l % 16] for the float64 one (checked on gfx950).
+template <typename T>
+__device__ __forceinline__ int mrow(int lane, int q);
+template <>
+__device__ __forceinline__ int mrow<float>(int lane, int q) { return 4 * (lane >> 4) + q; }
+template <>
+__device__ __forceinline__ int mrow<double>(int lane, int q) { return 4 * q + (lane >> 4); }
+__device__ __forceinline__ int mcol(int lane) { return lane & 15; }
+
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+
+template <typename T>
+struct Tile {
+  T ar[BK][BM + 1], ai[BK][BM + 1], br[BK][BN + 1], bi[BK][BN + 1];
+};
+
+// One BK slice of a 64x64 tile product held in LDS; each of the 4 waves owns a
+// 32x32 quadrant (2x2 blocks of 16x16).
+template <typename T>
+__device__ __forceinline__ void tile_mma(const Tile<T>& t, typename Mma<T>::v4 (&cr)[2][2],
+                                         typename Mma<T>::v4 (&ci)[2][2], int wm, int wn,
+                                         int lane) {
+  const int r = lane & 15, kq = lane >> 4;
+#pragma unroll
+  for (int k4 = 0; k4 < BK; k4 += 4) {
+    const int kk = k4 + kq;
+    T ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      ar[i] = t.ar[kk][wm * 32 + i * 16 + r];
+      ai[i] = t.ai[kk][wm * 32 + i * 16 + r];
+      br[i] = t.br[kk][wn * 32 + i * 16 + r];
+      bi[i] = t.bi[kk][wn * 32 + i * 16 + r];
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        cr[i][j] = Mma<T>::run(ar[i], br[j], cr[i][j]);
+        cr[i][j] = Mma<T>::run(-ai[i], bi[j], cr[i][j]);
+        ci[i][j] = Mma<T>::run(ar[i], bi[j], ci[i][j]);
+        ci[i][j] = Mma<T>::run(ai[i], br[j], ci[i][j]);
+      }
+  }
+}
+
+// partial[z][n][m] = sum_{k in chunk z} conj(A[m*lda + k]) B[n*ldb + k]
+template <typename T, typename TA, typename TB>
+__global__ void __launch_bounds__(NT)
+k_gemm_cn(int M, int N, int K, int kchunk, const cpx<TA>* __restrict__ A, int lda,
+          const cpx<TB>* __restrict__ B, int ldb, cpx<T>* __restrict__ P) {
+  __shared__ Tile<T> t;
+  typedef typename Mma<T>::v4 v4;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  v4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
+
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int it = 0; it < BM * BK / NT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, mi = idx / BK;
+      const int m = m0 + mi, k = k0 + kk;
+      cpx<TA> a{TA(0), TA(0)};
+      if (m < M && k < kend) a = A[(size_t)m * lda + k];
+      t.ar[kk][mi] = (T)a.x;
+      t.ai[kk][mi] = -(T)a.y;  // conj(A)
+      const int n = n0 + mi;
+      cpx<TB> b{TB(0), TB(0)};
+      if (n < N && k < kend) b = B[(size_t)n * ldb + k];
+      t.br[kk][mi] = (T)b.x;
+      t.bi[kk][mi] = (T)b.y;
+    }
+    __syncthreads();
+    tile_mma<T>(t, cr, ci, wm, wn, lane);
+    __syncthreads();
+  }
+  cpx<T>* out = P + (size_t)blockIdx.z * M * N;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+        const int n = n0 + wn * 32 + j * 16 + mcol(lane);
+        if (m < M && n < N) out[(size_t)n * M + m] = cpx<T>{cr[i][j][q], ci[i][j][q]};
+      }
+}
+
+// C[n*ldc + m] = alpha sum_k A[k*lda + m] B[n*ldb + k] + beta C[n*ldc + m]
+template <typename T, typename TA, typename TB>
+__global__ void __launch_bounds__(NT)
+k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int lda,
+          const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C, int ldc) {
+  __shared__ Tile<T> t;
+  typedef typename Mma<T>::v4 v4;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  v4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
+
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int it = 0; it < BM * BK / NT; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      {
+        const int mi = idx % BM, kk = idx / BM;
+        const int m = m0 + mi, k = k0 + kk;
+        cpx<TA> a{TA(0), TA(0)};
+        if (m < M && k < K) a = A[(size_t)k * lda + m];
+        t.ar[kk][mi] = (T)a.x;
+        t.ai[kk][mi] = (T)a.y;
+      }
+      {
+        const int kk = idx % BK, ni = idx / BK;
+        const int n = n0 + ni, k = k0 + kk;
+        cpx<TB> b{TB(0), TB(0)};
+        if (n < N && k < K) b = B[(size_t)n * ldb + k];
+        t.br[kk][ni] = (T)b.x;
+        t.bi[kk][ni] = (T)b.y;
+      }
+    }
+    __syncthreads();
+    tile_mma<T>(t, cr, ci, wm, wn, lane);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+        const int n = n0 + wn * 32 + j * 16 + mcol(lane);
+        if (m < M && n < N) {
+          c128* c = C + (size_t)n * ldc + m;
+          double re = alpha * (double)cr[i][j][q], im = alpha * (double)ci[i][j][q];
+          if (beta != 0.0) {
+            const c128 old = *c;
+            re += beta * old.x;
+            im += beta * old.y;
+          }
+          *c = c128{re, im};
+        }
+      }
+}
+
+// C[n*ldc + m] = sum_z P[z][n][m]   (fixed summation order)
+template <typename T>
+__global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
+                         c128* __restrict__ C, int ldc) {
+  const size_t total = (size_t)M * N;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int m = (int)(idx % M), n = (int)(idx / M);
+    T re = 0, im = 0;
+    for (int z = 0; z < nsplit; ++z) {
+      const cpx<T> v = P[(size_t)z * total + idx];
+      re += v.x;
+      im += v.y;
+    }
+    C[(size_t)n * ldc + m] = c128{(double)re, (double)im};
+  }
+}
+
+// One workgroup per band n: becp[j] = sum_z P[z][n][j] into LDS, then
+// out[n][j] = sum_{t < dlen_j} drow[j][t] becp[dstart_j + t].
+template <typename T>
+__global__ void k_reduce_dapply(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
+                                const int* __restrict__ dstart, const int* __restrict__ dlen,
+                                const cpx<T>* __restrict__ drow, int nhmax,
+                                cpx<T>* __restrict__ out) {
+  extern __shared__ __align__(16) char smem_raw[];
+  cpx<T>* red = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int n = blockIdx.x;
+  const size_t total = (size_t)M * N;
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    T re = 0, im = 0;
+    for (int z = 0; z < nsplit; ++z) {
+      const cpx<T> v = P[(size_t)z * total + (size_t)n * M + j];
+      re += v.x;
+      im += v.y;
+    }
+    red[j] = cpx<T>{re, im};
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < M; j += blockDim.x) {
+    const int j0 = dstart[j], nh = dlen[j];
+    cpx<T> acc{T(0), T(0)};
+    for (int t = 0; t < nh; ++t) acc = acc + cmul(drow[(size_t)j * nhmax + t], red[j0 + t]);
+    out[(size_t)n * M + j] = acc;
+  }
+}
+
+struct Split {
+  int nsplit, kchunk;
+};
+
+Split choose_split(int M, int N, int K) {
+  const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  const int target = 512;
+  int nsplit = std::max(1, ceil_div(target, tiles));
+  nsplit = std::min(nsplit, std::max(1, ceil_div(K, 4 * BK)));
+  int kchunk = ceil_div(ceil_div(K, nsplit), BK) * BK;
+  kchunk = std::max(kchunk, BK);
+  nsplit = std::max(1, ceil_div(K, kchunk));
+  return Split{nsplit, kchunk};
+}
+
+}  // namespace
+
+size_t pw::splitk_part_bytes(int M, int N, int K, int elem_bytes) {
+  // Upper bound over every M' <= M, N' <= N: nsplit <= 512/tiles + 1, so
+  // nsplit M' N' <= 512 BM BN + M N.
+  (void)K;
+  return ((size_t)512 * BM * BN + (size_t)std::max(M, 1) * std::max(N, 1)) * elem_bytes + 256;
+}
+
+template <typename T, typename TA, typename TB>
+pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>* B, int ldb,
+                       c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  const Split sp = choose_split(M, N, K);
+  const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
+  PW_CHECK(need <= part_bytes, PW_ENOMEM, "split-K workspace too small");
+  cpx<T>* P = static_cast<cpx<T>*>(part);
+  if (K <= 0) {
+    PW_HIP(hipMemsetAsync(P, 0, (size_t)M * N * sizeof(cpx<T>), s));
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, 1, P, C, ldc);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
+  k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+      M, N, K, sp.kchunk, A, lda, B, ldb, P);
+  k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, sp.nsplit, P, C, ldc);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+template <typename T>
+pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t s) {
+  const int M = p->nbeta, N = nb, K = p->npw;
+  const Split sp = choose_split(M, N, K);
+  const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
+  PW_CHECK(need <= p->part_bytes, PW_ENOMEM, "split-K workspace too small");
+  cpx<T>* P = static_cast<cpx<T>*>(p->part);
+  const cpx<T>* beta = sizeof(T) == 8 ? (const cpx<T>*)p->beta64 : (const cpx<T>*)p->beta32;
+  const cpx<T>* drow = sizeof(T) == 8 ? (const cpx<T>*)p->drow64 : (const cpx<T>*)p->drow32;
+  k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+      M, N, K, sp.kchunk, beta, p->ldb, psi, ldpsi, P);
+  k_reduce_dapply<T><<<N, 256, sizeof(cpx<T>) * M, s>>>(M, N, sp.nsplit, P, p->dstart, p->dlen,
+                                                      drow, p->nhmax, out);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+template <typename T, typename TA, typename TB>
+pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
+                       const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t s) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN)), NT, 0, s>>>(M, N, K, alpha, A, lda,
+                                                                            B, ldb, beta, C, ldc);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+template pw_status pw::zgemm_cn<double, double, double>(int, int, int, const c128*, int, const c128*,
+                                                        int, c128*, int, void*, size_t, hipStream_t);
+template pw_status pw::zgemm_cn<float, double, double>(int, int, int, const c128*, int, const c128*,
+                                                       int, c128*, int, void*, size_t, hipStream_t);
+template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, hipStream_t);
+template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t);
+template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,
+                                                        const c128*, int, double, c128*, int,
+                                                        hipStream_t);
+template pw_status pw::zgemm_nn<float, float, float>(int, int, int, double, const c64*, int,
+                                                     const c64*, int, double, c128*, int,
+                                                     hipStream_t);
+template pw_status pw::zgemm_nn<float, double, double>(int, int, int, double, const c128*, int,
+                                                       const c128*, int, double, c128*, int,
+                                                       hipStream_t);

@@ -1,0 +1,221 @@
+"""Python binding of libpwdft (ctypes; argument marshalling only).
+
+Every computation runs in the HIP library; torch tensors provide device
+memory and streams.  Loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwdft.so")
+
+PW_OK, PW_ENOTCONV = 0, 1
+PW_EINVAL, PW_ENOMEM, PW_EDEVICE, PW_EBREAKDOWN, PW_ENAN, PW_ECANCELLED = -1, -2, -3, -4, -5, -6
+PW_FP64, PW_MIXED = 0, 1
+STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", -3: "PW_EDEVICE",
+                -4: "PW_EBREAKDOWN", -5: "PW_ENAN", -6: "PW_ECANCELLED"}
+
+# every symbol include/pwdft.h declares
+EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
+           "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
+           "hpsi_apply", "davidson_solve"]
+
+
+class PwError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Problem(C.Structure):
+    _fields_ = [("npw", C.c_int32), ("miller", C.c_void_p), ("kpg", C.c_void_p),
+                ("nr", C.c_int32 * 3), ("vloc_r", C.c_void_p), ("nbeta", C.c_int32),
+                ("beta", C.c_void_p), ("ld_beta", C.c_int32), ("nblk", C.c_int32),
+                ("blk_off", C.c_void_p), ("dmat", C.c_void_p)]
+
+
+class PlanOpts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("nb_max", C.c_int32), ("ndim_max", C.c_int32)]
+
+
+class DavOpts(C.Structure):
+    _fields_ = [("ndim", C.c_int32), ("max_iter", C.c_int32), ("tol_resid", C.c_double),
+                ("tol_deig", C.c_double), ("precond_floor", C.c_double),
+                ("ladder_switch", C.c_double)]
+
+
+class DavStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("n_hpsi_fp32", C.c_int32),
+                ("n_hpsi_fp64", C.c_int32), ("nconv", C.c_int32), ("max_resid", C.c_double)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libpwdft.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run `python -m paper_0906_2569_amd.build`")
+    lib = C.CDLL(path)
+    lib.pw_last_error.restype = C.c_char_p
+    lib.pw_ctx_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+    lib.pw_ctx_destroy.argtypes = [C.c_void_p]
+    lib.pw_david_opts_default.argtypes = [C.POINTER(DavOpts)]
+    lib.pw_david_opts_default.restype = None
+    lib.pw_footprint_bytes.argtypes = [C.POINTER(Problem), C.POINTER(PlanOpts)]
+    lib.pw_footprint_bytes.restype = C.c_size_t
+    lib.pw_plan_create.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]
+    lib.pw_plan_destroy.argtypes = [C.c_void_p]
+    lib.pw_plan_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+    lib.hpsi_apply.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                               C.c_int32, C.c_void_p]
+    lib.davidson_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                   C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
+    for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
+                 "pw_plan_info", "hpsi_apply", "davidson_solve"):
+        getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != PW_OK:
+        raise PwError(st, load().pw_last_error().decode())
+    return st
+
+
+def default_opts(**kw) -> DavOpts:
+    o = DavOpts()
+    load().pw_david_opts_default(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.lib = load()
+        self.h = C.c_void_p()
+        _check(self.lib.pw_ctx_create(device, C.byref(self.h)))
+        self.device = device
+
+    def close(self):
+        if self.h:
+            self.lib.pw_ctx_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _problem_struct(p, dev):
+    """Marshal a generated problem into the C struct; returns (struct, keepalive)."""
+    import torch
+    miller = np.ascontiguousarray(p.miller, dtype=np.int32)
+    kpg = np.ascontiguousarray(p.kpg, dtype=np.float64)
+    vr = torch.from_numpy(np.ascontiguousarray(p.vloc_r, dtype=np.float64)).to(dev)
+    beta = torch.from_numpy(np.ascontiguousarray(p.beta, dtype=np.complex128)).to(dev)
+    blk = np.ascontiguousarray(p.blk_off, dtype=np.int32)
+    dmat = np.ascontiguousarray(p.dmat, dtype=np.complex128)
+    s = Problem()
+    s.npw = miller.shape[0]
+    s.miller = miller.ctypes.data
+    s.kpg = kpg.ctypes.data
+    s.nr[0], s.nr[1], s.nr[2] = (int(x) for x in p.nr)
+    s.vloc_r = vr.data_ptr()
+    s.nbeta = beta.shape[0]
+    s.beta = beta.data_ptr() if beta.shape[0] else None
+    s.ld_beta = s.npw
+    s.nblk = len(blk) - 1
+    s.blk_off = blk.ctypes.data
+    s.dmat = dmat.ctypes.data if dmat.size else None
+    return s, (miller, kpg, vr, beta, blk, dmat)
+
+
+def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0) -> int:
+    import torch
+    s, keep = _problem_struct(p, torch.device("cuda", device))
+    o = PlanOpts(precision, nb_max or p.nb, ndim_max)
+    return int(load().pw_footprint_bytes(C.byref(s), C.byref(o)))
+
+
+class Plan:
+    """A problem's maps, operator copies and workspace on one device."""
+
+    def __init__(self, ctx: Context, p, precision=PW_FP64, nb_max=None, ndim_max=4):
+        import torch
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.dev = torch.device("cuda", ctx.device)
+        s, keep = _problem_struct(p, self.dev)
+        self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max))
+        self.h = C.c_void_p()
+        _check(self.lib.pw_plan_create(ctx.h, C.byref(s), C.byref(self.opts), C.byref(self.h)))
+        del keep
+        self.npw = int(s.npw)
+        self.precision = precision
+
+    def info(self):
+        out = (C.c_int64 * 8)()
+        _check(self.lib.pw_plan_info(self.h, out))
+        keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "plane_batch64", "plane_batch32"]
+        return dict(zip(keys, list(out)))
+
+    def hpsi(self, psi, out=None, prec=PW_FP64, stream=None):
+        """out = H psi for psi [nb][>=npw] complex128 on the device."""
+        import torch
+        assert psi.dtype == torch.complex128 and psi.is_cuda and psi.dim() == 2
+        assert psi.stride(1) == 1
+        if out is None:
+            out = torch.empty_like(psi)
+        _check(self.lib.hpsi_apply(self.h, prec, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                   C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
+        return out
+
+    def davidson(self, psi, eig=None, resid=None, opts=None, stream=None):
+        """In-place block Davidson on psi [nb][>=npw]; returns (status, eig, resid, stats)."""
+        import torch
+        nb = psi.shape[0]
+        if eig is None:
+            eig = torch.empty(nb, dtype=torch.float64, device=psi.device)
+        if resid is None:
+            resid = torch.empty(nb, dtype=torch.float64, device=psi.device)
+        opts = opts or default_opts()
+        stats = DavStats()
+        st = self.lib.davidson_solve(self.h, nb, C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                     C.c_void_p(eig.data_ptr()), C.c_void_p(resid.data_ptr()),
+                                     C.byref(opts), C.byref(stats), _stream_ptr(stream))
+        if st not in (PW_OK, PW_ENOTCONV):
+            _check(st)
+        return st, eig, resid, stats
+
+    def close(self):
+        if self.h:
+            self.lib.pw_plan_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -164,6 +164,20 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
                          double* resid, const pw_david_opts* opts, pw_david_stats* stats,
                          void* stream);
 
+/*
+ * The float64 reduced-problem solver used inside davidson_solve, exposed on
+ * its own: lowest nev eigenpairs of the generalized Hermitian problem
+ * H c = w S c (S positive definite), as the iterative-diagonalization
+ * appendix's reduced step.  H, S [dev] n x n column-major (leading dimension
+ * ld, both triangles filled); w [dev] double[nev] ascending; C [dev]
+ * n x nev column-major (ldc), S-orthonormal.  If debug [dev] is not NULL it
+ * receives the Householder tridiagonal of L^-1 H L^-H: d (n doubles) then e
+ * (n-1 doubles).  Allocates and frees its own workspace; synchronous.
+ * Errors: PW_EINVAL, PW_EBREAKDOWN (S not positive definite), PW_EDEVICE.
+ */
+pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, const pw_c128* S,
+                          int32_t ld, double* w, pw_c128* C, int32_t ldc, double* debug, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

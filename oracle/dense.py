@@ -191,9 +191,11 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None 
     2. residuals g_i = (H - eps_i) psi_i;
     3. corrections dpsi_i = g_i / (H_GG - eps_i) for unconverged i
        (the diagonal approximation of (H - eps)^-1; |denominator| floored);
-    4. reduced problem sum_k (H_jk - eps S_jk) c_k = 0 on the basis phi;
+    4. reduced problem sum_k (H_jk - eps S_jk) c_k = 0 on the basis phi
+       (directions in which the overlap is numerically singular are dropped);
     5. psi_i = sum_j c^(i)_j phi_j; eps_i = <psi_i|H|psi_i>; iterate, growing the
-       basis with new corrections until ndim*nb, then restarting from psi.
+       basis with new corrections until ndim*nb, then restarting from psi
+       (with H psi applied afresh).
     Returns (eps, psi [nb][npw], iterations, residual norms).
     """
     psi = np.asarray(psi0, dtype=np.complex128).copy()
@@ -201,8 +203,8 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None 
         hdiag = np.real(np.diag(h))
     # step 1: orthonormalise (Cholesky of the overlap) and Rayleigh quotients
     s = np.conj(psi) @ psi.T
-    lo = np.linalg.cholesky(s)
-    psi = np.linalg.solve(lo, psi)            # rows: L^-1 psi  -> orthonormal
+    lo = np.linalg.cholesky(s)                # s = L L^H
+    psi = np.linalg.solve(np.conj(lo), psi)   # rows: conj(L)^-1 psi -> orthonormal
     hpsi_ = hpsi(h, psi)
     eps = np.real(np.einsum("bg,bg->b", np.conj(psi), hpsi_))
     phi = psi.copy()
@@ -222,20 +224,43 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None 
         dpsi = g[todo] / den
         dpsi /= np.linalg.norm(dpsi, axis=1, keepdims=True)
         if phi.shape[0] + len(todo) > ndim * nb:             # restart from Ritz vectors
-            phi, hphi = psi.copy(), hpsi_.copy()
+            # H psi is recomputed rather than carried over: rotating H phi by the
+            # Ritz coefficients multiplies its rounding error by their norm,
+            # which compounds over restarts when the basis is ill-conditioned
+            phi, hphi = psi.copy(), hpsi(h, psi)
         phi = np.concatenate([phi, dpsi], axis=0)
         hphi = np.concatenate([hphi, hpsi(h, dpsi)], axis=0)
         hred = np.conj(phi) @ hphi.T                         # step 4
         sred = np.conj(phi) @ phi.T
         hred = 0.5 * (hred + np.conj(hred.T))
         sred = 0.5 * (sred + np.conj(sred.T))
-        w, c = scipy.linalg.eigh(hred, sred, subset_by_index=[0, nb - 1])
+        w, c = reduced_eigh(hred, sred, nb)
         eps_prev = eps
         psi = c.T @ phi                                      # step 5
         hpsi_ = c.T @ hphi
         eps = np.real(np.einsum("bg,bg->b", np.conj(psi), hpsi_))
         it += 1
     return eps, psi, it, rn
+
+
+def reduced_eigh(hred: np.ndarray, sred: np.ndarray, nev: int, drop: float = 1e-10):
+    """Lowest nev solutions of hred c = w sred c on the numerically independent
+    part of the basis.
+
+    The overlap is diagonalized, directions with eigenvalue below
+    ``drop * max eigenvalue`` are discarded (corrections that fell inside the
+    span of the basis), and the standard problem is solved on the rest.
+    Returns (w, c) with c sred-orthonormal, shape [n][nev].
+    """
+    sig, u = np.linalg.eigh(sred)
+    keep = sig > drop * sig.max()
+    if keep.sum() < nev:
+        raise np.linalg.LinAlgError("reduced basis has rank < nev")
+    q = u[:, keep] / np.sqrt(sig[keep])[None, :]
+    a = np.conj(q.T) @ hred @ q
+    a = 0.5 * (a + np.conj(a.T))
+    w, y = np.linalg.eigh(a)
+    return w[:nev], q @ y[:, :nev]
 
 
 def secular_roots(t: np.ndarray, beta: np.ndarray, d: float, count: int, tol: float = 1e-15):

@@ -1,14 +1,449 @@
-// Block Davidson (placeholder until the solver lands).
-#include "plan.h"
+// Block Davidson for the nb lowest eigenpairs of the plane-wave Hamiltonian
+// (the iterative-diagonalization appendix, S = 1):
+//
+//   start: Rayleigh-Ritz on the trial block (orthonormalizes it and gives
+//          eps_i = <psi_i|H|psi_i>);
+//   loop:  residuals g_i = H psi_i - eps_i psi_i and their float64 norms;
+//          bands with ||g_i|| <= tol_resid and |d eps_i| <= tol_deig are
+//          converged; for the others the corrections
+//          dpsi_i(G) = g_i(G) / (h_diag(G) - eps_i)   (diagonal preconditioner,
+//          |denominator| floored) are normalized and appended to the basis phi;
+//          the reduced problem H_jk c = eps S_jk c on phi (new rows and columns
+//          only) is solved in float64 on the GPU, and psi = phi c, H psi = H phi c.
+//          The basis grows until ndim*nb (expanding-basis variant), then
+//          collapses onto the current Ritz vectors.
+//   end:   a float64 H.psi of the final block recomputes eps_i and ||g_i||.
+//
+// In mixed precision, H.psi runs in float32 until max ||g_i|| falls below
+// ladder_switch; then the basis restarts from the Ritz vectors with float64
+// H.psi (precision ladder).  Reduced matrices, Cholesky, the reduced
+// eigenproblem and residual norms are always float64.
+#include <algorithm>
+#include <cmath>
+#include <vector>
 
-struct DavWork {};
+#include "linalg.h"
 
-pw_status pw::dav_alloc(pw_plan) { return PW_OK; }
-void pw::dav_free(pw_plan) {}
-size_t pw::dav_bytes(int, int, int) { return 0; }
+struct DavFlags {
+  int n_new;
+  int nan;
+  int info;
+  int nconv;
+  double maxr;
+  double gamma;   // growth factor of the last Ritz rotation
+};
 
-extern "C" pw_status davidson_solve(pw_plan p, int32_t, pw_c128*, int32_t, double*, double*,
-                                    const pw_david_opts*, pw_david_stats*, void*) {
+struct DavWork {
+  int nbmax = 0, ndim = 0, nbasis = 0, ld = 0;
+  c128 *phi = nullptr, *hphi = nullptr, *psi = nullptr, *hpsi = nullptr;
+  c128 *hred = nullptr, *sred = nullptr, *cvec = nullptr;
+  double *eps = nullptr, *eps_prev = nullptr, *rn = nullptr;
+  int* idx = nullptr;
+  DavFlags* flags = nullptr;     // device
+  DavFlags* hflags = nullptr;    // pinned host
+  void* part = nullptr;
+  size_t part_bytes = 0;
+  pw::HeigWork hw;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+__device__ double block_sum256(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// rn[b] = || hpsi_b - eps_b psi_b ||_2
+__global__ void __launch_bounds__(256) k_resid(int npw, const c128* __restrict__ psi,
+                                               const c128* __restrict__ hpsi, int ld,
+                                               const double* __restrict__ eps, double* __restrict__ rn) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const double e = eps[b];
+  const c128* x = psi + (size_t)b * ld;
+  const c128* hx = hpsi + (size_t)b * ld;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
+    s += re * re + im * im;
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) rn[b] = sqrt(s);
+}
+
+// convergence flags, compaction of the unconverged bands (band order), NaN
+// guard, and the reduced-solver status, gathered for one host read.
+__global__ void k_select(int nb, const double* __restrict__ rn, const double* __restrict__ eps,
+                         const double* __restrict__ eps_prev, double tol_r, double tol_e,
+                         int* __restrict__ idx, const int* __restrict__ info, const double* __restrict__ gamma,
+                         DavFlags* __restrict__ f) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int n = 0, nan = 0, nconv = 0;
+  double maxr = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double r = rn[b], de = fabs(eps[b] - eps_prev[b]);
+    if (!isfinite(r) || !isfinite(eps[b])) nan = 1;
+    maxr = fmax(maxr, r);
+    if (r <= tol_r && de <= tol_e) {
+      ++nconv;
+    } else {
+      idx[n++] = b;
+    }
+  }
+  f->n_new = n;
+  f->nan = nan;
+  f->info = *info;
+  f->nconv = nconv;
+  f->maxr = maxr;
+  f->gamma = *gamma;
+}
+
+// out_t = (hpsi_b - eps_b psi_b) / floor(h_diag - eps_b), normalized; b = idx[t]
+__global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict__ idx,
+                                                 const c128* __restrict__ psi, const c128* __restrict__ hpsi,
+                                                 int ld, const double* __restrict__ eps,
+                                                 const double* __restrict__ hdiag, double floor_,
+                                                 c128* __restrict__ out, int ldo) {
+  __shared__ double red[4];
+  const int t = blockIdx.x;
+  const int b = idx[t];
+  const double e = eps[b];
+  const c128* x = psi + (size_t)b * ld;
+  const c128* hx = hpsi + (size_t)b * ld;
+  c128* o = out + (size_t)t * ldo;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    double den = hdiag[g] - e;
+    if (fabs(den) < floor_) den = copysign(floor_, den);
+    const double inv = 1.0 / den;
+    const c128 r = c128{(hx[g].x - e * x[g].x) * inv, (hx[g].y - e * x[g].y) * inv};
+    o[g] = r;
+    s += r.x * r.x + r.y * r.y;
+  }
+  s = block_sum256(s, red);
+  const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
+}
+
+// reduced matrices of the collapsed basis {psi}: H = diag(eps), S = I
+__global__ void k_restart(int nb, const double* __restrict__ eps, c128* __restrict__ h,
+                          c128* __restrict__ s, int ldm) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nb * nb; idx += gridDim.x * blockDim.x) {
+    const int i = idx % nb, j = idx / nb;
+    h[(size_t)j * ldm + i] = c128{i == j ? eps[i] : 0.0, 0.0};
+    s[(size_t)j * ldm + i] = c128{i == j ? 1.0 : 0.0, 0.0};
+  }
+}
+
+// columns [c0, c1) were computed for rows [0, c1): mirror them into rows
+// [c0, c1) of columns [0, c0), and make the new diagonal block exactly Hermitian
+__global__ void k_herm_fill(int c0, int c1, c128* __restrict__ m, int ldm) {
+  const int nn = c1 - c0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nn * c1; idx += gridDim.x * blockDim.x) {
+    const int i = c0 + idx % nn;   // new row
+    const int j = idx / nn;        // column in [0, c1)
+    if (j < c0) {
+      const c128 v = m[(size_t)i * ldm + j];
+      m[(size_t)j * ldm + i] = c128{v.x, -v.y};
+    } else if (j < i) {
+      const c128 up = m[(size_t)i * ldm + j];    // (j, i), j < i: upper
+      const c128 lo = m[(size_t)j * ldm + i];    // (i, j): lower
+      const c128 a = c128{0.5 * (up.x + lo.x), 0.5 * (up.y - lo.y)};   // average of up and conj(lo)
+      m[(size_t)i * ldm + j] = a;
+      m[(size_t)j * ldm + i] = c128{a.x, -a.y};
+    } else if (j == i) {
+      m[(size_t)i * ldm + i].y = 0.0;
+    }
+  }
+}
+
+__global__ void k_fill(int n, double v, double* __restrict__ x) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+// eig_b = Re <psi_b|H psi_b> / <psi_b|psi_b>,  resid_b = || H psi_b - eig_b psi_b ||
+__global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__ psi, int ldpsi,
+                                               const c128* __restrict__ hpsi, int ldh,
+                                               double* __restrict__ eig, double* __restrict__ resid) {
+  __shared__ double red[4];
+  const int b = blockIdx.x;
+  const c128* x = psi + (size_t)b * ldpsi;
+  const c128* hx = hpsi + (size_t)b * ldh;
+  double num = 0.0, den = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    num += x[g].x * hx[g].x + x[g].y * hx[g].y;
+    den += x[g].x * x[g].x + x[g].y * x[g].y;
+  }
+  num = block_sum256(num, red);
+  den = block_sum256(den, red);
+  const double e = num / den;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
+    s += re * re + im * im;
+  }
+  s = block_sum256(s, red);
+  if (threadIdx.x == 0) {
+    eig[b] = e;
+    resid[b] = sqrt(s);
+  }
+}
+
+}  // namespace
+
+size_t pw::dav_bytes(int npw, int nb_max, int ndim_max) {
+  const size_t ld = ((size_t)npw + 15) / 16 * 16;
+  const size_t nbasis = (size_t)nb_max * ndim_max;
+  size_t b = 0;
+  b += 2 * nbasis * ld * sizeof(c128);                  // phi, hphi
+  b += 2 * (size_t)nb_max * ld * sizeof(c128);          // psi, hpsi
+  b += 2 * nbasis * nbasis * sizeof(c128);              // hred, sred
+  b += nbasis * nb_max * sizeof(c128);                  // cvec
+  b += 3 * (size_t)nb_max * sizeof(double) + nb_max * sizeof(int) + 256;
+  b += pw::splitk_part_bytes((int)nbasis, (int)nbasis, npw, sizeof(c128));
+  b += pw::heig_work_bytes((int)nbasis);
+  return b + 32 * 256;
+}
+
+pw_status pw::dav_alloc(pw_plan p) {
+  PW_TRY(pw::heig_set_limits());
+  DavWork* W = new DavWork();
+  p->dav = W;
+  W->nbmax = p->opts.nb_max;
+  W->ndim = p->opts.ndim_max;
+  W->nbasis = W->nbmax * W->ndim;
+  W->ld = (p->npw + 15) / 16 * 16;
+  auto get = [&](size_t bytes, void** out) -> pw_status {
+    *out = nullptr;
+    if (hipMalloc(out, std::max<size_t>(bytes, 256)) != hipSuccess) {
+      (void)hipGetLastError();
+      return pw::fail(PW_ENOMEM, "hipMalloc failed for the Davidson workspace");
+    }
+    W->allocs.push_back(*out);
+    return PW_OK;
+  };
+  const size_t nbx = W->nbasis, ld = W->ld, nb = W->nbmax;
+  PW_TRY(get(nbx * ld * sizeof(c128), (void**)&W->phi));
+  PW_TRY(get(nbx * ld * sizeof(c128), (void**)&W->hphi));
+  PW_TRY(get(nb * ld * sizeof(c128), (void**)&W->psi));
+  PW_TRY(get(nb * ld * sizeof(c128), (void**)&W->hpsi));
+  PW_TRY(get(nbx * nbx * sizeof(c128), (void**)&W->hred));
+  PW_TRY(get(nbx * nbx * sizeof(c128), (void**)&W->sred));
+  PW_TRY(get(nbx * nb * sizeof(c128), (void**)&W->cvec));
+  PW_TRY(get(nb * sizeof(double), (void**)&W->eps));
+  PW_TRY(get(nb * sizeof(double), (void**)&W->eps_prev));
+  PW_TRY(get(nb * sizeof(double), (void**)&W->rn));
+  PW_TRY(get(nb * sizeof(int), (void**)&W->idx));
+  PW_TRY(get(sizeof(DavFlags), (void**)&W->flags));
+  W->part_bytes = pw::splitk_part_bytes((int)nbx, (int)nbx, p->npw, sizeof(c128));
+  PW_TRY(get(W->part_bytes, &W->part));
+  void* hwb = nullptr;
+  PW_TRY(get(pw::heig_work_bytes((int)nbx), &hwb));
+  PW_TRY(pw::heig_setup(W->hw, hwb, (int)nbx));
+  void* hf = nullptr;
+  if (hipHostMalloc(&hf, sizeof(DavFlags), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return pw::fail(PW_ENOMEM, "hipHostMalloc failed");
+  }
+  W->hflags = static_cast<DavFlags*>(hf);
+  return PW_OK;
+}
+
+void pw::dav_free(pw_plan p) {
+  DavWork* W = p->dav;
+  if (!W) return;
+  for (void* q : W->allocs) (void)hipFree(q);
+  if (W->hflags) (void)hipHostFree(W->hflags);
+  delete W;
+  p->dav = nullptr;
+}
+
+namespace {
+
+// largest accumulated error growth of H phi tolerated before H is re-applied
+constexpr double kMaxAmp = 1e4;
+
+struct Solver {
+  pw_plan p;
+  DavWork& W;
+  hipStream_t st;
+  pw_david_stats& stats;
+
+  pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx) {
+    PW_TRY(pw::hpsi_launch(p, prec, n, x, W.ld, hx, W.ld, st));
+    if (prec == PW_FP64) stats.n_hpsi_fp64 += n; else stats.n_hpsi_fp32 += n;
+    return PW_OK;
+  }
+
+  // reduced columns [c0, c1) of H and S over the basis phi[0:c1)
+  pw_status project(int c0, int c1) {
+    const int npw = p->npw, ldm = W.nbasis;
+    PW_TRY((pw::zgemm_cn<double, double, double>(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld,
+                                                 W.ld, W.hred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes, st)));
+    PW_TRY((pw::zgemm_cn<double, double, double>(c1, c1 - c0, npw, W.phi, W.ld, W.phi + (size_t)c0 * W.ld,
+                                                 W.ld, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes, st)));
+    const int blocks = std::min(1024, ceil_div((size_t)(c1 - c0) * c1, 256));
+    k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.hred, ldm);
+    k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.sred, ldm);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
+
+  // reduced eigenproblem on phi[0:nbase) and the Ritz rotation (skipped on
+  // device when the overlap matrix is not positive definite)
+  pw_status rayleigh_ritz(int nbase, int nb) {
+    const int ldm = W.nbasis;
+    PW_TRY(pw::heig_solve(W.hw, nbase, nb, W.hred, W.sred, ldm, W.eps, W.cvec, ldm, W.part, W.part_bytes, st));
+    PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.phi, W.ld, W.cvec, ldm, 0.0, W.psi,
+                                                 W.ld, st, W.hw.info)));
+    PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.hphi, W.ld, W.cvec, ldm, 0.0,
+                                                 W.hpsi, W.ld, st, W.hw.info)));
+    return PW_OK;
+  }
+
+  // basis <- current Ritz vectors
+  pw_status collapse(int nb) {
+    const size_t pitch = sizeof(c128) * W.ld;
+    PW_HIP(hipMemcpy2DAsync(W.phi, pitch, W.psi, pitch, sizeof(c128) * p->npw, nb, hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpy2DAsync(W.hphi, pitch, W.hpsi, pitch, sizeof(c128) * p->npw, nb, hipMemcpyDeviceToDevice, st));
+    k_restart<<<std::min(1024, ceil_div(nb * nb, 256)), 256, 0, st>>>(nb, W.eps, W.hred, W.sred, W.nbasis);
+    PW_HIP(hipGetLastError());
+    return PW_OK;
+  }
+
+  // full Rayleigh-Ritz on a block already in phi[0:nb) (start, precision switch)
+  pw_status start_block(pw_precision prec, int nb) {
+    PW_TRY(hpsi(prec, nb, W.phi, W.hphi));
+    PW_TRY(project(0, nb));
+    PW_TRY(rayleigh_ritz(nb, nb));
+    return PW_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ldpsi, double* eig,
+                                    double* resid, const pw_david_opts* o_, pw_david_stats* stats_out,
+                                    void* stream) {
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
-  return pw::fail(PW_EINVAL, "davidson_solve: not built yet");
+  PW_CHECK(p->dav != nullptr, PW_EINVAL, "plan was created without Davidson workspace (ndim_max = 0)");
+  pw_david_opts o;
+  if (o_) o = *o_; else pw_david_opts_default(&o);
+  DavWork& W = *p->dav;
+  PW_CHECK(nb >= 1 && nb <= W.nbmax, PW_EINVAL, "nb out of range [1, nb_max]");
+  PW_CHECK(nb <= p->npw, PW_EINVAL, "nb > npw");
+  PW_CHECK(o.ndim >= 2 && o.ndim <= W.ndim, PW_EINVAL, "ndim out of range [2, ndim_max]");
+  PW_CHECK(o.max_iter >= 0, PW_EINVAL, "max_iter < 0");
+  PW_CHECK(o.precond_floor > 0.0, PW_EINVAL, "precond_floor must be positive");
+  PW_CHECK(psi_u && eig && resid, PW_EINVAL, "NULL psi, eig or resid");
+  PW_CHECK(ldpsi >= p->npw, PW_EINVAL, "ldpsi < npw");
+  PW_HIP(hipSetDevice(p->ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  pw_david_stats stats{};
+  Solver S{p, W, st, stats};
+  const int npw = p->npw;
+  const int nbx = o.ndim * nb;
+  pw_precision prec = (p->opts.precision == PW_MIXED) ? PW_MIXED : PW_FP64;
+  c128* psi = reinterpret_cast<c128*>(psi_u);
+
+  PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, psi, sizeof(c128) * ldpsi, sizeof(c128) * npw, nb,
+                          hipMemcpyDeviceToDevice, st));
+  PW_TRY(S.start_block(prec, nb));
+  k_fill<<<1, 256, 0, st>>>(nb, INFINITY, W.eps_prev);
+  int nbase = nb;
+  double amp = 1.0;   // accumulated error growth of the carried-over H phi
+  bool retried = false;
+  pw_status result = PW_OK;
+  DavFlags f{};
+  for (;;) {
+    k_resid<<<nb, 256, 0, st>>>(npw, W.psi, W.hpsi, W.ld, W.eps, W.rn);
+    k_select<<<1, 64, 0, st>>>(nb, W.rn, W.eps, W.eps_prev, o.tol_resid, o.tol_deig, W.idx, W.hw.info,
+                               W.hw.gamma, W.flags);
+    PW_HIP(hipMemcpyAsync(W.hflags, W.flags, sizeof(DavFlags), hipMemcpyDeviceToHost, st));
+    PW_HIP(hipStreamSynchronize(st));
+    f = *W.hflags;
+    if (f.info != 0) {
+      // the newest corrections made the overlap singular: the Ritz vectors
+      // were not replaced; collapse onto them once and try again
+      if (retried || nbase == nb) { result = pw::fail(PW_EBREAKDOWN, "reduced overlap matrix not positive definite"); break; }
+      retried = true;
+      PW_HIP(hipMemsetAsync(W.hw.info, 0, sizeof(int), st));
+      PW_TRY(S.collapse(nb));
+      nbase = nb;
+      stats.restarts++;
+      continue;
+    }
+    if (f.nan) { result = pw::fail(PW_ENAN, "non-finite residual norm"); break; }
+    if (prec == PW_MIXED && f.maxr <= o.ladder_switch) {
+      // precision ladder: continue from the Ritz vectors with float64 H.psi
+      prec = PW_FP64;
+      PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
+                              hipMemcpyDeviceToDevice, st));
+      PW_TRY(S.start_block(prec, nb));
+      k_fill<<<1, 256, 0, st>>>(nb, INFINITY, W.eps_prev);
+      nbase = nb;
+      amp = 1.0;
+      stats.restarts++;
+      continue;
+    }
+    if (f.n_new == 0 && prec == PW_FP64) break;
+    if (stats.iters >= o.max_iter) { result = PW_ENOTCONV; break; }
+    int n_new = f.n_new;
+    if (n_new == 0) n_new = nb;   // converged in float32: keep refining until the switch
+    if (nbase + n_new > nbx) {
+      // The collapsed block inherits H psi = (H phi) c and is taken to be
+      // orthonormal: the rounding errors of both grow by ||c|| and ||c||^2 per
+      // collapse.  Once the accumulated growth is large, the block is rebuilt
+      // from the Ritz vectors with a fresh H psi and explicit reduced matrices.
+      amp *= std::max(1.0, f.gamma) * std::max(1.0, f.gamma);
+      if (amp > kMaxAmp) {
+        PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
+                                hipMemcpyDeviceToDevice, st));
+        PW_TRY(S.start_block(prec, nb));
+        amp = 1.0;
+        stats.restarts++;
+      }
+      PW_TRY(S.collapse(nb));
+      nbase = nb;
+      stats.restarts++;
+    }
+    if (f.n_new == 0) {
+      // every band converged at float32 accuracy: correct all of them
+      std::vector<int> all(nb);
+      for (int b = 0; b < nb; ++b) all[b] = b;
+      PW_HIP(hipMemcpyAsync(W.idx, all.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+      PW_HIP(hipStreamSynchronize(st));
+    }
+    k_correct<<<n_new, 256, 0, st>>>(npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, o.precond_floor,
+                                     W.phi + (size_t)nbase * W.ld, W.ld);
+    PW_TRY(S.hpsi(prec, n_new, W.phi + (size_t)nbase * W.ld, W.hphi + (size_t)nbase * W.ld));
+    PW_TRY(S.project(nbase, nbase + n_new));
+    nbase += n_new;
+    PW_HIP(hipMemcpyAsync(W.eps_prev, W.eps, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
+    PW_TRY(S.rayleigh_ritz(nbase, nb));
+    stats.iters++;
+  }
+  // final float64 verification of the output block
+  PW_HIP(hipMemcpy2DAsync(psi, sizeof(c128) * ldpsi, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
+                          hipMemcpyDeviceToDevice, st));
+  PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
+  stats.n_hpsi_fp64 += nb;
+  k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid);
+  PW_HIP(hipGetLastError());
+  std::vector<double> hr(nb);
+  PW_HIP(hipMemcpyAsync(hr.data(), resid, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  PW_HIP(hipStreamSynchronize(st));
+  stats.max_resid = 0.0;
+  for (double r : hr) stats.max_resid = std::max(stats.max_resid, r);
+  stats.nconv = f.nconv;
+  if (stats_out) *stats_out = stats;
+  return result;
 }

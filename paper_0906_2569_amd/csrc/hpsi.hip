@@ -223,12 +223,20 @@ template <typename T>
 size_t z_lds_bytes(int n3) { return sizeof(cpx<T>) * ((size_t)n3 + 2 * (size_t)ZSB * n3); }
 
 template <typename T>
+pw_status set_lds_limit(const void* fn) {
+  hipFuncAttributes at;
+  PW_HIP(hipFuncGetAttributes(&at, fn));
+  PW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - (int)at.sharedSizeBytes));
+  return PW_OK;
+}
+
+template <typename T>
 pw_status set_lds_limits() {
   static bool done = false;
   if (done) return PW_OK;
-  PW_HIP(hipFuncSetAttribute((const void*)k_plane<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  PW_HIP(hipFuncSetAttribute((const void*)k_zinv<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-  PW_HIP(hipFuncSetAttribute((const void*)k_zfwd<T>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+  PW_TRY(set_lds_limit<T>((const void*)k_plane<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_zinv<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_zfwd<T>));
   done = true;
   return PW_OK;
 }

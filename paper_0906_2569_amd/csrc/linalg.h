@@ -1,0 +1,26 @@
+// Float64 reduced-problem solver (generalized Hermitian eigenproblem) on the GPU.
+#pragma once
+#include <algorithm>
+#include <cfloat>
+
+#include "plan.h"
+
+namespace pw {
+
+struct HeigWork {
+  int nmax = 0;
+  c128 *L = nullptr, *X = nullptr, *T1 = nullptr, *A = nullptr, *Y = nullptr, *tau = nullptr;
+  double *d = nullptr, *e = nullptr, *w = nullptr, *Z = nullptr, *scratch = nullptr;
+  int* info = nullptr;     // 0, or 1 when fewer than nev independent directions remain
+  int* drop = nullptr;     // [n] 1 for basis directions dropped as dependent
+  double* gamma = nullptr; // max column norm of the last eigenvector block C
+};
+
+size_t heig_work_bytes(int nmax);
+pw_status heig_setup(HeigWork& hw, void* base, int nmax);
+pw_status heig_set_limits();
+// lowest nev eigenpairs of H c = w S c (n x n, col-major, leading dimension ld)
+pw_status heig_solve(HeigWork& hw, int n, int nev, const c128* H, const c128* S, int ld, double* w,
+                     c128* C, int ldc, void* part, size_t part_bytes, hipStream_t st);
+
+}  // namespace pw

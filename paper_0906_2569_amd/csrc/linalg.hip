@@ -1,0 +1,611 @@
+// Float64 dense linear algebra for the Davidson reduced problem, on the GPU.
+//
+// The reduced problem of the block Davidson iteration is the generalized
+// Hermitian eigenproblem  H_red c = eps S_red c  on the current basis
+// (the "conventional algorithms for matrix diagonalization" step).  It is
+// solved as
+//   S = L L^H (Cholesky),  X = L^-H,  A = X^H H X,
+//   A = Q T Q^H (Householder tridiagonalization, T real symmetric),
+//   lowest nev eigenvalues of T by multisection bisection on Sturm counts,
+//   eigenvectors of T by inverse iteration (reorthogonalized inside clusters
+//   of equal eigenvalues), back-transformed by the reflectors, and c = X Y.
+// The matrix products run on the MFMA GEMMs of zgemm.hip; the sequential
+// factorizations run inside one workgroup each.
+#include <cfloat>
+#include <cmath>
+
+#include "linalg.h"
+
+namespace {
+
+constexpr int NTL = 1024;  // threads of the single-workgroup factorizations
+// relative pivot below which a basis direction counts as dependent
+constexpr double kDropTol = 1e-10;
+
+__device__ __forceinline__ c128 cconj(c128 a) { return c128{a.x, -a.y}; }
+
+// block-wide sum of a double (all threads call; result valid in all threads)
+__device__ double block_sum(double v, double* red) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < nw; ++w) s += red[w];   // fixed order: deterministic
+  __syncthreads();
+  return s;
+}
+
+__device__ c128 block_sum_c(c128 v, double* red) {
+  const double re = block_sum(v.x, red);
+  const double im = block_sum(v.y, red);
+  return c128{re, im};
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky S = L L^H (lower), in place on a copy of S, dropping dependent
+// directions: a pivot below drop_tol times the original diagonal entry (a
+// basis vector that lies, to rounding, in the span of the earlier ones) gets
+// L[j][j] = 1 and a zero column, and drop[j] = 1.  info = 1 when fewer than
+// nev directions remain or a pivot is not finite.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c128* __restrict__ L, int ld,
+                                              int* __restrict__ drop, int* __restrict__ info) {
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* col = reinterpret_cast<c128*>(smem_raw);               // [n]
+  double* diag0 = reinterpret_cast<double*>(col + n);          // [n]
+  __shared__ double s_r;
+  __shared__ int s_keep, s_bad, s_ndrop;
+  if (threadIdx.x == 0) { s_bad = 0; s_ndrop = 0; }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) diag0[i] = L[(size_t)i * ld + i].x;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[(size_t)j * ld + j].x;
+      // a dependent direction leaves a pivot at rounding level; a clearly
+      // negative one (or a non-positive diagonal) means S is not positive definite
+      if (!isfinite(d) || !(diag0[j] > 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
+      s_keep = (d > drop_tol * diag0[j]) ? 1 : 0;
+      if (s_keep) {
+        s_r = sqrt(d);
+        L[(size_t)j * ld + j] = c128{s_r, 0.0};
+      } else {
+        L[(size_t)j * ld + j] = c128{1.0, 0.0};
+        ++s_ndrop;
+      }
+      drop[j] = 1 - s_keep;
+    }
+    __syncthreads();
+    if (s_bad) break;
+    const int m = n - j - 1;
+    if (!s_keep) {
+      for (int i = threadIdx.x; i < m; i += blockDim.x) L[(size_t)j * ld + j + 1 + i] = c128{0.0, 0.0};
+      __syncthreads();
+      continue;
+    }
+    const double inv = 1.0 / s_r;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      c128 v = L[(size_t)j * ld + j + 1 + i];
+      v = c128{v.x * inv, v.y * inv};
+      L[(size_t)j * ld + j + 1 + i] = v;
+      col[i] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int ii = idx % m, kk = idx / m;
+      if (ii >= kk) {
+        c128* a = L + (size_t)(j + 1 + kk) * ld + j + 1 + ii;
+        const c128 u = cmulc(col[kk], col[ii]);   // col[ii] conj(col[kk])
+        *a = c128{a->x - u.x, a->y - u.y};
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *info = (s_bad || n - s_ndrop < nev) ? 1 : 0;
+  // zero the strict upper triangle (the factor is used as a full matrix)
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx % n, k = idx / n;
+    if (i < k) L[(size_t)k * ld + i] = c128{0.0, 0.0};
+  }
+}
+
+// Dropped directions are decoupled from the transformed matrix and moved far
+// above the spectrum, so they never enter the lowest nev eigenpairs.
+__global__ void k_isolate(int n, c128* __restrict__ A, int ld, const int* __restrict__ drop,
+                          const int* __restrict__ info) {
+  if (*info != 0) return;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    if (drop[i] || drop[j]) A[(size_t)j * ld + i] = c128{(i == j) ? 1e12 : 0.0, 0.0};
+  }
+}
+
+// gamma = max_k || C[:, k] ||_2  (growth factor of the Ritz rotation)
+__global__ void k_colnorm_max(int n, int nev, const c128* __restrict__ C, int ldc, double* __restrict__ gamma,
+                              const int* __restrict__ info) {
+  __shared__ double red[16];
+  double mx = 0.0;
+  if (*info == 0) {
+    for (int k = threadIdx.x; k < nev; k += blockDim.x) {
+      double s = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const c128 v = C[(size_t)k * ldc + i];
+        s += v.x * v.x + v.y * v.y;
+      }
+      mx = fmax(mx, sqrt(s));
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, red[w]);
+    *gamma = m;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// X = L^-H (upper triangular).  One workgroup per column j of Y = L^-1:
+// forward substitution L y = e_j, row by row, then X[j, :] = conj(y)^T.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_trinv(int n, const c128* __restrict__ L, int ld,
+                                               c128* __restrict__ X, int ldx, const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* y = reinterpret_cast<c128*>(smem_raw);   // [n] right-hand side / solution
+  const int j = blockIdx.x;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = c128{i == j ? 1.0 : 0.0, 0.0};
+  __syncthreads();
+  for (int i = j; i < n; ++i) {
+    const c128 lii = L[(size_t)i * ld + i];
+    const double inv = 1.0 / lii.x;
+    const c128 yi = c128{y[i].x * inv, y[i].y * inv};
+    __syncthreads();
+    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) {
+      const c128 u = cmul(L[(size_t)i * ld + k], yi);
+      y[k] = c128{y[k].x - u.x, y[k].y - u.y};
+    }
+    if (threadIdx.x == 0) y[i] = yi;
+    __syncthreads();
+  }
+  // X[j][i] = conj(Y[i][j]) for i >= j (row j of X), zero for i < j
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    X[(size_t)i * ldx + j] = (i >= j) ? cconj(y[i]) : c128{0.0, 0.0};
+}
+
+// ---------------------------------------------------------------------------
+// Householder tridiagonalization of the full Hermitian A (n x n, col-major).
+// For k = 0..n-2 the reflector H_k = I - tau_k v v^H (v_0 = 1) maps
+// x = A[k+1:, k] to beta e_1 with beta real; A <- H^H A H on the trailing
+// block as A - v w^H - w v^H with w = p - (tau/2)(p^H v) v, p = tau A v.
+// v is stored in A[k+1:, k]; d, e get the real tridiagonal.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(NTL) k_tridiag(int n, c128* __restrict__ A, int ld,
+                                                 double* __restrict__ d, double* __restrict__ e,
+                                                 c128* __restrict__ tau, const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* v = reinterpret_cast<c128*>(smem_raw);   // [n]
+  c128* w = v + n;                               // [n]
+  c128* part = w + n;                            // [max(n, NTL)]
+  __shared__ double red[NTL / 64];
+  __shared__ c128 s_tau, s_scale;
+  __shared__ double s_beta;
+  const int bs = blockDim.x, tid = threadIdx.x;
+  for (int k = 0; k < n - 1; ++k) {
+    const int m = n - k - 1;
+    c128* x = A + (size_t)k * ld + k + 1;
+    double ss = 0.0;
+    for (int i = 1 + tid; i < m; i += bs) ss += x[i].x * x[i].x + x[i].y * x[i].y;
+    const double xn2 = block_sum(ss, red);
+    if (tid == 0) {
+      const c128 al = x[0];
+      if (xn2 == 0.0 && al.y == 0.0) {
+        s_tau = c128{0.0, 0.0};
+        s_beta = al.x;
+        s_scale = c128{0.0, 0.0};
+      } else {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+        const double beta = al.x >= 0.0 ? -nrm : nrm;
+        s_beta = beta;
+        s_tau = c128{(beta - al.x) / beta, -al.y / beta};
+        // scale = 1 / (alpha - beta)
+        const c128 den = c128{al.x - beta, al.y};
+        const double dd = den.x * den.x + den.y * den.y;
+        s_scale = c128{den.x / dd, -den.y / dd};
+      }
+      d[k] = A[(size_t)k * ld + k].x;
+      e[k] = s_beta;
+      tau[k] = s_tau;
+    }
+    __syncthreads();
+    const c128 t = s_tau, sc = s_scale;
+    for (int i = tid; i < m; i += bs) {
+      const c128 vi = (i == 0) ? c128{1.0, 0.0} : cmul(x[i], sc);
+      v[i] = vi;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += bs) x[i] = v[i];   // keep v for the back-transform
+    if (t.x == 0.0 && t.y == 0.0) {
+      __syncthreads();
+      continue;
+    }
+    c128* S = A + (size_t)(k + 1) * ld + k + 1;      // trailing block, m x m
+    // p = tau * S v : S slices of rows
+    const int ns = max(1, min(bs / m, 64));
+    for (int idx = tid; idx < m * ns; idx += bs) {
+      const int i = idx % m, s = idx / m;
+      c128 acc{0.0, 0.0};
+      for (int j = s; j < m; j += ns) {
+        const c128 u = cmul(S[(size_t)j * ld + i], v[j]);
+        acc.x += u.x;
+        acc.y += u.y;
+      }
+      part[idx] = acc;
+    }
+    __syncthreads();
+    double hr = 0.0, hi = 0.0;
+    for (int i = tid; i < m; i += bs) {
+      c128 acc{0.0, 0.0};
+      for (int s = 0; s < ns; ++s) { acc.x += part[s * m + i].x; acc.y += part[s * m + i].y; }
+      const c128 pi = cmul(t, acc);
+      w[i] = pi;
+      const c128 pv = cmulc(pi, v[i]);   // conj(p_i) v_i
+      hr += pv.x;
+      hi += pv.y;
+    }
+    // alpha = -1/2 tau (p^H v)
+    const c128 pv = block_sum_c(c128{hr, hi}, red);
+    const c128 al = cmul(c128{-0.5 * t.x, -0.5 * t.y}, pv);
+    for (int i = tid; i < m; i += bs) {
+      const c128 u = cmul(al, v[i]);
+      w[i] = c128{w[i].x + u.x, w[i].y + u.y};
+    }
+    __syncthreads();
+    for (int idx = tid; idx < m * m; idx += bs) {
+      const int i = idx % m, j = idx / m;
+      const c128 a1 = cmulc(w[j], v[i]);   // v_i conj(w_j)
+      const c128 a2 = cmulc(v[j], w[i]);   // w_i conj(v_j)
+      c128* a = S + (size_t)j * ld + i;
+      *a = c128{a->x - a1.x - a2.x, a->y - a1.y - a2.y};
+    }
+    __syncthreads();
+  }
+  if (tid == 0) d[n - 1] = A[(size_t)(n - 1) * ld + n - 1].x;
+}
+
+// ---------------------------------------------------------------------------
+// Lowest nev eigenvalues of the real symmetric tridiagonal (d, e): one wave
+// per eigenvalue, 64 shifts per round (Sturm counts), interval narrowed to
+// the two shifts around the k-th eigenvalue.
+// ---------------------------------------------------------------------------
+__device__ int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    if (fabs(q) < pivmin) q = -pivmin;
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
+__global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict__ dg,
+                                                const double* __restrict__ eg, int nev,
+                                                double* __restrict__ w, const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  double* d = reinterpret_cast<double*>(smem_raw);
+  double* e = d + n;
+  __shared__ double s_lo, s_hi, s_piv;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    d[i] = dg[i];
+    if (i < n - 1) e[i] = eg[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double lo = 1e300, hi = -1e300, emax = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+      if (i < n - 1) emax = fmax(emax, e[i] * e[i]);
+    }
+    const double nrm = fmax(fabs(lo), fabs(hi));
+    const double pad = 4.0 * DBL_EPSILON * nrm * n + 1e-300;
+    s_lo = lo - pad;
+    s_hi = hi + pad;
+    s_piv = DBL_MIN * fmax(1.0, emax);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (k >= nev) return;
+  double lo = s_lo, hi = s_hi;
+  const double pivmin = s_piv;
+  for (int round = 0; round < 64; ++round) {
+    if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    const double step = (hi - lo) / 65.0;
+    const double x = lo + step * (lane + 1);
+    const int c = sturm_count(n, d, e, x, pivmin);
+    const unsigned long long mask = __ballot(c > k);
+    if (mask == 0ull) {
+      lo = lo + step * 64;
+    } else {
+      const int f = __ffsll((long long)mask) - 1;
+      const double xf = lo + step * (f + 1);
+      const double xp = (f > 0) ? lo + step * f : lo;
+      hi = xf;
+      lo = xp;
+    }
+  }
+  if (lane == 0) w[k] = 0.5 * (lo + hi);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse iteration on T for the eigenvalues w[0..nev): thread i handles the
+// cluster that starts at i (eigenvalues closer than ctol to their neighbour),
+// solving (T - w I) x = b by Gaussian elimination with partial pivoting,
+// three iterations, orthogonalized against the earlier cluster members.
+// Z is real [nev][ldz]; scratch holds 5 n doubles per thread.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ d,
+                                              const double* __restrict__ e, int nev,
+                                              const double* __restrict__ w, double* __restrict__ Z,
+                                              int ldz, double* __restrict__ scratch,
+                                              const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= nev) return;
+  double tn = 0.0;
+  for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
+  tn = fmax(tn, DBL_MIN);
+  const double ctol = 1e-7 * tn;
+  if (i0 > 0 && w[i0] - w[i0 - 1] <= ctol) return;   // not a cluster leader
+  int i1 = i0 + 1;
+  while (i1 < nev && w[i1] - w[i1 - 1] <= ctol) ++i1;
+  const double tiny = DBL_EPSILON * tn;
+  double* D = scratch + (size_t)i0 * 5 * n;
+  double* DL = D + n;
+  double* DU = DL + n;
+  double* DU2 = DU + n;
+  double* PV = DU2 + n;   // pivot flags (0/1)
+  for (int i = i0; i < i1; ++i) {
+    const double lam = w[i];
+    // factor T - lam I
+    for (int r = 0; r < n; ++r) {
+      D[r] = d[r] - lam;
+      if (r < n - 1) { DL[r] = e[r]; DU[r] = e[r]; }
+      DU2[r] = 0.0;
+      PV[r] = 0.0;
+    }
+    for (int r = 0; r < n - 1; ++r) {
+      if (fabs(D[r]) >= fabs(DL[r])) {
+        if (D[r] == 0.0) D[r] = tiny;
+        const double f = DL[r] / D[r];
+        DL[r] = f;
+        D[r + 1] -= f * DU[r];
+      } else {
+        const double f = D[r] / DL[r];
+        D[r] = DL[r];
+        DL[r] = f;
+        const double tmp = DU[r];
+        DU[r] = D[r + 1];
+        D[r + 1] = tmp - f * D[r + 1];
+        if (r < n - 2) {
+          DU2[r] = DU[r + 1];
+          DU[r + 1] = -f * DU[r + 1];
+        }
+        PV[r] = 1.0;
+      }
+    }
+    for (int r = 0; r < n; ++r)
+      if (fabs(D[r]) < tiny) D[r] = (D[r] >= 0.0) ? tiny : -tiny;
+    double* x = Z + (size_t)i * ldz;
+    for (int r = 0; r < n; ++r) x[r] = cos(0.7 * r + 1.3 * i) + 0.1;
+    for (int it = 0; it < 3; ++it) {
+      for (int r = 0; r < n - 1; ++r) {
+        if (PV[r] != 0.0) {
+          const double tmp = x[r];
+          x[r] = x[r + 1];
+          x[r + 1] = tmp - DL[r] * x[r + 1];
+        } else {
+          x[r + 1] -= DL[r] * x[r];
+        }
+      }
+      x[n - 1] /= D[n - 1];
+      if (n >= 2) x[n - 2] = (x[n - 2] - DU[n - 2] * x[n - 1]) / D[n - 2];
+      for (int r = n - 3; r >= 0; --r) x[r] = (x[r] - DU[r] * x[r + 1] - DU2[r] * x[r + 2]) / D[r];
+      for (int j = i0; j < i; ++j) {
+        const double* zj = Z + (size_t)j * ldz;
+        double dot = 0.0;
+        for (int r = 0; r < n; ++r) dot += zj[r] * x[r];
+        for (int r = 0; r < n; ++r) x[r] -= dot * zj[r];
+      }
+      double nrm = 0.0;
+      for (int r = 0; r < n; ++r) nrm += x[r] * x[r];
+      const double inv = 1.0 / sqrt(nrm);
+      for (int r = 0; r < n; ++r) x[r] *= inv;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Y = Q Z for a block of CB columns per workgroup, Q = H_0 H_1 ... H_{n-2}:
+// Y <- H_k Y = Y - tau_k v_k (v_k^H Y) for k = n-2 down to 0; the column block
+// stays in LDS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ A, int lda,
+                                                const c128* __restrict__ tau, const double* __restrict__ Z,
+                                                int ldz, int nev, int cb, c128* __restrict__ Y, int ldy,
+                                                const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* y = reinterpret_cast<c128*>(smem_raw);   // [cb][n]
+  c128* s = y + (size_t)cb * n;                  // [cb]
+  c128* part = s + cb;                           // [256]
+  const int c0 = blockIdx.x * cb;
+  const int nc = min(cb, nev - c0);
+  for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
+    const int r = idx % n, c = idx / n;
+    y[c * n + r] = c128{Z[(size_t)(c0 + c) * ldz + r], 0.0};
+  }
+  __syncthreads();
+  const int tpc = max(1, (int)blockDim.x / nc);   // threads per column for the dot products
+  for (int k = n - 2; k >= 0; --k) {
+    const c128 t = tau[k];
+    if (t.x == 0.0 && t.y == 0.0) continue;
+    const int m = n - k - 1;
+    const c128* v = A + (size_t)k * lda + k + 1;
+    // s_c = v^H y_c
+    if (threadIdx.x < tpc * nc) {
+      const int c = threadIdx.x / tpc, l = threadIdx.x % tpc;
+      c128 acc{0.0, 0.0};
+      for (int r = l; r < m; r += tpc) {
+        const c128 u = cmulc(v[r], y[c * n + k + 1 + r]);
+        acc.x += u.x;
+        acc.y += u.y;
+      }
+      part[threadIdx.x] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x < nc) {
+      c128 acc{0.0, 0.0};
+      for (int l = 0; l < tpc; ++l) { acc.x += part[threadIdx.x * tpc + l].x; acc.y += part[threadIdx.x * tpc + l].y; }
+      s[threadIdx.x] = cmul(t, acc);
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
+      const int r = idx % m, c = idx / m;
+      const c128 u = cmul(v[r], s[c]);
+      c128* p = y + c * n + k + 1 + r;
+      *p = c128{p->x - u.x, p->y - u.y};
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
+    const int r = idx % n, c = idx / n;
+    Y[(size_t)(c0 + c) * ldy + r] = y[c * n + r];
+  }
+}
+
+}  // namespace
+
+size_t pw::heig_work_bytes(int nmax) {
+  const size_t n = (size_t)std::max(nmax, 1);
+  return sizeof(c128) * (5 * n * n + 2 * n) + sizeof(double) * (3 * n + n * n + 5 * n * n) +
+         sizeof(int) * n + 20 * 256;
+}
+
+pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
+  const size_t n = (size_t)std::max(nmax, 1);
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  hw.nmax = nmax;
+  hw.L = reinterpret_cast<c128*>(take(sizeof(c128) * n * n));
+  hw.X = reinterpret_cast<c128*>(take(sizeof(c128) * n * n));
+  hw.T1 = reinterpret_cast<c128*>(take(sizeof(c128) * n * n));
+  hw.A = reinterpret_cast<c128*>(take(sizeof(c128) * n * n));
+  hw.Y = reinterpret_cast<c128*>(take(sizeof(c128) * n * n));
+  hw.tau = reinterpret_cast<c128*>(take(sizeof(c128) * n));
+  hw.d = reinterpret_cast<double*>(take(sizeof(double) * n));
+  hw.e = reinterpret_cast<double*>(take(sizeof(double) * n));
+  hw.w = reinterpret_cast<double*>(take(sizeof(double) * n));
+  hw.Z = reinterpret_cast<double*>(take(sizeof(double) * n * n));
+  hw.scratch = reinterpret_cast<double*>(take(sizeof(double) * 5 * n * n));
+  hw.info = reinterpret_cast<int*>(take(256));
+  hw.gamma = reinterpret_cast<double*>(take(256));
+  hw.drop = reinterpret_cast<int*>(take(sizeof(int) * n));
+  return PW_OK;
+}
+
+// Generalized eigenproblem of the n x n Hermitian pair (H, S) (col-major, ld):
+// lowest nev eigenvalues -> w (device), eigenvectors -> C (n x nev, ldc).
+pw_status pw::heig_solve(HeigWork& hw, int n, int nev, const c128* H, const c128* S, int ld,
+                         double* w, c128* C, int ldc, void* part, size_t part_bytes, hipStream_t st) {
+  PW_CHECK(n <= hw.nmax && nev <= n && nev > 0, PW_EINVAL, "reduced problem larger than its workspace");
+  const int ldw = hw.nmax;
+  // L = chol(S)
+  PW_HIP(hipMemcpy2DAsync(hw.L, sizeof(c128) * ldw, S, sizeof(c128) * ld, sizeof(c128) * n, n,
+                          hipMemcpyDeviceToDevice, st));
+  k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * n, st>>>(n, nev, kDropTol, hw.L, ldw, hw.drop, hw.info);
+  // X = L^-H
+  k_trinv<<<n, 256, sizeof(c128) * n, st>>>(n, hw.L, ldw, hw.X, ldw, hw.info);
+  // A = X^H (H X)
+  PW_TRY((pw::zgemm_nn<double, double, double>(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, st)));
+  PW_TRY((pw::zgemm_cn<double, double, double>(n, n, n, hw.X, ldw, hw.T1, ldw, hw.A, ldw, part,
+                                               part_bytes, st)));
+  k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.A, ldw, hw.drop, hw.info);
+  // tridiagonalize, eigenvalues, eigenvectors of T, back-transform
+  k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info);
+  k_bisect<<<ceil_div(nev, 4), 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
+  k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
+  int cb = std::max(1, std::min(16, (48 * 1024) / (int)(sizeof(c128) * n)));
+  k_backtr<<<ceil_div(nev, cb), 256, sizeof(c128) * ((size_t)cb * n + cb + 256), st>>>(
+      n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, cb, hw.Y, ldw, hw.info);
+  // C = X Y
+  PW_TRY((pw::zgemm_nn<double, double, double>(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, st)));
+  k_colnorm_max<<<1, 256, 0, st>>>(n, nev, C, ldc, hw.gamma, hw.info);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw::heig_set_limits() {
+  static bool done = false;
+  if (done) return PW_OK;
+  // only the tridiagonalization can need more than the default 64 KB of
+  // dynamic LDS (n > 1365); allow what is left next to its static LDS
+  hipFuncAttributes at;
+  PW_HIP(hipFuncGetAttributes(&at, (const void*)k_tridiag));
+  const int lim = 160 * 1024 - (int)at.sharedSizeBytes;
+  PW_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  done = true;
+  return PW_OK;
+}
+
+extern "C" pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, const pw_c128* S,
+                                     int32_t ld, double* w, pw_c128* C, int32_t ldc, double* debug,
+                                     void* stream) {
+  PW_CHECK(ctx != nullptr, PW_EINVAL, "NULL context");
+  PW_CHECK(n >= 1 && nev >= 1 && nev <= n && ld >= n && ldc >= n, PW_EINVAL, "bad sizes");
+  PW_CHECK(H && S && w && C, PW_EINVAL, "NULL pointer");
+  PW_HIP(hipSetDevice(ctx->device));
+  PW_TRY(pw::heig_set_limits());
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t hb = pw::heig_work_bytes(n);
+  const size_t pb = pw::splitk_part_bytes(n, n, n, sizeof(c128));
+  void *base = nullptr, *part = nullptr;
+  if (hipMalloc(&base, hb) != hipSuccess || hipMalloc(&part, pb) != hipSuccess) {
+    (void)hipGetLastError();
+    if (base) (void)hipFree(base);
+    return pw::fail(PW_ENOMEM, "workspace allocation failed");
+  }
+  pw::HeigWork hw;
+  pw::heig_setup(hw, base, n);
+  pw_status stt = pw::heig_solve(hw, n, nev, reinterpret_cast<const c128*>(H), reinterpret_cast<const c128*>(S),
+                                 ld, w, reinterpret_cast<c128*>(C), ldc, part, pb, st);
+  int info = 0;
+  if (stt == PW_OK && debug) {
+    if (hipMemcpyAsync(debug, hw.d, sizeof(double) * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        (n > 1 && hipMemcpyAsync(debug + n, hw.e, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st) != hipSuccess))
+      stt = pw::fail(PW_EDEVICE, "copy of the tridiagonal failed");
+  }
+  if (stt == PW_OK) {
+    if (hipMemcpyAsync(&info, hw.info, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      stt = pw::fail(PW_EDEVICE, "reduced eigensolver failed");
+    else if (info != 0)
+      stt = pw::fail(PW_EBREAKDOWN, "S is not positive definite or has rank < nev");
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(base);
+  (void)hipFree(part);
+  return stt;
+}

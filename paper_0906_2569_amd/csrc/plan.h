@@ -95,9 +95,11 @@ pw_status calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, h
 
 // C[m, n] = alpha sum_k A[m, k] B[k, n] + beta C[m, n];  A M-contiguous (A[k*lda + m]),
 // B K-contiguous (B[n*ldb + k]), C M-contiguous complex128 (C[n*ldc + m]).
+// `guard (device int, optional): when nonzero at run time the product is skipped.
 template <typename T, typename TA, typename TB>
 pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
-                   const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream);
+                   const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream,
+                   const int* guard = nullptr);
 
 size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
 

@@ -141,7 +141,9 @@ k_gemm_cn(int M, int N, int K, int kchunk, const cpx<TA>* __restrict__ A, int ld
 template <typename T, typename TA, typename TB>
 __global__ void __launch_bounds__(NT)
 k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int lda,
-          const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C, int ldc) {
+          const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C, int ldc,
+          const int* __restrict__ guard) {
+  if (guard != nullptr && *guard != 0) return;
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -310,10 +312,11 @@ pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* ou
 
 template <typename T, typename TA, typename TB>
 pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
-                       const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t s) {
+                       const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t s,
+                       const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
   k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN)), NT, 0, s>>>(M, N, K, alpha, A, lda,
-                                                                            B, ldb, beta, C, ldc);
+                                                                            B, ldb, beta, C, ldc, guard);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -326,10 +329,10 @@ template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, h
 template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t);
 template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,
                                                         const c128*, int, double, c128*, int,
-                                                        hipStream_t);
+                                                        hipStream_t, const int*);
 template pw_status pw::zgemm_nn<float, float, float>(int, int, int, double, const c64*, int,
                                                      const c64*, int, double, c128*, int,
-                                                     hipStream_t);
+                                                     hipStream_t, const int*);
 template pw_status pw::zgemm_nn<float, double, double>(int, int, int, double, const c128*, int,
                                                        const c128*, int, double, c128*, int,
-                                                       hipStream_t);
+                                                        hipStream_t, const int*);

@@ -22,7 +22,7 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 # every symbol include/pwdft.h declares
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
-           "hpsi_apply", "davidson_solve"]
+           "hpsi_apply", "davidson_solve", "pw_reduced_eigh"]
 
 
 class PwError(RuntimeError):
@@ -81,8 +81,10 @@ def load(path: str = LIB_PATH):
                                C.c_int32, C.c_void_p]
     lib.davidson_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
+    lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                    C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "davidson_solve"):
+                 "pw_plan_info", "hpsi_apply", "davidson_solve", "pw_reduced_eigh"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -157,6 +159,24 @@ def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0) -> 
     s, keep = _problem_struct(p, torch.device("cuda", device))
     o = PlanOpts(precision, nb_max or p.nb, ndim_max)
     return int(load().pw_footprint_bytes(C.byref(s), C.byref(o)))
+
+
+def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):
+    """Lowest nev eigenpairs of h c = w s c (torch complex128 n x n on the device).
+
+    The matrices are read column-major: pass the transpose-free torch tensors
+    of the matrices as [col][row] (i.e. ``m.T.contiguous()`` of a row-major
+    NumPy-style matrix).  Returns (w, C[nev][n], tridiag or None).
+    """
+    import torch
+    n = h.shape[0]
+    w = torch.empty(nev, dtype=torch.float64, device=h.device)
+    c = torch.empty((nev, n), dtype=torch.complex128, device=h.device)
+    dbg = torch.empty(2 * n, dtype=torch.float64, device=h.device) if debug else None
+    _check(load().pw_reduced_eigh(ctx.h, n, nev, C.c_void_p(h.data_ptr()), C.c_void_p(s.data_ptr()), n,
+                                  C.c_void_p(w.data_ptr()), C.c_void_p(c.data_ptr()), n,
+                                  C.c_void_p(dbg.data_ptr()) if debug else None, _stream_ptr(stream)))
+    return w, c, dbg
 
 
 class Plan:

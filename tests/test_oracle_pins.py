@@ -214,3 +214,35 @@ def test_a_posteriori_bounds_hold():
     finite = np.isfinite(kt)
     assert finite.any()
     assert np.all(np.abs(theta - w[:8])[finite] <= kt[finite] * (1 + 1e-6) + 1e-15)
+
+
+def test_davidson_projectors_only():
+    # V = 0: near-dependent corrections; the reduced problem drops them and
+    # H psi is re-applied at restarts, so the iteration still converges
+    p = pwgen.config1(with_vloc=False)
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, p.nb)
+    eps, psi, it, rn = oracle.davidson(h, p.psi0, p.nb, ndim=4, max_iter=400)
+    assert rn.max() <= 1e-6
+    np.testing.assert_allclose(eps, w, atol=5e-9)
+
+
+def test_reduced_eigh_drops_dependent_directions():
+    rng = np.random.default_rng(4)
+    n = 12
+    x = rng.standard_normal((n, 30)) + 1j * rng.standard_normal((n, 30))
+    x[7] = x[2] + 1e-14 * x[5]              # dependent basis vector
+    a = rng.standard_normal((30, 30)) + 1j * rng.standard_normal((30, 30))
+    a = a + a.conj().T
+    hred = np.conj(x) @ a @ x.T
+    sred = np.conj(x) @ x.T
+    w, c = oracle.reduced_eigh(hred, sred, 5)
+    # same Ritz values as the basis without the duplicate
+    keep = [i for i in range(n) if i != 7]
+    w2 = scipy_eigh(hred[np.ix_(keep, keep)], sred[np.ix_(keep, keep)])[:5]
+    np.testing.assert_allclose(w, w2, atol=1e-9)
+
+
+def scipy_eigh(h, s):
+    import scipy.linalg
+    return scipy.linalg.eigh(h, s, eigvals_only=True)

@@ -92,11 +92,13 @@ typedef struct {
 } pw_plan_opts;
 
 typedef struct {
-  int32_t ndim;              /* basis cap = ndim*nb, 2..8 (default 4)                               */
+  int32_t ndim;              /* basis cap = ndim*nb, 2..8 (default 2: the paper's 2N form)          */
   int32_t max_iter;          /* default 200                                                          */
   double  tol_resid;         /* Ha, band converged when ||g_i||_2 <= tol_resid (default 1e-6) ...   */
   double  tol_deig;          /* ... and |eps_i - eps_i(previous)| <= tol_deig (default 5e-9 Ha)     */
-  double  precond_floor;     /* Ha, |h_diag - eps_i| is floored to this (default 0.1)               */
+  double  precond_floor;     /* Ha, tau of the preconditioner denominator
+                                smax(x, tau) = (x + tau + sqrt((x - tau)^2 + tau^2)) / 2,
+                                x = h_diag(G) - eps_i (default 0.2)                              */
   double  ladder_switch;     /* mixed only: max ||g_i|| below which float64 H.psi takes over (1e-4) */
 } pw_david_opts;
 
@@ -177,6 +179,22 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
  */
 pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, const pw_c128* S,
                           int32_t ld, double* w, pw_c128* C, int32_t ldc, double* debug, void* stream);
+
+/*
+ * Per-kernel timing for measurement: when enabled, each library launch of a
+ * timed kernel class is bracketed by HIP events on its stream.
+ * pw_profile_enable(on) resets the accumulators; pw_profile_read(k, ...)
+ * synchronizes on the recorded events and returns the launch count, the
+ * summed elapsed milliseconds and the summed algorithmic work of class k
+ * (0 <= k < pw_profile_count(); bytes for the transform passes and vector
+ * kernels, flops for matrix products and factorizations); pw_profile_name(k)
+ * names the class.  Process-wide; not for concurrent use
+ * from several host threads while enabled.
+ */
+pw_status   pw_profile_enable(int on);
+int32_t     pw_profile_count(void);
+const char* pw_profile_name(int32_t k);
+pw_status   pw_profile_read(int32_t k, int64_t* launches, double* total_ms, double* units);
 
 #ifdef __cplusplus
 }

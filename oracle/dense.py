@@ -184,13 +184,14 @@ def eigh_lowest(h: np.ndarray, nb: int):
 
 def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None = None,
              ndim: int = 2, tol_resid: float = 1e-6, tol_deig: float = 5e-9,
-             max_iter: int = 200, precond_floor: float = 0.1):
+             max_iter: int = 200, precond_floor: float = 0.2):
     """Block Davidson on a dense H, in the order the appendix states it.
 
     1. orthonormalise the trial orbitals and take eps_i = <psi_i|H|psi_i>;
     2. residuals g_i = (H - eps_i) psi_i;
-    3. corrections dpsi_i = g_i / (H_GG - eps_i) for unconverged i
-       (the diagonal approximation of (H - eps)^-1; |denominator| floored);
+    3. corrections dpsi_i = g_i / (H_GG - eps_i) for unconverged i (the
+       diagonal approximation of (H - eps)^-1, with the denominator replaced
+       by its smooth maximum with a floor tau so it stays positive);
     4. reduced problem sum_k (H_jk - eps S_jk) c_k = 0 on the basis phi
        (directions in which the overlap is numerically singular are dropped);
     5. psi_i = sum_j c^(i)_j phi_j; eps_i = <psi_i|H|psi_i>; iterate, growing the
@@ -219,8 +220,9 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None 
         if conv.all() or it >= max_iter:
             break
         todo = np.nonzero(~conv)[0]
-        den = hdiag[None, :] - eps[todo, None]               # step 3
-        den = np.where(np.abs(den) < precond_floor, np.copysign(precond_floor, den), den)
+        x = hdiag[None, :] - eps[todo, None]                 # step 3
+        # smooth maximum of x and the floor tau: x far above tau, >= tau/2
+        den = 0.5 * (x + precond_floor + np.sqrt((x - precond_floor) ** 2 + precond_floor ** 2))
         dpsi = g[todo] / den
         dpsi /= np.linalg.norm(dpsi, axis=1, keepdims=True)
         if phi.shape[0] + len(todo) > ndim * nb:             # restart from Ritz vectors

@@ -36,10 +36,10 @@ extern "C" pw_status pw_ctx_destroy(pw_ctx c) {
 
 extern "C" void pw_david_opts_default(pw_david_opts* o) {
   if (!o) return;
-  o->ndim = 4;
+  o->ndim = 2;
   o->max_iter = 200;
   o->tol_resid = 1e-6;
   o->tol_deig = 5e-9;
-  o->precond_floor = 0.1;
+  o->precond_floor = 0.2;
   o->ladder_switch = 1e-4;
 }

@@ -7,7 +7,7 @@
 //          bands with ||g_i|| <= tol_resid and |d eps_i| <= tol_deig are
 //          converged; for the others the corrections
 //          dpsi_i(G) = g_i(G) / (h_diag(G) - eps_i)   (diagonal preconditioner,
-//          |denominator| floored) are normalized and appended to the basis phi;
+//          denominator smoothly bounded below) are normalized and appended;
 //          the reduced problem H_jk c = eps S_jk c on phi (new rows and columns
 //          only) is solved in float64 on the GPU, and psi = phi c, H psi = H phi c.
 //          The basis grows until ndim*nb (expanding-basis variant), then
@@ -106,7 +106,7 @@ __global__ void k_select(int nb, const double* __restrict__ rn, const double* __
   f->gamma = *gamma;
 }
 
-// out_t = (hpsi_b - eps_b psi_b) / floor(h_diag - eps_b), normalized; b = idx[t]
+// out_t = (hpsi_b - eps_b psi_b) / smax(h_diag - eps_b, floor), normalized; b = idx[t]
 __global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict__ idx,
                                                  const c128* __restrict__ psi, const c128* __restrict__ hpsi,
                                                  int ld, const double* __restrict__ eps,
@@ -121,8 +121,10 @@ __global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict_
   c128* o = out + (size_t)t * ldo;
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    double den = hdiag[g] - e;
-    if (fabs(den) < floor_) den = copysign(floor_, den);
+    // diagonal of H - eps, replaced by its smooth maximum with floor_: equal
+    // to it far above floor_, positive and >= floor_/2 everywhere
+    const double dg = hdiag[g] - e;
+    const double den = 0.5 * (dg + floor_ + sqrt((dg - floor_) * (dg - floor_) + floor_ * floor_));
     const double inv = 1.0 / den;
     const c128 r = c128{(hx[g].x - e * x[g].x) * inv, (hx[g].y - e * x[g].y) * inv};
     o[g] = r;
@@ -276,6 +278,7 @@ struct Solver {
   DavWork& W;
   hipStream_t st;
   pw_david_stats& stats;
+  int nfact = 0;   // leading basis size whose overlap factor is current
 
   pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx) {
     PW_TRY(pw::hpsi_launch(p, prec, n, x, W.ld, hx, W.ld, st));
@@ -301,7 +304,9 @@ struct Solver {
   // device when the overlap matrix is not positive definite)
   pw_status rayleigh_ritz(int nbase, int nb) {
     const int ldm = W.nbasis;
-    PW_TRY(pw::heig_solve(W.hw, nbase, nb, W.hred, W.sred, ldm, W.eps, W.cvec, ldm, W.part, W.part_bytes, st));
+    PW_TRY(pw::heig_solve(W.hw, nfact, nbase, nb, W.hred, W.sred, ldm, W.eps, W.cvec, ldm, W.part, W.part_bytes,
+                          st));
+    nfact = nbase;
     PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.phi, W.ld, W.cvec, ldm, 0.0, W.psi,
                                                  W.ld, st, W.hw.info)));
     PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.hphi, W.ld, W.cvec, ldm, 0.0,
@@ -316,11 +321,14 @@ struct Solver {
     PW_HIP(hipMemcpy2DAsync(W.hphi, pitch, W.hpsi, pitch, sizeof(c128) * p->npw, nb, hipMemcpyDeviceToDevice, st));
     k_restart<<<std::min(1024, ceil_div(nb * nb, 256)), 256, 0, st>>>(nb, W.eps, W.hred, W.sred, W.nbasis);
     PW_HIP(hipGetLastError());
+    PW_TRY(pw::heig_reset(W.hw, nb, st));
+    nfact = nb;
     return PW_OK;
   }
 
   // full Rayleigh-Ritz on a block already in phi[0:nb) (start, precision switch)
   pw_status start_block(pw_precision prec, int nb) {
+    nfact = 0;
     PW_TRY(hpsi(prec, nb, W.phi, W.hphi));
     PW_TRY(project(0, nb));
     PW_TRY(rayleigh_ritz(nb, nb));
@@ -404,7 +412,8 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       // collapse.  Once the accumulated growth is large, the block is rebuilt
       // from the Ritz vectors with a fresh H psi and explicit reduced matrices.
       amp *= std::max(1.0, f.gamma) * std::max(1.0, f.gamma);
-      if (amp > kMaxAmp) {
+      // float32 H.psi carries ~1e-7 relative error already: no growth allowed
+      if (amp > (prec == PW_MIXED ? 1.0 : kMaxAmp)) {
         PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
                                 hipMemcpyDeviceToDevice, st));
         PW_TRY(S.start_block(prec, nb));

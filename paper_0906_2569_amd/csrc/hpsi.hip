@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "plan.h"
+#include "profile.h"
 
 namespace {
 
@@ -596,13 +597,25 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
+  // algorithmic bytes per band: sphere in/out (complex128) and one write plus
+  // one read of the stick columns per transform direction; V(r) once per pass
+  const double sphere_b = 16.0 * p->npw, stick_b = (double)sizeof(cpx<T>) * p->n3 * p->nst;
   for (int c0 = 0; c0 < nb; c0 += p->band_chunk) {
     const int nbc = std::min(p->band_chunk, nb - c0);
-    k_zinv<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3);
-    k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
-    k_zfwd<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
-                                                   hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
-                                                   1.0 / (double)p->N);
+    {
+      pw::ProfScope ps(pw::PK_ZINV, s, nbc * (sphere_b + stick_b));
+      k_zinv<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3);
+    }
+    {
+      pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
+      k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
+    }
+    {
+      pw::ProfScope ps(pw::PK_ZFWD, s, nbc * (sphere_b + stick_b));
+      k_zfwd<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
+                                                     hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
+                                                     1.0 / (double)p->N);
+    }
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -617,6 +630,7 @@ pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi,
     if (p->nbeta > 0) {
       c128* bd = static_cast<c128*>(p->becpd);
       PW_TRY(pw::calbec_d<double>(p, nb, psi, ldpsi, bd, s));
+      pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
       PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, p->nbeta, 1.0, p->beta64, p->ldb,
                                                    bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
     }
@@ -626,6 +640,7 @@ pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi,
     if (p->nbeta > 0) {
       c64* bd = static_cast<c64*>(p->becpd);
       PW_TRY(pw::calbec_d<float>(p, nb, psi, ldpsi, bd, s));
+      pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
       PW_TRY((pw::zgemm_nn<float, float, float>(p->npw, nb, p->nbeta, 1.0, p->beta32, p->ldb,
                                                 bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
     }

@@ -19,8 +19,11 @@ struct HeigWork {
 size_t heig_work_bytes(int nmax);
 pw_status heig_setup(HeigWork& hw, void* base, int nmax);
 pw_status heig_set_limits();
-// lowest nev eigenpairs of H c = w S c (n x n, col-major, leading dimension ld)
-pw_status heig_solve(HeigWork& hw, int n, int nev, const c128* H, const c128* S, int ld, double* w,
+// lowest nev eigenpairs of H c = w S c (n x n, col-major, leading dimension ld);
+// the Cholesky factor of S[0:n0, 0:n0] from the previous call is reused
+pw_status heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, const c128* S, int ld, double* w,
                      c128* C, int ldc, void* part, size_t part_bytes, hipStream_t st);
+// factor of an orthonormal leading block of size n: L = X = I
+pw_status heig_reset(HeigWork& hw, int n, hipStream_t st);
 
 }  // namespace pw

@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "linalg.h"
+#include "profile.h"
 
 namespace {
 
@@ -108,6 +109,36 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
     const int i = idx % n, k = idx / n;
     if (i < k) L[(size_t)k * ld + i] = c128{0.0, 0.0};
   }
+}
+
+// info |= fewer than nev directions kept in [0, n)
+__global__ void k_rank_check(int n, int nev, const int* __restrict__ drop, int* __restrict__ info) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c += drop[i] ? 0 : 1;
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0 && *info == 0 && cnt < nev) *info = 1;
+}
+
+// L = X = I and no dropped directions on [0, n) (the collapsed, orthonormal basis)
+__global__ void k_identity(int n, c128* __restrict__ L, c128* __restrict__ X, int ld, int* __restrict__ drop) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    const c128 v = c128{i == j ? 1.0 : 0.0, 0.0};
+    L[(size_t)j * ld + i] = v;
+    X[(size_t)j * ld + i] = v;
+    if (j == 0) drop[i] = 0;
+  }
+}
+
+// X[r, c] = 0 for r in [r0, r1), c in [0, c1)
+__global__ void k_zero_block(int r0, int r1, int c1, c128* __restrict__ X, int ld) {
+  const int nr = r1 - r0;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nr * c1; idx += gridDim.x * blockDim.x)
+    X[(size_t)(idx / nr) * ld + r0 + idx % nr] = c128{0.0, 0.0};
 }
 
 // Dropped directions are decoupled from the transformed matrix and moved far
@@ -347,7 +378,8 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
 
 // ---------------------------------------------------------------------------
 // Inverse iteration on T for the eigenvalues w[0..nev): thread i handles the
-// cluster that starts at i (eigenvalues closer than ctol to their neighbour),
+// cluster that starts at i (eigenvalues within 1e-7 of the wanted spectrum's
+// scale of their neighbour),
 // solving (T - w I) x = b by Gaussian elimination with partial pivoting,
 // three iterations, orthogonalized against the earlier cluster members.
 // Z is real [nev][ldz]; scratch holds 5 n doubles per thread.
@@ -360,135 +392,141 @@ __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ 
   if (*info != 0) return;
   const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
   if (i0 >= nev) return;
-  double tn = 0.0;
-  for (int i = 0; i < n; ++i) tn = fmax(tn, fabs(d[i]) + (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0));
-  tn = fmax(tn, DBL_MIN);
+  // scale of the wanted part of the spectrum (dropped basis directions sit
+  // far above it and must not widen the clusters)
+  const double tn = fmax(fmax(fabs(w[0]), fabs(w[nev - 1])), fmax(w[nev - 1] - w[0], 1e-300));
   const double ctol = 1e-7 * tn;
   if (i0 > 0 && w[i0] - w[i0 - 1] <= ctol) return;   // not a cluster leader
   int i1 = i0 + 1;
   while (i1 < nev && w[i1] - w[i1 - 1] <= ctol) ++i1;
   const double tiny = DBL_EPSILON * tn;
-  double* D = scratch + (size_t)i0 * 5 * n;
-  double* DL = D + n;
-  double* DU = DL + n;
-  double* DU2 = DU + n;
-  double* PV = DU2 + n;   // pivot flags (0/1)
+  // per-thread arrays interleaved across threads: element r of thread t at
+  // [r * S + t], so that the threads of a wave access consecutive addresses
+  const size_t S = (size_t)gridDim.x * blockDim.x;
+  double* D = scratch + i0;
+  double* DL = D + (size_t)n * S;
+  double* DU = DL + (size_t)n * S;
+  double* DU2 = DU + (size_t)n * S;
+  double* X = DU2 + (size_t)n * S;
+  unsigned long long* PV = reinterpret_cast<unsigned long long*>(X + (size_t)n * S);  // pivot bits
   for (int i = i0; i < i1; ++i) {
     const double lam = w[i];
-    // factor T - lam I
-    for (int r = 0; r < n; ++r) {
-      D[r] = d[r] - lam;
-      if (r < n - 1) { DL[r] = e[r]; DU[r] = e[r]; }
-      DU2[r] = 0.0;
-      PV[r] = 0.0;
-    }
+    // factor T - lam I with partial pivoting; the running pivot stays in a register
+    double dcur = d[0] - lam;
+    double du_next = (n > 1) ? e[0] : 0.0;   // DU[r] before row r's update
     for (int r = 0; r < n - 1; ++r) {
-      if (fabs(D[r]) >= fabs(DL[r])) {
-        if (D[r] == 0.0) D[r] = tiny;
-        const double f = DL[r] / D[r];
-        DL[r] = f;
-        D[r + 1] -= f * DU[r];
+      const double er = e[r];
+      const double dnext = d[r + 1] - lam;
+      const double du_after = (r < n - 2) ? e[r + 1] : 0.0;
+      double dr, dlr, dur, du2r, dn, dun;
+      int piv;
+      if (fabs(dcur) >= fabs(er)) {
+        const double dd = (dcur == 0.0) ? tiny : dcur;
+        const double f = er / dd;
+        dr = dd; dlr = f; dur = du_next; du2r = 0.0; dn = dnext - f * du_next; dun = du_after; piv = 0;
       } else {
-        const double f = D[r] / DL[r];
-        D[r] = DL[r];
-        DL[r] = f;
-        const double tmp = DU[r];
-        DU[r] = D[r + 1];
-        D[r + 1] = tmp - f * D[r + 1];
-        if (r < n - 2) {
-          DU2[r] = DU[r + 1];
-          DU[r + 1] = -f * DU[r + 1];
-        }
-        PV[r] = 1.0;
+        const double f = dcur / er;
+        dr = er; dlr = f; dur = dnext; dn = du_next - f * dnext;
+        du2r = du_after; dun = -f * du_after; piv = 1;
       }
+      D[(size_t)r * S] = dr; DL[(size_t)r * S] = dlr; DU[(size_t)r * S] = dur; DU2[(size_t)r * S] = du2r;
+      PV[(size_t)r * S] = (unsigned long long)piv;
+      dcur = dn;
+      du_next = dun;
     }
-    for (int r = 0; r < n; ++r)
-      if (fabs(D[r]) < tiny) D[r] = (D[r] >= 0.0) ? tiny : -tiny;
-    double* x = Z + (size_t)i * ldz;
-    for (int r = 0; r < n; ++r) x[r] = cos(0.7 * r + 1.3 * i) + 0.1;
+    D[(size_t)(n - 1) * S] = dcur;
+    for (int r = 0; r < n; ++r) {
+      double v = D[(size_t)r * S];
+      if (fabs(v) < tiny) D[(size_t)r * S] = (v >= 0.0) ? tiny : -tiny;
+      X[(size_t)r * S] = cos(0.7 * r + 1.3 * i) + 0.1;
+    }
     for (int it = 0; it < 3; ++it) {
+      double xr = X[0];
       for (int r = 0; r < n - 1; ++r) {
-        if (PV[r] != 0.0) {
-          const double tmp = x[r];
-          x[r] = x[r + 1];
-          x[r + 1] = tmp - DL[r] * x[r + 1];
+        const double xn = X[(size_t)(r + 1) * S];
+        if (PV[(size_t)r * S]) {
+          X[(size_t)r * S] = xn;
+          xr = xr - DL[(size_t)r * S] * xn;
         } else {
-          x[r + 1] -= DL[r] * x[r];
+          X[(size_t)r * S] = xr;
+          xr = xn - DL[(size_t)r * S] * xr;
         }
       }
-      x[n - 1] /= D[n - 1];
-      if (n >= 2) x[n - 2] = (x[n - 2] - DU[n - 2] * x[n - 1]) / D[n - 2];
-      for (int r = n - 3; r >= 0; --r) x[r] = (x[r] - DU[r] * x[r + 1] - DU2[r] * x[r + 2]) / D[r];
+      X[(size_t)(n - 1) * S] = xr;
+      double x2 = 0.0, x1 = X[(size_t)(n - 1) * S] / D[(size_t)(n - 1) * S];
+      X[(size_t)(n - 1) * S] = x1;
+      for (int r = n - 2; r >= 0; --r) {
+        const double xv = (X[(size_t)r * S] - DU[(size_t)r * S] * x1 - DU2[(size_t)r * S] * x2) / D[(size_t)r * S];
+        X[(size_t)r * S] = xv;
+        x2 = x1;
+        x1 = xv;
+      }
       for (int j = i0; j < i; ++j) {
         const double* zj = Z + (size_t)j * ldz;
         double dot = 0.0;
-        for (int r = 0; r < n; ++r) dot += zj[r] * x[r];
-        for (int r = 0; r < n; ++r) x[r] -= dot * zj[r];
+        for (int r = 0; r < n; ++r) dot += zj[r] * X[(size_t)r * S];
+        for (int r = 0; r < n; ++r) X[(size_t)r * S] -= dot * zj[r];
       }
       double nrm = 0.0;
-      for (int r = 0; r < n; ++r) nrm += x[r] * x[r];
+      for (int r = 0; r < n; ++r) nrm += X[(size_t)r * S] * X[(size_t)r * S];
       const double inv = 1.0 / sqrt(nrm);
-      for (int r = 0; r < n; ++r) x[r] *= inv;
+      for (int r = 0; r < n; ++r) X[(size_t)r * S] *= inv;
     }
+    double* z = Z + (size_t)i * ldz;
+    for (int r = 0; r < n; ++r) z[r] = X[(size_t)r * S];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Y = Q Z for a block of CB columns per workgroup, Q = H_0 H_1 ... H_{n-2}:
-// Y <- H_k Y = Y - tau_k v_k (v_k^H Y) for k = n-2 down to 0; the column block
-// stays in LDS.
+// Y = Q Z, Q = H_0 H_1 ... H_{n-2}: Y <- H_k Y = Y - tau_k v_k (v_k^H Y) for
+// k = n-2 down to 0.  One wave per column of Y, held in registers (row
+// r = lane + 64 t in slot t); the dot product is a wave reduction, so no
+// workgroup barrier is needed.
 // ---------------------------------------------------------------------------
+template <int NPL>
 __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ A, int lda,
                                                 const c128* __restrict__ tau, const double* __restrict__ Z,
-                                                int ldz, int nev, int cb, c128* __restrict__ Y, int ldy,
+                                                int ldz, int nev, c128* __restrict__ Y, int ldy,
                                                 const int* __restrict__ info) {
   if (*info != 0) return;
-  extern __shared__ __align__(16) char smem_raw[];
-  c128* y = reinterpret_cast<c128*>(smem_raw);   // [cb][n]
-  c128* s = y + (size_t)cb * n;                  // [cb]
-  c128* part = s + cb;                           // [256]
-  const int c0 = blockIdx.x * cb;
-  const int nc = min(cb, nev - c0);
-  for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
-    const int r = idx % n, c = idx / n;
-    y[c * n + r] = c128{Z[(size_t)(c0 + c) * ldz + r], 0.0};
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (col >= nev) return;
+  c128 y[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int r = lane + 64 * t;
+    y[t] = c128{r < n ? Z[(size_t)col * ldz + r] : 0.0, 0.0};
   }
-  __syncthreads();
-  const int tpc = max(1, (int)blockDim.x / nc);   // threads per column for the dot products
   for (int k = n - 2; k >= 0; --k) {
-    const c128 t = tau[k];
-    if (t.x == 0.0 && t.y == 0.0) continue;
-    const int m = n - k - 1;
-    const c128* v = A + (size_t)k * lda + k + 1;
-    // s_c = v^H y_c
-    if (threadIdx.x < tpc * nc) {
-      const int c = threadIdx.x / tpc, l = threadIdx.x % tpc;
-      c128 acc{0.0, 0.0};
-      for (int r = l; r < m; r += tpc) {
-        const c128 u = cmulc(v[r], y[c * n + k + 1 + r]);
-        acc.x += u.x;
-        acc.y += u.y;
-      }
-      part[threadIdx.x] = acc;
+    const c128 tk = tau[k];
+    if (tk.x == 0.0 && tk.y == 0.0) continue;
+    const c128* v = A + (size_t)k * lda;   // v_k at rows k+1 .. n-1
+    double sr = 0.0, si = 0.0;
+    c128 vv[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const int r = lane + 64 * t;
+      vv[t] = (r > k && r < n) ? v[r] : c128{0.0, 0.0};
+      const c128 u = cmulc(vv[t], y[t]);   // conj(v_r) y_r
+      sr += u.x;
+      si += u.y;
     }
-    __syncthreads();
-    if (threadIdx.x < nc) {
-      c128 acc{0.0, 0.0};
-      for (int l = 0; l < tpc; ++l) { acc.x += part[threadIdx.x * tpc + l].x; acc.y += part[threadIdx.x * tpc + l].y; }
-      s[threadIdx.x] = cmul(t, acc);
+    for (int o = 32; o > 0; o >>= 1) {
+      sr += __shfl_xor(sr, o, 64);
+      si += __shfl_xor(si, o, 64);
     }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < nc * m; idx += blockDim.x) {
-      const int r = idx % m, c = idx / m;
-      const c128 u = cmul(v[r], s[c]);
-      c128* p = y + c * n + k + 1 + r;
-      *p = c128{p->x - u.x, p->y - u.y};
+    const c128 sc = cmul(tk, c128{sr, si});
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
+      const c128 u = cmul(vv[t], sc);
+      y[t] = c128{y[t].x - u.x, y[t].y - u.y};
     }
-    __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < nc * n; idx += blockDim.x) {
-    const int r = idx % n, c = idx / n;
-    Y[(size_t)(c0 + c) * ldy + r] = y[c * n + r];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int r = lane + 64 * t;
+    if (r < n) Y[(size_t)col * ldy + r] = y[t];
   }
 }
 
@@ -496,7 +534,7 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
 
 size_t pw::heig_work_bytes(int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
-  return sizeof(c128) * (5 * n * n + 2 * n) + sizeof(double) * (3 * n + n * n + 5 * n * n) +
+  return sizeof(c128) * (5 * n * n + 2 * n) + sizeof(double) * (3 * n + n * n + 6 * n * (n + 64)) +
          sizeof(int) * n + 20 * 256;
 }
 
@@ -519,7 +557,7 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   hw.e = reinterpret_cast<double*>(take(sizeof(double) * n));
   hw.w = reinterpret_cast<double*>(take(sizeof(double) * n));
   hw.Z = reinterpret_cast<double*>(take(sizeof(double) * n * n));
-  hw.scratch = reinterpret_cast<double*>(take(sizeof(double) * 5 * n * n));
+  hw.scratch = reinterpret_cast<double*>(take(sizeof(double) * 6 * n * (n + 64)));
   hw.info = reinterpret_cast<int*>(take(256));
   hw.gamma = reinterpret_cast<double*>(take(256));
   hw.drop = reinterpret_cast<int*>(take(sizeof(int) * n));
@@ -528,31 +566,83 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
 
 // Generalized eigenproblem of the n x n Hermitian pair (H, S) (col-major, ld):
 // lowest nev eigenvalues -> w (device), eigenvectors -> C (n x nev, ldc).
-pw_status pw::heig_solve(HeigWork& hw, int n, int nev, const c128* H, const c128* S, int ld,
+// When n0 > 0 the factor L of S[0:n0, 0:n0] and X = L^-H from the previous
+// call (or heig_reset) are still valid, and only the new block rows are
+// factored:  U12 = X11^H S12,  L22 L22^H = S22 - U12^H U12,  X22 = L22^-H,
+// X12 = -X11 U12 X22.
+pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, const c128* S, int ld,
                          double* w, c128* C, int ldc, void* part, size_t part_bytes, hipStream_t st) {
-  PW_CHECK(n <= hw.nmax && nev <= n && nev > 0, PW_EINVAL, "reduced problem larger than its workspace");
+  PW_CHECK(n <= hw.nmax && nev <= n && nev > 0 && n0 >= 0 && n0 < n, PW_EINVAL,
+           "reduced problem larger than its workspace");
   const int ldw = hw.nmax;
-  // L = chol(S)
-  PW_HIP(hipMemcpy2DAsync(hw.L, sizeof(c128) * ldw, S, sizeof(c128) * ld, sizeof(c128) * n, n,
-                          hipMemcpyDeviceToDevice, st));
-  k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * n, st>>>(n, nev, kDropTol, hw.L, ldw, hw.drop, hw.info);
-  // X = L^-H
-  k_trinv<<<n, 256, sizeof(c128) * n, st>>>(n, hw.L, ldw, hw.X, ldw, hw.info);
+  const int m = n - n0;
+  c128* L22 = hw.L + (size_t)n0 * ldw + n0;
+  c128* X22 = hw.X + (size_t)n0 * ldw + n0;
+  if (n0 > 0) {
+    PW_TRY((pw::zgemm_cn<double, double, double>(n0, m, n0, hw.X, ldw, S + (size_t)n0 * ld, ld, hw.T1, ldw,
+                                                 part, part_bytes, st)));
+  }
+  PW_HIP(hipMemcpy2DAsync(L22, sizeof(c128) * ldw, S + (size_t)n0 * ld + n0, sizeof(c128) * ld,
+                          sizeof(c128) * m, m, hipMemcpyDeviceToDevice, st));
+  if (n0 > 0) {
+    PW_TRY((pw::zgemm_cn<double, double, double>(m, m, n0, hw.T1, ldw, hw.T1, ldw, L22, ldw, part, part_bytes,
+                                                 st, -1.0, 1.0)));
+  }
+  {
+    pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);
+    k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+  }
+  k_rank_check<<<1, 256, 0, st>>>(n, nev, hw.drop, hw.info);
+  {
+    pw::ProfScope ps(pw::PK_TRINV, st, 8.0 / 3.0 * m * m * (double)m);
+    k_trinv<<<m, 256, sizeof(c128) * m, st>>>(m, L22, ldw, X22, ldw, hw.info);
+  }
+  if (n0 > 0) {
+    // X12 = -X11 (U12 X22)
+    PW_TRY((pw::zgemm_nn<double, double, double>(n0, m, m, 1.0, hw.T1, ldw, X22, ldw, 0.0, hw.Y, ldw, st)));
+    PW_TRY((pw::zgemm_nn<double, double, double>(n0, m, n0, -1.0, hw.X, ldw, hw.Y, ldw, 0.0,
+                                                 hw.X + (size_t)n0 * ldw, ldw, st)));
+    k_zero_block<<<std::min(1024, ceil_div(m * n0, 256)), 256, 0, st>>>(n0, n, n0, hw.X, ldw);
+  }
   // A = X^H (H X)
   PW_TRY((pw::zgemm_nn<double, double, double>(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, st)));
   PW_TRY((pw::zgemm_cn<double, double, double>(n, n, n, hw.X, ldw, hw.T1, ldw, hw.A, ldw, part,
                                                part_bytes, st)));
   k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.A, ldw, hw.drop, hw.info);
   // tridiagonalize, eigenvalues, eigenvectors of T, back-transform
-  k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info);
-  k_bisect<<<ceil_div(nev, 4), 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
-  k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
-  int cb = std::max(1, std::min(16, (48 * 1024) / (int)(sizeof(c128) * n)));
-  k_backtr<<<ceil_div(nev, cb), 256, sizeof(c128) * ((size_t)cb * n + cb + 256), st>>>(
-      n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, cb, hw.Y, ldw, hw.info);
+  {
+    pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
+    k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info);
+  }
+  {
+    pw::ProfScope ps(pw::PK_BISECT, st);
+    k_bisect<<<ceil_div(nev, 4), 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
+  }
+  {
+    pw::ProfScope ps(pw::PK_INVIT, st);
+    k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
+  }
+  {
+    pw::ProfScope ps(pw::PK_BACKTR, st, 8.0 * n * n * (double)nev);
+    const dim3 g(ceil_div(nev, 4)), b(256);
+    const int npl = ceil_div(n, 64);
+    if (npl <= 2) k_backtr<2><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 4) k_backtr<4><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 8) k_backtr<8><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 16) k_backtr<16><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 32) k_backtr<32><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 64) k_backtr<64><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else return pw::fail(PW_EINVAL, "reduced problem larger than 4096");
+  }
   // C = X Y
   PW_TRY((pw::zgemm_nn<double, double, double>(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, st)));
   k_colnorm_max<<<1, 256, 0, st>>>(n, nev, C, ldc, hw.gamma, hw.info);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw::heig_reset(HeigWork& hw, int n, hipStream_t st) {
+  k_identity<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.L, hw.X, hw.nmax, hw.drop);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -589,7 +679,7 @@ extern "C" pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const p
   }
   pw::HeigWork hw;
   pw::heig_setup(hw, base, n);
-  pw_status stt = pw::heig_solve(hw, n, nev, reinterpret_cast<const c128*>(H), reinterpret_cast<const c128*>(S),
+  pw_status stt = pw::heig_solve(hw, 0, n, nev, reinterpret_cast<const c128*>(H), reinterpret_cast<const c128*>(S),
                                  ld, w, reinterpret_cast<c128*>(C), ldc, part, pb, st);
   int info = 0;
   if (stt == PW_OK && debug) {

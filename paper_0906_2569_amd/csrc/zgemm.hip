@@ -18,6 +18,7 @@
 #include <algorithm>
 
 #include "plan.h"
+#include "profile.h"
 
 namespace {
 
@@ -201,10 +202,10 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int 
       }
 }
 
-// C[n*ldc + m] = sum_z P[z][n][m]   (fixed summation order)
+// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]   (fixed summation order)
 template <typename T>
 __global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
-                         c128* __restrict__ C, int ldc) {
+                         c128* __restrict__ C, int ldc, double alpha, double beta) {
   const size_t total = (size_t)M * N;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
@@ -215,7 +216,13 @@ __global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
       re += v.x;
       im += v.y;
     }
-    C[(size_t)n * ldc + m] = c128{(double)re, (double)im};
+    c128* c = C + (size_t)n * ldc + m;
+    double r = alpha * (double)re, i = alpha * (double)im;
+    if (beta != 0.0) {
+      r += beta * c->x;
+      i += beta * c->y;
+    }
+    *c = c128{r, i};
   }
 }
 
@@ -274,7 +281,8 @@ size_t pw::splitk_part_bytes(int M, int N, int K, int elem_bytes) {
 
 template <typename T, typename TA, typename TB>
 pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>* B, int ldb,
-                       c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s) {
+                       c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s, double alpha,
+                       double beta) {
   if (M <= 0 || N <= 0) return PW_OK;
   const Split sp = choose_split(M, N, K);
   const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
@@ -282,13 +290,20 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   cpx<T>* P = static_cast<cpx<T>*>(part);
   if (K <= 0) {
     PW_HIP(hipMemsetAsync(P, 0, (size_t)M * N * sizeof(cpx<T>), s));
-    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, 1, P, C, ldc);
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, 1, P, C, ldc, alpha, beta);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
-  k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
-      M, N, K, sp.kchunk, A, lda, B, ldb, P);
-  k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, sp.nsplit, P, C, ldc);
+  {
+    pw::ProfScope ps(pw::PK_GEMM_CN, s, 8.0 * M * N * K);
+    k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+        M, N, K, sp.kchunk, A, lda, B, ldb, P);
+  }
+  {
+    pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + 16.0 * M * N);
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, sp.nsplit, P, C, ldc, alpha,
+                                                                          beta);
+  }
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -302,10 +317,16 @@ pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* ou
   cpx<T>* P = static_cast<cpx<T>*>(p->part);
   const cpx<T>* beta = sizeof(T) == 8 ? (const cpx<T>*)p->beta64 : (const cpx<T>*)p->beta32;
   const cpx<T>* drow = sizeof(T) == 8 ? (const cpx<T>*)p->drow64 : (const cpx<T>*)p->drow32;
-  k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
-      M, N, K, sp.kchunk, beta, p->ldb, psi, ldpsi, P);
-  k_reduce_dapply<T><<<N, 256, sizeof(cpx<T>) * M, s>>>(M, N, sp.nsplit, P, p->dstart, p->dlen,
-                                                      drow, p->nhmax, out);
+  {
+    pw::ProfScope ps(pw::PK_CALBEC, s, 8.0 * M * N * K);
+    k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+        M, N, K, sp.kchunk, beta, p->ldb, psi, ldpsi, P);
+  }
+  {
+    pw::ProfScope ps(pw::PK_CALBEC_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + (double)M * N * sizeof(cpx<T>));
+    k_reduce_dapply<T><<<N, 256, sizeof(cpx<T>) * M, s>>>(M, N, sp.nsplit, P, p->dstart, p->dlen,
+                                                        drow, p->nhmax, out);
+  }
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -315,6 +336,7 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
                        const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t s,
                        const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
+  pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
   k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN)), NT, 0, s>>>(M, N, K, alpha, A, lda,
                                                                             B, ldb, beta, C, ldc, guard);
   PW_HIP(hipGetLastError());
@@ -322,9 +344,11 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
 }
 
 template pw_status pw::zgemm_cn<double, double, double>(int, int, int, const c128*, int, const c128*,
-                                                        int, c128*, int, void*, size_t, hipStream_t);
+                                                        int, c128*, int, void*, size_t, hipStream_t,
+                                                        double, double);
 template pw_status pw::zgemm_cn<float, double, double>(int, int, int, const c128*, int, const c128*,
-                                                       int, c128*, int, void*, size_t, hipStream_t);
+                                                       int, c128*, int, void*, size_t, hipStream_t,
+                                                       double, double);
 template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, hipStream_t);
 template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t);
 template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,

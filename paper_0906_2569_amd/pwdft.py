@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 # every symbol include/pwdft.h declares
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
-           "hpsi_apply", "davidson_solve", "pw_reduced_eigh"]
+           "hpsi_apply", "davidson_solve", "pw_reduced_eigh", "pw_profile_enable",
+           "pw_profile_count", "pw_profile_name", "pw_profile_read"]
 
 
 class PwError(RuntimeError):
@@ -83,8 +84,14 @@ def load(path: str = LIB_PATH):
                                    C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
     lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    lib.pw_profile_enable.argtypes = [C.c_int]
+    lib.pw_profile_count.restype = C.c_int32
+    lib.pw_profile_name.argtypes = [C.c_int32]
+    lib.pw_profile_name.restype = C.c_char_p
+    lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "davidson_solve", "pw_reduced_eigh"):
+                 "pw_plan_info", "hpsi_apply", "davidson_solve", "pw_reduced_eigh", "pw_profile_enable",
+                 "pw_profile_read"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -159,6 +166,21 @@ def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0) -> 
     s, keep = _problem_struct(p, torch.device("cuda", device))
     o = PlanOpts(precision, nb_max or p.nb, ndim_max)
     return int(load().pw_footprint_bytes(C.byref(s), C.byref(o)))
+
+
+def profile_enable(on=True):
+    _check(load().pw_profile_enable(1 if on else 0))
+
+
+def profile_read():
+    """{kernel class: (launches, total ms, algorithmic units)} since profile_enable()."""
+    lib = load()
+    out = {}
+    for k in range(lib.pw_profile_count()):
+        n, ms, u = C.c_int64(), C.c_double(), C.c_double()
+        _check(lib.pw_profile_read(k, C.byref(n), C.byref(ms), C.byref(u)))
+        out[lib.pw_profile_name(k).decode()] = (int(n.value), float(ms.value), float(u.value))
+    return out
 
 
 def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):

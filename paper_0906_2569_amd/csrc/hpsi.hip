@@ -20,6 +20,7 @@
 #include <numeric>
 #include <vector>
 
+#include "fft_reg.h"
 #include "plan.h"
 #include "profile.h"
 
@@ -136,6 +137,126 @@ k_plane(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   for (int s = threadIdx.x; s < nst; s += blockDim.x) st[s] = Y[m.st_hx[s] * n2 + m.st_i2[s]];
 }
 
+
+// ---------------------------------------------------------------------------
+// pass 2, register-resident variant for n1 = n2 = 4 LS: one workgroup per
+// (z plane, band); each 1D transform runs on one quad of lanes in VGPRs
+// (see fft_reg.h); LDS only holds the plane's x columns Y[nxr][n2 + 1] as
+// the transpose between the y and x transforms.
+// ---------------------------------------------------------------------------
+template <typename T, int LS>
+__global__ void __launch_bounds__(512)
+k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
+            const cpx<T>* __restrict__ tw1g, const cpx<T>* __restrict__ tw2g) {
+  constexpr int N = 4 * LS;     // n1 = n2 = N
+  constexpr int YS = N + 1;     // padded column stride
+  extern __shared__ __align__(16) char smem_raw[];
+  const int nxr = m.nxr, nst = m.nst;
+  cpx<T>* tw1 = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw2 = tw1 + N;
+  cpx<T>* Y = tw2 + N;                                   // [nxr][YS]
+  int* hx_of = reinterpret_cast<int*>(Y + nxr * YS);     // [N]
+  const int z = blockIdx.x, band = blockIdx.y;
+  cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
+  const T* vz = vr + (size_t)z * N * N;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    tw1[i] = tw1g[i];
+    tw2[i] = tw2g[i];
+    hx_of[i] = m.i1_hx[i];
+  }
+  for (int i = threadIdx.x; i < nxr * YS; i += blockDim.x) Y[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  for (int s = threadIdx.x; s < nst; s += blockDim.x) Y[m.st_hx[s] * YS + m.st_i2[s]] = st[s];
+  __syncthreads();
+  const int q = threadIdx.x & 3, nquads = blockDim.x >> 2;
+  const int pb = regfft::quad_block(q);   // block of the transform held after inv_dit
+  // inverse y transforms of the x columns
+  for (int c = threadIdx.x >> 2; c < nxr; c += nquads) {
+    cpx<T> x[LS];
+    cpx<T>* col = Y + c * YS;
+#pragma unroll
+    for (int j = 0; j < LS; ++j) x[j] = col[q + 4 * j];
+    regfft::inv_dit<LS, T>(x, q, tw2);
+#pragma unroll
+    for (int k = 0; k < LS; ++k) col[k + LS * pb] = x[k];
+  }
+  __syncthreads();
+  // rows: inverse x, V(r), forward x; only the x columns of the sphere are read and written
+  for (int r = threadIdx.x >> 2; r < N; r += nquads) {
+    cpx<T> x[LS];
+#pragma unroll
+    for (int j = 0; j < LS; ++j) {
+      const int hx = hx_of[q + 4 * j];
+      x[j] = hx >= 0 ? Y[hx * YS + r] : cpx<T>{T(0), T(0)};
+    }
+    regfft::inv_dit<LS, T>(x, q, tw1);
+    const T* vrow = vz + (size_t)r * N + LS * pb;
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = x[k] * vrow[k];
+    regfft::fwd_dif<LS, T>(x, q, tw1);
+#pragma unroll
+    for (int j = 0; j < LS; ++j) {
+      const int hx = hx_of[q + 4 * j];
+      if (hx >= 0) Y[hx * YS + r] = x[j];
+    }
+  }
+  __syncthreads();
+  // forward y transforms
+  for (int c = threadIdx.x >> 2; c < nxr; c += nquads) {
+    cpx<T> x[LS];
+    cpx<T>* col = Y + c * YS;
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = col[k + LS * pb];
+    regfft::fwd_dif<LS, T>(x, q, tw2);
+#pragma unroll
+    for (int j = 0; j < LS; ++j) col[q + 4 * j] = x[j];
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < nst; s += blockDim.x) st[s] = Y[m.st_hx[s] * YS + m.st_i2[s]];
+}
+
+template <typename T>
+using PlaneRegFn = void (*)(SphereMap, cpx<T>*, const T*, const cpx<T>*, const cpx<T>*);
+
+// register-resident plane kernel for n1 = n2 = 4 LS, or nullptr
+template <typename T>
+PlaneRegFn<T> plane_reg_kernel(int n1, int n2) {
+  if (n1 != n2 || n1 % 4 != 0) return nullptr;
+  const int ls = n1 / 4;
+  const bool f64 = sizeof(T) == 8;
+  switch (ls) {
+    case 8: return k_plane_reg<T, 8>;
+    case 9: return k_plane_reg<T, 9>;
+    case 10: return k_plane_reg<T, 10>;
+    case 12: return k_plane_reg<T, 12>;
+    case 15: return k_plane_reg<T, 15>;
+    case 16: return k_plane_reg<T, 16>;
+    case 18: return k_plane_reg<T, 18>;
+    case 20: return f64 ? nullptr : k_plane_reg<T, 20>;
+    case 24: return f64 ? nullptr : k_plane_reg<T, 24>;
+    case 25: return f64 ? nullptr : k_plane_reg<T, 25>;
+    case 27: return f64 ? nullptr : k_plane_reg<T, 27>;
+    case 30: return f64 ? nullptr : k_plane_reg<T, 30>;
+    case 32: return f64 ? nullptr : k_plane_reg<T, 32>;
+    case 36: return f64 ? nullptr : k_plane_reg<T, 36>;
+    default: return nullptr;
+  }
+}
+
+template <typename T>
+size_t plane_reg_lds_bytes(int n, int nxr) {
+  return sizeof(cpx<T>) * (2 * (size_t)n + (size_t)nxr * (n + 1)) + sizeof(int) * (size_t)n;
+}
+
+// float64 transforms use ~240 VGPRs (2 waves per SIMD): 256-thread groups
+// keep two planes in flight per CU; float32 ones use up to a full quad per row
+template <typename T>
+int plane_reg_threads(int n, int nxr) {
+  const int need = 4 * std::max(n, nxr);
+  const int cap = sizeof(T) == 8 ? 256 : 512;
+  return std::min(cap, (need + 63) / 64 * 64);
+}
+
 // ---------------------------------------------------------------------------
 // pass 3: forward z transform, gather to the sphere, kinetic term
 // ---------------------------------------------------------------------------
@@ -143,7 +264,7 @@ template <typename T>
 __global__ void __launch_bounds__(ZTHREADS)
 k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
        const c128* __restrict__ psi, int ldpsi, c128* __restrict__ hpsi, int ldhpsi,
-       const cpx<T>* __restrict__ twg, double inv_n) {
+       const cpx<T>* __restrict__ twg, double inv_n, int accumulate) {
   extern __shared__ __align__(16) char smem_raw[];
   const int n3 = m.n3;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -170,7 +291,12 @@ k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
     const cpx<T> v = X[(m.ent_s[e] - s0) * n3 + m.ent_z[e]];
     const c128 p = pb[g];
     const double t = m.kin[g];
-    hb[g] = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
+    c128 r = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
+    if (accumulate) {   // the projector term is already in hpsi
+      const c128 o = hb[g];
+      r = c128{r.x + o.x, r.y + o.y};
+    }
+    hb[g] = r;
   }
 }
 
@@ -548,6 +674,10 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
   p->part_bytes = pw::splitk_part_bytes(nbeta1, o->nb_max, npw, sizeof(c128));
   PLAN_TRY(dalloc(p, reinterpret_cast<char**>(&p->part), p->part_bytes));
+  if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
+    return fail_cleanup(pw::fail(PW_EDEVICE, "stream/event creation failed"));
   if (o->ndim_max > 0) PLAN_TRY(pw::dav_alloc(p));
   if (hipDeviceSynchronize() != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "plan initialisation kernels failed"));
@@ -563,6 +693,9 @@ extern "C" pw_status pw_plan_destroy(pw_plan p) {
   pw::dav_free(p);
   for (void* q : p->allocs)
     if (q) (void)hipFree(q);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
+  if (p->side) (void)hipStreamDestroy(p->side);
   delete p;
   return PW_OK;
 }
@@ -583,7 +716,7 @@ extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
 namespace {
 template <typename T>
 pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, int ldhpsi,
-                   hipStream_t s) {
+                   hipStream_t s, bool accumulate, hipEvent_t join) {
   const bool f64 = sizeof(T) == 8;
   const SphereMap m = p->map();
   const cpx<T>* tw1 = f64 ? (const cpx<T>*)p->tw64_1 : (const cpx<T>*)p->tw32_1;
@@ -595,6 +728,8 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   PW_CHECK(cb > 0, PW_EINVAL, "grid too large for this precision's plane pass");
   const size_t zl = z_lds_bytes<T>(p->n3);
   const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
+  PlaneRegFn<T> preg = p->use_reg_plane ? plane_reg_kernel<T>(p->n1, p->n2) : nullptr;
+  if (preg && plane_reg_lds_bytes<T>(p->n1, p->nxr) > 64 * 1024) preg = nullptr;
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
   // algorithmic bytes per band: sphere in/out (complex128) and one write plus
@@ -608,13 +743,18 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     }
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
-      k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
+      if (preg)
+        preg<<<dim3(p->n3, nbc), plane_reg_threads<T>(p->n1, p->nxr), plane_reg_lds_bytes<T>(p->n1, p->nxr), s>>>(
+            m, st, vr, tw1, tw2);
+      else
+        k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
     }
+    if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
     {
       pw::ProfScope ps(pw::PK_ZFWD, s, nbc * (sphere_b + stick_b));
       k_zfwd<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
                                                      hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
-                                                     1.0 / (double)p->N);
+                                                     1.0 / (double)p->N, accumulate ? 1 : 0);
     }
   }
   PW_HIP(hipGetLastError());
@@ -622,29 +762,37 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
 }
 }  // namespace
 
+// Projector term on the plan's side stream, written into hpsi (overwrite):
+// hpsi = beta (D <beta|psi>).  Runs concurrently with the transform passes
+// (matrix cores vs vector ALUs); the final transform pass adds to it.
+template <typename T>
+pw_status nonlocal_side(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, int ldhpsi,
+                        hipStream_t side) {
+  cpx<T>* bd = static_cast<cpx<T>*>(p->becpd);
+  const cpx<T>* beta = sizeof(T) == 8 ? (const cpx<T>*)p->beta64 : (const cpx<T>*)p->beta32;
+  PW_TRY(pw::calbec_d<T>(p, nb, psi, ldpsi, bd, side));
+  pw::ProfScope ps(pw::PK_ADDNL, side, 8.0 * p->npw * nb * p->nbeta);
+  PW_TRY((pw::zgemm_nn<T, T, T>(p->npw, nb, p->nbeta, 1.0, beta, p->ldb, bd, p->nbeta, 0.0, hpsi, ldhpsi, side)));
+  return PW_OK;
+}
+
 pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
                           c128* hpsi, int ldhpsi, hipStream_t s) {
   if (nb == 0) return PW_OK;
-  if (prec == PW_FP64) {
-    PW_TRY(hpsi_fft<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
-    if (p->nbeta > 0) {
-      c128* bd = static_cast<c128*>(p->becpd);
-      PW_TRY(pw::calbec_d<double>(p, nb, psi, ldpsi, bd, s));
-      pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
-      PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, p->nbeta, 1.0, p->beta64, p->ldb,
-                                                   bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
-    }
-  } else {
-    PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
-    PW_TRY(hpsi_fft<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
-    if (p->nbeta > 0) {
-      c64* bd = static_cast<c64*>(p->becpd);
-      PW_TRY(pw::calbec_d<float>(p, nb, psi, ldpsi, bd, s));
-      pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
-      PW_TRY((pw::zgemm_nn<float, float, float>(p->npw, nb, p->nbeta, 1.0, p->beta32, p->ldb,
-                                                bd, p->nbeta, 1.0, hpsi, ldhpsi, s)));
-    }
+  const bool f64 = prec == PW_FP64;
+  if (!f64) PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
+  hipEvent_t join = nullptr;
+  if (p->nbeta > 0) {
+    // fork: the side stream starts once psi is ready on s
+    PW_HIP(hipEventRecord(p->ev_fork, s));
+    PW_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
+    if (f64) PW_TRY(nonlocal_side<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, p->side));
+    else PW_TRY(nonlocal_side<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, p->side));
+    PW_HIP(hipEventRecord(p->ev_join, p->side));
+    join = p->ev_join;
   }
+  if (f64) PW_TRY(hpsi_fft<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, s, p->nbeta > 0, join));
+  else PW_TRY(hpsi_fft<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, s, p->nbeta > 0, join));
   return PW_OK;
 }
 

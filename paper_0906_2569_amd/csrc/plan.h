@@ -37,6 +37,7 @@ struct pw_plan_s {
   int nbeta = 0, nblk = 0, nhmax = 0;
   int ldb = 0;              // leading dimension of the plan's beta copies
   int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
+  bool use_reg_plane = true;  // register-resident plane pass where the grid allows
 
   // maps (device)
   int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
@@ -66,6 +67,8 @@ struct pw_plan_s {
 
   DavWork* dav = nullptr;
   std::vector<void*> allocs;
+  hipStream_t side = nullptr;          // projector term runs here, beside the transforms
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   SphereMap map() const {
     SphereMap m;

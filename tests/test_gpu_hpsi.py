@@ -140,3 +140,22 @@ def test_mixed_precision_error(ctx):
     err = _rel_err(got, ref)
     # float32 transforms and projector products: relative error of order 1e-6
     assert 1e-9 < err <= 2e-6
+
+
+@pytest.mark.parametrize("n,prec", [(32, 0), (36, 0), (40, 0), (48, 0), (60, 0), (64, 0), (72, 0),
+                                    (36, 1), (48, 1), (64, 1), (72, 1), (80, 1), (96, 1)])
+def test_register_plane_pass_sizes(ctx, n, prec):
+    # cubic grids n = 4 LS take the register-resident plane pass
+    ecut = {32: 9.0, 36: 10.0, 40: 13.0, 48: 18.0, 60: 28.0, 64: 32.0, 72: 40.0, 80: 50.0, 96: 70.0}[n]
+    p = pwgen.tiny_cell(40 + n, a=6.0, ecut_ry=ecut, natoms=2, nb=5, kfrac=(0.25, -0.25, 0.0),
+                        nr=(n, n, n))
+    assert max(pwgen.min_grid(p.miller)) <= n
+    got = _hpsi(ctx, p, p.psi0, prec=prec)
+    if p.npw <= 2500:
+        ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
+    else:
+        rows = np.sort(np.random.default_rng(n).choice(p.npw, 300, replace=False))
+        ref_rows = oracle.hpsi_rows_of(p, p.psi0, rows)
+        got, ref = got[:, rows], ref_rows
+    err = _rel_err(got, ref)
+    assert err <= (1e-11 if prec == 0 else 2e-6), err

@@ -44,11 +44,14 @@ void set_error(const std::string& msg);
 pw_status fail(pw_status st, const std::string& msg);
 }  // namespace pw
 
-#define PW_HIP(call)                                                                   \
-  do {                                                                                 \
-    hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
-      return pw::fail(PW_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+#define PW_STR2(x) #x
+#define PW_STR(x) PW_STR2(x)
+#define PW_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return pw::fail(PW_EDEVICE, std::string(__FILE__ ":" PW_STR(__LINE__) ": ") + #call ": " + \
+                                      hipGetErrorString(e_));                                 \
   } while (0)
 
 #define PW_CHECK(cond, st, msg)             \

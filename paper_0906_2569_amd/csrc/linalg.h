@@ -14,6 +14,7 @@ struct HeigWork {
   int* info = nullptr;     // 0, or 1 when fewer than nev independent directions remain
   int* drop = nullptr;     // [n] 1 for basis directions dropped as dependent
   double* gamma = nullptr; // max column norm of the last eigenvector block C
+  c128 *PV = nullptr, *PW = nullptr;   // tridiagonalization panel vectors (conjugated, row-major)
 };
 
 size_t heig_work_bytes(int nmax);

@@ -44,6 +44,32 @@ __device__ c128 block_sum_c(c128 v, double* red) {
   return c128{re, im};
 }
 
+
+// partial[s * m + i] = sum_{j = s, s + ns, ...} S[j * ld + i] v[j]: four
+// independent accumulators keep several L2 loads in flight per thread
+__device__ __forceinline__ void matvec_slices(int m, int ns, const c128* __restrict__ S, int ld,
+                                              const c128* __restrict__ v, c128* __restrict__ part) {
+  for (int idx = threadIdx.x; idx < m * ns; idx += blockDim.x) {
+    const int i = idx % m, sl = idx / m;
+    double r0 = 0, i0 = 0, r1 = 0, i1 = 0, r2 = 0, i2 = 0, r3 = 0, i3 = 0;
+    int j = sl;
+    for (; j + 3 * ns < m; j += 4 * ns) {
+      const c128 a0 = S[(size_t)j * ld + i], a1 = S[(size_t)(j + ns) * ld + i];
+      const c128 a2 = S[(size_t)(j + 2 * ns) * ld + i], a3 = S[(size_t)(j + 3 * ns) * ld + i];
+      const c128 b0 = v[j], b1 = v[j + ns], b2 = v[j + 2 * ns], b3 = v[j + 3 * ns];
+      r0 += a0.x * b0.x - a0.y * b0.y; i0 += a0.x * b0.y + a0.y * b0.x;
+      r1 += a1.x * b1.x - a1.y * b1.y; i1 += a1.x * b1.y + a1.y * b1.x;
+      r2 += a2.x * b2.x - a2.y * b2.y; i2 += a2.x * b2.y + a2.y * b2.x;
+      r3 += a3.x * b3.x - a3.y * b3.y; i3 += a3.x * b3.y + a3.y * b3.x;
+    }
+    for (; j < m; j += ns) {
+      const c128 a0 = S[(size_t)j * ld + i], b0 = v[j];
+      r0 += a0.x * b0.x - a0.y * b0.y; i0 += a0.x * b0.y + a0.y * b0.x;
+    }
+    part[idx] = c128{(r0 + r1) + (r2 + r3), (i0 + i1) + (i2 + i3)};
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Cholesky S = L L^H (lower), in place on a copy of S, dropping dependent
 // directions: a pivot below drop_tol times the original diagonal entry (a
@@ -93,6 +119,7 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
       col[i] = v;
     }
     __syncthreads();
+#pragma unroll 4
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
       const int ii = idx % m, kk = idx / m;
       if (ii >= kk) {
@@ -266,16 +293,7 @@ __global__ void __launch_bounds__(NTL) k_tridiag(int n, c128* __restrict__ A, in
     c128* S = A + (size_t)(k + 1) * ld + k + 1;      // trailing block, m x m
     // p = tau * S v : S slices of rows
     const int ns = max(1, min(bs / m, 64));
-    for (int idx = tid; idx < m * ns; idx += bs) {
-      const int i = idx % m, s = idx / m;
-      c128 acc{0.0, 0.0};
-      for (int j = s; j < m; j += ns) {
-        const c128 u = cmul(S[(size_t)j * ld + i], v[j]);
-        acc.x += u.x;
-        acc.y += u.y;
-      }
-      part[idx] = acc;
-    }
+    matvec_slices(m, ns, S, ld, v, part);
     __syncthreads();
     double hr = 0.0, hi = 0.0;
     for (int i = tid; i < m; i += bs) {
@@ -295,6 +313,7 @@ __global__ void __launch_bounds__(NTL) k_tridiag(int n, c128* __restrict__ A, in
       w[i] = c128{w[i].x + u.x, w[i].y + u.y};
     }
     __syncthreads();
+#pragma unroll 4
     for (int idx = tid; idx < m * m; idx += bs) {
       const int i = idx % m, j = idx / m;
       const c128 a1 = cmulc(w[j], v[i]);   // v_i conj(w_j)
@@ -305,6 +324,157 @@ __global__ void __launch_bounds__(NTL) k_tridiag(int n, c128* __restrict__ A, in
     __syncthreads();
   }
   if (tid == 0) d[n - 1] = A[(size_t)(n - 1) * ld + n - 1].x;
+}
+
+
+// ---------------------------------------------------------------------------
+// Panel form of the tridiagonalization: one workgroup computes the reflectors
+// of columns k0 .. k0+bb-1 from the trailing matrix as it stood before the
+// panel, corrected by the panel's earlier (v_j, w_j):
+//   column k  <- A[:, k] - sum_j (v_j conj(w_j[k]) + w_j conj(v_j[k]))
+//   p         =  A_stale v - V (W^H v) - W (V^H v),  w = tau p - (tau/2)(..)v
+// The trailing block A[k0+bb:, k0+bb:] then takes one rank-2bb update
+// (two MFMA GEMMs).  PV / PW hold conj(v_j) / conj(w_j) row-major [n][bmax].
+// ---------------------------------------------------------------------------
+constexpr int PANEL = 32;
+// below this size the unblocked single-workgroup reduction is faster
+constexpr int kPanelMinN = 256;
+
+__global__ void __launch_bounds__(NTL) k_tridiag_panel(int n, int k0, int bb, c128* __restrict__ A, int ld,
+                                                       c128* __restrict__ PV, c128* __restrict__ PW,
+                                                       double* __restrict__ d, double* __restrict__ e,
+                                                       c128* __restrict__ tau, const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* v = reinterpret_cast<c128*>(smem_raw);   // [n]  column, then reflector
+  c128* p = v + n;                               // [n]  A v, then w
+  c128* part = p + n;                            // [max(n, NTL)]
+  __shared__ double red[NTL / 64];
+  __shared__ c128 s_tau, s_scale, pvk[PANEL], pwk[PANEL], t1[PANEL], t2[PANEL];
+  __shared__ c128 tpart[NTL / PANEL][2 * PANEL];
+  __shared__ double s_beta;
+  const int bs = blockDim.x, tid = threadIdx.x;
+  for (int i = 0; i < bb; ++i) {
+    const int k = k0 + i;
+    // a. column k, updated by the earlier vectors of the panel
+    if (tid < i) {
+      pvk[tid] = PV[(size_t)k * PANEL + tid];
+      pwk[tid] = PW[(size_t)k * PANEL + tid];
+    }
+    __syncthreads();
+    for (int r = k + tid; r < n; r += bs) {
+      c128 a = A[(size_t)k * ld + r];
+      const c128* pvr = PV + (size_t)r * PANEL;
+      const c128* pwr = PW + (size_t)r * PANEL;
+      for (int j = 0; j < i; ++j) {
+        // v_j[r] conj(w_j[k]) + w_j[r] conj(v_j[k]) = conj(pv_r) pw_k + conj(pw_r) pv_k
+        const c128 u1 = cmulc(pvr[j], pwk[j]);
+        const c128 u2 = cmulc(pwr[j], pvk[j]);
+        a = c128{a.x - u1.x - u2.x, a.y - u1.y - u2.y};
+      }
+      A[(size_t)k * ld + r] = a;
+      v[r] = a;
+    }
+    __syncthreads();
+    // b. reflector for x = column k below the diagonal
+    const int m = n - k - 1;
+    double ss = 0.0;
+    for (int r = k + 2 + tid; r < n; r += bs) ss += v[r].x * v[r].x + v[r].y * v[r].y;
+    const double xn2 = block_sum(ss, red);
+    if (tid == 0) {
+      const c128 al = v[k + 1];
+      if (xn2 == 0.0 && al.y == 0.0) {
+        s_tau = c128{0.0, 0.0};
+        s_beta = al.x;
+        s_scale = c128{0.0, 0.0};
+      } else {
+        const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+        const double beta = al.x >= 0.0 ? -nrm : nrm;
+        s_beta = beta;
+        s_tau = c128{(beta - al.x) / beta, -al.y / beta};
+        const c128 den = c128{al.x - beta, al.y};
+        const double dd = den.x * den.x + den.y * den.y;
+        s_scale = c128{den.x / dd, -den.y / dd};
+      }
+      d[k] = v[k].x;
+      e[k] = s_beta;
+      tau[k] = s_tau;
+    }
+    __syncthreads();
+    const c128 t = s_tau, sc = s_scale;
+    for (int r = k + 1 + tid; r < n; r += bs) {
+      const c128 vr = (r == k + 1) ? c128{1.0, 0.0} : cmul(v[r], sc);
+      v[r] = vr;
+      A[(size_t)k * ld + r] = vr;
+      PV[(size_t)r * PANEL + i] = c128{vr.x, -vr.y};
+    }
+    __syncthreads();
+    if (t.x == 0.0 && t.y == 0.0) {
+      for (int r = k + 1 + tid; r < n; r += bs) PW[(size_t)r * PANEL + i] = c128{0.0, 0.0};
+      __syncthreads();
+      continue;
+    }
+    // c. p = A_stale v over the trailing rows/columns
+    const c128* S = A + (size_t)(k + 1) * ld + k + 1;
+    const c128* vv = v + k + 1;
+    const int ns = max(1, min(bs / m, 64));
+    matvec_slices(m, ns, S, ld, vv, part);
+    //    t1 = W^H v, t2 = V^H v over rows k+1.. (thread = (row slice, j))
+    if (i > 0) {
+      const int j = tid % PANEL, sl = tid / PANEL, nsl = bs / PANEL;
+      c128 a1{0.0, 0.0}, a2{0.0, 0.0};
+      if (j < i) {
+        for (int r = k + 1 + sl; r < n; r += nsl) {
+          const c128 u1 = cmul(PW[(size_t)r * PANEL + j], v[r]);
+          const c128 u2 = cmul(PV[(size_t)r * PANEL + j], v[r]);
+          a1.x += u1.x; a1.y += u1.y;
+          a2.x += u2.x; a2.y += u2.y;
+        }
+      }
+      tpart[sl][j] = a1;
+      tpart[sl][PANEL + j] = a2;
+    }
+    __syncthreads();
+    if (i > 0 && tid < 2 * PANEL) {
+      c128 acc{0.0, 0.0};
+      for (int sl = 0; sl < bs / PANEL; ++sl) { acc.x += tpart[sl][tid].x; acc.y += tpart[sl][tid].y; }
+      if (tid < PANEL) t1[tid] = acc; else t2[tid - PANEL] = acc;
+    }
+    __syncthreads();
+    double hr = 0.0, hi = 0.0;
+    for (int ii = tid; ii < m; ii += bs) {
+      c128 acc{0.0, 0.0};
+      for (int sl = 0; sl < ns; ++sl) { acc.x += part[sl * m + ii].x; acc.y += part[sl * m + ii].y; }
+      const int r = k + 1 + ii;
+      for (int j = 0; j < i; ++j) {
+        // - v_j[r] t1_j - w_j[r] t2_j
+        const c128 pv = PV[(size_t)r * PANEL + j], pw = PW[(size_t)r * PANEL + j];
+        const c128 u1 = cmul(c128{pv.x, -pv.y}, t1[j]);
+        const c128 u2 = cmul(c128{pw.x, -pw.y}, t2[j]);
+        acc.x -= u1.x + u2.x;
+        acc.y -= u1.y + u2.y;
+      }
+      const c128 wi = cmul(t, acc);
+      p[r] = wi;
+      const c128 pv = cmulc(wi, v[r]);   // conj(w_r) v_r
+      hr += pv.x;
+      hi += pv.y;
+    }
+    const c128 wv = block_sum_c(c128{hr, hi}, red);
+    const c128 al = cmul(c128{-0.5 * t.x, -0.5 * t.y}, wv);
+    for (int r = k + 1 + tid; r < n; r += bs) {
+      const c128 u = cmul(al, v[r]);
+      const c128 wr = c128{p[r].x + u.x, p[r].y + u.y};
+      PW[(size_t)r * PANEL + i] = c128{wr.x, -wr.y};
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double* __restrict__ d,
+                               const int* __restrict__ info) {
+  if (*info != 0) return;
+  if (threadIdx.x == 0) d[n - 1] = A[(size_t)(n - 1) * ld + n - 1].x;
 }
 
 // ---------------------------------------------------------------------------
@@ -534,8 +704,8 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
 
 size_t pw::heig_work_bytes(int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
-  return sizeof(c128) * (5 * n * n + 2 * n) + sizeof(double) * (3 * n + n * n + 6 * n * (n + 64)) +
-         sizeof(int) * n + 20 * 256;
+  return sizeof(c128) * (5 * n * n + 2 * n + 2 * n * PANEL) + sizeof(double) * (3 * n + n * n + 6 * n * (n + 64)) +
+         sizeof(int) * n + 24 * 256;
 }
 
 pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
@@ -561,6 +731,8 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   hw.info = reinterpret_cast<int*>(take(256));
   hw.gamma = reinterpret_cast<double*>(take(256));
   hw.drop = reinterpret_cast<int*>(take(sizeof(int) * n));
+  hw.PV = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
+  hw.PW = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
   return PW_OK;
 }
 
@@ -612,7 +784,27 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   // tridiagonalize, eigenvalues, eigenvectors of T, back-transform
   {
     pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
-    k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info);
+    if (n <= kPanelMinN) {
+      k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau,
+                                                                          hw.info);
+    } else {
+      const size_t lds = sizeof(c128) * (2 * (size_t)n + std::max(n, NTL));
+      for (int k0 = 0; k0 < n - 1; k0 += PANEL) {
+        const int bb = std::min(PANEL, n - 1 - k0);
+        k_tridiag_panel<<<1, NTL, lds, st>>>(n, k0, bb, hw.A, ldw, hw.PV, hw.PW, hw.d, hw.e, hw.tau, hw.info);
+        const int r = k0 + bb, mm = n - r;
+        if (mm > 0) {
+          c128* C = hw.A + (size_t)r * ldw + r;
+          PW_TRY((pw::zgemm_cn<double, double, double>(mm, mm, bb, hw.PV + (size_t)r * PANEL, PANEL,
+                                                       hw.PW + (size_t)r * PANEL, PANEL, C, ldw, part,
+                                                       part_bytes, st, -1.0, 1.0)));
+          PW_TRY((pw::zgemm_cn<double, double, double>(mm, mm, bb, hw.PW + (size_t)r * PANEL, PANEL,
+                                                       hw.PV + (size_t)r * PANEL, PANEL, C, ldw, part,
+                                                       part_bytes, st, -1.0, 1.0)));
+        }
+      }
+      k_tridiag_last<<<1, 64, 0, st>>>(n, hw.A, ldw, hw.d, hw.info);
+    }
   }
   {
     pw::ProfScope ps(pw::PK_BISECT, st);
@@ -652,10 +844,12 @@ pw_status pw::heig_set_limits() {
   if (done) return PW_OK;
   // only the tridiagonalization can need more than the default 64 KB of
   // dynamic LDS (n > 1365); allow what is left next to its static LDS
-  hipFuncAttributes at;
-  PW_HIP(hipFuncGetAttributes(&at, (const void*)k_tridiag));
-  const int lim = 160 * 1024 - (int)at.sharedSizeBytes;
-  PW_HIP(hipFuncSetAttribute((const void*)k_tridiag, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  for (const void* fn : {(const void*)k_tridiag, (const void*)k_tridiag_panel}) {
+    hipFuncAttributes at;
+    PW_HIP(hipFuncGetAttributes(&at, fn));
+    const int lim = 160 * 1024 - (int)at.sharedSizeBytes;
+    PW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim));
+  }
   done = true;
   return PW_OK;
 }

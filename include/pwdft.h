@@ -99,7 +99,13 @@ typedef struct {
   double  precond_floor;     /* Ha, tau of the preconditioner denominator
                                 smax(x, tau) = (x + tau + sqrt((x - tau)^2 + tau^2)) / 2,
                                 x = h_diag(G) - eps_i (default 0.2)                              */
-  double  ladder_switch;     /* mixed only: max ||g_i|| below which float64 H.psi takes over (1e-4) */
+  double  ladder_switch;     /* mixed only: float32 H.psi until every ||g_i|| <= ladder_switch (or,
+                                once below 100*ladder_switch, the largest stops halving for 12
+                                iterations), then float64 (default 1e-5)                          */
+  double* history;           /* [host] optional (NULL by default): for iteration t < max_iter,
+                                history[2t] = max_i ||g_i|| and history[2t+1] = the largest column
+                                norm of the Ritz rotation that produced the block (its error
+                                growth); 2*max_iter entries, entries past stats.iters untouched */
 } pw_david_opts;
 
 typedef struct {
@@ -108,6 +114,8 @@ typedef struct {
   int32_t n_hpsi_fp32;       /* band-H.psi applications in float32                                   */
   int32_t n_hpsi_fp64;       /* band-H.psi applications in float64                                   */
   int32_t nconv;             /* converged bands at exit                                              */
+  int32_t iters_fp32;        /* iterations done with float32 H.psi (mixed precision)                 */
+  int32_t fresh_starts;      /* rebuilds of the basis with a fresh H.psi (growth budget, ladder)     */
   double  max_resid;         /* max_i ||g_i||_2 of the final float64 verification                    */
 } pw_david_stats;
 

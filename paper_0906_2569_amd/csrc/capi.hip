@@ -41,5 +41,6 @@ extern "C" void pw_david_opts_default(pw_david_opts* o) {
   o->tol_resid = 1e-6;
   o->tol_deig = 5e-9;
   o->precond_floor = 0.2;
-  o->ladder_switch = 1e-4;
+  o->ladder_switch = 1e-5;
+  o->history = nullptr;
 }

@@ -14,8 +14,9 @@
 //          collapses onto the current Ritz vectors.
 //   end:   a float64 H.psi of the final block recomputes eps_i and ||g_i||.
 //
-// In mixed precision, H.psi runs in float32 until max ||g_i|| falls below
-// ladder_switch; then the basis restarts from the Ritz vectors with float64
+// In mixed precision, H.psi runs in float32 and only bands with ||g_i|| above
+// ladder_switch are corrected; once every band is below it (or the largest
+// residual stalls), the basis restarts from the Ritz vectors with float64
 // H.psi (precision ladder).  Reduced matrices, Cholesky, the reduced
 // eigenproblem and residual norms are always float64.
 #include <algorithm>
@@ -274,6 +275,11 @@ namespace {
 // (float64 / float32 stage)
 constexpr double kMaxAmp = 1e4;
 constexpr double kMaxAmp32 = 1e2;
+// float32 stage: once max ||g_i|| is within kStallZone of ladder_switch,
+// kStall32 iterations without it halving end the stage (the float32 noise
+// floor lies above ladder_switch)
+constexpr double kStallZone = 100.0;
+constexpr int kStall32 = 12;
 
 struct Solver {
   pw_plan p;
@@ -370,16 +376,25 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   k_fill<<<1, 256, 0, st>>>(nb, INFINITY, W.eps_prev);
   int nbase = nb;
   double amp = 1.0;   // accumulated error growth of the carried-over H phi
+  double best32 = INFINITY;   // float32 stage: smallest max ||g_i|| so far ...
+  int stall32 = 0;            // ... and iterations since it last halved
   bool retried = false;
   pw_status result = PW_OK;
   DavFlags f{};
   for (;;) {
     k_resid<<<nb, 256, 0, st>>>(npw, W.psi, W.hpsi, W.ld, W.eps, W.rn);
-    k_select<<<1, 64, 0, st>>>(nb, W.rn, W.eps, W.eps_prev, o.tol_resid, o.tol_deig, W.idx, W.hw.info,
-                               W.hw.gamma, W.flags);
+    // float32 stage: a band needs no more corrections once its residual is
+    // below the switch threshold (its eigenvalue change is float32 noise)
+    const bool fp32_stage = prec == PW_MIXED;
+    k_select<<<1, 64, 0, st>>>(nb, W.rn, W.eps, W.eps_prev, fp32_stage ? o.ladder_switch : o.tol_resid,
+                               fp32_stage ? INFINITY : o.tol_deig, W.idx, W.hw.info, W.hw.gamma, W.flags);
     PW_HIP(hipMemcpyAsync(W.hflags, W.flags, sizeof(DavFlags), hipMemcpyDeviceToHost, st));
     PW_HIP(hipStreamSynchronize(st));
     f = *W.hflags;
+    if (o.history && stats.iters < o.max_iter) {
+      o.history[2 * stats.iters] = f.maxr;
+      o.history[2 * stats.iters + 1] = f.gamma;
+    }
     if (f.info != 0) {
       // the newest corrections made the overlap singular: the Ritz vectors
       // were not replaced; collapse onto them once and try again
@@ -392,7 +407,10 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       continue;
     }
     if (f.nan) { result = pw::fail(PW_ENAN, "non-finite residual norm"); break; }
-    if (prec == PW_MIXED && f.maxr <= o.ladder_switch) {
+    if (fp32_stage && f.maxr < kStallZone * o.ladder_switch) {
+      if (f.maxr < 0.5 * best32) { best32 = f.maxr; stall32 = 0; } else { ++stall32; }
+    }
+    if (fp32_stage && (f.n_new == 0 || stall32 >= kStall32)) {
       // precision ladder: continue from the Ritz vectors with float64 H.psi
       prec = PW_FP64;
       PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
@@ -402,12 +420,12 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       nbase = nb;
       amp = 1.0;
       stats.restarts++;
+      stats.fresh_starts++;
       continue;
     }
-    if (f.n_new == 0 && prec == PW_FP64) break;
+    if (f.n_new == 0) break;
     if (stats.iters >= o.max_iter) { result = PW_ENOTCONV; break; }
-    int n_new = f.n_new;
-    if (n_new == 0) n_new = nb;   // converged in float32: keep refining until the switch
+    const int n_new = f.n_new;
     if (nbase + n_new > nbx) {
       // The collapsed block inherits H psi = (H phi) c and is taken to be
       // orthonormal: the rounding errors of both grow by ||c|| and ||c||^2 per
@@ -420,18 +438,11 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
                                 hipMemcpyDeviceToDevice, st));
         PW_TRY(S.start_block(prec, nb));
         amp = 1.0;
-        stats.restarts++;
+        stats.fresh_starts++;
       }
       PW_TRY(S.collapse(nb));
       nbase = nb;
       stats.restarts++;
-    }
-    if (f.n_new == 0) {
-      // every band converged at float32 accuracy: correct all of them
-      std::vector<int> all(nb);
-      for (int b = 0; b < nb; ++b) all[b] = b;
-      PW_HIP(hipMemcpyAsync(W.idx, all.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
-      PW_HIP(hipStreamSynchronize(st));
     }
     k_correct<<<n_new, 256, 0, st>>>(npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, o.precond_floor,
                                      W.phi + (size_t)nbase * W.ld, W.ld);
@@ -440,6 +451,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     nbase += n_new;
     PW_HIP(hipMemcpyAsync(W.eps_prev, W.eps, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
     PW_TRY(S.rayleigh_ritz(nbase, nb));
+    if (prec == PW_MIXED) stats.iters_fp32++;
     stats.iters++;
   }
   // final float64 verification of the output block

@@ -1,6 +1,7 @@
 // Optional per-kernel timing with HIP events on the launch stream.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cstdint>
 
 namespace pw {
 enum ProfKernel {
@@ -8,19 +9,21 @@ enum ProfKernel {
   PK_CHOL, PK_TRINV, PK_TRIDIAG, PK_BISECT, PK_INVIT, PK_BACKTR, PK_VECTOR, PK_COUNT
 };
 bool prof_on();
-void prof_begin(int kernel, hipStream_t s, double units);
-void prof_end(int kernel, hipStream_t s);
+// returns the id of the open scope, passed back to prof_end
+uint64_t prof_begin(int kernel, hipStream_t s, double units);
+void prof_end(uint64_t id, hipStream_t s);
 
 // RAII helper: times everything launched on `s` during its lifetime.
 // `units` is the algorithmic work of the scope: bytes for memory-bound
 // kernels, flops for the matrix products and factorizations.
 struct ProfScope {
-  int k;
+  uint64_t id = 0;
   hipStream_t s;
-  bool on;
-  ProfScope(int kernel, hipStream_t st, double units = 0.0) : k(kernel), s(st), on(prof_on()) {
-    if (on) prof_begin(k, s, units);
+  ProfScope(int kernel, hipStream_t st, double units = 0.0) : s(st) {
+    if (prof_on()) id = prof_begin(kernel, s, units);
   }
-  ~ProfScope() { if (on) prof_end(k, s); }
+  ~ProfScope() { if (id) prof_end(id, s); }
+  ProfScope(const ProfScope&) = delete;
+  ProfScope& operator=(const ProfScope&) = delete;
 };
 }  // namespace pw

@@ -1,7 +1,8 @@
-// Per-kernel event timing (off by default).  Each timed launch records a pair
+// Per-kernel event timing (off by default).  Each timed scope records a pair
 // of events on its stream; pw_profile_read synchronizes and sums the elapsed
-// times per kernel class.
+// times of the closed scopes per kernel class.
 #include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "plan.h"
@@ -18,9 +19,10 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
-std::vector<Rec> g_recs;
+uint64_t g_next = 1;
+std::unordered_map<uint64_t, Rec> g_open;   // scopes whose end event is not yet recorded
+std::vector<Rec> g_recs;                    // closed scopes, not yet summed
 std::vector<hipEvent_t> g_pool;
-std::vector<Rec*> g_open[pw::PK_COUNT];
 double g_ms[pw::PK_COUNT];
 double g_units[pw::PK_COUNT];
 long g_n[pw::PK_COUNT];
@@ -53,26 +55,33 @@ void drain() {
 
 bool pw::prof_on() { return g_on; }
 
-void pw::prof_begin(int k, hipStream_t s, double units) {
+uint64_t pw::prof_begin(int k, hipStream_t s, double units) {
   std::lock_guard<std::mutex> l(g_mu);
   Rec r{k, units, take(), take()};
   (void)hipEventRecord(r.a, s);
-  g_recs.push_back(r);
+  const uint64_t id = g_next++;
+  g_open.emplace(id, r);
+  return id;
 }
 
-void pw::prof_end(int k, hipStream_t s) {
+void pw::prof_end(uint64_t id, hipStream_t s) {
   std::lock_guard<std::mutex> l(g_mu);
-  for (size_t i = g_recs.size(); i-- > 0;)
-    if (g_recs[i].k == k) {
-      (void)hipEventRecord(g_recs[i].b, s);
-      break;
-    }
+  auto it = g_open.find(id);
+  if (it == g_open.end()) return;   // profiling was reset while the scope was open
+  (void)hipEventRecord(it->second.b, s);
+  g_recs.push_back(it->second);
+  g_open.erase(it);
   if (g_recs.size() > 4096) drain();
 }
 
 extern "C" pw_status pw_profile_enable(int on) {
   std::lock_guard<std::mutex> l(g_mu);
   drain();
+  for (auto& kv : g_open) {   // scopes still open are dropped
+    g_pool.push_back(kv.second.a);
+    g_pool.push_back(kv.second.b);
+  }
+  g_open.clear();
   for (int k = 0; k < pw::PK_COUNT; ++k) { g_ms[k] = 0.0; g_n[k] = 0; g_units[k] = 0.0; }
   g_on = on != 0;
   return PW_OK;

@@ -46,12 +46,13 @@ class PlanOpts(C.Structure):
 class DavOpts(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("max_iter", C.c_int32), ("tol_resid", C.c_double),
                 ("tol_deig", C.c_double), ("precond_floor", C.c_double),
-                ("ladder_switch", C.c_double)]
+                ("ladder_switch", C.c_double), ("history", C.POINTER(C.c_double))]
 
 
 class DavStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("n_hpsi_fp32", C.c_int32),
-                ("n_hpsi_fp64", C.c_int32), ("nconv", C.c_int32), ("max_resid", C.c_double)]
+                ("n_hpsi_fp64", C.c_int32), ("nconv", C.c_int32), ("iters_fp32", C.c_int32),
+                ("fresh_starts", C.c_int32), ("max_resid", C.c_double)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -234,8 +235,11 @@ class Plan:
                                    C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
         return out
 
-    def davidson(self, psi, eig=None, resid=None, opts=None, stream=None):
-        """In-place block Davidson on psi [nb][>=npw]; returns (status, eig, resid, stats)."""
+    def davidson(self, psi, eig=None, resid=None, opts=None, stream=None, history=None):
+        """In-place block Davidson on psi [nb][>=npw]; returns (status, eig, resid, stats).
+
+        history: optional float64 numpy array of >= 2*max_iter entries that
+        receives (max residual norm, Ritz rotation growth) per iteration."""
         import torch
         nb = psi.shape[0]
         if eig is None:
@@ -243,6 +247,10 @@ class Plan:
         if resid is None:
             resid = torch.empty(nb, dtype=torch.float64, device=psi.device)
         opts = opts or default_opts()
+        if history is not None:
+            assert history.dtype == np.float64 and history.flags.c_contiguous
+            assert history.size >= 2 * opts.max_iter
+            opts.history = history.ctypes.data_as(C.POINTER(C.c_double))
         stats = DavStats()
         st = self.lib.davidson_solve(self.h, nb, C.c_void_p(psi.data_ptr()), psi.stride(0),
                                      C.c_void_p(eig.data_ptr()), C.c_void_p(resid.data_ptr()),

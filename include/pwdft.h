@@ -175,6 +175,72 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
                          void* stream);
 
 /*
+ * Batches of independent problems (cells x k-points; the paper's pool level,
+ * whose problems need no communication).  Item i uses plans[i] (all plans of
+ * ctx, each at most once per call) with nb[i] bands and the [dev] blocks
+ * psi[i] (ldpsi[i]), ... as in the single-problem call; the pointer arrays
+ * are [host].
+ *
+ * hpsi_apply_batched: hpsi[i] = H_i psi[i] for every i, launched round robin
+ * on nstreams (<= 0: 8) worker streams of ctx that wait for the work already
+ * queued on `stream` and are joined back into it.  Asynchronous.  Results are
+ * bitwise those of hpsi_apply.  Errors: PW_EINVAL, PW_EDEVICE.
+ *
+ * davidson_solve_batched: davidson_solve for every item, nworkers (<= 0: 8)
+ * at a time, each on its own worker stream driven by its own host thread.
+ * Synchronous.  stats [host, n] and status [host, n] may be NULL; status[i]
+ * is item i's own return code.  Returns the first hard error (with the
+ * item's message), else PW_ENOTCONV if any item did not converge, else PW_OK.
+ * opts->history must be NULL.  Concurrent solves use the cooperative
+ * reduced-eigensolver kernels only while nworkers x ceil(ndim nb / 16) <= 128.
+ * One batched call per context at a time.
+ */
+pw_status hpsi_apply_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, pw_precision prec,
+                             const int32_t* nb, const pw_c128* const* psi, const int32_t* ldpsi,
+                             pw_c128* const* hpsi, const int32_t* ldhpsi, int32_t nstreams, void* stream);
+pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, const int32_t* nb,
+                                 pw_c128* const* psi, const int32_t* ldpsi, double* const* eig,
+                                 double* const* resid, const pw_david_opts* opts, pw_david_stats* stats,
+                                 pw_status* status, int32_t nworkers, void* stream);
+
+/*
+ * Serving loop for independent requests of different sizes (the paper's pool
+ * level applied to a request stream).  Requests are admitted in arrival
+ * order as soon as one of nworkers host workers is idle and the device
+ * memory of the request's plan (pw_footprint_bytes) fits in mem_budget next
+ * to the running ones; each runs pw_plan_create, davidson_solve on the
+ * worker's stream and pw_plan_destroy.
+ *   pw_server_create: opts may be NULL (4 workers, mem_budget 0 = 60% of the
+ *     free device memory, PW_MIXED plans).
+ *   pw_server_submit: enqueue one request and return its ticket at once.
+ *     The problem's arrays (host and device) and psi [dev, in/out], eig and
+ *     resid [dev] must stay valid until the request completes.  PW_ENOMEM if
+ *     the request alone exceeds mem_budget; PW_EINVAL for invalid problems.
+ *   pw_server_wait: block until the ticket's request is done; returns its
+ *     davidson_solve status (message in pw_last_error), its stats, and
+ *     times[3] = submit, start and end in seconds on the server's clock.  A
+ *     ticket can be waited for once.
+ *   pw_server_poll: done = 1 when the request has completed.
+ *   pw_server_clock: seconds since pw_server_create.
+ *   pw_server_destroy: finish every submitted request, then stop.
+ */
+typedef struct pw_server_s* pw_server;
+typedef struct {
+  int32_t      nworkers;     /* concurrent requests, 1..64                                          */
+  size_t       mem_budget;   /* device bytes the running requests' plans may hold (0: 60% of free)  */
+  pw_precision precision;    /* precision of the requests' plans                                    */
+} pw_server_opts;
+void      pw_server_opts_default(pw_server_opts* opts);
+pw_status pw_server_create(pw_ctx ctx, const pw_server_opts* opts, pw_server* out);
+pw_status pw_server_submit(pw_server server, const pw_problem* problem, int32_t nb, pw_c128* psi,
+                           int32_t ldpsi, double* eig, double* resid, const pw_david_opts* opts,
+                           int64_t* ticket);
+pw_status pw_server_wait(pw_server server, int64_t ticket, pw_david_stats* stats, double times[3]);
+pw_status pw_server_poll(pw_server server, int64_t ticket, int32_t* done);
+double    pw_server_clock(pw_server server);
+pw_status pw_server_destroy(pw_server server);
+
+/*
  * The float64 reduced-problem solver used inside davidson_solve, exposed on
  * its own: lowest nev eigenpairs of the generalized Hermitian problem
  * H c = w S c (S positive definite), as the iterative-diagonalization

@@ -30,6 +30,9 @@ extern "C" pw_status pw_ctx_create(int device, pw_ctx* out) {
 }
 
 extern "C" pw_status pw_ctx_destroy(pw_ctx c) {
+  if (!c) return PW_OK;
+  (void)hipSetDevice(c->device);
+  pw::ctx_release_pool(c);
   delete c;
   return PW_OK;
 }

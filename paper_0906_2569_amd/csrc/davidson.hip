@@ -260,6 +260,15 @@ pw_status pw::dav_alloc(pw_plan p) {
   return PW_OK;
 }
 
+bool pw::dav_set_coop(pw_plan p, bool ok) {
+  if (!p || !p->dav) return false;
+  const bool prev = p->dav->hw.coop_ok;
+  p->dav->hw.coop_ok = ok;
+  return prev;
+}
+
+bool pw::dav_get_coop(pw_plan p) { return p && p->dav && p->dav->hw.coop_ok; }
+
 void pw::dav_free(pw_plan p) {
   DavWork* W = p->dav;
   if (!W) return;
@@ -394,6 +403,10 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     if (o.history && stats.iters < o.max_iter) {
       o.history[2 * stats.iters] = f.maxr;
       o.history[2 * stats.iters + 1] = f.gamma;
+    }
+    if (f.info == 2) {
+      result = pw::fail(PW_EDEVICE, "workgroups of the cooperative tridiagonalization were not co-resident");
+      break;
     }
     if (f.info != 0) {
       // the newest corrections made the overlap singular: the Ritz vectors

@@ -11,10 +11,15 @@ struct HeigWork {
   int nmax = 0;
   c128 *L = nullptr, *X = nullptr, *T1 = nullptr, *A = nullptr, *Y = nullptr, *tau = nullptr;
   double *d = nullptr, *e = nullptr, *w = nullptr, *Z = nullptr, *scratch = nullptr;
-  int* info = nullptr;     // 0, or 1 when fewer than nev independent directions remain
+  int* info = nullptr;     // 0; 1 when fewer than nev independent directions remain; 2 when the
+                           // workgroups of a cooperative kernel were not all resident
   int* drop = nullptr;     // [n] 1 for basis directions dropped as dependent
   double* gamma = nullptr; // max column norm of the last eigenvector block C
   c128 *PV = nullptr, *PW = nullptr;   // tridiagonalization panel vectors (conjugated, row-major)
+  void* coop = nullptr;    // exchange buffers of the cooperative tridiagonalization
+  bool coop_ok = true;     // cooperative (multi-workgroup) kernels allowed: every workgroup of a
+                           // launch must be resident at once, so callers that run several
+                           // solves concurrently on one device switch them off
 };
 
 size_t heig_work_bytes(int nmax);

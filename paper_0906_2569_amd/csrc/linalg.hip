@@ -478,6 +478,373 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 }
 
 // ---------------------------------------------------------------------------
+// Cooperative Householder tridiagonalization for 64 <= n <= 512: P =
+// ceil(n / CR) workgroups, workgroup q holding rows [q CR, q CR + CR) of the
+// Hermitian matrix B (row r = conj of column r of A) in registers; thread t
+// holds columns t and t + CT of the workgroup's rows (one wave per SIMD, so
+// the small per-step scalar work is repeated four times, not sixteen).
+//
+// Step k (the reflector v_k, tau_k is known in every workgroup, and every
+// workgroup holds y = B v_k for its rows):
+//   1. p_r = tau_k y_r and the partial sum of conj(p_r) v_r are published;
+//      the owner of row k+1 also publishes that row (updated through k-1);
+//   2. one barrier across the workgroups;
+//   3. every workgroup reads all of p and forms w = p - 1/2 tau_k (p^H v) v,
+//      applies the rank-2 update to its copy of row k+1 and derives the
+//      reflector k+1 from it -- the same data and the same instruction
+//      sequence in every workgroup, so all agree bit for bit;
+//   4. each workgroup updates its rows, B -= v w^H + w v^H, and multiplies
+//      them by v_{k+1} in the same pass.
+// Reflectors, d, e and tau are stored as k_tridiag stores them.  Every wait
+// is bounded: if the workgroups are not all resident, the kernel gives up,
+// sets info = 2 and exits.
+// ---------------------------------------------------------------------------
+constexpr int CR = 16;      // rows per workgroup
+constexpr int CT = 256;     // threads per workgroup (one wave per SIMD)
+constexpr int kCoopMinN = 64, kCoopMaxN = 512;
+constexpr int kCoopMaxP = kCoopMaxN / CR;
+constexpr long kCoopSpin = 1l << 22;   // polls of a barrier before giving up
+
+struct CoopBuf {
+  c128* p;         // [2][kCoopMaxN]   p_r of every row, by step parity
+  c128* s;         // [2][kCoopMaxP]   partial sums conj(p)^T v of each workgroup
+  c128* row;       // [2][kCoopMaxN]   row k+1 before the update of step k
+  unsigned* count; // barrier arrivals (zeroed before each launch)
+  unsigned* fail;  // set when a barrier timed out
+};
+
+__global__ void k_coop_reset(CoopBuf cb) {
+  if (threadIdx.x == 0) { *cb.count = 0u; *cb.fail = 0u; }
+}
+
+// Cross-lane moves of a double through DPP (no LDS traffic).  The four row
+// permutations used pair lane i with i^1, i^2 (quad permutes), 7-i within
+// each half row and 15-i within each row: each is an involution that flips
+// bit 0, 1, 2 and 3 of the lane index respectively.
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
+template <int LEVEL>
+__device__ __forceinline__ double row_partner(double v) {
+  if constexpr (LEVEL == 0) return dpp_f64<kDppXor1>(v);
+  else if constexpr (LEVEL == 1) return dpp_f64<kDppXor2>(v);
+  else if constexpr (LEVEL == 2) return dpp_f64<kDppHalfMirror>(v);
+  else return dpp_f64<kDppMirror>(v);
+}
+
+// sum of one double over the 64 lanes; every lane ends with the same bits
+// (each pairwise sum is formed from the same two operands, and the four row
+// sums are combined in one fixed order)
+__device__ __forceinline__ double wave_sum(double v) {
+  v += row_partner<0>(v);
+  v += row_partner<1>(v);
+  v += row_partner<2>(v);
+  v += row_partner<3>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// sum over the 64 lanes of the V values in v[] (V a power of two <= 16).  The
+// row pairings are taken in the order 15-i, 7-i, i^2, i^1 (each leaves the
+// lane bits the earlier ones tested unchanged); at the first log2(V) of them
+// a lane keeps half of its values (the upper half when the tested bit --
+// bit 3, 2, 1, 0 in turn -- is set) and adds its partner's copy of that
+// half, at the others it adds the partner's value; then the four rows are
+// summed.  Afterwards every lane l < 16 with msum_writer<V>(l) holds in v[0]
+// the total of value msum_slot<V>(l).
+template <int CNT, int STEP, int V>
+__device__ __forceinline__ void msum_level(double (&v)[V], int lane) {
+  if constexpr (STEP < 4) {
+    constexpr int LEVEL = 3 - STEP;   // pairing: mirror, half mirror, xor 2, xor 1
+    const bool up = (lane >> LEVEL) & 1;
+    if constexpr (CNT > 1) {
+      constexpr int half = CNT / 2;
+#pragma unroll
+      for (int q = 0; q < half; ++q) {
+        const double mine = up ? v[half + q] : v[q];
+        const double other = up ? v[q] : v[half + q];
+        v[q] = mine + row_partner<LEVEL>(other);
+      }
+      msum_level<half, STEP + 1, V>(v, lane);
+    } else {
+      v[0] += row_partner<LEVEL>(v[0]);
+      msum_level<1, STEP + 1, V>(v, lane);
+    }
+  }
+}
+template <int V>
+__device__ __forceinline__ void wave_multi_sum(double (&v)[V]) {
+  static_assert(V >= 1 && V <= 16 && (V & (V - 1)) == 0, "V a power of two <= 16");
+  msum_level<V, 0, V>(v, threadIdx.x & 63);
+  v[0] += __shfl_xor(v[0], 16, 64);
+  v[0] += __shfl_xor(v[0], 32, 64);
+}
+template <int V>
+constexpr int ilog2c() { return V <= 1 ? 0 : 1 + ilog2c<V / 2>(); }
+template <int V>
+__device__ __forceinline__ bool msum_writer(int l) {
+  return l < 16 && (l & ((1 << (4 - ilog2c<V>())) - 1)) == 0;
+}
+template <int V>
+__device__ __forceinline__ int msum_slot(int l) {
+  int idx = 0, cnt = V, t = 0;
+  while (cnt > 1) { cnt >>= 1; if ((l >> (3 - t)) & 1) idx += cnt; ++t; }
+  return idx;
+}
+
+// Householder vector of x = (alpha, x_1, ...) given alpha and sum |x_i|^2 (i >= 1):
+// tau, beta and the scale 1 / (alpha - beta) of x_1.. (the same rule as k_tridiag)
+struct Refl { c128 tau, scale; double beta; };
+__device__ __forceinline__ Refl householder(c128 al, double xn2) {
+  Refl r;
+  if (xn2 == 0.0 && al.y == 0.0) {
+    r.tau = c128{0.0, 0.0}; r.beta = al.x; r.scale = c128{0.0, 0.0};
+  } else {
+    const double nrm = sqrt(al.x * al.x + al.y * al.y + xn2);
+    const double beta = al.x >= 0.0 ? -nrm : nrm;
+    r.beta = beta;
+    r.tau = c128{(beta - al.x) / beta, -al.y / beta};
+    const c128 den = c128{al.x - beta, al.y};
+    const double dd = den.x * den.x + den.y * den.y;
+    r.scale = c128{den.x / dd, -den.y / dd};
+  }
+  return r;
+}
+
+template <int NC>
+__global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A, int ld, double* __restrict__ d,
+                                                     double* __restrict__ e, c128* __restrict__ tau,
+                                                     int* __restrict__ info, CoopBuf cb) {
+  constexpr int NW = CT / 64;
+  if (*info != 0) return;
+  __shared__ c128 s_rowbuf[kCoopMaxN];    // owned row k+1 (for publication)
+  __shared__ double s_red[NW][2 * CR];    // per-wave row sums of B v (re, then im)
+  __shared__ c128 s_rv[2][CR], s_rw[CR];  // v_k (by step parity) and w on the own rows
+  __shared__ double s_xn2[NW];
+  __shared__ c128 s_alx;
+  __shared__ int s_fail;
+
+  const int P = gridDim.x, q = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
+  const int rowbase = q * CR;
+  int jc[NC];
+  bool ok[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) { jc[c] = tid + CT * c; ok[c] = jc[c] < n; }
+
+  // rows of B: a[c][i] = B[rowbase + i][j_c] = conj(A[(rowbase + i) * ld + j_c])
+  c128 a[NC][CR];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+      const int R = rowbase + i;
+      a[c][i] = (ok[c] && R < n) ? cconj(A[(size_t)R * ld + jc[c]]) : c128{0.0, 0.0};
+      if (R == 1 && ok[c]) s_rowbuf[jc[c]] = a[c][i];   // row 1 is published at step 0
+    }
+  if (tid == 0) s_fail = 0;
+
+  // own-row values of a column vector to LDS
+  auto put_own = [&](c128* dst, const c128 (&val)[NC]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (jc[c] >= rowbase && jc[c] < rowbase + CR) dst[jc[c] - rowbase] = val[c];
+  };
+  // y = B v on the own rows: per-thread partial sums, then per-wave totals to s_red
+  auto rows_times = [&](const c128 (&acc)[CR]) {
+    double vr[CR], vi[CR];
+#pragma unroll
+    for (int i = 0; i < CR; ++i) { vr[i] = acc[i].x; vi[i] = acc[i].y; }
+    wave_multi_sum<CR>(vr);
+    wave_multi_sum<CR>(vi);
+    if (msum_writer<CR>(lane)) {
+      const int sl = msum_slot<CR>(lane);
+      s_red[wid][sl] = vr[0];
+      s_red[wid][CR + sl] = vi[0];
+    }
+  };
+
+  // reflector 0 from column 0 of B below the diagonal: x_j = conj(B[0][j]) = A[0 * ld + j]
+  c128 vk[NC], tk;
+  double beta0;
+  {
+    c128 x[NC];
+    double xx = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      x[c] = (ok[c] && jc[c] >= 1) ? A[jc[c]] : c128{0.0, 0.0};
+      if (ok[c] && jc[c] >= 2) xx += x[c].x * x[c].x + x[c].y * x[c].y;
+      if (jc[c] == 1) s_alx = x[c];
+    }
+    const double r = wave_sum(xx);
+    if (lane == 0) s_xn2[wid] = r;
+    __syncthreads();
+    const Refl h = householder(s_alx, wave_sum(lane < NW ? s_xn2[lane] : 0.0));
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      vk[c] = (jc[c] == 1) ? c128{1.0, 0.0} : (jc[c] > 1 && ok[c] ? cmul(x[c], h.scale) : c128{0.0, 0.0});
+    tk = h.tau;
+    beta0 = h.beta;
+    put_own(s_rv[0], vk);
+  }
+  {
+    c128 acc[CR];
+#pragma unroll
+    for (int i = 0; i < CR; ++i) {
+      acc[i] = c128{0.0, 0.0};
+      const int R = rowbase + i;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (R >= 1 && R < n && jc[c] >= 1 && ok[c]) acc[i] = acc[i] + cmul(a[c][i], vk[c]);
+    }
+    rows_times(acc);
+  }
+  __syncthreads();
+
+  for (int k = 0; k <= n - 2; ++k) {
+    const int par = k & 1;
+    // 1. wave 0: finish y on the own rows, publish p_r = tau_k y_r, the
+    //    partial sum of conj(p_r) v_r, and (owner) row k+1; then the barrier
+    if (wid == 0) {
+      c128 p{0.0, 0.0};
+      const int R = rowbase + lane;
+      if (lane < CR && R >= k + 1 && R < n) {
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { re += s_red[w][lane]; im += s_red[w][CR + lane]; }
+        p = cmul(tk, c128{re, im});
+      }
+      const c128 t = (lane < CR) ? cmulc(p, s_rv[par][lane]) : c128{0.0, 0.0};   // conj(p_r) v_r
+      const double sre = wave_sum(t.x), sim = wave_sum(t.y);
+      if (lane < CR && R < n) cb.p[par * kCoopMaxN + R] = p;
+      if (lane == 0) cb.s[par * kCoopMaxP + q] = c128{sre, sim};
+      const int lr = k + 1 - rowbase;
+      if (lr >= 0 && lr < CR)
+        for (int c = k + 1 + lane; c < n; c += 64) cb.row[par * kCoopMaxN + c] = s_rowbuf[c];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      if (lane == 0) {
+        __hip_atomic_fetch_add(cb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // 2. barrier: all P workgroups have published step k
+        const unsigned target = (unsigned)P * (unsigned)(k + 1);
+        long spins = 0;
+        for (;;) {
+          if (__hip_atomic_load(cb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
+          if (__hip_atomic_load(cb.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > kCoopSpin) {
+            __hip_atomic_store(cb.fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_fail = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (s_fail) {
+      if (q == 0 && tid == 0) *info = 2;
+      return;
+    }
+    // 3. every wave: p^H v, w, row k+1 after the update, and the partial norm
+    //    of the next reflector's vector
+    c128 pj[NC], rowj[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool live = ok[c] && jc[c] >= k + 1;
+      pj[c] = live ? cb.p[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
+      rowj[c] = live ? cb.row[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
+    }
+    const c128 pk1 = cb.p[par * kCoopMaxN + k + 1];
+    const c128 sl = (lane < P) ? cb.s[par * kCoopMaxP + lane] : c128{0.0, 0.0};
+    const c128 psum{wave_sum(sl.x), wave_sum(sl.y)};
+    const c128 al = cmul(c128{-0.5 * tk.x, -0.5 * tk.y}, psum);   // -1/2 tau (p^H v)
+    const c128 wk1 = pk1 + cmul(al, c128{1.0, 0.0});              // v_k[k+1] = 1
+    c128 wj[NC], x[NC];
+    double xx = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool live = ok[c] && jc[c] >= k + 1;
+      wj[c] = live ? pj[c] + cmul(al, vk[c]) : c128{0.0, 0.0};
+      // row'_j = row_j - conj(w_j) - w_{k+1} conj(v_j)
+      c128 rj{0.0, 0.0};
+      if (live) {
+        const c128 t = cmulc(vk[c], wk1);
+        rj = c128{rowj[c].x - wj[c].x - t.x, rowj[c].y + wj[c].y - t.y};
+      }
+      if (q == 0 && jc[c] == k + 1) d[k + 1] = rj.x;
+      // x_j = conj(row'_j), j >= k+2; alpha = x_{k+2}
+      x[c] = (jc[c] >= k + 2) ? cconj(rj) : c128{0.0, 0.0};
+      if (ok[c] && jc[c] >= k + 3) xx += x[c].x * x[c].x + x[c].y * x[c].y;
+      if (jc[c] == k + 2) s_alx = x[c];
+    }
+    if (q == 0 && k == 0) {
+      // reflector 0 is stored only now: every workgroup has read column 0
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        if (ok[c] && jc[c] >= 1) A[jc[c]] = vk[c];
+      if (tid == 0) { d[0] = cconj(a[0][0]).x; e[0] = beta0; tau[0] = tk; }
+    }
+    put_own(s_rw, wj);
+    if (k + 1 > n - 2) break;
+    {
+      const double r = wave_sum(xx);
+      if (lane == 0) s_xn2[wid] = r;
+    }
+    __syncthreads();
+    // 4. every wave: reflector k+1 (identical everywhere)
+    const Refl h = householder(s_alx, wave_sum(lane < NW ? s_xn2[lane] : 0.0));
+    c128 vk1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      vk1[c] = (jc[c] == k + 2) ? c128{1.0, 0.0} : (jc[c] > k + 2 && ok[c] ? cmul(x[c], h.scale) : c128{0.0, 0.0});
+      if (q == 0 && ok[c] && jc[c] >= k + 2) A[(size_t)(k + 1) * ld + jc[c]] = vk1[c];
+      if (q == 0 && jc[c] == k + 2) { e[k + 1] = h.beta; tau[k + 1] = h.tau; }
+    }
+    put_own(s_rv[par ^ 1], vk1);
+    __syncthreads();
+    // 5. B -= v w^H + w v^H on rows and columns >= k+2, and y = B v_{k+1};
+    //    the owner of row k+2 keeps it for the next publication
+    {
+      c128 acc[CR];
+#pragma unroll
+      for (int i = 0; i < CR; ++i) acc[i] = c128{0.0, 0.0};
+      if (rowbase + CR > k + 2) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          // columns of this wave: [64 wid + CT c, + 64)
+          if (64 * wid + CT * c + 63 < k + 2 || 64 * wid + CT * c >= n) continue;
+          if (!(ok[c] && jc[c] >= k + 2)) continue;
+          const c128 cw = cconj(wj[c]), cv = cconj(vk[c]);
+#pragma unroll
+          for (int i = 0; i < CR; ++i) {
+            if (rowbase + i >= k + 2 && rowbase + i < n) {
+              const c128 u1 = cmul(s_rv[par][i], cw), u2 = cmul(s_rw[i], cv);
+              a[c][i] = c128{a[c][i].x - u1.x - u2.x, a[c][i].y - u1.y - u2.y};
+              acc[i] = acc[i] + cmul(a[c][i], vk1[c]);
+              if (rowbase + i == k + 2) s_rowbuf[jc[c]] = a[c][i];
+            }
+          }
+        }
+      }
+      rows_times(acc);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) vk[c] = vk1[c];
+    tk = h.tau;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Lowest nev eigenvalues of the real symmetric tridiagonal (d, e): one wave
 // per eigenvalue, 64 shifts per round (Sturm counts), interval narrowed to
 // the two shifts around the k-th eigenvalue.
@@ -552,16 +919,20 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
 // scale of their neighbour),
 // solving (T - w I) x = b by Gaussian elimination with partial pivoting,
 // three iterations, orthogonalized against the earlier cluster members.
-// Z is real [nev][ldz]; scratch holds 5 n doubles per thread.
+// Z is real [nev][ldz].  The per-thread factors and iterate (5 n doubles and
+// n pivot flags) live in a Work view: LDS for up to TPW threads per
+// workgroup when they fit, else the global scratch (element r of thread t at
+// [r * S + t], so that neighbouring threads touch neighbouring addresses).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ d,
-                                              const double* __restrict__ e, int nev,
-                                              const double* __restrict__ w, double* __restrict__ Z,
-                                              int ldz, double* __restrict__ scratch,
-                                              const int* __restrict__ info) {
-  if (*info != 0) return;
-  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i0 >= nev) return;
+struct InvitView {
+  double *D, *DL, *DU, *DU2, *X;
+  unsigned char* PV;
+  size_t S;   // stride between consecutive elements of one thread
+};
+
+__device__ void invit_cluster(int n, const double* __restrict__ d, const double* __restrict__ e, int nev,
+                              const double* __restrict__ w, double* __restrict__ Z, int ldz, int i0,
+                              InvitView v) {
   // scale of the wanted part of the spectrum (dropped basis directions sit
   // far above it and must not widen the clusters)
   const double tn = fmax(fmax(fabs(w[0]), fabs(w[nev - 1])), fmax(w[nev - 1] - w[0], 1e-300));
@@ -570,15 +941,9 @@ __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ 
   int i1 = i0 + 1;
   while (i1 < nev && w[i1] - w[i1 - 1] <= ctol) ++i1;
   const double tiny = DBL_EPSILON * tn;
-  // per-thread arrays interleaved across threads: element r of thread t at
-  // [r * S + t], so that the threads of a wave access consecutive addresses
-  const size_t S = (size_t)gridDim.x * blockDim.x;
-  double* D = scratch + i0;
-  double* DL = D + (size_t)n * S;
-  double* DU = DL + (size_t)n * S;
-  double* DU2 = DU + (size_t)n * S;
-  double* X = DU2 + (size_t)n * S;
-  unsigned long long* PV = reinterpret_cast<unsigned long long*>(X + (size_t)n * S);  // pivot bits
+  const size_t S = v.S;
+  double *D = v.D, *DL = v.DL, *DU = v.DU, *DU2 = v.DU2, *X = v.X;
+  unsigned char* PV = v.PV;
   for (int i = i0; i < i1; ++i) {
     const double lam = w[i];
     // factor T - lam I with partial pivoting; the running pivot stays in a register
@@ -589,7 +954,7 @@ __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ 
       const double dnext = d[r + 1] - lam;
       const double du_after = (r < n - 2) ? e[r + 1] : 0.0;
       double dr, dlr, dur, du2r, dn, dun;
-      int piv;
+      unsigned char piv;
       if (fabs(dcur) >= fabs(er)) {
         const double dd = (dcur == 0.0) ? tiny : dcur;
         const double f = er / dd;
@@ -599,52 +964,94 @@ __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ 
         dr = er; dlr = f; dur = dnext; dn = du_next - f * dnext;
         du2r = du_after; dun = -f * du_after; piv = 1;
       }
-      D[(size_t)r * S] = dr; DL[(size_t)r * S] = dlr; DU[(size_t)r * S] = dur; DU2[(size_t)r * S] = du2r;
-      PV[(size_t)r * S] = (unsigned long long)piv;
+      D[r * S] = (fabs(dr) < tiny) ? ((dr >= 0.0) ? tiny : -tiny) : dr;
+      DL[r * S] = dlr; DU[r * S] = dur; DU2[r * S] = du2r;
+      PV[r * S] = piv;
       dcur = dn;
       du_next = dun;
     }
-    D[(size_t)(n - 1) * S] = dcur;
-    for (int r = 0; r < n; ++r) {
-      double v = D[(size_t)r * S];
-      if (fabs(v) < tiny) D[(size_t)r * S] = (v >= 0.0) ? tiny : -tiny;
-      X[(size_t)r * S] = cos(0.7 * r + 1.3 * i) + 0.1;
-    }
+    D[(n - 1) * S] = (fabs(dcur) < tiny) ? ((dcur >= 0.0) ? tiny : -tiny) : dcur;
+    for (int r = 0; r < n; ++r) X[r * S] = cos(0.7 * r + 1.3 * i) + 0.1;
     for (int it = 0; it < 3; ++it) {
       double xr = X[0];
       for (int r = 0; r < n - 1; ++r) {
-        const double xn = X[(size_t)(r + 1) * S];
-        if (PV[(size_t)r * S]) {
-          X[(size_t)r * S] = xn;
-          xr = xr - DL[(size_t)r * S] * xn;
+        const double xn = X[(r + 1) * S];
+        if (PV[r * S]) {
+          X[r * S] = xn;
+          xr = xr - DL[r * S] * xn;
         } else {
-          X[(size_t)r * S] = xr;
-          xr = xn - DL[(size_t)r * S] * xr;
+          X[r * S] = xr;
+          xr = xn - DL[r * S] * xr;
         }
       }
-      X[(size_t)(n - 1) * S] = xr;
-      double x2 = 0.0, x1 = X[(size_t)(n - 1) * S] / D[(size_t)(n - 1) * S];
-      X[(size_t)(n - 1) * S] = x1;
+      X[(n - 1) * S] = xr;
+      double x2 = 0.0, x1 = X[(n - 1) * S] / D[(n - 1) * S];
+      X[(n - 1) * S] = x1;
       for (int r = n - 2; r >= 0; --r) {
-        const double xv = (X[(size_t)r * S] - DU[(size_t)r * S] * x1 - DU2[(size_t)r * S] * x2) / D[(size_t)r * S];
-        X[(size_t)r * S] = xv;
+        const double xv = (X[r * S] - DU[r * S] * x1 - DU2[r * S] * x2) / D[r * S];
+        X[r * S] = xv;
         x2 = x1;
         x1 = xv;
       }
       for (int j = i0; j < i; ++j) {
         const double* zj = Z + (size_t)j * ldz;
         double dot = 0.0;
-        for (int r = 0; r < n; ++r) dot += zj[r] * X[(size_t)r * S];
-        for (int r = 0; r < n; ++r) X[(size_t)r * S] -= dot * zj[r];
+        for (int r = 0; r < n; ++r) dot += zj[r] * X[r * S];
+        for (int r = 0; r < n; ++r) X[r * S] -= dot * zj[r];
       }
       double nrm = 0.0;
-      for (int r = 0; r < n; ++r) nrm += X[(size_t)r * S] * X[(size_t)r * S];
+      for (int r = 0; r < n; ++r) nrm += X[r * S] * X[r * S];
       const double inv = 1.0 / sqrt(nrm);
-      for (int r = 0; r < n; ++r) X[(size_t)r * S] *= inv;
+      for (int r = 0; r < n; ++r) X[r * S] *= inv;
     }
     double* z = Z + (size_t)i * ldz;
-    for (int r = 0; r < n; ++r) z[r] = X[(size_t)r * S];
+    for (int r = 0; r < n; ++r) z[r] = X[r * S];
   }
+}
+
+// scratch in global memory: 5 n doubles + n bytes per thread
+__global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ d,
+                                              const double* __restrict__ e, int nev,
+                                              const double* __restrict__ w, double* __restrict__ Z,
+                                              int ldz, double* __restrict__ scratch,
+                                              const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int i0 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i0 >= nev) return;
+  const size_t S = (size_t)gridDim.x * blockDim.x;
+  InvitView v;
+  v.S = S;
+  v.D = scratch + i0;
+  v.DL = v.D + (size_t)n * S;
+  v.DU = v.DL + (size_t)n * S;
+  v.DU2 = v.DU + (size_t)n * S;
+  v.X = v.DU2 + (size_t)n * S;
+  v.PV = reinterpret_cast<unsigned char*>(scratch + 5 * (size_t)n * S) + i0;
+  invit_cluster(n, d, e, nev, w, Z, ldz, i0, v);
+}
+
+// scratch in LDS: TPW threads per workgroup, 41 n bytes each
+constexpr int kInvitLdsBytes = 96 * 1024;
+template <int TPW>
+__global__ void __launch_bounds__(64) k_invit_lds(int n, const double* __restrict__ d,
+                                                  const double* __restrict__ e, int nev,
+                                                  const double* __restrict__ w, double* __restrict__ Z,
+                                                  int ldz, const int* __restrict__ info) {
+  if (*info != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * TPW + t;
+  if (t >= TPW || i0 >= nev) return;
+  double* base = reinterpret_cast<double*>(smem_raw);
+  InvitView v;
+  v.S = TPW;
+  v.D = base + t;
+  v.DL = v.D + (size_t)n * TPW;
+  v.DU = v.DL + (size_t)n * TPW;
+  v.DU2 = v.DU + (size_t)n * TPW;
+  v.X = v.DU2 + (size_t)n * TPW;
+  v.PV = reinterpret_cast<unsigned char*>(base + 5 * (size_t)n * TPW) + t;
+  invit_cluster(n, d, e, nev, w, Z, ldz, i0, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -702,10 +1109,24 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
 
 }  // namespace
 
+namespace {
+size_t coop_bytes() { return sizeof(c128) * (4 * kCoopMaxN + 2 * kCoopMaxP) + 2 * 256; }
+CoopBuf coop_buf(const pw::HeigWork& hw) {
+  char* p = static_cast<char*>(hw.coop);
+  CoopBuf cb;
+  cb.p = reinterpret_cast<c128*>(p);
+  cb.row = cb.p + 2 * kCoopMaxN;
+  cb.s = cb.row + 2 * kCoopMaxN;
+  cb.count = reinterpret_cast<unsigned*>(p + sizeof(c128) * (4 * kCoopMaxN + 2 * kCoopMaxP));
+  cb.fail = reinterpret_cast<unsigned*>(p + sizeof(c128) * (4 * kCoopMaxN + 2 * kCoopMaxP) + 256);
+  return cb;
+}
+}  // namespace
+
 size_t pw::heig_work_bytes(int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
   return sizeof(c128) * (5 * n * n + 2 * n + 2 * n * PANEL) + sizeof(double) * (3 * n + n * n + 6 * n * (n + 64)) +
-         sizeof(int) * n + 24 * 256;
+         sizeof(int) * n + 24 * 256 + coop_bytes();
 }
 
 pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
@@ -733,6 +1154,7 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   hw.drop = reinterpret_cast<int*>(take(sizeof(int) * n));
   hw.PV = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
   hw.PW = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
+  hw.coop = take(coop_bytes());
   return PW_OK;
 }
 
@@ -784,7 +1206,13 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   // tridiagonalize, eigenvalues, eigenvectors of T, back-transform
   {
     pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
-    if (n <= kPanelMinN) {
+    if (hw.coop_ok && n >= kCoopMinN && n <= kCoopMaxN) {
+      const CoopBuf cb = coop_buf(hw);
+      const int P = ceil_div(n, CR);
+      k_coop_reset<<<1, 64, 0, st>>>(cb);
+      if (n <= CT) k_tridiag_coop<1><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else k_tridiag_coop<2><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+    } else if (n <= kPanelMinN) {
       k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau,
                                                                           hw.info);
     } else {
@@ -812,7 +1240,13 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_INVIT, st);
-    k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
+    const size_t per_thread = 41 * (size_t)n;
+    if (8 * per_thread <= (size_t)kInvitLdsBytes)
+      k_invit_lds<8><<<ceil_div(nev, 8), 64, 8 * per_thread, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.info);
+    else if (4 * per_thread <= (size_t)kInvitLdsBytes)
+      k_invit_lds<4><<<ceil_div(nev, 4), 64, 4 * per_thread, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.info);
+    else
+      k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
   }
   {
     pw::ProfScope ps(pw::PK_BACKTR, st, 8.0 * n * n * (double)nev);
@@ -844,7 +1278,8 @@ pw_status pw::heig_set_limits() {
   if (done) return PW_OK;
   // only the tridiagonalization can need more than the default 64 KB of
   // dynamic LDS (n > 1365); allow what is left next to its static LDS
-  for (const void* fn : {(const void*)k_tridiag, (const void*)k_tridiag_panel}) {
+  for (const void* fn : {(const void*)k_tridiag, (const void*)k_tridiag_panel, (const void*)k_invit_lds<8>,
+                         (const void*)k_invit_lds<4>}) {
     hipFuncAttributes at;
     PW_HIP(hipFuncGetAttributes(&at, fn));
     const int lim = 160 * 1024 - (int)at.sharedSizeBytes;
@@ -885,6 +1320,8 @@ extern "C" pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const p
     if (hipMemcpyAsync(&info, hw.info, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
         hipStreamSynchronize(st) != hipSuccess)
       stt = pw::fail(PW_EDEVICE, "reduced eigensolver failed");
+    else if (info == 2)
+      stt = pw::fail(PW_EDEVICE, "workgroups of the cooperative tridiagonalization were not co-resident");
     else if (info != 0)
       stt = pw::fail(PW_EBREAKDOWN, "S is not positive definite or has rank < nev");
   }

@@ -1,12 +1,16 @@
 // Internal plan / context layout shared by the library's translation units.
 #pragma once
+#include <mutex>
 #include <vector>
 
 #include "common.h"
 #include "fft.h"
 
 struct pw_ctx_s {
-  int device;
+  int device = 0;
+  std::mutex mu;                       // guards the stream pool
+  std::vector<hipStream_t> pool;       // worker streams of the batched calls (default priority)
+  std::vector<hipEvent_t> pool_events; // one per worker stream
 };
 
 // Device-side description of the sphere <-> FFT-box maps, passed by value.
@@ -108,6 +112,12 @@ pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
 size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
 
 pw_status dav_alloc(pw_plan p);
+// allow or forbid the cooperative (multi-workgroup) kernels of the plan's
+// reduced eigensolver; returns the previous setting
+bool dav_set_coop(pw_plan p, bool ok);
+bool dav_get_coop(pw_plan p);
+// destroy the context's worker streams (pw_ctx_destroy)
+void ctx_release_pool(pw_ctx ctx);
 void dav_free(pw_plan p);
 size_t dav_bytes(int npw, int nb_max, int ndim_max);
 }  // namespace pw

@@ -22,7 +22,9 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 # every symbol include/pwdft.h declares
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
-           "hpsi_apply", "davidson_solve", "pw_reduced_eigh", "pw_profile_enable",
+           "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
+           "pw_reduced_eigh", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
+           "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
            "pw_profile_count", "pw_profile_name", "pw_profile_read"]
 
 
@@ -47,6 +49,10 @@ class DavOpts(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("max_iter", C.c_int32), ("tol_resid", C.c_double),
                 ("tol_deig", C.c_double), ("precond_floor", C.c_double),
                 ("ladder_switch", C.c_double), ("history", C.POINTER(C.c_double))]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("nworkers", C.c_int32), ("mem_budget", C.c_size_t), ("precision", C.c_int)]
 
 
 class DavStats(C.Structure):
@@ -83,6 +89,23 @@ def load(path: str = LIB_PATH):
                                C.c_int32, C.c_void_p]
     lib.davidson_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
+    P = C.POINTER
+    lib.hpsi_apply_batched.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p), C.c_int, P(C.c_int32),
+                                       P(C.c_void_p), P(C.c_int32), P(C.c_void_p), P(C.c_int32), C.c_int32,
+                                       C.c_void_p]
+    lib.davidson_solve_batched.argtypes = [C.c_void_p, C.c_int32, P(C.c_void_p), P(C.c_int32), P(C.c_void_p),
+                                           P(C.c_int32), P(C.c_void_p), P(C.c_void_p), P(DavOpts), P(DavStats),
+                                           P(C.c_int), C.c_int32, C.c_void_p]
+    lib.pw_server_opts_default.argtypes = [P(ServerOpts)]
+    lib.pw_server_opts_default.restype = None
+    lib.pw_server_create.argtypes = [C.c_void_p, P(ServerOpts), P(C.c_void_p)]
+    lib.pw_server_submit.argtypes = [C.c_void_p, P(Problem), C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                     C.c_void_p, P(DavOpts), P(C.c_int64)]
+    lib.pw_server_wait.argtypes = [C.c_void_p, C.c_int64, P(DavStats), P(C.c_double)]
+    lib.pw_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
+    lib.pw_server_clock.argtypes = [C.c_void_p]
+    lib.pw_server_clock.restype = C.c_double
+    lib.pw_server_destroy.argtypes = [C.c_void_p]
     lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     lib.pw_profile_enable.argtypes = [C.c_int]
@@ -91,8 +114,9 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_name.restype = C.c_char_p
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "davidson_solve", "pw_reduced_eigh", "pw_profile_enable",
-                 "pw_profile_read"):
+                 "pw_plan_info", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
+                 "pw_reduced_eigh", "pw_profile_enable", "pw_profile_read", "pw_server_create",
+                 "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -184,6 +208,42 @@ def profile_read():
     return out
 
 
+def _ptrs(tensors):
+    return (C.c_void_p * len(tensors))(*[C.c_void_p(t.data_ptr()) for t in tensors])
+
+
+def _ints(vals):
+    return (C.c_int32 * len(vals))(*[int(v) for v in vals])
+
+
+def hpsi_batched(ctx, plans, psis, outs, prec=PW_FP64, nstreams=0, stream=None):
+    """outs[i] = H_i psis[i] for every plan (asynchronous, worker streams of ctx)."""
+    n = len(plans)
+    assert len(psis) == n and len(outs) == n
+    hs = (C.c_void_p * n)(*[p.h.value for p in plans])
+    _check(ctx.lib.hpsi_apply_batched(ctx.h, n, hs, prec, _ints([x.shape[0] for x in psis]), _ptrs(psis),
+                                      _ints([x.stride(0) for x in psis]), _ptrs(outs),
+                                      _ints([y.stride(0) for y in outs]), nstreams, _stream_ptr(stream)))
+
+
+def davidson_batched(ctx, plans, psis, opts=None, nworkers=0, stream=None):
+    """Davidson on every (plan, psi) pair; returns (status, per-item status, eig list, resid list, stats list)."""
+    import torch
+    n = len(plans)
+    eigs = [torch.empty(x.shape[0], dtype=torch.float64, device=x.device) for x in psis]
+    res = [torch.empty(x.shape[0], dtype=torch.float64, device=x.device) for x in psis]
+    stats = (DavStats * n)()
+    status = (C.c_int * n)()
+    opts = opts or default_opts()
+    hs = (C.c_void_p * n)(*[p.h.value for p in plans])
+    st = ctx.lib.davidson_solve_batched(ctx.h, n, hs, _ints([x.shape[0] for x in psis]), _ptrs(psis),
+                                        _ints([x.stride(0) for x in psis]), _ptrs(eigs), _ptrs(res),
+                                        C.byref(opts), stats, status, nworkers, _stream_ptr(stream))
+    if st not in (PW_OK, PW_ENOTCONV):
+        _check(st)
+    return st, list(status), eigs, res, [stats[i] for i in range(n)]
+
+
 def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):
     """Lowest nev eigenpairs of h c = w s c (torch complex128 n x n on the device).
 
@@ -263,6 +323,59 @@ class Plan:
         if self.h:
             self.lib.pw_plan_destroy(self.h)
             self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Serving loop of the library (see pw_server_* in include/pwdft.h)."""
+
+    def __init__(self, ctx: Context, nworkers=4, mem_budget=0, precision=PW_MIXED):
+        self.ctx, self.lib = ctx, ctx.lib
+        o = ServerOpts()
+        self.lib.pw_server_opts_default(C.byref(o))
+        o.nworkers, o.mem_budget, o.precision = int(nworkers), int(mem_budget), int(precision)
+        self.h = C.c_void_p()
+        _check(self.lib.pw_server_create(ctx.h, C.byref(o), C.byref(self.h)))
+        self._keep = {}
+
+    def clock(self) -> float:
+        return float(self.lib.pw_server_clock(self.h))
+
+    def submit(self, p, psi, opts=None):
+        """Enqueue problem p with trial block psi (torch [nb][npw] on the device, solved in place);
+        returns (ticket, eig, resid)."""
+        import torch
+        s, keep = _problem_struct(p, psi.device)
+        eig = torch.empty(psi.shape[0], dtype=torch.float64, device=psi.device)
+        res = torch.empty_like(eig)
+        opts = opts or default_opts()
+        t = C.c_int64()
+        _check(self.lib.pw_server_submit(self.h, C.byref(s), psi.shape[0], C.c_void_p(psi.data_ptr()),
+                                         psi.stride(0), C.c_void_p(eig.data_ptr()), C.c_void_p(res.data_ptr()),
+                                         C.byref(opts), C.byref(t)))
+        self._keep[t.value] = (s, keep, psi, eig, res, opts)
+        return t.value, eig, res
+
+    def wait(self, ticket):
+        """Block until done; returns (status, stats dict, (t_submit, t_start, t_end))."""
+        st = DavStats()
+        times = (C.c_double * 3)()
+        rc = self.lib.pw_server_wait(self.h, ticket, C.byref(st), times)
+        self._keep.pop(ticket, None)
+        if rc not in (PW_OK, PW_ENOTCONV):
+            _check(rc)
+        return rc, st.asdict(), (times[0], times[1], times[2])
+
+    def close(self):
+        if self.h:
+            self.lib.pw_server_destroy(self.h)
+            self.h = C.c_void_p()
+            self._keep.clear()
 
     def __del__(self):
         try:

@@ -36,7 +36,11 @@ def _run(ctx, h, s, nev, debug=False):
     return w.cpu().numpy(), c.cpu().numpy().T, (dbg.cpu().numpy() if debug else None)
 
 
-@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (16, 8), (32, 16), (64, 32), (256, 128)])
+# n from 64 to 512 takes the cooperative (multi-workgroup) tridiagonalization,
+# smaller n the single-workgroup one, larger n the panel form
+@pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (16, 8), (32, 16), (63, 30), (64, 32), (65, 33),
+                                   (128, 64), (129, 64), (200, 100), (256, 128), (257, 128), (384, 192),
+                                   (512, 256), (600, 300)])
 def test_standard_problem(ctx, n, nev):
     rng = np.random.default_rng(n)
     h = _herm(rng, n)
@@ -74,6 +78,32 @@ def test_degenerate_clusters(ctx):
     np.testing.assert_allclose(w, lam[:19], atol=1e-12)
     np.testing.assert_allclose(c.conj().T @ c, np.eye(19), atol=1e-11)
     assert np.linalg.norm(h @ c - c * w, axis=0).max() <= 1e-11
+
+
+@pytest.mark.parametrize("n", [100, 300])
+def test_already_tridiagonal_and_diagonal(ctx, n):
+    # columns with nothing below the subdiagonal: reflectors with tau = 0
+    rng = np.random.default_rng(n)
+    d = rng.standard_normal(n)
+    for h in (np.diag(d).astype(complex),
+              np.diag(d) + np.diag(0.3 * np.ones(n - 1), 1) + np.diag(0.3 * np.ones(n - 1), -1) + 0j):
+        w, c, _ = _run(ctx, h, np.eye(n, dtype=complex), n // 2)
+        ref = np.linalg.eigvalsh(h)[: n // 2]
+        np.testing.assert_allclose(w, ref, atol=1e-12 * n)
+        assert np.linalg.norm(h @ c - c * w, axis=0).max() <= 1e-11 * n
+
+
+def test_cooperative_degenerate_clusters(ctx):
+    rng = np.random.default_rng(8)
+    n = 160
+    q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    lam = np.concatenate([[0.0] * 4, [1.0] * 20, [2.0] * 40, np.linspace(3, 5, n - 64)])
+    h = (q * lam) @ q.conj().T
+    h = (h + h.conj().T) / 2
+    w, c, _ = _run(ctx, h, np.eye(n, dtype=complex), 64)
+    np.testing.assert_allclose(w, lam[:64], atol=1e-12 * n)
+    np.testing.assert_allclose(c.conj().T @ c, np.eye(64), atol=1e-10)
+    assert np.linalg.norm(h @ c - c * w, axis=0).max() <= 1e-11 * n
 
 
 def test_diagonal_and_not_positive_definite(ctx):

@@ -44,6 +44,17 @@ def parse():
     ap.add_argument("--hpsi-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["cell64", "batch", "serve"], default="cell64",
+                    help="cell64: the 64-atom cell (default line); batch: 32 cells x 4 k-points solved "
+                         "concurrently vs one at a time in FP64; serve: Poisson request trace through the "
+                         "serving loop (p50/p99 latency)")
+    ap.add_argument("--workers", type=int, default=8, help="batch/serve: concurrent solves")
+    ap.add_argument("--requests", type=int, default=48, help="serve: timed requests")
+    ap.add_argument("--max-atoms", type=int, default=128, help="serve: largest request (atoms)")
+    ap.add_argument("--ecut", type=float, default=30.0, help="serve: cutoff in Ry")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after the timed region, copy 1 GiB device to device once (reference kernel "
+                         "for the FETCH_SIZE / WRITE_SIZE counter scale)")
     ap.add_argument("--mode", choices=["solve", "hpsi"], default="solve",
                     help="solve: a step is one Davidson solve; hpsi: a step is one hpsi_apply of the "
                          "128-band block (for kernel profiles of H.psi alone)")
@@ -106,12 +117,170 @@ def cpu_baseline(p, band_hpsi_per_solve, seconds):
     }
 
 
+def percentile(xs, q):
+    """Nearest-rank percentile."""
+    xs = sorted(xs)
+    k = max(1, int(np.ceil(q / 100.0 * len(xs))))
+    return xs[k - 1]
+
+
+def bench_batch(args):
+    """32 cells x 4 k-points: every problem solved one at a time in FP64, then all of
+    them through davidson_solve_batched (mixed precision, concurrent workers)."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    dev = torch.device("cuda", 0)
+    ps = pwgen.config4()
+    ctx = pwdft.Context(0)
+    opts = pwdft.default_opts(ndim=args.ndim, max_iter=400)
+    psi0 = [torch.from_numpy(p.psi0).to(dev) for p in ps]
+    nbands = sum(p.nb for p in ps)
+
+    def run_seq(plans):
+        xs = [x.clone() for x in psi0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, nh = [], 0
+        for pl, x in zip(plans, xs):
+            s, _, _, stt = pl.davidson(x, opts=opts)
+            st.append(s)
+            nh += stt.n_hpsi_fp64 + stt.n_hpsi_fp32
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, st, nh
+
+    def run_batch(plans):
+        xs = [x.clone() for x in psi0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, sts, eigs, res, stats = pwdft.davidson_batched(ctx, plans, xs, opts=opts, nworkers=args.workers)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sts, sum(s.n_hpsi_fp64 + s.n_hpsi_fp32 for s in stats), eigs
+
+    def hpsi_rate(plans, prec, batched):
+        xs = psi0
+        ys = [torch.empty_like(x) for x in xs]
+        reps = 5
+        for _ in range(2):
+            pwdft.hpsi_batched(ctx, plans, xs, ys, prec=prec, nstreams=args.workers)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            if batched:
+                pwdft.hpsi_batched(ctx, plans, xs, ys, prec=prec, nstreams=args.workers)
+            else:
+                for pl, x, y in zip(plans, xs, ys):
+                    pl.hpsi(x, y, prec=prec)
+        torch.cuda.synchronize()
+        return nbands * reps / (time.perf_counter() - t0)
+
+    plans64 = [pwdft.Plan(ctx, p, precision=pwdft.PW_FP64, nb_max=p.nb, ndim_max=args.ndim) for p in ps]
+    run_seq(plans64[:4])
+    t_seq, st_seq, nh_seq = run_seq(plans64)
+    hp_seq = hpsi_rate(plans64, pwdft.PW_FP64, False)
+    hp_b64 = hpsi_rate(plans64, pwdft.PW_FP64, True)
+    for pl in plans64:
+        pl.close()
+    prec = pwdft.PW_MIXED if args.precision == "mixed" else pwdft.PW_FP64
+    plans = [pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=args.ndim) for p in ps]
+    run_batch(plans)
+    times, last = [], None
+    for _ in range(max(1, args.steps)):
+        t, sts, nh_b, eigs = run_batch(plans)
+        times.append(t)
+        last = (sts, nh_b)
+    t_b = float(np.median(times))
+    hp_bm = hpsi_rate(plans, pwdft.PW_MIXED, True) if prec == pwdft.PW_MIXED else None
+    for pl in plans:
+        pl.close()
+    line = {
+        "metric": "band H·ψ/s and Davidson solves/s vs plain FP64 at 1e-8 Ry; p50/p99 latency",
+        "value": len(ps) / t_b, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": t_b * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if prec == pwdft.PW_MIXED else "f64",
+        "data": "synthetic (32 seeded cells a~U[10,20] bohr, 8-64 atoms, 25 Ry, k=(+-1/4,+-1/4,0))",
+        "config": {"workload": "batch of 128 problems: 32 cells x 4 k-points, npw 2157-16382, nb 20-128, "
+                               "Davidson to 1e-8 Ry", "problems": len(ps), "workers": args.workers,
+                   "ndim": args.ndim, "precision": args.precision},
+        "sequential_fp64_solves_per_s": len(ps) / t_seq,
+        "speedup_vs_sequential_fp64": t_seq / t_b,
+        "band_hpsi_per_s": {"fp64_sequential": hp_seq, "fp64_batched": hp_b64, "mixed_batched": hp_bm},
+        "band_hpsi_per_solve": {"sequential_fp64": nh_seq / len(ps), "batched": last[1] / len(ps)},
+        "status": {"sequential_fp64_ok": int(sum(s == 0 for s in st_seq)), "batched_ok": int(sum(s == 0 for s in last[0]))},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_serve(args):
+    """Open-loop Poisson trace of requests (log-uniform atom counts at constant
+    density) through the serving loop: a closed burst first measures the
+    capacity, then the trace runs at 0.7 x capacity."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    dev = torch.device("cuda", 0)
+    ctx = pwdft.Context(0)
+    opts = pwdft.default_opts(ndim=args.ndim, max_iter=400)
+    nreq = args.requests
+    t0 = time.perf_counter()
+    reqs = [pwgen.serving_request(i, ecut_ry=args.ecut, max_atoms=args.max_atoms) for i in range(2 * nreq)]
+    t_gen = time.perf_counter() - t0
+    prec = pwdft.PW_MIXED if args.precision == "mixed" else pwdft.PW_FP64
+
+    def run(batch, arrivals):
+        srv = pwdft.Server(ctx, nworkers=args.workers, precision=prec)
+        start = srv.clock()
+        subs = []
+        for p, ta in zip(batch, arrivals):
+            while srv.clock() - start < ta:
+                time.sleep(min(0.002, max(0.0, ta - (srv.clock() - start))))
+            x = torch.from_numpy(p.psi0).to(dev)
+            subs.append(srv.submit(p, x, opts=opts))
+        res = [srv.wait(t) for t, _, _ in subs]
+        srv.close()
+        lat = [r[2][2] - r[2][0] for r in res]
+        t_end = max(r[2][2] for r in res) - start
+        ok = sum(r[0] == 0 for r in res)
+        return lat, t_end, ok, res
+
+    # warm-up and capacity: the first half of the requests submitted at once
+    run(reqs[:4], [0.0] * 4)
+    lat_b, t_b, ok_b, _ = run(reqs[:nreq], [0.0] * nreq)
+    capacity = nreq / t_b
+    lam = 0.7 * capacity
+    rng = np.random.default_rng(20090605)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=nreq)).tolist()
+    lat, t_end, ok, res = run(reqs[nreq:], arrivals)
+    nat = [int(p.nbeta // 4) for p in reqs[nreq:]]
+    line = {
+        "metric": "band H·ψ/s and Davidson solves/s vs plain FP64 at 1e-8 Ry; p50/p99 latency",
+        "value": nreq / t_end, "unit": "solves/s", "n_gpus": 1, "steps": nreq, "warmup": 4,
+        "ms_per_step": t_end * 1e3 / nreq, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if prec == pwdft.PW_MIXED else "f64",
+        "data": "synthetic requests: atoms log-uniform 8..max, a = 41 (n/512)^(1/3) bohr, k = t b1",
+        "config": {"workload": f"served requests, {args.ecut:g} Ry, 8-{args.max_atoms} atoms (nb = 2 atoms), "
+                               f"Poisson arrivals at 0.7 x measured capacity", "requests": nreq,
+                   "workers": args.workers, "ndim": args.ndim, "precision": args.precision},
+        "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
+        "offered_load_req_per_s": lam,
+        "capacity_solves_per_s": capacity,
+        "burst_latency_s": {"p50": percentile(lat_b, 50), "p99": percentile(lat_b, 99)},
+        "atoms": {"min": min(nat), "median": int(np.median(nat)), "max": max(nat)},
+        "ok": int(ok), "input_generation_s": t_gen,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent cells / k-points shard one per GPU, see the design notes)", file=sys.stderr)
         return 2
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     import torch
     from paper_0906_2569_amd import pwdft, pwgen
 
@@ -204,6 +373,13 @@ def main():
     }
     if not args.no_cpu_baseline and args.mode == "solve":
         line["cpu_baseline"] = cpu_baseline(p, hpsi_per_solve, args.cpu_seconds)
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 2 * src.numel() * 8
     print(json.dumps(line), flush=True)
     plan.close()
     return 0

@@ -105,23 +105,35 @@ k_gemm_cn(int M, int N, int K, int kchunk, const cpx<TA>* __restrict__ A, int ld
 #pragma unroll
     for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
 
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+  // the next K slice is loaded into registers while the current one is
+  // multiplied out of LDS
+  constexpr int PER = BM * BK / NT;
+  cpx<TA> ra[PER];
+  cpx<TB> rb[PER];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < BM * BK / NT; ++it) {
+    for (int it = 0; it < PER; ++it) {
       const int idx = threadIdx.x + it * NT;
       const int kk = idx % BK, mi = idx / BK;
-      const int m = m0 + mi, k = k0 + kk;
-      cpx<TA> a{TA(0), TA(0)};
-      if (m < M && k < kend) a = A[(size_t)m * lda + k];
-      t.ar[kk][mi] = (T)a.x;
-      t.ai[kk][mi] = -(T)a.y;  // conj(A)
-      const int n = n0 + mi;
-      cpx<TB> b{TB(0), TB(0)};
-      if (n < N && k < kend) b = B[(size_t)n * ldb + k];
-      t.br[kk][mi] = (T)b.x;
-      t.bi[kk][mi] = (T)b.y;
+      const int k = k0 + kk;
+      const int m = m0 + mi, n = n0 + mi;
+      ra[it] = (m < M && k < kend) ? A[(size_t)m * lda + k] : cpx<TA>{TA(0), TA(0)};
+      rb[it] = (n < N && k < kend) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
+    }
+  };
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, mi = idx / BK;
+      t.ar[kk][mi] = (T)ra[it].x;
+      t.ai[kk][mi] = -(T)ra[it].y;  // conj(A)
+      t.br[kk][mi] = (T)rb[it].x;
+      t.bi[kk][mi] = (T)rb[it].y;
     }
     __syncthreads();
+    if (k0 + BK < kend) load(k0 + BK);
     tile_mma<T>(t, cr, ci, wm, wn, lane);
     __syncthreads();
   }
@@ -156,28 +168,43 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int 
 #pragma unroll
     for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
 
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  constexpr int PER = BM * BK / NT;
+  cpx<TA> ra[PER];
+  cpx<TB> rb[PER];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < BM * BK / NT; ++it) {
+    for (int it = 0; it < PER; ++it) {
       const int idx = threadIdx.x + it * NT;
       {
         const int mi = idx % BM, kk = idx / BM;
         const int m = m0 + mi, k = k0 + kk;
-        cpx<TA> a{TA(0), TA(0)};
-        if (m < M && k < K) a = A[(size_t)k * lda + m];
-        t.ar[kk][mi] = (T)a.x;
-        t.ai[kk][mi] = (T)a.y;
+        ra[it] = (m < M && k < K) ? A[(size_t)k * lda + m] : cpx<TA>{TA(0), TA(0)};
       }
       {
         const int kk = idx % BK, ni = idx / BK;
         const int n = n0 + ni, k = k0 + kk;
-        cpx<TB> b{TB(0), TB(0)};
-        if (n < N && k < K) b = B[(size_t)n * ldb + k];
-        t.br[kk][ni] = (T)b.x;
-        t.bi[kk][ni] = (T)b.y;
+        rb[it] = (n < N && k < K) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
+      }
+    }
+  };
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      {
+        const int mi = idx % BM, kk = idx / BM;
+        t.ar[kk][mi] = (T)ra[it].x;
+        t.ai[kk][mi] = (T)ra[it].y;
+      }
+      {
+        const int kk = idx % BK, ni = idx / BK;
+        t.br[kk][ni] = (T)rb[it].x;
+        t.bi[kk][ni] = (T)rb[it].y;
       }
     }
     __syncthreads();
+    if (k0 + BK < K) load(k0 + BK);
     tile_mma<T>(t, cr, ci, wm, wn, lane);
     __syncthreads();
   }
@@ -202,6 +229,29 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int 
       }
 }
 
+// sum_z P[z * stride + off] for z < nsplit, in increasing z (the order is
+// fixed, so results are reproducible); the loads of eight partials are
+// issued before they are added
+template <typename T>
+__device__ __forceinline__ cpx<T> sum_partials(const cpx<T>* __restrict__ P, int nsplit, size_t stride,
+                                               size_t off) {
+  T re = 0, im = 0;
+  int z = 0;
+  for (; z + 8 <= nsplit; z += 8) {
+    cpx<T> v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = P[(size_t)(z + u) * stride + off];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) { re += v[u].x; im += v[u].y; }
+  }
+  for (; z < nsplit; ++z) {
+    const cpx<T> v = P[(size_t)z * stride + off];
+    re += v.x;
+    im += v.y;
+  }
+  return cpx<T>{re, im};
+}
+
 // C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]   (fixed summation order)
 template <typename T>
 __global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
@@ -210,12 +260,8 @@ __global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int m = (int)(idx % M), n = (int)(idx / M);
-    T re = 0, im = 0;
-    for (int z = 0; z < nsplit; ++z) {
-      const cpx<T> v = P[(size_t)z * total + idx];
-      re += v.x;
-      im += v.y;
-    }
+    const cpx<T> sum = sum_partials(P, nsplit, total, idx);
+    const T re = sum.x, im = sum.y;
     c128* c = C + (size_t)n * ldc + m;
     double r = alpha * (double)re, i = alpha * (double)im;
     if (beta != 0.0) {
@@ -237,15 +283,7 @@ __global__ void k_reduce_dapply(int M, int N, int nsplit, const cpx<T>* __restri
   cpx<T>* red = reinterpret_cast<cpx<T>*>(smem_raw);
   const int n = blockIdx.x;
   const size_t total = (size_t)M * N;
-  for (int j = threadIdx.x; j < M; j += blockDim.x) {
-    T re = 0, im = 0;
-    for (int z = 0; z < nsplit; ++z) {
-      const cpx<T> v = P[(size_t)z * total + (size_t)n * M + j];
-      re += v.x;
-      im += v.y;
-    }
-    red[j] = cpx<T>{re, im};
-  }
+  for (int j = threadIdx.x; j < M; j += blockDim.x) red[j] = sum_partials(P, nsplit, total, (size_t)n * M + j);
   __syncthreads();
   for (int j = threadIdx.x; j < M; j += blockDim.x) {
     const int j0 = dstart[j], nh = dlen[j];

@@ -849,44 +849,78 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 // per eigenvalue, 64 shifts per round (Sturm counts), interval narrowed to
 // the two shifts around the k-th eigenvalue.
 // ---------------------------------------------------------------------------
-__device__ int sturm_count(int n, const double* d, const double* e, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (q < 0.0) ++cnt;
-  for (int i = 1; i < n; ++i) {
-    if (fabs(q) < pivmin) q = -pivmin;
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
-    if (q < 0.0) ++cnt;
-  }
-  return cnt;
+// 1/q to a few units in the last place: the hardware reciprocal refined by
+// one Newton step (a shorter dependent chain than an IEEE division; a Sturm
+// count only needs the signs of the pivots)
+__device__ __forceinline__ double fast_rcp(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
 }
 
+// Sturm counts (number of eigenvalues below x) of the tridiagonal (d, e2 =
+// e^2) at CH shifts at once: the CH recurrences are independent, so their
+// latencies overlap
+template <int CH>
+__device__ __forceinline__ void sturm_counts(int n, const double* d, const double* e2, const double (&x)[CH],
+                                             double pivmin, int (&cnt)[CH]) {
+  double q[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) {
+    q[c] = d[0] - x[c];
+    cnt[c] = q[c] < 0.0 ? 1 : 0;
+  }
+#pragma unroll 4
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      const double qq = (fabs(q[c]) < pivmin) ? -pivmin : q[c];
+      q[c] = di - x[c] - ei * fast_rcp(qq);
+      cnt[c] += q[c] < 0.0 ? 1 : 0;
+    }
+  }
+}
+
+// One wave per wanted eigenvalue k: each round evaluates the Sturm count at
+// 64 x CH equally spaced shifts and keeps the interval between the two shifts
+// that bracket the k-th eigenvalue.
+constexpr int kBisectChains = 2;
 __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict__ dg,
                                                 const double* __restrict__ eg, int nev,
                                                 double* __restrict__ w, const int* __restrict__ info) {
   if (*info != 0) return;
+  constexpr int CH = kBisectChains, NS = 64 * CH;
   extern __shared__ __align__(16) char smem_raw[];
   double* d = reinterpret_cast<double*>(smem_raw);
-  double* e = d + n;
+  double* e2 = d + n;
   __shared__ double s_lo, s_hi, s_piv;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     d[i] = dg[i];
-    if (i < n - 1) e[i] = eg[i];
+    if (i < n - 1) e2[i] = eg[i] * eg[i];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // Gershgorin interval of T (the first wave, one row per lane at a time)
+  if (threadIdx.x < 64) {
     double lo = 1e300, hi = -1e300, emax = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < n - 1 ? fabs(e[i]) : 0.0);
+    for (int i = threadIdx.x; i < n; i += 64) {
+      const double r = (i > 0 ? sqrt(e2[i - 1]) : 0.0) + (i < n - 1 ? sqrt(e2[i]) : 0.0);
       lo = fmin(lo, d[i] - r);
       hi = fmax(hi, d[i] + r);
-      if (i < n - 1) emax = fmax(emax, e[i] * e[i]);
+      if (i < n - 1) emax = fmax(emax, e2[i]);
     }
-    const double nrm = fmax(fabs(lo), fabs(hi));
-    const double pad = 4.0 * DBL_EPSILON * nrm * n + 1e-300;
-    s_lo = lo - pad;
-    s_hi = hi + pad;
-    s_piv = DBL_MIN * fmax(1.0, emax);
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      emax = fmax(emax, __shfl_xor(emax, o, 64));
+    }
+    if (threadIdx.x == 0) {
+      const double nrm = fmax(fabs(lo), fabs(hi));
+      const double pad = 4.0 * DBL_EPSILON * nrm * n + 1e-300;
+      s_lo = lo - pad;
+      s_hi = hi + pad;
+      s_piv = DBL_MIN * fmax(1.0, emax);
+    }
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
@@ -896,16 +930,25 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
   const double pivmin = s_piv;
   for (int round = 0; round < 64; ++round) {
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    const double step = (hi - lo) / 65.0;
-    const double x = lo + step * (lane + 1);
-    const int c = sturm_count(n, d, e, x, pivmin);
-    const unsigned long long mask = __ballot(c > k);
+    const double step = (hi - lo) / (double)(NS + 1);
+    double x[CH];
+    int c[CH];
+#pragma unroll
+    for (int j = 0; j < CH; ++j) x[j] = lo + step * (CH * lane + j + 1);
+    sturm_counts<CH>(n, d, e2, x, pivmin, c);
+    // first shift (in increasing order) with more than k eigenvalues below it
+    int jf = CH;
+#pragma unroll
+    for (int j = CH - 1; j >= 0; --j)
+      if (c[j] > k) jf = j;
+    const unsigned long long mask = __ballot(jf < CH);
     if (mask == 0ull) {
-      lo = lo + step * 64;
+      lo = lo + step * NS;
     } else {
       const int f = __ffsll((long long)mask) - 1;
-      const double xf = lo + step * (f + 1);
-      const double xp = (f > 0) ? lo + step * f : lo;
+      const int s = CH * f + __shfl(jf, f, 64);   // 0-based shift index
+      const double xf = lo + step * (s + 1);
+      const double xp = (s > 0) ? lo + step * s : lo;
       hi = xf;
       lo = xp;
     }
@@ -919,17 +962,20 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
 // scale of their neighbour),
 // solving (T - w I) x = b by Gaussian elimination with partial pivoting,
 // three iterations, orthogonalized against the earlier cluster members.
-// Z is real [nev][ldz].  The per-thread factors and iterate (5 n doubles and
-// n pivot flags) live in a Work view: LDS for up to TPW threads per
+// Z is real [nev][ldz].  The per-thread factors (pivots kept as reciprocals)
+// and iterate (5 n doubles and n pivot flags) live in a Work view: LDS for up to TPW threads per
 // workgroup when they fit, else the global scratch (element r of thread t at
 // [r * S + t], so that neighbouring threads touch neighbouring addresses).
 // ---------------------------------------------------------------------------
 struct InvitView {
-  double *D, *DL, *DU, *DU2, *X;
+  double *D, *DL, *DU, *DU2, *X, *Y;
   unsigned char* PV;
-  size_t S;   // stride between consecutive elements of one thread
+  size_t S;   // stride between consecutive elements of one thread (SC when SC > 0)
 };
 
+// SC > 0: compile-time stride (the compiler can then overlap the loads of one
+// row with the stores of the previous one)
+template <int SC>
 __device__ void invit_cluster(int n, const double* __restrict__ d, const double* __restrict__ e, int nev,
                               const double* __restrict__ w, double* __restrict__ Z, int ldz, int i0,
                               InvitView v) {
@@ -941,14 +987,20 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
   int i1 = i0 + 1;
   while (i1 < nev && w[i1] - w[i1 - 1] <= ctol) ++i1;
   const double tiny = DBL_EPSILON * tn;
-  const size_t S = v.S;
-  double *D = v.D, *DL = v.DL, *DU = v.DU, *DU2 = v.DU2, *X = v.X;
-  unsigned char* PV = v.PV;
+  const size_t S = SC > 0 ? (size_t)SC : v.S;
+  double* __restrict__ D = v.D;      // reciprocal pivots
+  double* __restrict__ DL = v.DL;
+  double* __restrict__ DU = v.DU;
+  double* __restrict__ DU2 = v.DU2;
+  double* __restrict__ X = v.X;
+  double* __restrict__ Y = v.Y;
+  unsigned char* __restrict__ PV = v.PV;
   for (int i = i0; i < i1; ++i) {
     const double lam = w[i];
     // factor T - lam I with partial pivoting; the running pivot stays in a register
     double dcur = d[0] - lam;
     double du_next = (n > 1) ? e[0] : 0.0;   // DU[r] before row r's update
+#pragma unroll 2
     for (int r = 0; r < n - 1; ++r) {
       const double er = e[r];
       const double dnext = d[r + 1] - lam;
@@ -964,31 +1016,41 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
         dr = er; dlr = f; dur = dnext; dn = du_next - f * dnext;
         du2r = du_after; dun = -f * du_after; piv = 1;
       }
-      D[r * S] = (fabs(dr) < tiny) ? ((dr >= 0.0) ? tiny : -tiny) : dr;
+      D[r * S] = 1.0 / ((fabs(dr) < tiny) ? ((dr >= 0.0) ? tiny : -tiny) : dr);
       DL[r * S] = dlr; DU[r * S] = dur; DU2[r * S] = du2r;
       PV[r * S] = piv;
       dcur = dn;
       du_next = dun;
     }
-    D[(n - 1) * S] = (fabs(dcur) < tiny) ? ((dcur >= 0.0) ? tiny : -tiny) : dcur;
-    for (int r = 0; r < n; ++r) X[r * S] = cos(0.7 * r + 1.3 * i) + 0.1;
+    D[(n - 1) * S] = 1.0 / ((fabs(dcur) < tiny) ? ((dcur >= 0.0) ? tiny : -tiny) : dcur);
+    // generic start vector: an integer hash of (r, i) mapped to [0.5, 1.5)
+    for (int r = 0; r < n; ++r) {
+      unsigned h = (unsigned)r * 2654435761u ^ ((unsigned)i * 2246822519u + 0x9e3779b9u);
+      h ^= h >> 15;
+      h *= 2246822519u;
+      h ^= h >> 13;
+      X[r * S] = 0.5 + (double)(h & 0xffffu) * (1.0 / 65536.0);
+    }
     for (int it = 0; it < 3; ++it) {
+      // forward substitution with the row interchanges: X -> Y
       double xr = X[0];
+#pragma unroll 4
       for (int r = 0; r < n - 1; ++r) {
         const double xn = X[(r + 1) * S];
         if (PV[r * S]) {
-          X[r * S] = xn;
+          Y[r * S] = xn;
           xr = xr - DL[r * S] * xn;
         } else {
-          X[r * S] = xr;
+          Y[r * S] = xr;
           xr = xn - DL[r * S] * xr;
         }
       }
-      X[(n - 1) * S] = xr;
-      double x2 = 0.0, x1 = X[(n - 1) * S] / D[(n - 1) * S];
+      // back substitution with the upper factor: Y -> X
+      double x2 = 0.0, x1 = xr * D[(n - 1) * S];
       X[(n - 1) * S] = x1;
+#pragma unroll 4
       for (int r = n - 2; r >= 0; --r) {
-        const double xv = (X[r * S] - DU[r * S] * x1 - DU2[r * S] * x2) / D[r * S];
+        const double xv = (Y[r * S] - DU[r * S] * x1 - DU2[r * S] * x2) * D[r * S];
         X[r * S] = xv;
         x2 = x1;
         x1 = xv;
@@ -1000,8 +1062,10 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
         for (int r = 0; r < n; ++r) X[r * S] -= dot * zj[r];
       }
       double nrm = 0.0;
+#pragma unroll 4
       for (int r = 0; r < n; ++r) nrm += X[r * S] * X[r * S];
       const double inv = 1.0 / sqrt(nrm);
+#pragma unroll 4
       for (int r = 0; r < n; ++r) X[r * S] *= inv;
     }
     double* z = Z + (size_t)i * ldz;
@@ -1009,7 +1073,7 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
   }
 }
 
-// scratch in global memory: 5 n doubles + n bytes per thread
+// scratch in global memory: 6 n doubles + n bytes per thread
 __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ d,
                                               const double* __restrict__ e, int nev,
                                               const double* __restrict__ w, double* __restrict__ Z,
@@ -1026,12 +1090,14 @@ __global__ void __launch_bounds__(64) k_invit(int n, const double* __restrict__ 
   v.DU = v.DL + (size_t)n * S;
   v.DU2 = v.DU + (size_t)n * S;
   v.X = v.DU2 + (size_t)n * S;
-  v.PV = reinterpret_cast<unsigned char*>(scratch + 5 * (size_t)n * S) + i0;
-  invit_cluster(n, d, e, nev, w, Z, ldz, i0, v);
+  v.Y = v.X + (size_t)n * S;
+  v.PV = reinterpret_cast<unsigned char*>(scratch + 6 * (size_t)n * S) + i0;
+  invit_cluster<0>(n, d, e, nev, w, Z, ldz, i0, v);
 }
 
-// scratch in LDS: TPW threads per workgroup, 41 n bytes each
-constexpr int kInvitLdsBytes = 96 * 1024;
+// scratch in LDS: the tridiagonal (16 n bytes) and TPW threads per workgroup,
+// 49 n bytes each
+constexpr int kInvitLdsBytes = 120 * 1024;
 template <int TPW>
 __global__ void __launch_bounds__(64) k_invit_lds(int n, const double* __restrict__ d,
                                                   const double* __restrict__ e, int nev,
@@ -1041,8 +1107,16 @@ __global__ void __launch_bounds__(64) k_invit_lds(int n, const double* __restric
   extern __shared__ __align__(16) char smem_raw[];
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * TPW + t;
+  // the tridiagonal, read once per step of every recurrence, is staged in LDS
+  double* sd = reinterpret_cast<double*>(smem_raw);
+  double* se = sd + n;
+  for (int i = t; i < n; i += blockDim.x) {
+    sd[i] = d[i];
+    se[i] = (i < n - 1) ? e[i] : 0.0;
+  }
+  __syncthreads();
   if (t >= TPW || i0 >= nev) return;
-  double* base = reinterpret_cast<double*>(smem_raw);
+  double* base = se + n;
   InvitView v;
   v.S = TPW;
   v.D = base + t;
@@ -1050,8 +1124,9 @@ __global__ void __launch_bounds__(64) k_invit_lds(int n, const double* __restric
   v.DU = v.DL + (size_t)n * TPW;
   v.DU2 = v.DU + (size_t)n * TPW;
   v.X = v.DU2 + (size_t)n * TPW;
-  v.PV = reinterpret_cast<unsigned char*>(base + 5 * (size_t)n * TPW) + t;
-  invit_cluster(n, d, e, nev, w, Z, ldz, i0, v);
+  v.Y = v.X + (size_t)n * TPW;
+  v.PV = reinterpret_cast<unsigned char*>(base + 6 * (size_t)n * TPW) + t;
+  invit_cluster<TPW>(n, sd, se, nev, w, Z, ldz, i0, v);
 }
 
 // ---------------------------------------------------------------------------
@@ -1075,25 +1150,32 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
     const int r = lane + 64 * t;
     y[t] = c128{r < n ? Z[(size_t)col * ldz + r] : 0.0, 0.0};
   }
-  for (int k = n - 2; k >= 0; --k) {
-    const c128 tk = tau[k];
-    if (tk.x == 0.0 && tk.y == 0.0) continue;
+  // the reflector of the next step is loaded while the current one is applied
+  auto load_v = [&](int k, c128 (&vv)[NPL]) {
     const c128* v = A + (size_t)k * lda;   // v_k at rows k+1 .. n-1
-    double sr = 0.0, si = 0.0;
-    c128 vv[NPL];
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const int r = lane + 64 * t;
       vv[t] = (r > k && r < n) ? v[r] : c128{0.0, 0.0};
+    }
+  };
+  c128 vn[NPL];
+  if (n >= 2) load_v(n - 2, vn);
+  for (int k = n - 2; k >= 0; --k) {
+    c128 vv[NPL];
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) vv[t] = vn[t];
+    const c128 tk = tau[k];
+    if (k > 0) load_v(k - 1, vn);
+    if (tk.x == 0.0 && tk.y == 0.0) continue;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int t = 0; t < NPL; ++t) {
       const c128 u = cmulc(vv[t], y[t]);   // conj(v_r) y_r
       sr += u.x;
       si += u.y;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-      sr += __shfl_xor(sr, o, 64);
-      si += __shfl_xor(si, o, 64);
-    }
-    const c128 sc = cmul(tk, c128{sr, si});
+    const c128 sc = cmul(tk, c128{wave_sum(sr), wave_sum(si)});
 #pragma unroll
     for (int t = 0; t < NPL; ++t) {
       const c128 u = cmul(vv[t], sc);
@@ -1125,7 +1207,7 @@ CoopBuf coop_buf(const pw::HeigWork& hw) {
 
 size_t pw::heig_work_bytes(int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
-  return sizeof(c128) * (5 * n * n + 2 * n + 2 * n * PANEL) + sizeof(double) * (3 * n + n * n + 6 * n * (n + 64)) +
+  return sizeof(c128) * (5 * n * n + 2 * n + 2 * n * PANEL) + sizeof(double) * (3 * n + n * n + 7 * n * (n + 64)) +
          sizeof(int) * n + 24 * 256 + coop_bytes();
 }
 
@@ -1148,7 +1230,7 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   hw.e = reinterpret_cast<double*>(take(sizeof(double) * n));
   hw.w = reinterpret_cast<double*>(take(sizeof(double) * n));
   hw.Z = reinterpret_cast<double*>(take(sizeof(double) * n * n));
-  hw.scratch = reinterpret_cast<double*>(take(sizeof(double) * 6 * n * (n + 64)));
+  hw.scratch = reinterpret_cast<double*>(take(sizeof(double) * 7 * n * (n + 64)));
   hw.info = reinterpret_cast<int*>(take(256));
   hw.gamma = reinterpret_cast<double*>(take(256));
   hw.drop = reinterpret_cast<int*>(take(sizeof(int) * n));
@@ -1236,15 +1318,17 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_BISECT, st);
-    k_bisect<<<ceil_div(nev, 4), 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
+    k_bisect<<<nev, 64, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
   }
   {
     pw::ProfScope ps(pw::PK_INVIT, st);
-    const size_t per_thread = 41 * (size_t)n;
-    if (8 * per_thread <= (size_t)kInvitLdsBytes)
-      k_invit_lds<8><<<ceil_div(nev, 8), 64, 8 * per_thread, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.info);
-    else if (4 * per_thread <= (size_t)kInvitLdsBytes)
-      k_invit_lds<4><<<ceil_div(nev, 4), 64, 4 * per_thread, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.info);
+    const size_t per_thread = 49 * (size_t)n, shared = 16 * (size_t)n;
+    if (8 * per_thread + shared <= (size_t)kInvitLdsBytes)
+      k_invit_lds<8><<<ceil_div(nev, 8), 64, 8 * per_thread + shared, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw,
+                                                                          hw.info);
+    else if (4 * per_thread + shared <= (size_t)kInvitLdsBytes)
+      k_invit_lds<4><<<ceil_div(nev, 4), 64, 4 * per_thread + shared, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw,
+                                                                          hw.info);
     else
       k_invit<<<ceil_div(nev, 64), 64, 0, st>>>(n, hw.d, hw.e, nev, w, hw.Z, ldw, hw.scratch, hw.info);
   }

@@ -122,7 +122,8 @@ typedef struct {
 /* Last error message of the calling host thread ("" if none). */
 const char* pw_last_error(void);
 
-/* Create / destroy a context bound to HIP device `device`. */
+/* Create / destroy a context bound to HIP device `device`.  Destroy the
+   context's plans and servers before the context. */
 pw_status pw_ctx_create(int device, pw_ctx* out);
 pw_status pw_ctx_destroy(pw_ctx ctx);
 

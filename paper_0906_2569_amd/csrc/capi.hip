@@ -34,6 +34,7 @@ extern "C" pw_status pw_ctx_destroy(pw_ctx c) {
   (void)hipSetDevice(c->device);
   pw::ctx_release_pool(c);
   delete c;
+  (void)hipGetLastError();
   return PW_OK;
 }
 

@@ -49,9 +49,11 @@ pw_status fail(pw_status st, const std::string& msg);
 #define PW_HIP(call)                                                                          \
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \
-    if (e_ != hipSuccess)                                                                     \
+    if (e_ != hipSuccess) {                                                                   \
+      (void)hipGetLastError(); /* the status carries it; do not leave it to other HIP users */ \
       return pw::fail(PW_EDEVICE, std::string(__FILE__ ":" PW_STR(__LINE__) ": ") + #call ": " + \
                                       hipGetErrorString(e_));                                 \
+    }                                                                                         \
   } while (0)
 
 #define PW_CHECK(cond, st, msg)             \

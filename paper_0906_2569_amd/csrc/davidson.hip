@@ -370,7 +370,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_CHECK(o.precond_floor > 0.0, PW_EINVAL, "precond_floor must be positive");
   PW_CHECK(psi_u && eig && resid, PW_EINVAL, "NULL psi, eig or resid");
   PW_CHECK(ldpsi >= p->npw, PW_EINVAL, "ldpsi < npw");
-  PW_HIP(hipSetDevice(p->ctx->device));
+  PW_HIP(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   pw_david_stats stats{};
   Solver S{p, W, st, stats};

@@ -578,6 +578,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
 
   pw_plan p = new pw_plan_s();
   p->ctx = ctx;
+  p->device = ctx->device;
   p->opts = *o;
   p->npw = npw;
   p->n1 = n1; p->n2 = n2; p->n3 = n3;
@@ -688,7 +689,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
 
 extern "C" pw_status pw_plan_destroy(pw_plan p) {
   if (!p) return PW_OK;
-  (void)hipSetDevice(p->ctx ? p->ctx->device : 0);
+  (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   pw::dav_free(p);
   for (void* q : p->allocs)
@@ -697,6 +698,7 @@ extern "C" pw_status pw_plan_destroy(pw_plan p) {
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->side) (void)hipStreamDestroy(p->side);
   delete p;
+  (void)hipGetLastError();   // leave no error of the teardown behind for other HIP users
   return PW_OK;
 }
 
@@ -810,7 +812,7 @@ extern "C" pw_status hpsi_apply(pw_plan p, pw_precision prec, int32_t nb, const 
   const char* b0 = reinterpret_cast<const char*>(hpsi);
   const char* b1 = b0 + sizeof(pw_c128) * ((size_t)(nb - 1) * ldhpsi + p->npw);
   PW_CHECK(a1 <= b0 || b1 <= a0, PW_EINVAL, "psi and hpsi overlap");
-  PW_HIP(hipSetDevice(p->ctx->device));
+  PW_HIP(hipSetDevice(p->device));
   return pw::hpsi_launch(p, prec, nb, reinterpret_cast<const c128*>(psi), ldpsi,
                          reinterpret_cast<c128*>(hpsi), ldhpsi, static_cast<hipStream_t>(stream));
 }

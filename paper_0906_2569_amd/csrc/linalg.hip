@@ -479,10 +479,11 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 
 // ---------------------------------------------------------------------------
 // Cooperative Householder tridiagonalization for 64 <= n <= 512: P =
-// ceil(n / CR) workgroups, workgroup q holding rows [q CR, q CR + CR) of the
-// Hermitian matrix B (row r = conj of column r of A) in registers; thread t
-// holds columns t and t + CT of the workgroup's rows (one wave per SIMD, so
-// the small per-step scalar work is repeated four times, not sixteen).
+// ceil(n / CR) workgroups, workgroup q holding CR rows of the
+// Hermitian matrix B (row r = conj of column r of A) in registers.  Rows are
+// dealt cyclically (row r to workgroup r mod P), so every workgroup keeps
+// about (n - k) / P live rows at step k; thread t holds columns t mod 256 and
+// t mod 256 + 256 of half of its workgroup's rows (two waves per SIMD).
 //
 // Step k (the reflector v_k, tau_k is known in every workgroup, and every
 // workgroup holds y = B v_k for its rows):
@@ -500,7 +501,8 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 // sets info = 2 and exits.
 // ---------------------------------------------------------------------------
 constexpr int CR = 16;      // rows per workgroup
-constexpr int CT = 256;     // threads per workgroup (one wave per SIMD)
+constexpr int CT = 512;     // threads per workgroup (two waves per SIMD)
+constexpr int CB = 256;     // columns covered by one pass of the threads
 constexpr int kCoopMinN = 64, kCoopMaxN = 512;
 constexpr int kCoopMaxP = kCoopMaxN / CR;
 constexpr long kCoopSpin = 1l << 22;   // polls of a barrier before giving up
@@ -512,6 +514,23 @@ struct CoopBuf {
   unsigned* count; // barrier arrivals (zeroed before each launch)
   unsigned* fail;  // set when a barrier timed out
 };
+
+// The exchanged values are written and read with agent-scope atomic 64-bit
+// accesses: they bypass caches that are not coherent across the XCDs, so a
+// value written by a workgroup on one XCD is never read stale from another
+// XCD's L2 (the counter's release/acquire orders them).
+__device__ __forceinline__ void xstore(c128* p, c128 v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ c128 xload(const c128* p) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<c128*>(p));
+  const unsigned long long lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return c128{__longlong_as_double((long long)lo), __longlong_as_double((long long)hi)};
+}
 
 __global__ void k_coop_reset(CoopBuf cb) {
   if (threadIdx.x == 0) { *cb.count = 0u; *cb.fail = 0u; }
@@ -625,10 +644,13 @@ template <int NC>
 __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A, int ld, double* __restrict__ d,
                                                      double* __restrict__ e, c128* __restrict__ tau,
                                                      int* __restrict__ info, CoopBuf cb) {
-  constexpr int NW = CT / 64;
+  constexpr int NW = CT / 64;             // waves
+  constexpr int NH = CT / CB;             // row halves (threads t and t + CB share columns)
+  constexpr int RH = CR / NH;             // rows per thread
+  constexpr int WH = CB / 64;             // waves per half
   if (*info != 0) return;
   __shared__ c128 s_rowbuf[kCoopMaxN];    // owned row k+1 (for publication)
-  __shared__ double s_red[NW][2 * CR];    // per-wave row sums of B v (re, then im)
+  __shared__ double s_red[NW][2 * RH];    // per-wave row sums of B v (re, then im)
   __shared__ c128 s_rv[2][CR], s_rw[CR];  // v_k (by step parity) and w on the own rows
   __shared__ double s_xn2[NW];
   __shared__ c128 s_alx;
@@ -636,41 +658,52 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 
   const int P = gridDim.x, q = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int rowbase = q * CR;
+  const int half = tid / CB;
+  // own rows: row(i) = q + P i (cyclic, so that every workgroup keeps about
+  // the same number of live rows as the reduction proceeds)
+  auto row_of = [&](int i) { return q + P * i; };
+  // local index of row r if it is an own row, else -1
+  auto local_of = [&](int r) { return (r >= q && (r - q) % P == 0 && (r - q) / P < CR) ? (r - q) / P : -1; };
   int jc[NC];
   bool ok[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) { jc[c] = tid + CT * c; ok[c] = jc[c] < n; }
+  for (int c = 0; c < NC; ++c) { jc[c] = (tid % CB) + CB * c; ok[c] = jc[c] < n; }
 
-  // rows of B: a[c][i] = B[rowbase + i][j_c] = conj(A[(rowbase + i) * ld + j_c])
-  c128 a[NC][CR];
+  // rows of B: a[c][i] = B[row(half RH + i)][j_c] = conj(A[row * ld + j_c])
+  c128 a[NC][RH];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
-    for (int i = 0; i < CR; ++i) {
-      const int R = rowbase + i;
+    for (int i = 0; i < RH; ++i) {
+      const int R = row_of(half * RH + i);
       a[c][i] = (ok[c] && R < n) ? cconj(A[(size_t)R * ld + jc[c]]) : c128{0.0, 0.0};
       if (R == 1 && ok[c]) s_rowbuf[jc[c]] = a[c][i];   // row 1 is published at step 0
     }
   if (tid == 0) s_fail = 0;
+  // own rows past the end of the matrix are never written: start from zeros
+  if (tid < CR) { s_rv[0][tid] = s_rv[1][tid] = s_rw[tid] = c128{0.0, 0.0}; }
+  __syncthreads();
 
-  // own-row values of a column vector to LDS
+  // own-row values of a column vector to LDS (one copy: the first half writes)
   auto put_own = [&](c128* dst, const c128 (&val)[NC]) {
+    if (half != 0) return;
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (jc[c] >= rowbase && jc[c] < rowbase + CR) dst[jc[c] - rowbase] = val[c];
+    for (int c = 0; c < NC; ++c) {
+      const int li = local_of(jc[c]);
+      if (li >= 0 && ok[c]) dst[li] = val[c];
+    }
   };
   // y = B v on the own rows: per-thread partial sums, then per-wave totals to s_red
-  auto rows_times = [&](const c128 (&acc)[CR]) {
-    double vr[CR], vi[CR];
+  auto rows_times = [&](const c128 (&acc)[RH]) {
+    double vr[RH], vi[RH];
 #pragma unroll
-    for (int i = 0; i < CR; ++i) { vr[i] = acc[i].x; vi[i] = acc[i].y; }
-    wave_multi_sum<CR>(vr);
-    wave_multi_sum<CR>(vi);
-    if (msum_writer<CR>(lane)) {
-      const int sl = msum_slot<CR>(lane);
+    for (int i = 0; i < RH; ++i) { vr[i] = acc[i].x; vi[i] = acc[i].y; }
+    wave_multi_sum<RH>(vr);
+    wave_multi_sum<RH>(vi);
+    if (msum_writer<RH>(lane)) {
+      const int sl = msum_slot<RH>(lane);
       s_red[wid][sl] = vr[0];
-      s_red[wid][CR + sl] = vi[0];
+      s_red[wid][RH + sl] = vi[0];
     }
   };
 
@@ -683,8 +716,8 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       x[c] = (ok[c] && jc[c] >= 1) ? A[jc[c]] : c128{0.0, 0.0};
-      if (ok[c] && jc[c] >= 2) xx += x[c].x * x[c].x + x[c].y * x[c].y;
-      if (jc[c] == 1) s_alx = x[c];
+      if (half == 0 && ok[c] && jc[c] >= 2) xx += x[c].x * x[c].x + x[c].y * x[c].y;
+      if (half == 0 && jc[c] == 1) s_alx = x[c];
     }
     const double r = wave_sum(xx);
     if (lane == 0) s_xn2[wid] = r;
@@ -698,11 +731,11 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     put_own(s_rv[0], vk);
   }
   {
-    c128 acc[CR];
+    c128 acc[RH];
 #pragma unroll
-    for (int i = 0; i < CR; ++i) {
+    for (int i = 0; i < RH; ++i) {
       acc[i] = c128{0.0, 0.0};
-      const int R = rowbase + i;
+      const int R = row_of(half * RH + i);
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (R >= 1 && R < n && jc[c] >= 1 && ok[c]) acc[i] = acc[i] + cmul(a[c][i], vk[c]);
@@ -717,20 +750,21 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     //    partial sum of conj(p_r) v_r, and (owner) row k+1; then the barrier
     if (wid == 0) {
       c128 p{0.0, 0.0};
-      const int R = rowbase + lane;
+      const int R = (lane < CR) ? row_of(lane) : n;
       if (lane < CR && R >= k + 1 && R < n) {
+        const int hh = lane / RH, ii = lane % RH;
         double re = 0.0, im = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) { re += s_red[w][lane]; im += s_red[w][CR + lane]; }
+        for (int w = hh * WH; w < hh * WH + WH; ++w) { re += s_red[w][ii]; im += s_red[w][RH + ii]; }
         p = cmul(tk, c128{re, im});
       }
-      const c128 t = (lane < CR) ? cmulc(p, s_rv[par][lane]) : c128{0.0, 0.0};   // conj(p_r) v_r
+      // rows outside [k+1, n) contribute nothing (and their v entries are not read)
+      const c128 t = (lane < CR && R >= k + 1 && R < n) ? cmulc(p, s_rv[par][lane]) : c128{0.0, 0.0};
       const double sre = wave_sum(t.x), sim = wave_sum(t.y);
-      if (lane < CR && R < n) cb.p[par * kCoopMaxN + R] = p;
-      if (lane == 0) cb.s[par * kCoopMaxP + q] = c128{sre, sim};
-      const int lr = k + 1 - rowbase;
-      if (lr >= 0 && lr < CR)
-        for (int c = k + 1 + lane; c < n; c += 64) cb.row[par * kCoopMaxN + c] = s_rowbuf[c];
+      if (lane < CR && R < n) xstore(&cb.p[par * kCoopMaxN + R], p);
+      if (lane == 0) xstore(&cb.s[par * kCoopMaxP + q], c128{sre, sim});
+      if ((k + 1) % P == q)
+        for (int c = k + 1 + lane; c < n; c += 64) xstore(&cb.row[par * kCoopMaxN + c], s_rowbuf[c]);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (lane == 0) {
         __hip_atomic_fetch_add(cb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -760,11 +794,11 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const bool live = ok[c] && jc[c] >= k + 1;
-      pj[c] = live ? cb.p[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
-      rowj[c] = live ? cb.row[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
+      pj[c] = live ? xload(&cb.p[par * kCoopMaxN + jc[c]]) : c128{0.0, 0.0};
+      rowj[c] = live ? xload(&cb.row[par * kCoopMaxN + jc[c]]) : c128{0.0, 0.0};
     }
-    const c128 pk1 = cb.p[par * kCoopMaxN + k + 1];
-    const c128 sl = (lane < P) ? cb.s[par * kCoopMaxP + lane] : c128{0.0, 0.0};
+    const c128 pk1 = xload(&cb.p[par * kCoopMaxN + k + 1]);
+    const c128 sl = (lane < P) ? xload(&cb.s[par * kCoopMaxP + lane]) : c128{0.0, 0.0};
     const c128 psum{wave_sum(sl.x), wave_sum(sl.y)};
     const c128 al = cmul(c128{-0.5 * tk.x, -0.5 * tk.y}, psum);   // -1/2 tau (p^H v)
     const c128 wk1 = pk1 + cmul(al, c128{1.0, 0.0});              // v_k[k+1] = 1
@@ -780,18 +814,18 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
         const c128 t = cmulc(vk[c], wk1);
         rj = c128{rowj[c].x - wj[c].x - t.x, rowj[c].y + wj[c].y - t.y};
       }
-      if (q == 0 && jc[c] == k + 1) d[k + 1] = rj.x;
+      if (q == 0 && half == 0 && jc[c] == k + 1) d[k + 1] = rj.x;
       // x_j = conj(row'_j), j >= k+2; alpha = x_{k+2}
       x[c] = (jc[c] >= k + 2) ? cconj(rj) : c128{0.0, 0.0};
-      if (ok[c] && jc[c] >= k + 3) xx += x[c].x * x[c].x + x[c].y * x[c].y;
-      if (jc[c] == k + 2) s_alx = x[c];
+      if (half == 0 && ok[c] && jc[c] >= k + 3) xx += x[c].x * x[c].x + x[c].y * x[c].y;
+      if (half == 0 && jc[c] == k + 2) s_alx = x[c];
     }
-    if (q == 0 && k == 0) {
+    if (q == 0 && k == 0 && half == 0) {
       // reflector 0 is stored only now: every workgroup has read column 0
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         if (ok[c] && jc[c] >= 1) A[jc[c]] = vk[c];
-      if (tid == 0) { d[0] = cconj(a[0][0]).x; e[0] = beta0; tau[0] = tk; }
+      if (tid == 0) { d[0] = A[0].x; e[0] = beta0; tau[0] = tk; }
     }
     put_own(s_rw, wj);
     if (k + 1 > n - 2) break;
@@ -806,32 +840,33 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       vk1[c] = (jc[c] == k + 2) ? c128{1.0, 0.0} : (jc[c] > k + 2 && ok[c] ? cmul(x[c], h.scale) : c128{0.0, 0.0});
-      if (q == 0 && ok[c] && jc[c] >= k + 2) A[(size_t)(k + 1) * ld + jc[c]] = vk1[c];
-      if (q == 0 && jc[c] == k + 2) { e[k + 1] = h.beta; tau[k + 1] = h.tau; }
+      if (q == 0 && half == 0 && ok[c] && jc[c] >= k + 2) A[(size_t)(k + 1) * ld + jc[c]] = vk1[c];
+      if (q == 0 && half == 0 && jc[c] == k + 2) { e[k + 1] = h.beta; tau[k + 1] = h.tau; }
     }
     put_own(s_rv[par ^ 1], vk1);
     __syncthreads();
     // 5. B -= v w^H + w v^H on rows and columns >= k+2, and y = B v_{k+1};
     //    the owner of row k+2 keeps it for the next publication
     {
-      c128 acc[CR];
+      c128 acc[RH];
 #pragma unroll
-      for (int i = 0; i < CR; ++i) acc[i] = c128{0.0, 0.0};
-      if (rowbase + CR > k + 2) {
+      for (int i = 0; i < RH; ++i) acc[i] = c128{0.0, 0.0};
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-          // columns of this wave: [64 wid + CT c, + 64)
-          if (64 * wid + CT * c + 63 < k + 2 || 64 * wid + CT * c >= n) continue;
-          if (!(ok[c] && jc[c] >= k + 2)) continue;
-          const c128 cw = cconj(wj[c]), cv = cconj(vk[c]);
+      for (int c = 0; c < NC; ++c) {
+        // columns of this wave: [64 (wid % WH) + CB c, + 64)
+        const int cbase = 64 * (wid % WH) + CB * c;
+        if (cbase + 63 < k + 2 || cbase >= n) continue;
+        if (!(ok[c] && jc[c] >= k + 2)) continue;
+        const c128 cw = cconj(wj[c]), cv = cconj(vk[c]);
 #pragma unroll
-          for (int i = 0; i < CR; ++i) {
-            if (rowbase + i >= k + 2 && rowbase + i < n) {
-              const c128 u1 = cmul(s_rv[par][i], cw), u2 = cmul(s_rw[i], cv);
-              a[c][i] = c128{a[c][i].x - u1.x - u2.x, a[c][i].y - u1.y - u2.y};
-              acc[i] = acc[i] + cmul(a[c][i], vk1[c]);
-              if (rowbase + i == k + 2) s_rowbuf[jc[c]] = a[c][i];
-            }
+        for (int i = 0; i < RH; ++i) {
+          const int li = half * RH + i;
+          const int R = row_of(li);
+          if (R >= k + 2 && R < n) {
+            const c128 u1 = cmul(s_rv[par][li], cw), u2 = cmul(s_rw[li], cv);
+            a[c][i] = c128{a[c][i].x - u1.x - u2.x, a[c][i].y - u1.y - u2.y};
+            acc[i] = acc[i] + cmul(a[c][i], vk1[c]);
+            if (R == k + 2) s_rowbuf[jc[c]] = a[c][i];
           }
         }
       }
@@ -1292,7 +1327,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
       const CoopBuf cb = coop_buf(hw);
       const int P = ceil_div(n, CR);
       k_coop_reset<<<1, 64, 0, st>>>(cb);
-      if (n <= CT) k_tridiag_coop<1><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      if (n <= CB) k_tridiag_coop<1><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
       else k_tridiag_coop<2><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
     } else if (n <= kPanelMinN) {
       k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau,

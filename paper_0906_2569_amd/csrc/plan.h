@@ -34,6 +34,7 @@ struct DavWork;  // Davidson workspace (davidson.hip)
 
 struct pw_plan_s {
   pw_ctx ctx = nullptr;
+  int device = 0;           // HIP device of the plan (kept here: the plan never reads ctx after creation)
   pw_plan_opts opts{};
   int npw = 0, n1 = 0, n2 = 0, n3 = 0;
   long N = 0;

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -147,11 +148,20 @@ class Context:
     def __init__(self, device: int = 0):
         self.lib = load()
         self.h = C.c_void_p()
+        self._children = weakref.WeakSet()
         _check(self.lib.pw_ctx_create(device, C.byref(self.h)))
         self.device = device
 
+    def _adopt(self, obj):
+        """Track a plan or server of this context: they are closed before it."""
+        self._children.add(obj)
+
     def close(self):
         if self.h:
+            # plans and servers hold the context; close them first (a garbage
+            # cycle may finalize the context before them)
+            for obj in list(self._children):
+                obj.close()
             self.lib.pw_ctx_destroy(self.h)
             self.h = C.c_void_p()
 
@@ -274,6 +284,7 @@ class Plan:
         self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max))
         self.h = C.c_void_p()
         _check(self.lib.pw_plan_create(ctx.h, C.byref(s), C.byref(self.opts), C.byref(self.h)))
+        ctx._adopt(self)
         del keep
         self.npw = int(s.npw)
         self.precision = precision
@@ -340,8 +351,9 @@ class Server:
         self.lib.pw_server_opts_default(C.byref(o))
         o.nworkers, o.mem_budget, o.precision = int(nworkers), int(mem_budget), int(precision)
         self.h = C.c_void_p()
-        _check(self.lib.pw_server_create(ctx.h, C.byref(o), C.byref(self.h)))
         self._keep = {}
+        _check(self.lib.pw_server_create(ctx.h, C.byref(o), C.byref(self.h)))
+        ctx._adopt(self)
 
     def clock(self) -> float:
         return float(self.lib.pw_server_clock(self.h))

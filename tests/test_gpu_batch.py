@@ -110,3 +110,31 @@ def test_batched_not_converged_status(ctx, batch):
     for p, e in zip(ps, eigs):
         w, _ = oracle.eigh_lowest(oracle.dense_h_of(p), p.nb)
         assert np.all(e.cpu().numpy() >= w - 1e-10)   # Ritz values bound the eigenvalues from above
+
+
+def test_concurrent_cooperative_eigensolver(ctx):
+    # reduced problems of 64..512 rows use the multi-workgroup
+    # tridiagonalization; several of them running at once (other kernels
+    # sharing the compute units) must give the same results as one at a time
+    from paper_0906_2569_amd import pwdft
+    ps = [pwgen.serving_request(i, ecut_ry=12.0, max_atoms=24, min_atoms=8) for i in range(1, 5)]
+    assert all(2 * p.nb >= 64 for p in ps)
+    opts = pwdft.default_opts(ndim=2)
+    plans = [pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=2) for p in ps]
+    try:
+        alone = []
+        for pl, p in zip(plans, ps):
+            x = torch.from_numpy(p.psi0).cuda()
+            st, e, _, _ = pl.davidson(x, opts=opts)
+            torch.cuda.synchronize()
+            assert st == 0
+            alone.append(e.cpu().numpy())
+        for _ in range(2):
+            xs = [torch.from_numpy(p.psi0).cuda() for p in ps]
+            st, sts, eigs, res, stats = pwdft.davidson_batched(ctx, plans, xs, opts=opts, nworkers=4)
+            assert st == 0 and all(s == 0 for s in sts)
+            for e, ea in zip(eigs, alone):
+                np.testing.assert_allclose(e.cpu().numpy(), ea, atol=1e-10, rtol=0)
+    finally:
+        for pl in plans:
+            pl.close()

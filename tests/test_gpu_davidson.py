@@ -27,13 +27,14 @@ def _solve(ctx, p, psi0=None, precision=0, ndim=4, **opts):
     psi0 = p.psi0 if psi0 is None else psi0
     nb = psi0.shape[0]
     plan = pwdft.Plan(ctx, p, precision=precision, nb_max=nb, ndim_max=max(ndim, 2))
-    x = torch.from_numpy(np.ascontiguousarray(psi0)).cuda()
-    o = pwdft.default_opts(ndim=ndim, **opts)
-    st, eig, resid, stats = plan.davidson(x, opts=o)
-    torch.cuda.synchronize()
-    out = (st, eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy(), stats.asdict())
-    plan.close()
-    return out
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(psi0)).cuda()
+        o = pwdft.default_opts(ndim=ndim, **opts)
+        st, eig, resid, stats = plan.davidson(x, opts=o)
+        torch.cuda.synchronize()
+        return st, eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy(), stats.asdict()
+    finally:
+        plan.close()
 
 
 @pytest.mark.parametrize("ndim", [2, 4])

@@ -33,18 +33,20 @@ def _rel_err(got, ref):
 def _hpsi(ctx, p, psi, prec=0, nb_max=None, ld=None):
     from paper_0906_2569_amd import pwdft
     plan = pwdft.Plan(ctx, p, precision=max(prec, 0), nb_max=nb_max or max(psi.shape[0], 1), ndim_max=0)
-    npw = p.npw
-    ld = ld or npw
-    x = torch.zeros((psi.shape[0], ld), dtype=torch.complex128, device="cuda")
-    x[:, :npw] = _dev(psi)
-    y = torch.full_like(x, complex(float("nan"), 0.0))
-    plan.hpsi(x, y, prec=prec)
-    torch.cuda.synchronize()
-    out = y[:, :npw].cpu().numpy()
-    if ld > npw:   # padding untouched
-        assert torch.isnan(y[:, npw:].real).all()
-    plan.close()
-    return out
+    try:
+        npw = p.npw
+        ld = ld or npw
+        x = torch.zeros((psi.shape[0], ld), dtype=torch.complex128, device="cuda")
+        x[:, :npw] = _dev(psi)
+        y = torch.full_like(x, complex(float("nan"), 0.0))
+        plan.hpsi(x, y, prec=prec)
+        torch.cuda.synchronize()
+        out = y[:, :npw].cpu().numpy()
+        if ld > npw:   # padding untouched
+            assert torch.isnan(y[:, npw:].real).all()
+        return out
+    finally:
+        plan.close()
 
 
 def test_free_electron_kinetic_only(ctx):

@@ -170,6 +170,10 @@ pw_status hpsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128*
  * (stream synchronization).  Returns PW_OK, PW_ENOTCONV (max_iter reached;
  * outputs valid), PW_EBREAKDOWN, PW_ENAN, PW_EINVAL, PW_EDEVICE.
  * No allocation; needs a plan with nb_max >= nb and ndim_max >= opts->ndim.
+ * Reduced problems of 64 to 2048 rows are tridiagonalized by ceil(n / 16)
+ * workgroups that must be resident together; run concurrent solves through
+ * davidson_solve_batched or the server, which bound how many of them spin
+ * at once (a launch that cannot become resident ends with PW_EDEVICE).
  */
 pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, double* eig,
                          double* resid, const pw_david_opts* opts, pw_david_stats* stats,
@@ -193,7 +197,8 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
  * is item i's own return code.  Returns the first hard error (with the
  * item's message), else PW_ENOTCONV if any item did not converge, else PW_OK.
  * opts->history must be NULL.  Concurrent solves use the cooperative
- * reduced-eigensolver kernels only while nworkers x ceil(ndim nb / 16) <= 128.
+ * reduced-eigensolver kernels only while nworkers x ceil(ndim nb / 16) <= 128
+ * (the server applies the same rule to its workers).
  * One batched call per context at a time.
  */
 pw_status hpsi_apply_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, pw_precision prec,

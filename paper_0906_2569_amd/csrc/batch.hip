@@ -20,10 +20,6 @@
 namespace {
 
 constexpr int kMaxWorkers = 32;
-// workgroups the cooperative tridiagonalization may keep spinning at once:
-// concurrent solves use it only while (workers x its workgroups) stays below
-// this share of the device's 256 compute units
-constexpr int kCoopWgBudget = 128;
 
 pw_status ensure_pool(pw_ctx ctx, int nw) {
   std::lock_guard<std::mutex> l(ctx->mu);
@@ -137,7 +133,7 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
   PW_TRY(fork_from(ctx, caller, nw));
 
   // cooperative kernels only while every concurrently spinning launch fits
-  const bool coop = nw == 1 || nw * pmax <= kCoopWgBudget;
+  const bool coop = nw == 1 || nw * pmax <= pw::kCoopWgBudget;
   std::vector<char> prev(n);
   for (int i = 0; i < n; ++i) prev[i] = pw::dav_set_coop(plans[i], coop && pw::dav_get_coop(plans[i]));
 

@@ -17,6 +17,7 @@ struct HeigWork {
   double* gamma = nullptr; // max column norm of the last eigenvector block C
   c128 *PV = nullptr, *PW = nullptr;   // tridiagonalization panel vectors (conjugated, row-major)
   void* coop = nullptr;    // exchange buffers of the cooperative tridiagonalization
+  int* cflags = nullptr;   // blocked Cholesky: [0] = not positive definite
   bool coop_ok = true;     // cooperative (multi-workgroup) kernels allowed: every workgroup of a
                            // launch must be resident at once, so callers that run several
                            // solves concurrently on one device switch them off

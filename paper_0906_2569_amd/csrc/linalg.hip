@@ -138,6 +138,95 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
   }
 }
 
+// Blocked form of the same factorization for large n (right-looking): a
+// workgroup factors a panel of kChPanel columns with the rule above (only
+// the panel's own columns are updated), the trailing matrix then receives
+// the panel's rank-kChPanel update as one MFMA product
+//   L22 -= L21 L21^H   (zgemm with the conjugate transpose PT of L21),
+// and a last kernel sets info and clears the strict upper triangle.
+// flags[0] = not positive definite (also the guard that skips the products).
+constexpr int kChPanel = 32;
+constexpr int kChBlockedMinN = 192;
+
+__global__ void k_chol_init(int n, const c128* __restrict__ L, int ld, double* __restrict__ diag0,
+                            int* __restrict__ flags) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    diag0[i] = L[(size_t)i * ld + i].x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
+}
+
+__global__ void __launch_bounds__(NTL) k_chol_panel(int n, int j0, int bb, double drop_tol, c128* __restrict__ L,
+                                                    int ld, const double* __restrict__ diag0,
+                                                    int* __restrict__ drop, int* __restrict__ flags,
+                                                    c128* __restrict__ PT) {
+  if (flags[0] != 0) return;
+  extern __shared__ __align__(16) char smem_raw[];
+  c128* col = reinterpret_cast<c128*>(smem_raw);   // [n]
+  __shared__ double s_r;
+  __shared__ int s_keep, s_bad;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  const int jend = j0 + bb;
+  for (int j = j0; j < jend; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = L[(size_t)j * ld + j].x;
+      if (!isfinite(d) || !(diag0[j] > 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
+      s_keep = (d > drop_tol * diag0[j]) ? 1 : 0;
+      if (s_keep) {
+        s_r = sqrt(d);
+        L[(size_t)j * ld + j] = c128{s_r, 0.0};
+      } else {
+        L[(size_t)j * ld + j] = c128{1.0, 0.0};
+      }
+      drop[j] = 1 - s_keep;
+      if (s_bad) flags[0] = 1;
+    }
+    __syncthreads();
+    if (s_bad) return;
+    const int m = n - j - 1;
+    if (!s_keep) {
+      for (int i = threadIdx.x; i < m; i += blockDim.x) L[(size_t)j * ld + j + 1 + i] = c128{0.0, 0.0};
+      __syncthreads();
+      continue;
+    }
+    const double inv = 1.0 / s_r;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      c128 v = L[(size_t)j * ld + j + 1 + i];
+      v = c128{v.x * inv, v.y * inv};
+      L[(size_t)j * ld + j + 1 + i] = v;
+      col[i] = v;
+    }
+    __syncthreads();
+    // rank-1 update of the panel's remaining columns j+1 .. jend-1 (rows >= column)
+    const int pc = jend - j - 1;
+    for (int idx = threadIdx.x; idx < m * pc; idx += blockDim.x) {
+      const int ii = idx % m, kk = idx / m;
+      if (ii >= kk) {
+        c128* a = L + (size_t)(j + 1 + kk) * ld + j + 1 + ii;
+        const c128 u = cmulc(col[kk], col[ii]);   // col[ii] conj(col[kk])
+        *a = c128{a->x - u.x, a->y - u.y};
+      }
+    }
+    __syncthreads();
+  }
+  // PT[r * kChPanel + t] = conj(L[jend + r][j0 + t]): the panel below its diagonal block
+  const int mt = n - jend;
+  for (int idx = threadIdx.x; idx < mt * bb; idx += blockDim.x) {
+    const int r = idx % mt, t = idx / mt;
+    PT[(size_t)r * kChPanel + t] = cconj(L[(size_t)(j0 + t) * ld + jend + r]);
+  }
+}
+
+__global__ void k_chol_finish(int n, c128* __restrict__ L, int ld, const int* __restrict__ flags,
+                              int* __restrict__ info) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *info = flags[0] ? 1 : 0;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < (size_t)n * n;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx % n), k = (int)(idx / n);
+    if (i < k) L[(size_t)k * ld + i] = c128{0.0, 0.0};
+  }
+}
+
 // info |= fewer than nev directions kept in [0, n)
 __global__ void k_rank_check(int n, int nev, const int* __restrict__ drop, int* __restrict__ info) {
   __shared__ int cnt;
@@ -478,7 +567,7 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 }
 
 // ---------------------------------------------------------------------------
-// Cooperative Householder tridiagonalization for 64 <= n <= 512: P =
+// Cooperative Householder tridiagonalization for 64 <= n <= 2048: P =
 // ceil(n / CR) workgroups, workgroup q holding CR rows of the
 // Hermitian matrix B (row r = conj of column r of A) in registers.  Rows are
 // dealt cyclically (row r to workgroup r mod P), so every workgroup keeps
@@ -503,7 +592,7 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 constexpr int CR = 16;      // rows per workgroup
 constexpr int CT = 512;     // threads per workgroup (two waves per SIMD)
 constexpr int CB = 256;     // columns covered by one pass of the threads
-constexpr int kCoopMinN = 64, kCoopMaxN = 512;
+constexpr int kCoopMinN = 64, kCoopMaxN = 2048;
 constexpr int kCoopMaxP = kCoopMaxN / CR;
 constexpr long kCoopSpin = 1l << 22;   // polls of a barrier before giving up
 
@@ -798,7 +887,12 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
       rowj[c] = live ? xload(&cb.row[par * kCoopMaxN + jc[c]]) : c128{0.0, 0.0};
     }
     const c128 pk1 = xload(&cb.p[par * kCoopMaxN + k + 1]);
-    const c128 sl = (lane < P) ? xload(&cb.s[par * kCoopMaxP + lane]) : c128{0.0, 0.0};
+    c128 sl{0.0, 0.0};   // partial sums of workgroups lane, lane + 64, ... (fixed order)
+    for (int w = lane; w < P; w += 64) {
+      const c128 t = xload(&cb.s[par * kCoopMaxP + w]);
+      sl.x += t.x;
+      sl.y += t.y;
+    }
     const c128 psum{wave_sum(sl.x), wave_sum(sl.y)};
     const c128 al = cmul(c128{-0.5 * tk.x, -0.5 * tk.y}, psum);   // -1/2 tau (p^H v)
     const c128 wk1 = pk1 + cmul(al, c128{1.0, 0.0});              // v_k[k+1] = 1
@@ -1243,7 +1337,7 @@ CoopBuf coop_buf(const pw::HeigWork& hw) {
 size_t pw::heig_work_bytes(int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
   return sizeof(c128) * (5 * n * n + 2 * n + 2 * n * PANEL) + sizeof(double) * (3 * n + n * n + 7 * n * (n + 64)) +
-         sizeof(int) * n + 24 * 256 + coop_bytes();
+         sizeof(int) * n + 25 * 256 + coop_bytes();
 }
 
 pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
@@ -1272,6 +1366,7 @@ pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   hw.PV = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
   hw.PW = reinterpret_cast<c128*>(take(sizeof(c128) * n * PANEL));
   hw.coop = take(coop_bytes());
+  hw.cflags = reinterpret_cast<int*>(take(256));
   return PW_OK;
 }
 
@@ -1301,7 +1396,28 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);
-    k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+    if (m < kChBlockedMinN) {
+      k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+    } else {
+      double* diag0 = hw.scratch;   // free until the eigenvector step
+      c128* PT = hw.Y;              // free until X12 is formed
+      k_chol_init<<<std::min(64, ceil_div(m, 256)), 256, 0, st>>>(m, L22, ldw, diag0, hw.cflags);
+      for (int j0 = 0; j0 < m; j0 += kChPanel) {
+        const int bb = std::min(kChPanel, m - j0);
+        k_chol_panel<<<1, NTL, sizeof(c128) * m, st>>>(m, j0, bb, kDropTol, L22, ldw, diag0, hw.drop + n0,
+                                                      hw.cflags, PT);
+        const int mt = m - j0 - bb;
+        if (mt > 0) {
+          // trailing L22 -= L21 L21^H (full square; the upper triangle is cleared at the end)
+          c128* L21 = L22 + (size_t)j0 * ldw + j0 + bb;
+          c128* T22 = L22 + (size_t)(j0 + bb) * ldw + j0 + bb;
+          PW_TRY((pw::zgemm_nn<double, double, double>(mt, mt, bb, -1.0, L21, ldw, PT, kChPanel, 1.0, T22, ldw,
+                                                       st, hw.cflags)));
+        }
+      }
+      k_chol_finish<<<std::min(1024, ceil_div((size_t)m * m, 256)), 256, 0, st>>>(m, L22, ldw, hw.cflags,
+                                                                                hw.info);
+    }
   }
   k_rank_check<<<1, 256, 0, st>>>(n, nev, hw.drop, hw.info);
   {
@@ -1328,7 +1444,9 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
       const int P = ceil_div(n, CR);
       k_coop_reset<<<1, 64, 0, st>>>(cb);
       if (n <= CB) k_tridiag_coop<1><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
-      else k_tridiag_coop<2><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 2 * CB) k_tridiag_coop<2><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 4 * CB) k_tridiag_coop<4><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else k_tridiag_coop<8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
     } else if (n <= kPanelMinN) {
       k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau,
                                                                           hw.info);

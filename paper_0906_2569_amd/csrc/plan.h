@@ -116,6 +116,10 @@ pw_status dav_alloc(pw_plan p);
 // allow or forbid the cooperative (multi-workgroup) kernels of the plan's
 // reduced eigensolver; returns the previous setting
 bool dav_set_coop(pw_plan p, bool ok);
+// workgroups that cooperative launches of concurrent solves may keep
+// spinning at once (half of the device's 256 compute units): concurrent
+// solves use them only while workers x ceil(ndim nb / 16) stays within it
+constexpr int kCoopWgBudget = 128;
 bool dav_get_coop(pw_plan p);
 // destroy the context's worker streams (pw_ctx_destroy)
 void ctx_release_pool(pw_ctx ctx);

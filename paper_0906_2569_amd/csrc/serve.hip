@@ -67,6 +67,10 @@ struct pw_server_s {
       pw_plan plan = nullptr;
       pw_status st = pw_plan_create(ctx, &r->prob, &po, &plan);
       if (st == PW_OK) {
+        // cooperative reduced-eigensolver kernels only while every worker's
+        // launch can be resident at once
+        const int pmax = ceil_div((int64_t)r->dopts.ndim * r->nb, 16);
+        (void)pw::dav_set_coop(plan, opts.nworkers * pmax <= pw::kCoopWgBudget);
         st = davidson_solve(plan, r->nb, r->psi, r->ldpsi, r->eig, r->resid, &r->dopts, &r->stats, streams[w]);
         if (st != PW_OK) r->msg = pw_last_error();
         (void)hipStreamSynchronize(streams[w]);

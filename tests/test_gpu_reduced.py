@@ -36,11 +36,11 @@ def _run(ctx, h, s, nev, debug=False):
     return w.cpu().numpy(), c.cpu().numpy().T, (dbg.cpu().numpy() if debug else None)
 
 
-# n from 64 to 512 takes the cooperative (multi-workgroup) tridiagonalization,
+# n from 64 to 2048 takes the cooperative (multi-workgroup) tridiagonalization,
 # smaller n the single-workgroup one, larger n the panel form
 @pytest.mark.parametrize("n,nev", [(1, 1), (2, 1), (5, 3), (16, 8), (32, 16), (63, 30), (64, 32), (65, 33),
                                    (128, 64), (129, 64), (200, 100), (256, 128), (257, 128), (384, 192),
-                                   (512, 256), (600, 300)])
+                                   (512, 256), (600, 300), (1024, 512), (1500, 700), (2048, 1024), (2100, 64)])
 def test_standard_problem(ctx, n, nev):
     rng = np.random.default_rng(n)
     h = _herm(rng, n)
@@ -56,7 +56,8 @@ def test_standard_problem(ctx, n, nev):
     np.testing.assert_allclose(c.conj().T @ c, np.eye(nev), atol=1e-11)
 
 
-@pytest.mark.parametrize("n,nev", [(8, 4), (48, 24), (256, 128)])
+# n >= 192 factors S in 32-column panels with MFMA trailing updates
+@pytest.mark.parametrize("n,nev", [(8, 4), (48, 24), (191, 90), (192, 96), (256, 128), (700, 350), (1030, 500)])
 def test_generalized_problem(ctx, n, nev):
     rng = np.random.default_rng(100 + n)
     h, s = _herm(rng, n), _spd(rng, n)
@@ -104,6 +105,26 @@ def test_cooperative_degenerate_clusters(ctx):
     np.testing.assert_allclose(w, lam[:64], atol=1e-12 * n)
     np.testing.assert_allclose(c.conj().T @ c, np.eye(64), atol=1e-10)
     assert np.linalg.norm(h @ c - c * w, axis=0).max() <= 1e-11 * n
+
+
+@pytest.mark.parametrize("n", [120, 300])
+def test_dependent_basis_directions_are_dropped(ctx, n):
+    # S of a basis whose last columns repeat earlier ones (to rounding): the
+    # dependent directions are dropped and the spectrum is that of the
+    # independent part
+    rng = np.random.default_rng(n)
+    k = n - 10
+    b = rng.standard_normal((n + 40, k)) + 1j * rng.standard_normal((n + 40, k))
+    b = np.concatenate([b, b[:, :10] * (1 + 1e-14)], axis=1)
+    g = rng.standard_normal((n + 40, n + 40)) + 1j * rng.standard_normal((n + 40, n + 40))
+    g = (g + g.conj().T) / 2
+    h, s_ = b.conj().T @ g @ b, b.conj().T @ b
+    h, s_ = (h + h.conj().T) / 2, (s_ + s_.conj().T) / 2
+    nev = 20
+    w, c, _ = _run(ctx, h, s_, nev)
+    q, _ = np.linalg.qr(b[:, :k])
+    ref = np.linalg.eigvalsh(q.conj().T @ g @ q)[:nev]
+    np.testing.assert_allclose(w, ref, atol=1e-8 * np.abs(ref).max())
 
 
 def test_diagonal_and_not_positive_definite(ctx):

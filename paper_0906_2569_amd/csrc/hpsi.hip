@@ -33,21 +33,35 @@ constexpr int PTHREADS = 256;
 template <typename T>
 __device__ __forceinline__ cpx<T> to_t(c128 v) { return cpx<T>{(T)v.x, (T)v.y}; }
 
+// Workgroup -> (stick chunk, band) of the z passes.  Workgroups go to the 8
+// XCDs round-robin by linear id, so all chunks of one band get ids of one
+// residue mod 8: each band's scattered sphere reads then meet one L2.  The
+// grid has gz * roundup(nb, 8) workgroups; those past the last band exit.
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool z_tile(int gz, int nb, int& chunk, int& band) {
+  const int id = blockIdx.x;
+  const int slot = id / kXcds;
+  band = (slot / gz) * kXcds + id % kXcds;
+  chunk = slot % gz;
+  return band < nb;
+}
+
 // ---------------------------------------------------------------------------
 // pass 1: sphere -> sticks, inverse z transform
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(ZTHREADS)
 k_zinv(SphereMap m, const c128* __restrict__ psi, int ldpsi,
-       cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ twg) {
+       cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ twg, int gz, int nb) {
   extern __shared__ __align__(16) char smem_raw[];
   const int n3 = m.n3;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = tw + n3;
   cpx<T>* B = A + ZSB * n3;
-  const int s0 = blockIdx.x * ZSB;
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  const int s0 = chunk * ZSB;
   const int ns = min(ZSB, m.nst - s0);
-  const int band = blockIdx.y;
   const c128* pb = psi + (size_t)band * ldpsi;
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
   for (int i = threadIdx.x; i < ZSB * n3; i += blockDim.x) B[i] = cpx<T>{T(0), T(0)};
@@ -170,13 +184,14 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   __syncthreads();
   const int q = threadIdx.x & 3, nquads = blockDim.x >> 2;
   const int pb = regfft::quad_block(q);   // block of the transform held after inv_dit
+  const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
   // inverse y transforms of the x columns
   for (int c = threadIdx.x >> 2; c < nxr; c += nquads) {
     cpx<T> x[LS];
     cpx<T>* col = Y + c * YS;
 #pragma unroll
     for (int j = 0; j < LS; ++j) x[j] = col[q + 4 * j];
-    regfft::inv_dit<LS, T>(x, q, tw2);
+    regfft::inv_dit<LS, T>(x, q, ql, tw2);
 #pragma unroll
     for (int k = 0; k < LS; ++k) col[k + LS * pb] = x[k];
   }
@@ -189,11 +204,11 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
       const int hx = hx_of[q + 4 * j];
       x[j] = hx >= 0 ? Y[hx * YS + r] : cpx<T>{T(0), T(0)};
     }
-    regfft::inv_dit<LS, T>(x, q, tw1);
+    regfft::inv_dit<LS, T>(x, q, ql, tw1);
     const T* vrow = vz + (size_t)r * N + LS * pb;
 #pragma unroll
     for (int k = 0; k < LS; ++k) x[k] = x[k] * vrow[k];
-    regfft::fwd_dif<LS, T>(x, q, tw1);
+    regfft::fwd_dif<LS, T>(x, q, ql, tw1);
 #pragma unroll
     for (int j = 0; j < LS; ++j) {
       const int hx = hx_of[q + 4 * j];
@@ -207,7 +222,7 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
     cpx<T>* col = Y + c * YS;
 #pragma unroll
     for (int k = 0; k < LS; ++k) x[k] = col[k + LS * pb];
-    regfft::fwd_dif<LS, T>(x, q, tw2);
+    regfft::fwd_dif<LS, T>(x, q, ql, tw2);
 #pragma unroll
     for (int j = 0; j < LS; ++j) col[q + 4 * j] = x[j];
   }
@@ -264,15 +279,16 @@ template <typename T>
 __global__ void __launch_bounds__(ZTHREADS)
 k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
        const c128* __restrict__ psi, int ldpsi, c128* __restrict__ hpsi, int ldhpsi,
-       const cpx<T>* __restrict__ twg, double inv_n, int accumulate) {
+       const cpx<T>* __restrict__ twg, double inv_n, int accumulate, int gz, int nb) {
   extern __shared__ __align__(16) char smem_raw[];
   const int n3 = m.n3;
   cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* A = tw + n3;
   cpx<T>* B = A + ZSB * n3;
-  const int s0 = blockIdx.x * ZSB;
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  const int s0 = chunk * ZSB;
   const int ns = min(ZSB, m.nst - s0);
-  const int band = blockIdx.y;
   for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
   __syncthreads();
   const cpx<T>* in = sticks + (size_t)band * n3 * m.ldst + s0;
@@ -297,6 +313,125 @@ k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
       r = c128{r.x + o.x, r.y + o.y};
     }
     hb[g] = r;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z passes, register-resident variant for n3 = 4 LS: one quad of lanes per
+// stick holds the whole column in VGPRs (see fft_reg.h); no LDS staging.
+// The (z, stick) -> sphere index map gives every lane its gather and scatter
+// positions directly, zero where the column leaves the sphere.
+// ---------------------------------------------------------------------------
+constexpr int ZRTHREADS = 128;
+constexpr int ZRSTICKS = ZRTHREADS / 4;   // sticks per workgroup
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZRTHREADS)
+k_zinv_reg(SphereMap m, const c128* __restrict__ psi, int ldpsi, cpx<T>* __restrict__ sticks,
+           const cpx<T>* __restrict__ twg, int gz, int nb) {
+  constexpr int N3 = 4 * LS;
+  __shared__ cpx<T> tw[N3];
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const int s = chunk * ZRSTICKS + (threadIdx.x >> 2);
+  if (s >= m.nst) return;   // the whole quad of the stick leaves together
+  const int q = threadIdx.x & 3, nst = m.nst;
+  const c128* pb = psi + (size_t)band * ldpsi;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int j = 0; j < LS; ++j) {
+    const int g = m.zidx[(size_t)(q + 4 * j) * nst + s];
+    x[j] = g >= 0 ? to_t<T>(pb[g]) : cpx<T>{T(0), T(0)};
+  }
+  const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
+  regfft::inv_dit<LS, T>(x, q, ql, tw);
+  const int blk = regfft::quad_block(q);
+  cpx<T>* out = sticks + (size_t)band * N3 * m.ldst + s;
+#pragma unroll
+  for (int k = 0; k < LS; ++k) out[(size_t)(k + LS * blk) * m.ldst] = x[k];
+}
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZRTHREADS)
+k_zfwd_reg(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restrict__ psi, int ldpsi,
+           c128* __restrict__ hpsi, int ldhpsi, const cpx<T>* __restrict__ twg, double inv_n,
+           int accumulate, int gz, int nb) {
+  constexpr int N3 = 4 * LS, XS = N3 + 1;   // padded stick stride of the LDS copy
+  __shared__ cpx<T> tw[N3];
+  __shared__ cpx<T> X[ZRSTICKS * XS];
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const int s0 = chunk * ZRSTICKS, sl = threadIdx.x >> 2, s = s0 + sl;
+  const int q = threadIdx.x & 3;
+  if (s < m.nst) {
+    const int blk = regfft::quad_block(q);
+    const cpx<T>* in = sticks + (size_t)band * N3 * m.ldst + s;
+    cpx<T> x[LS];
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = in[(size_t)(k + LS * blk) * m.ldst];
+    const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
+    regfft::fwd_dif<LS, T>(x, q, ql, tw);
+#pragma unroll
+    for (int j = 0; j < LS; ++j) X[sl * XS + q + 4 * j] = x[j];
+  }
+  __syncthreads();
+  // the chunk's sphere entries in stick order: coalesced index reads
+  const c128* pb = psi + (size_t)band * ldpsi;
+  c128* hb = hpsi + (size_t)band * ldhpsi;
+  const int e0 = m.st_ptr[s0], e1 = m.st_ptr[min(s0 + ZRSTICKS, m.nst)];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int g = m.ent_g[e];
+    const cpx<T> v = X[(m.ent_s[e] - s0) * XS + m.ent_z[e]];
+    const c128 p = pb[g];
+    const double t = m.kin[g];
+    c128 r = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
+    if (accumulate) {   // the projector term is already in hpsi
+      const c128 o = hb[g];
+      r = c128{r.x + o.x, r.y + o.y};
+    }
+    hb[g] = r;
+  }
+}
+
+template <typename T>
+struct ZRegFns {
+  void (*inv)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int) = nullptr;
+  void (*fwd)(SphereMap, const cpx<T>*, const c128*, int, c128*, int, const cpx<T>*, double, int, int, int) = nullptr;
+};
+
+template <typename T, int LS>
+ZRegFns<T> zreg_pair() {
+  ZRegFns<T> f;
+  f.inv = k_zinv_reg<T, LS>;
+  f.fwd = k_zfwd_reg<T, LS>;
+  return f;
+}
+
+// register-resident z passes for n3 = 4 LS (same lengths as the plane pass)
+template <typename T>
+ZRegFns<T> zreg_kernels(int n3) {
+  if (n3 % 4 != 0) return {};
+  const bool f64 = sizeof(T) == 8;
+  switch (n3 / 4) {
+    case 8: return zreg_pair<T, 8>();
+    case 9: return zreg_pair<T, 9>();
+    case 10: return zreg_pair<T, 10>();
+    case 12: return zreg_pair<T, 12>();
+    case 15: return zreg_pair<T, 15>();
+    case 16: return zreg_pair<T, 16>();
+    case 18: return zreg_pair<T, 18>();
+    case 20: return f64 ? ZRegFns<T>{} : zreg_pair<T, 20>();
+    case 24: return f64 ? ZRegFns<T>{} : zreg_pair<T, 24>();
+    case 25: return f64 ? ZRegFns<T>{} : zreg_pair<T, 25>();
+    case 27: return f64 ? ZRegFns<T>{} : zreg_pair<T, 27>();
+    case 30: return f64 ? ZRegFns<T>{} : zreg_pair<T, 30>();
+    case 32: return f64 ? ZRegFns<T>{} : zreg_pair<T, 32>();
+    case 36: return f64 ? ZRegFns<T>{} : zreg_pair<T, 36>();
+    default: return {};
   }
 }
 
@@ -482,6 +617,7 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
   size_t b = 0;
   b += (size_t)pr->npw * (4 * sizeof(int) + 2 * sizeof(double));
   b += (size_t)geo.nst * 3 * sizeof(int) + geo.n1 * sizeof(int);
+  b += (size_t)geo.nst * geo.n3 * sizeof(int);   // (z, stick) -> sphere map
   b += N * (sizeof(double) + (mixed ? sizeof(float) : 0));
   b += (size_t)pr->nbeta * ldb * (sizeof(c128) + (mixed ? sizeof(c64) : 0));
   b += (size_t)pr->nbeta * (2 * sizeof(int) + geo.nhmax * (sizeof(c128) + sizeof(c64)));
@@ -570,6 +706,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
     ent_s[e] = (int)st_hx.size() - 1;
   }
   st_ptr.push_back(npw);
+  std::vector<int> zidx((size_t)n3 * st_hx.size(), -1);
+  for (int e = 0; e < npw; ++e) zidx[(size_t)ent_z[e] * st_hx.size() + ent_s[e]] = ent_g[e];
   std::vector<double> kin(npw);
   for (int g = 0; g < npw; ++g) {
     const double* q = pr->kpg + 3 * g;
@@ -613,6 +751,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(upload(p, &p->ent_z, ent_z));
   PLAN_TRY(upload(p, &p->ent_s, ent_s));
   PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
+  PLAN_TRY(upload(p, &p->zidx, zidx));
   PLAN_TRY(upload(p, &p->kin, kin));
   {
     std::vector<c128> t64;
@@ -734,14 +873,21 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   if (preg && plane_reg_lds_bytes<T>(p->n1, p->nxr) > 64 * 1024) preg = nullptr;
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
+  const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
+  const int gzr = ceil_div(p->nst, ZRSTICKS);
   // algorithmic bytes per band: sphere in/out (complex128) and one write plus
   // one read of the stick columns per transform direction; V(r) once per pass
   const double sphere_b = 16.0 * p->npw, stick_b = (double)sizeof(cpx<T>) * p->n3 * p->nst;
   for (int c0 = 0; c0 < nb; c0 += p->band_chunk) {
     const int nbc = std::min(p->band_chunk, nb - c0);
+    const int nbc8 = ceil_div(nbc, 8) * 8;
+    const int zgrid = gz * nbc8, zrgrid = gzr * nbc8;
     {
       pw::ProfScope ps(pw::PK_ZINV, s, nbc * (sphere_b + stick_b));
-      k_zinv<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3);
+      if (zr.inv)
+        zr.inv<<<zrgrid, ZRTHREADS, 0, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gzr, nbc);
+      else
+        k_zinv<T><<<zgrid, ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gz, nbc);
     }
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
@@ -754,9 +900,14 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
     {
       pw::ProfScope ps(pw::PK_ZFWD, s, nbc * (sphere_b + stick_b));
-      k_zfwd<T><<<dim3(gz, nbc), ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
-                                                     hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
-                                                     1.0 / (double)p->N, accumulate ? 1 : 0);
+      if (zr.fwd)
+        zr.fwd<<<zrgrid, ZRTHREADS, 0, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
+                                            hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
+                                            1.0 / (double)p->N, accumulate ? 1 : 0, gzr, nbc);
+      else
+        k_zfwd<T><<<zgrid, ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
+                                               hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
+                                               1.0 / (double)p->N, accumulate ? 1 : 0, gz, nbc);
     }
   }
   PW_HIP(hipGetLastError());

@@ -26,6 +26,7 @@ struct SphereMap {
   const int* st_hx;    // [nst]     x-column index of stick s
   const int* st_i2;    // [nst]     y grid index (k mod n2) of stick s
   const int* i1_hx;    // [n1]      x-column index at x grid index i1, or -1
+  const int* zidx;     // [n3][nst] sphere index of (z, stick), or -1
   const double* kin;   // [npw]     |k+G|^2 / 2
   FftDesc f1, f2, f3;  // transforms along x, y, z
 };
@@ -46,7 +47,7 @@ struct pw_plan_s {
 
   // maps (device)
   int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
-      *st_i2 = nullptr, *i1_hx = nullptr;
+      *st_i2 = nullptr, *i1_hx = nullptr, *zidx = nullptr;
   double* kin = nullptr;     // [npw]
   double* hdiag = nullptr;   // [npw] exact diagonal of H
   FftDesc f1{}, f2{}, f3{};
@@ -80,7 +81,7 @@ struct pw_plan_s {
     m.npw = npw; m.n1 = n1; m.n2 = n2; m.n3 = n3;
     m.nst = nst; m.nxr = nxr; m.ldst = ldst;
     m.st_ptr = st_ptr; m.ent_g = ent_g; m.ent_z = ent_z; m.ent_s = ent_s;
-    m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.kin = kin;
+    m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.zidx = zidx; m.kin = kin;
     m.f1 = f1; m.f2 = f2; m.f3 = f3;
     return m;
   }

@@ -40,10 +40,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--ndim", type=int, default=2)
+    ap.add_argument("--ndim", type=int, default=None,
+                    help="Davidson basis cap (x nb); default: 4 for the float64 cell solve "
+                         "(fewest reduced solves per solve), 2 otherwise")
     ap.add_argument("--hpsi-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stages", action="store_true",
+                    help="skip the per-stage H.psi measurement (keeps kernel profiles to the timed steps)")
     ap.add_argument("--workload", choices=["cell64", "batch", "serve"], default="cell64",
                     help="cell64: the 64-atom cell (default line); batch: 32 cells x 4 k-points solved "
                          "concurrently vs one at a time in FP64; serve: Poisson request trace through the "
@@ -58,7 +62,10 @@ def parse():
     ap.add_argument("--mode", choices=["solve", "hpsi"], default="solve",
                     help="solve: a step is one Davidson solve; hpsi: a step is one hpsi_apply of the "
                          "128-band block (for kernel profiles of H.psi alone)")
-    return ap.parse_args()
+    args = ap.parse_args()
+    if args.ndim is None:
+        args.ndim = 4 if (args.workload == "cell64" and args.precision == "fp64") else 2
+    return args
 
 
 def roofline(prof, dtype):
@@ -82,6 +89,68 @@ def roofline(prof, dtype):
     out["avg_us"] = avg_s * 1e6
     out["units_per_launch"] = per_launch
     return out
+
+
+FFT_KERNELS = ("k_zinv", "k_plane", "k_zfwd")
+NL_KERNELS = ("calbec_gemm", "add_nl_gemm")
+
+
+def hpsi_stages(ctx, p, plan, psi0, prec, reps):
+    """Per-stage rates of one 128-band H.psi: the transform stage (sphere -> sticks ->
+    planes -> sticks -> sphere) against HBM, the projector products against the
+    matrix cores.  "in_hpsi": the full product, where the projector products run on
+    a side stream beside the transforms; "fft_alone": the same transforms of a plan
+    without projectors (no contention)."""
+    import dataclasses
+    import torch
+    from paper_0906_2569_amd import pwdft
+
+    def measure(pl, pr):
+        x = psi0.clone()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            pl.hpsi(x, y, prec=pr)
+        torch.cuda.synchronize()
+        pwdft.profile_enable(True)
+        for _ in range(reps):
+            pl.hpsi(x, y, prec=pr)
+        torch.cuda.synchronize()
+        prof = pwdft.profile_read()
+        pwdft.profile_enable(False)
+        return prof
+
+    def summarize(prof, pr):
+        out = {}
+        calls = max(prof.get("k_zinv", (0, 0, 0))[0], 1)
+        t_fft = sum(prof[k][1] for k in FFT_KERNELS if k in prof) / calls * 1e-3
+        b_fft = sum(prof[k][2] for k in FFT_KERNELS if k in prof) / calls
+        if t_fft > 0:
+            gbs = b_fft / t_fft / 1e9
+            out["fft"] = {"us_per_hpsi": t_fft * 1e6, "alg_bytes": b_fft, "GB_per_s": gbs,
+                          "hbm_frac": gbs / HBM_PEAK_GBS}
+        ks = [k for k in NL_KERNELS if k in prof and prof[k][0]]
+        if ks:
+            t_nl = sum(prof[k][1] for k in ks) / calls * 1e-3
+            f_nl = sum(prof[k][2] for k in ks) / calls
+            peak = FP64_PEAK_TF if pr == pwdft.PW_FP64 else FP32_MFMA_PEAK_TF
+            tf = f_nl / t_nl / 1e12
+            out["nl_gemms"] = {"us_per_hpsi": t_nl * 1e6, "flops": f_nl, "TFLOP_per_s": tf, "peak": peak,
+                               "mfma_frac": tf / peak}
+        return out
+
+    precs = [pwdft.PW_FP64] + ([pwdft.PW_MIXED] if prec == pwdft.PW_MIXED else [])
+    res = {}
+    q = dataclasses.replace(p, beta=np.zeros((0, p.npw), np.complex128), blk_off=np.zeros(1, np.int32),
+                            dmat=np.zeros(0, np.complex128), tau=np.zeros((0, 3)))
+    bare = pwdft.Plan(ctx, q, precision=prec, nb_max=p.nb, ndim_max=0)
+    try:
+        for pr in precs:
+            key = "fp64" if pr == pwdft.PW_FP64 else "fp32"
+            res[key] = {"in_hpsi": summarize(measure(plan, pr), pr),
+                        "fft_alone": summarize(measure(bare, pr), pr).get("fft")}
+    finally:
+        bare.close()
+    return res
 
 
 def cpu_baseline(p, band_hpsi_per_solve, seconds):
@@ -274,8 +343,8 @@ def bench_serve(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(independent cells / k-points shard one per GPU, see the design notes)", file=sys.stderr)
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(independent cells and k-points would shard one group per GPU)", file=sys.stderr)
         return 2
     if args.workload == "batch":
         return bench_batch(args)
@@ -337,6 +406,7 @@ def main():
     rate_mixed = None
     if prec == pwdft.PW_MIXED:
         rate_mixed = hpsi_rate(pwdft.PW_MIXED)
+    stages = None if args.no_stages else hpsi_stages(ctx, p, plan, psi0, prec, args.hpsi_reps)
 
     dtype = "f64" if prec == pwdft.PW_FP64 else "f64+f32"
     if args.mode == "hpsi":
@@ -369,6 +439,7 @@ def main():
         "eig_min_max_ha": [float(eig.min()), float(eig.max())] if args.mode == "solve" else None,
         "max_resid_ha": float(resid.max()) if args.mode == "solve" else None,
         "roofline": roofline({k: v for k, v in prof.items() if v[0] > 0}, "f64" if prec == 0 else "f32"),
+        "hpsi_stages": stages,
         "kernel_ms": {k: round(v[1], 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1]) if v[0]},
     }
     if not args.no_cpu_baseline and args.mode == "solve":

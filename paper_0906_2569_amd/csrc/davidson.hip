@@ -306,10 +306,10 @@ struct Solver {
   // reduced columns [c0, c1) of H and S over the basis phi[0:c1)
   pw_status project(int c0, int c1) {
     const int npw = p->npw, ldm = W.nbasis;
-    PW_TRY((pw::zgemm_cn<double, double, double>(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld,
-                                                 W.ld, W.hred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes, st)));
-    PW_TRY((pw::zgemm_cn<double, double, double>(c1, c1 - c0, npw, W.phi, W.ld, W.phi + (size_t)c0 * W.ld,
-                                                 W.ld, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes, st)));
+    // phi^H (H phi_new) and phi^H phi_new in one launch
+    PW_TRY(pw::zgemm_cn_pair(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld, W.phi + (size_t)c0 * W.ld,
+                             W.ld, W.hred + (size_t)c0 * ldm, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes,
+                             st));
     const int blocks = std::min(1024, ceil_div((size_t)(c1 - c0) * c1, 256));
     k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.hred, ldm);
     k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.sred, ldm);
@@ -324,10 +324,9 @@ struct Solver {
     PW_TRY(pw::heig_solve(W.hw, nfact, nbase, nb, W.hred, W.sred, ldm, W.eps, W.cvec, ldm, W.part, W.part_bytes,
                           st));
     nfact = nbase;
-    PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.phi, W.ld, W.cvec, ldm, 0.0, W.psi,
-                                                 W.ld, st, W.hw.info)));
-    PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, nbase, 1.0, W.hphi, W.ld, W.cvec, ldm, 0.0,
-                                                 W.hpsi, W.ld, st, W.hw.info)));
+    // psi = phi c and hpsi = (H phi) c in one launch
+    PW_TRY(pw::zgemm_nn_pair(p->npw, nb, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi, W.hpsi, W.ld, st,
+                             W.hw.info));
     return PW_OK;
   }
 

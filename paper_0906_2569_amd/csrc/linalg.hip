@@ -859,10 +859,13 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
         __hip_atomic_fetch_add(cb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // 2. barrier: all P workgroups have published step k
         const unsigned target = (unsigned)P * (unsigned)(k + 1);
+        // one counter load per poll; the failure flag of the other
+        // workgroups is looked at every 256 polls
         long spins = 0;
         for (;;) {
           if (__hip_atomic_load(cb.count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= target) break;
-          if (__hip_atomic_load(cb.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || ++spins > kCoopSpin) {
+          if ((++spins & 255) == 0 &&
+              (__hip_atomic_load(cb.fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u || spins > kCoopSpin)) {
             __hip_atomic_store(cb.fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_fail = 1;
             break;
@@ -937,8 +940,10 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
       if (q == 0 && half == 0 && ok[c] && jc[c] >= k + 2) A[(size_t)(k + 1) * ld + jc[c]] = vk1[c];
       if (q == 0 && half == 0 && jc[c] == k + 2) { e[k + 1] = h.beta; tau[k + 1] = h.tau; }
     }
+    // v_{k+1} on the own rows is read by the update of the next step only
+    // (three barriers later), and this step's update reads the other parity
+    // buffer: no barrier here
     put_own(s_rv[par ^ 1], vk1);
-    __syncthreads();
     // 5. B -= v w^H + w v^H on rows and columns >= k+2, and y = B v_{k+1};
     //    the owner of row k+2 keeps it for the next publication
     {

@@ -111,6 +111,14 @@ pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
                    const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream,
                    const int* guard = nullptr);
 
+// C0 = A^H B0 and C1 = A^H B1 (float64, as zgemm_cn with alpha 1, beta 0) in one launch
+pw_status zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c128* B0, const c128* B1, int ldb,
+                        c128* C0, c128* C1, int ldc, void* part, size_t part_bytes, hipStream_t stream);
+
+// C0 = A0 B and C1 = A1 B (float64, same shapes and leading dimensions) in one launch
+pw_status zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1, int lda, const c128* B, int ldb,
+                        c128* C0, c128* C1, int ldc, hipStream_t stream, const int* guard = nullptr);
+
 size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
 
 pw_status dav_alloc(pw_plan p);

@@ -89,14 +89,18 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, typename Mma<T>::v4 (
 }
 
 // partial[z][n][m] = sum_{k in chunk z} conj(A[m*lda + k]) B[n*ldb + k]
+// gridDim.z = 2 nsplit for two products of one launch: z >= nsplit takes B1
+// and writes the partials after those of the first product
 template <typename T, typename TA, typename TB>
 __global__ void __launch_bounds__(NT)
-k_gemm_cn(int M, int N, int K, int kchunk, const cpx<TA>* __restrict__ A, int lda,
-          const cpx<TB>* __restrict__ B, int ldb, cpx<T>* __restrict__ P) {
+k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict__ A, int lda,
+          const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+  const int zs = (int)blockIdx.z % nsplit;
+  const cpx<TB>* __restrict__ B = (int)blockIdx.z >= nsplit ? B1 : B0;
+  const int kbeg = zs * kchunk, kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   v4 cr[2][2], ci[2][2];
@@ -151,12 +155,16 @@ k_gemm_cn(int M, int N, int K, int kchunk, const cpx<TA>* __restrict__ A, int ld
 }
 
 // C[n*ldc + m] = alpha sum_k A[k*lda + m] B[n*ldb + k] + beta C[n*ldc + m]
+// blockIdx.z selects the product: (A0, C0) or (A1, C1), same B (two products of
+// one launch fill the device better than two launches)
 template <typename T, typename TA, typename TB>
 __global__ void __launch_bounds__(NT)
-k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A, int lda,
-          const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C, int ldc,
-          const int* __restrict__ guard) {
+k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, const cpx<TA>* __restrict__ A1,
+          int lda, const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C0,
+          c128* __restrict__ C1, int ldc, const int* __restrict__ guard) {
   if (guard != nullptr && *guard != 0) return;
+  const cpx<TA>* __restrict__ A = blockIdx.z ? A1 : A0;
+  c128* __restrict__ C = blockIdx.z ? C1 : C0;
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -335,12 +343,41 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   {
     pw::ProfScope ps(pw::PK_GEMM_CN, s, 8.0 * M * N * K);
     k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
-        M, N, K, sp.kchunk, A, lda, B, ldb, P);
+        M, N, K, sp.kchunk, sp.nsplit, A, lda, B, B, ldb, P);
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + 16.0 * M * N);
     k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, sp.nsplit, P, C, ldc, alpha,
                                                                           beta);
+  }
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c128* B0, const c128* B1,
+                            int ldb, c128* C0, c128* C1, int ldc, void* part, size_t part_bytes, hipStream_t s) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  Split sp = choose_split(M, N, K);
+  // half the splits per product: the two products together fill the device
+  const int ns = std::max(1, sp.nsplit / 2);
+  const int kchunk = std::max(BK, ceil_div(ceil_div(K, ns), BK) * BK);
+  const int nsplit = std::max(1, ceil_div(K, kchunk));
+  const size_t need = 2 * (size_t)nsplit * M * N * sizeof(c128);
+  if (K <= 0 || need > part_bytes) {
+    PW_TRY((zgemm_cn<double, double, double>(M, N, K, A, lda, B0, ldb, C0, ldc, part, part_bytes, s)));
+    return zgemm_cn<double, double, double>(M, N, K, A, lda, B1, ldb, C1, ldc, part, part_bytes, s);
+  }
+  c128* P = static_cast<c128*>(part);
+  {
+    pw::ProfScope ps(pw::PK_GEMM_CN, s, 16.0 * M * N * K);
+    k_gemm_cn<double, double, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 2 * nsplit), NT, 0, s>>>(
+        M, N, K, kchunk, nsplit, A, lda, B0, B1, ldb, P);
+  }
+  {
+    pw::ProfScope ps(pw::PK_GEMM_RED, s, 2.0 * ((double)nsplit * M * N * sizeof(c128) + 16.0 * M * N));
+    const int g = std::min(4096, ceil_div((size_t)M * N, 256));
+    k_reduce<double><<<g, 256, 0, s>>>(M, N, nsplit, P, C0, ldc, 1.0, 0.0);
+    k_reduce<double><<<g, 256, 0, s>>>(M, N, nsplit, P + (size_t)nsplit * M * N, C1, ldc, 1.0, 0.0);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -358,7 +395,7 @@ pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* ou
   {
     pw::ProfScope ps(pw::PK_CALBEC, s, 8.0 * M * N * K);
     k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
-        M, N, K, sp.kchunk, beta, p->ldb, psi, ldpsi, P);
+        M, N, K, sp.kchunk, sp.nsplit, beta, p->ldb, psi, psi, ldpsi, P);
   }
   {
     pw::ProfScope ps(pw::PK_CALBEC_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + (double)M * N * sizeof(cpx<T>));
@@ -375,8 +412,18 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
                        const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
-  k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN)), NT, 0, s>>>(M, N, K, alpha, A, lda,
-                                                                            B, ldb, beta, C, ldc, guard);
+  k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 1), NT, 0, s>>>(
+      M, N, K, alpha, A, A, lda, B, ldb, beta, C, C, ldc, guard);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw::zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1, int lda, const c128* B,
+                            int ldb, c128* C0, c128* C1, int ldc, hipStream_t s, const int* guard) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  pw::ProfScope ps(pw::PK_GEMM_NN, s, 16.0 * M * N * K);
+  k_gemm_nn<double, double, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 2), NT, 0, s>>>(
+      M, N, K, 1.0, A0, A1, lda, B, ldb, 0.0, C0, C1, ldc, guard);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

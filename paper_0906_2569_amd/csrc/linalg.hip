@@ -1101,6 +1101,8 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
 // workgroup when they fit, else the global scratch (element r of thread t at
 // [r * S + t], so that neighbouring threads touch neighbouring addresses).
 // ---------------------------------------------------------------------------
+constexpr int IC = 8;   // recurrence steps whose operands are loaded ahead
+
 struct InvitView {
   double *D, *DL, *DU, *DU2, *X, *Y;
   unsigned char* PV;
@@ -1131,32 +1133,44 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
   unsigned char* __restrict__ PV = v.PV;
   for (int i = i0; i < i1; ++i) {
     const double lam = w[i];
-    // factor T - lam I with partial pivoting; the running pivot stays in a register
+    // factor T - lam I with partial pivoting; the running pivot stays in a
+    // register.  The tridiagonal is read IC steps ahead (independent of the
+    // recurrence), and the multipliers and reciprocal pivots use the hardware
+    // reciprocal refined by one Newton step instead of an IEEE division.
     double dcur = d[0] - lam;
     double du_next = (n > 1) ? e[0] : 0.0;   // DU[r] before row r's update
-#pragma unroll 2
-    for (int r = 0; r < n - 1; ++r) {
-      const double er = e[r];
-      const double dnext = d[r + 1] - lam;
-      const double du_after = (r < n - 2) ? e[r + 1] : 0.0;
+    auto fstep = [&](int r, double er, double dnext, double du_after) {
       double dr, dlr, dur, du2r, dn, dun;
       unsigned char piv;
       if (fabs(dcur) >= fabs(er)) {
         const double dd = (dcur == 0.0) ? tiny : dcur;
-        const double f = er / dd;
+        const double f = er * fast_rcp(dd);
         dr = dd; dlr = f; dur = du_next; du2r = 0.0; dn = dnext - f * du_next; dun = du_after; piv = 0;
       } else {
-        const double f = dcur / er;
+        const double f = dcur * fast_rcp(er);
         dr = er; dlr = f; dur = dnext; dn = du_next - f * dnext;
         du2r = du_after; dun = -f * du_after; piv = 1;
       }
-      D[r * S] = 1.0 / ((fabs(dr) < tiny) ? ((dr >= 0.0) ? tiny : -tiny) : dr);
+      D[r * S] = fast_rcp((fabs(dr) < tiny) ? ((dr >= 0.0) ? tiny : -tiny) : dr);
       DL[r * S] = dlr; DU[r * S] = dur; DU2[r * S] = du2r;
       PV[r * S] = piv;
       dcur = dn;
       du_next = dun;
+    };
+    int r0 = 0;
+    for (; r0 + IC < n - 1; r0 += IC) {   // full chunks: rows r0 .. r0+IC-1, all < n-2
+      double er_[IC], dn_[IC], ea_[IC];
+#pragma unroll
+      for (int u = 0; u < IC; ++u) {
+        er_[u] = e[r0 + u];
+        dn_[u] = d[r0 + u + 1];
+        ea_[u] = e[r0 + u + 1];
+      }
+#pragma unroll
+      for (int u = 0; u < IC; ++u) fstep(r0 + u, er_[u], dn_[u] - lam, ea_[u]);
     }
-    D[(n - 1) * S] = 1.0 / ((fabs(dcur) < tiny) ? ((dcur >= 0.0) ? tiny : -tiny) : dcur);
+    for (int r = r0; r < n - 1; ++r) fstep(r, e[r], d[r + 1] - lam, (r < n - 2) ? e[r + 1] : 0.0);
+    D[(n - 1) * S] = fast_rcp((fabs(dcur) < tiny) ? ((dcur >= 0.0) ? tiny : -tiny) : dcur);
     // generic start vector: an integer hash of (r, i) mapped to [0.5, 1.5)
     for (int r = 0; r < n; ++r) {
       unsigned h = (unsigned)r * 2654435761u ^ ((unsigned)i * 2246822519u + 0x9e3779b9u);
@@ -1166,29 +1180,56 @@ __device__ void invit_cluster(int n, const double* __restrict__ d, const double*
       X[r * S] = 0.5 + (double)(h & 0xffffu) * (1.0 / 65536.0);
     }
     for (int it = 0; it < 3; ++it) {
-      // forward substitution with the row interchanges: X -> Y
+      // forward substitution with the row interchanges: X -> Y (operands of
+      // IC steps loaded ahead of the recurrence)
       double xr = X[0];
-#pragma unroll 4
-      for (int r = 0; r < n - 1; ++r) {
-        const double xn = X[(r + 1) * S];
-        if (PV[r * S]) {
+      auto sstep = [&](int r, double xn, double dl, unsigned char pv) {
+        if (pv) {
           Y[r * S] = xn;
-          xr = xr - DL[r * S] * xn;
+          xr = xr - dl * xn;
         } else {
           Y[r * S] = xr;
-          xr = xn - DL[r * S] * xr;
+          xr = xn - dl * xr;
         }
+      };
+      int q0 = 0;
+      for (; q0 + IC <= n - 1; q0 += IC) {
+        double xn_[IC], dl_[IC];
+        unsigned char pv_[IC];
+#pragma unroll
+        for (int u = 0; u < IC; ++u) {
+          xn_[u] = X[(q0 + u + 1) * S];
+          dl_[u] = DL[(q0 + u) * S];
+          pv_[u] = PV[(q0 + u) * S];
+        }
+#pragma unroll
+        for (int u = 0; u < IC; ++u) sstep(q0 + u, xn_[u], dl_[u], pv_[u]);
       }
+      for (int r = q0; r < n - 1; ++r) sstep(r, X[(r + 1) * S], DL[r * S], PV[r * S]);
       // back substitution with the upper factor: Y -> X
       double x2 = 0.0, x1 = xr * D[(n - 1) * S];
       X[(n - 1) * S] = x1;
-#pragma unroll 4
-      for (int r = n - 2; r >= 0; --r) {
-        const double xv = (Y[r * S] - DU[r * S] * x1 - DU2[r * S] * x2) * D[r * S];
+      auto bstep = [&](int r, double yv, double du, double du2, double dd) {
+        const double xv = (yv - du * x1 - du2 * x2) * dd;
         X[r * S] = xv;
         x2 = x1;
         x1 = xv;
+      };
+      int p0 = n - 2;
+      for (; p0 - IC + 1 >= 0; p0 -= IC) {
+        double y_[IC], du_[IC], du2_[IC], dd_[IC];
+#pragma unroll
+        for (int u = 0; u < IC; ++u) {
+          const int r = p0 - u;
+          y_[u] = Y[r * S];
+          du_[u] = DU[r * S];
+          du2_[u] = DU2[r * S];
+          dd_[u] = D[r * S];
+        }
+#pragma unroll
+        for (int u = 0; u < IC; ++u) bstep(p0 - u, y_[u], du_[u], du2_[u], dd_[u]);
       }
+      for (int r = p0; r >= 0; --r) bstep(r, Y[r * S], DU[r * S], DU2[r * S], D[r * S]);
       for (int j = i0; j < i; ++j) {
         const double* zj = Z + (size_t)j * ldz;
         double dot = 0.0;

@@ -41,8 +41,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--ndim", type=int, default=None,
-                    help="Davidson basis cap (x nb); default: 4 for the float64 cell solve "
-                         "(fewest reduced solves per solve), 2 otherwise")
+                    help="Davidson basis cap (x nb); default: 3 for the float64 cell solve, 2 otherwise "
+                         "(the fastest settings measured for the bench cell)")
     ap.add_argument("--hpsi-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -64,7 +64,7 @@ def parse():
                          "128-band block (for kernel profiles of H.psi alone)")
     args = ap.parse_args()
     if args.ndim is None:
-        args.ndim = 4 if (args.workload == "cell64" and args.precision == "fp64") else 2
+        args.ndim = 3 if (args.workload == "cell64" and args.precision == "fp64") else 2
     return args
 
 

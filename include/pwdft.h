@@ -101,11 +101,15 @@ typedef struct {
                                 x = h_diag(G) - eps_i (default 0.2)                              */
   double  ladder_switch;     /* mixed only: float32 H.psi until every ||g_i|| <= ladder_switch (or,
                                 once below 100*ladder_switch, the largest stops halving for 12
-                                iterations), then float64 (default 1e-5)                          */
+                                iterations), then float64 (default 3e-4)                          */
   double* history;           /* [host] optional (NULL by default): for iteration t < max_iter,
                                 history[2t] = max_i ||g_i|| and history[2t+1] = the largest column
                                 norm of the Ritz rotation that produced the block (its error
                                 growth); 2*max_iter entries, entries past stats.iters untouched */
+  int32_t lock;              /* 1 (default): when the basis collapses in the float64 stage, bands
+                                already converged are locked: kept fixed, projected out of every
+                                later correction and left out of the reduced problems, which then
+                                only hold the unconverged bands; 0: every band stays in the basis */
 } pw_david_opts;
 
 typedef struct {

@@ -45,6 +45,7 @@ extern "C" void pw_david_opts_default(pw_david_opts* o) {
   o->tol_resid = 1e-6;
   o->tol_deig = 5e-9;
   o->precond_floor = 0.2;
-  o->ladder_switch = 1e-5;
+  o->ladder_switch = 3e-4;
   o->history = nullptr;
+  o->lock = 1;
 }

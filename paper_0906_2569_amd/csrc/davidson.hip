@@ -40,6 +40,9 @@ struct DavWork {
   c128 *hred = nullptr, *sred = nullptr, *cvec = nullptr;
   double *eps = nullptr, *eps_prev = nullptr, *rn = nullptr;
   int* idx = nullptr;
+  int* perm = nullptr;       // [nb] band order (locking, final sort)
+  c128* lockc = nullptr;     // [nb][nb] overlaps of locked bands with new corrections
+  double* etmp = nullptr;    // [2 nb] staging of permuted values
   DavFlags* flags = nullptr;     // device
   DavFlags* hflags = nullptr;    // pinned host
   void* part = nullptr;
@@ -136,6 +139,51 @@ __global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict_
   for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
 }
 
+// out_t = hpsi_b - eps_b psi_b, b = idx[t] (residual vectors, for projection before preconditioning)
+__global__ void __launch_bounds__(256) k_residvec(int npw, const int* __restrict__ idx,
+                                                  const c128* __restrict__ psi, const c128* __restrict__ hpsi,
+                                                  int ld, const double* __restrict__ eps, c128* __restrict__ out,
+                                                  int ldo) {
+  const int b = idx[blockIdx.x];
+  const double e = eps[b];
+  const c128* x = psi + (size_t)b * ld;
+  const c128* hx = hpsi + (size_t)b * ld;
+  c128* o = out + (size_t)blockIdx.x * ldo;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{hx[g].x - e * x[g].x, hx[g].y - e * x[g].y};
+}
+
+// column t of x <- x_t / smax(h_diag - eps_b, floor), b = idx[t], normalized (as k_correct)
+__global__ void __launch_bounds__(256) k_precond(int npw, const int* __restrict__ idx,
+                                                 const double* __restrict__ eps, const double* __restrict__ hdiag,
+                                                 double floor_, c128* __restrict__ x, int ldx) {
+  __shared__ double red[4];
+  const double e = eps[idx[blockIdx.x]];
+  c128* o = x + (size_t)blockIdx.x * ldx;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    const double dg = hdiag[g] - e;
+    const double den = 0.5 * (dg + floor_ + sqrt((dg - floor_) * (dg - floor_) + floor_ * floor_));
+    const double inv = 1.0 / den;
+    const c128 r = c128{o[g].x * inv, o[g].y * inv};
+    o[g] = r;
+    s += r.x * r.x + r.y * r.y;
+  }
+  s = block_sum256(s, red);
+  const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
+}
+
+// columns of x scaled to unit norm (a zero column stays zero)
+__global__ void __launch_bounds__(256) k_normalize(int npw, c128* __restrict__ x, int ld) {
+  __shared__ double red[4];
+  c128* o = x + (size_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) s += o[g].x * o[g].x + o[g].y * o[g].y;
+  s = block_sum256(s, red);
+  const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
+}
+
 // reduced matrices of the collapsed basis {psi}: H = diag(eps), S = I
 __global__ void k_restart(int nb, const double* __restrict__ eps, c128* __restrict__ h,
                           c128* __restrict__ s, int ldm) {
@@ -170,6 +218,41 @@ __global__ void k_herm_fill(int c0, int c1, c128* __restrict__ m, int ldm) {
 
 __global__ void k_fill(int n, double v, double* __restrict__ x) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] = v;
+}
+
+// Locking: order of the active bands [nl, nb) with the converged ones first and
+// the n_new unconverged ones (idx, ascending) after them, both in band order;
+// eps follows that order, and idx is renumbered to the new positions.
+__global__ void k_lock_order(int nl, int nb, int n_new, int* __restrict__ idx, int* __restrict__ perm,
+                             double* __restrict__ eps, double* __restrict__ etmp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int nact = nb - nl, nc = nact - n_new;
+  int c = 0, u = 0;
+  for (int b = nl; b < nb; ++b) {
+    if (u < n_new && idx[u] == b) perm[nc + u++] = b;
+    else perm[c++] = b;
+  }
+  for (int j = 0; j < nact; ++j) etmp[j] = eps[perm[j]];
+  for (int j = 0; j < nact; ++j) eps[nl + j] = etmp[j];
+  for (int t = 0; t < n_new; ++t) idx[t] = nl + nc + t;
+}
+
+// dst column j = src column perm[j], j < n (complex columns of length npw)
+__global__ void k_gather_cols(int npw, int n, const int* __restrict__ perm, const c128* __restrict__ src, int lds,
+                              c128* __restrict__ dst, int ldd) {
+  for (int j = blockIdx.y; j < n; j += gridDim.y) {
+    const c128* a = src + (size_t)perm[j] * lds;
+    c128* b = dst + (size_t)j * ldd;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < npw; g += gridDim.x * blockDim.x) b[g] = a[g];
+  }
+}
+
+// x[j] = x[perm[j]] for j < n (through tmp)
+__global__ void k_permute_vals(int n, const int* __restrict__ perm, double* __restrict__ x,
+                               double* __restrict__ tmp) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int j = 0; j < n; ++j) tmp[j] = x[perm[j]];
+  for (int j = 0; j < n; ++j) x[j] = tmp[j];
 }
 
 // eig_b = Re <psi_b|H psi_b> / <psi_b|psi_b>,  resid_b = || H psi_b - eig_b psi_b ||
@@ -210,7 +293,8 @@ size_t pw::dav_bytes(int npw, int nb_max, int ndim_max) {
   b += 2 * (size_t)nb_max * ld * sizeof(c128);          // psi, hpsi
   b += 2 * nbasis * nbasis * sizeof(c128);              // hred, sred
   b += nbasis * nb_max * sizeof(c128);                  // cvec
-  b += 3 * (size_t)nb_max * sizeof(double) + nb_max * sizeof(int) + 256;
+  b += 5 * (size_t)nb_max * sizeof(double) + 2 * nb_max * sizeof(int) + 256;
+  b += (size_t)nb_max * nb_max * sizeof(c128);          // lockc
   b += pw::splitk_part_bytes((int)nbasis, (int)nbasis, npw, sizeof(c128));
   b += pw::heig_work_bytes((int)nbasis);
   return b + 32 * 256;
@@ -245,6 +329,9 @@ pw_status pw::dav_alloc(pw_plan p) {
   PW_TRY(get(nb * sizeof(double), (void**)&W->eps_prev));
   PW_TRY(get(nb * sizeof(double), (void**)&W->rn));
   PW_TRY(get(nb * sizeof(int), (void**)&W->idx));
+  PW_TRY(get(nb * sizeof(int), (void**)&W->perm));
+  PW_TRY(get(nb * nb * sizeof(c128), (void**)&W->lockc));
+  PW_TRY(get(2 * nb * sizeof(double), (void**)&W->etmp));
   PW_TRY(get(sizeof(DavFlags), (void**)&W->flags));
   W->part_bytes = pw::splitk_part_bytes((int)nbx, (int)nbx, p->npw, sizeof(c128));
   PW_TRY(get(W->part_bytes, &W->part));
@@ -296,6 +383,7 @@ struct Solver {
   hipStream_t st;
   pw_david_stats& stats;
   int nfact = 0;   // leading basis size whose overlap factor is current
+  int nl = 0;      // locked bands: psi[0:nl), hpsi[0:nl), eps[0:nl) stay fixed
 
   pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx) {
     PW_TRY(pw::hpsi_launch(p, prec, n, x, W.ld, hx, W.ld, st));
@@ -317,38 +405,100 @@ struct Solver {
     return PW_OK;
   }
 
-  // reduced eigenproblem on phi[0:nbase) and the Ritz rotation (skipped on
-  // device when the overlap matrix is not positive definite)
-  pw_status rayleigh_ritz(int nbase, int nb) {
+  // reduced eigenproblem on phi[0:nbase) for the nact active bands and the
+  // Ritz rotation into psi[nl:nl+nact) (skipped on device when the overlap
+  // matrix is not positive definite)
+  pw_status rayleigh_ritz(int nbase, int nact) {
     const int ldm = W.nbasis;
-    PW_TRY(pw::heig_solve(W.hw, nfact, nbase, nb, W.hred, W.sred, ldm, W.eps, W.cvec, ldm, W.part, W.part_bytes,
-                          st));
+    PW_TRY(pw::heig_solve(W.hw, nfact, nbase, nact, W.hred, W.sred, ldm, W.eps + nl, W.cvec, ldm, W.part,
+                          W.part_bytes, st));
     nfact = nbase;
     // psi = phi c and hpsi = (H phi) c in one launch
-    PW_TRY(pw::zgemm_nn_pair(p->npw, nb, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi, W.hpsi, W.ld, st,
-                             W.hw.info));
+    PW_TRY(pw::zgemm_nn_pair(p->npw, nact, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi + (size_t)nl * W.ld,
+                             W.hpsi + (size_t)nl * W.ld, W.ld, st, W.hw.info));
     return PW_OK;
   }
 
-  // basis <- current Ritz vectors
-  pw_status collapse(int nb) {
+  // basis <- current Ritz vectors of the nact active bands
+  pw_status collapse(int nact) {
     const size_t pitch = sizeof(c128) * W.ld;
-    PW_HIP(hipMemcpy2DAsync(W.phi, pitch, W.psi, pitch, sizeof(c128) * p->npw, nb, hipMemcpyDeviceToDevice, st));
-    PW_HIP(hipMemcpy2DAsync(W.hphi, pitch, W.hpsi, pitch, sizeof(c128) * p->npw, nb, hipMemcpyDeviceToDevice, st));
-    k_restart<<<std::min(1024, ceil_div(nb * nb, 256)), 256, 0, st>>>(nb, W.eps, W.hred, W.sred, W.nbasis);
+    PW_HIP(hipMemcpy2DAsync(W.phi, pitch, W.psi + (size_t)nl * W.ld, pitch, sizeof(c128) * p->npw, nact,
+                            hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpy2DAsync(W.hphi, pitch, W.hpsi + (size_t)nl * W.ld, pitch, sizeof(c128) * p->npw, nact,
+                            hipMemcpyDeviceToDevice, st));
+    k_restart<<<std::min(1024, ceil_div(nact * nact, 256)), 256, 0, st>>>(nact, W.eps + nl, W.hred, W.sred,
+                                                                          W.nbasis);
     PW_HIP(hipGetLastError());
-    PW_TRY(pw::heig_reset(W.hw, nb, st));
-    nfact = nb;
+    PW_TRY(pw::heig_reset(W.hw, nact, st));
+    nfact = nact;
     return PW_OK;
   }
 
-  // full Rayleigh-Ritz on a block already in phi[0:nb) (start, precision switch)
-  pw_status start_block(pw_precision prec, int nb) {
+  // full Rayleigh-Ritz on a block already in phi[0:nact) (start, precision switch, rebuild)
+  pw_status start_block(pw_precision prec, int nact) {
     nfact = 0;
-    PW_TRY(hpsi(prec, nb, W.phi, W.hphi));
-    PW_TRY(project(0, nb));
-    PW_TRY(rayleigh_ritz(nb, nb));
+    PW_TRY(hpsi(prec, nact, W.phi, W.hphi));
+    PW_TRY(project(0, nact));
+    PW_TRY(rayleigh_ritz(nact, nact));
     return PW_OK;
+  }
+
+  // lock the nc = nact - n_new converged active bands: they move to the front
+  // of the active range (band order kept) and become psi[nl:nl+nc); idx then
+  // lists the unconverged bands at their new positions
+  pw_status lock(int nb, int n_new) {
+    const int nact = nb - nl, nc = nact - n_new;
+    if (nc <= 0) return PW_OK;
+    const size_t pitch = sizeof(c128) * W.ld;
+    const int npw = p->npw;
+    k_lock_order<<<1, 1, 0, st>>>(nl, nb, n_new, W.idx, W.perm, W.eps, W.etmp);
+    const dim3 g(std::min(64, ceil_div(npw, 256)), std::min(nact, 1024));
+    k_gather_cols<<<g, 256, 0, st>>>(npw, nact, W.perm, W.psi, W.ld, W.phi, W.ld);
+    k_gather_cols<<<g, 256, 0, st>>>(npw, nact, W.perm, W.hpsi, W.ld, W.hphi, W.ld);
+    PW_HIP(hipGetLastError());
+    PW_HIP(hipMemcpy2DAsync(W.psi + (size_t)nl * W.ld, pitch, W.phi, pitch, sizeof(c128) * npw, nact,
+                            hipMemcpyDeviceToDevice, st));
+    PW_HIP(hipMemcpy2DAsync(W.hpsi + (size_t)nl * W.ld, pitch, W.hphi, pitch, sizeof(c128) * npw, nact,
+                            hipMemcpyDeviceToDevice, st));
+    nl += nc;
+    return PW_OK;
+  }
+
+  // phi[c0:c0+n) <- (1 - psi_L psi_L^H) phi[c0:c0+n), `passes` times, each
+  // pass followed by a normalization when `normalize` is set (a vector mostly
+  // inside the locked span keeps, after one pass, rounding-level components
+  // along it): no locked direction re-enters the basis
+  pw_status project_out_locked(int c0, int n, int passes = 2, bool normalize = true) {
+    if (nl == 0 || n == 0) return PW_OK;
+    c128* x = W.phi + (size_t)c0 * W.ld;
+    for (int pass = 0; pass < passes; ++pass) {
+      PW_TRY((pw::zgemm_cn<double, double, double>(nl, n, p->npw, W.psi, W.ld, x, W.ld, W.lockc, nl, W.part,
+                                                   W.part_bytes, st)));
+      PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, n, nl, -1.0, W.psi, W.ld, W.lockc, nl, 1.0, x, W.ld,
+                                                   st)));
+      if (normalize) k_normalize<<<n, 256, 0, st>>>(p->npw, x, W.ld);
+      PW_HIP(hipGetLastError());
+    }
+    return PW_OK;
+  }
+
+  // corrections of the bands idx[0:n) into phi[c0:c0+n).  With locked bands
+  // the residual is first projected off the locked span, so that the
+  // preconditioner is applied to its active part only (the locked span's part
+  // of a residual is the coupling that locking drops; preconditioned, it would
+  // come back as a spurious direction), and the correction is projected again.
+  pw_status corrections(int c0, int n, double floor_) {
+    c128* x = W.phi + (size_t)c0 * W.ld;
+    if (nl == 0) {
+      k_correct<<<n, 256, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, floor_, x, W.ld);
+      PW_HIP(hipGetLastError());
+      return PW_OK;
+    }
+    k_residvec<<<n, 256, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, x, W.ld);
+    PW_TRY(project_out_locked(c0, n, 1, false));
+    k_precond<<<n, 256, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, floor_, x, W.ld);
+    PW_HIP(hipGetLastError());
+    return project_out_locked(c0, n);
   }
 };
 
@@ -374,7 +524,6 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   pw_david_stats stats{};
   Solver S{p, W, st, stats};
   const int npw = p->npw;
-  const int nbx = o.ndim * nb;
   pw_precision prec = (p->opts.precision == PW_MIXED) ? PW_MIXED : PW_FP64;
   c128* psi = reinterpret_cast<c128*>(psi_u);
 
@@ -410,11 +559,11 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     if (f.info != 0) {
       // the newest corrections made the overlap singular: the Ritz vectors
       // were not replaced; collapse onto them once and try again
-      if (retried || nbase == nb) { result = pw::fail(PW_EBREAKDOWN, "reduced overlap matrix not positive definite"); break; }
+      if (retried || nbase == nb - S.nl) { result = pw::fail(PW_EBREAKDOWN, "reduced overlap matrix not positive definite"); break; }
       retried = true;
       PW_HIP(hipMemsetAsync(W.hw.info, 0, sizeof(int), st));
-      PW_TRY(S.collapse(nb));
-      nbase = nb;
+      PW_TRY(S.collapse(nb - S.nl));
+      nbase = nb - S.nl;
       stats.restarts++;
       continue;
     }
@@ -425,6 +574,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     if (fp32_stage && (f.n_new == 0 || stall32 >= kStall32)) {
       // precision ladder: continue from the Ritz vectors with float64 H.psi
       prec = PW_FP64;
+      S.nl = 0;
       PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
                               hipMemcpyDeviceToDevice, st));
       PW_TRY(S.start_block(prec, nb));
@@ -438,7 +588,9 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     if (f.n_new == 0) break;
     if (stats.iters >= o.max_iter) { result = PW_ENOTCONV; break; }
     const int n_new = f.n_new;
-    if (nbase + n_new > nbx) {
+    // the basis cap stays ndim nb: with bands locked, the active ones keep a
+    // longer history of corrections before the next collapse
+    if (nbase + n_new > o.ndim * nb) {
       // The collapsed block inherits H psi = (H phi) c and is taken to be
       // orthonormal: the rounding errors of both grow by ||c|| and ||c||^2 per
       // collapse.  Once the accumulated growth is large, the block is rebuilt
@@ -446,23 +598,26 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       amp *= std::max(1.0, f.gamma) * std::max(1.0, f.gamma);
       // float32 H.psi carries ~1e-7 relative error already: a smaller budget
       if (amp > (prec == PW_MIXED ? kMaxAmp32 : kMaxAmp)) {
-        PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
-                                hipMemcpyDeviceToDevice, st));
-        PW_TRY(S.start_block(prec, nb));
+        PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi + (size_t)S.nl * W.ld, sizeof(c128) * W.ld,
+                                sizeof(c128) * npw, nb - S.nl, hipMemcpyDeviceToDevice, st));
+        PW_TRY(S.start_block(prec, nb - S.nl));
         amp = 1.0;
         stats.fresh_starts++;
       }
-      PW_TRY(S.collapse(nb));
-      nbase = nb;
+      // converged bands leave the basis for good (float64 stage only: a
+      // float32-stage band counts as converged at ladder_switch, and locking
+      // at that accuracy was seen to leave the basis nearly degenerate)
+      if (o.lock && prec == PW_FP64) PW_TRY(S.lock(nb, n_new));
+      PW_TRY(S.collapse(nb - S.nl));
+      nbase = nb - S.nl;
       stats.restarts++;
     }
-    k_correct<<<n_new, 256, 0, st>>>(npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, o.precond_floor,
-                                     W.phi + (size_t)nbase * W.ld, W.ld);
+    PW_TRY(S.corrections(nbase, n_new, o.precond_floor));
     PW_TRY(S.hpsi(prec, n_new, W.phi + (size_t)nbase * W.ld, W.hphi + (size_t)nbase * W.ld));
     PW_TRY(S.project(nbase, nbase + n_new));
     nbase += n_new;
     PW_HIP(hipMemcpyAsync(W.eps_prev, W.eps, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
-    PW_TRY(S.rayleigh_ritz(nbase, nb));
+    PW_TRY(S.rayleigh_ritz(nbase, nb - S.nl));
     if (prec == PW_MIXED) stats.iters_fp32++;
     stats.iters++;
   }
@@ -473,11 +628,31 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   stats.n_hpsi_fp64 += nb;
   k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid);
   PW_HIP(hipGetLastError());
-  std::vector<double> hr(nb);
+  std::vector<double> hr(nb), he(nb);
   PW_HIP(hipMemcpyAsync(hr.data(), resid, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+  PW_HIP(hipMemcpyAsync(he.data(), eig, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
   PW_HIP(hipStreamSynchronize(st));
   stats.max_resid = 0.0;
   for (double r : hr) stats.max_resid = std::max(stats.max_resid, r);
+  if (S.nl > 0) {
+    // locked bands sit in the order they converged: sort the output by eigenvalue
+    std::vector<int> order(nb);
+    for (int b = 0; b < nb; ++b) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return he[a] < he[b]; });
+    bool ident = true;
+    for (int b = 0; b < nb; ++b) ident = ident && order[b] == b;
+    if (!ident) {
+      PW_HIP(hipMemcpyAsync(W.perm, order.data(), sizeof(int) * nb, hipMemcpyHostToDevice, st));
+      const dim3 g(std::min(64, ceil_div(npw, 256)), std::min(nb, 1024));
+      k_gather_cols<<<g, 256, 0, st>>>(npw, nb, W.perm, psi, ldpsi, W.phi, W.ld);
+      PW_HIP(hipMemcpy2DAsync(psi, sizeof(c128) * ldpsi, W.phi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
+                              hipMemcpyDeviceToDevice, st));
+      k_permute_vals<<<1, 1, 0, st>>>(nb, W.perm, eig, W.etmp);
+      k_permute_vals<<<1, 1, 0, st>>>(nb, W.perm, resid, W.etmp);
+      PW_HIP(hipGetLastError());
+      PW_HIP(hipStreamSynchronize(st));   // `order` is read by the copy above
+    }
+  }
   stats.nconv = f.nconv;
   if (stats_out) *stats_out = stats;
   return result;

@@ -90,9 +90,10 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
   for (int j = 0; j < n; ++j) {
     if (threadIdx.x == 0) {
       const double d = L[(size_t)j * ld + j].x;
-      // a dependent direction leaves a pivot at rounding level; a clearly
-      // negative one (or a non-positive diagonal) means S is not positive definite
-      if (!isfinite(d) || !(diag0[j] > 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
+      // a dependent direction leaves a pivot at rounding level (a zero basis
+      // vector a zero one); a clearly negative pivot (or a negative diagonal)
+      // means S is not positive definite
+      if (!isfinite(d) || !(diag0[j] >= 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
       s_keep = (d > drop_tol * diag0[j]) ? 1 : 0;
       if (s_keep) {
         s_r = sqrt(d);
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(NTL) k_chol_panel(int n, int j0, int bb, doubl
   for (int j = j0; j < jend; ++j) {
     if (threadIdx.x == 0) {
       const double d = L[(size_t)j * ld + j].x;
-      if (!isfinite(d) || !(diag0[j] > 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
+      if (!isfinite(d) || !(diag0[j] >= 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
       s_keep = (d > drop_tol * diag0[j]) ? 1 : 0;
       if (s_keep) {
         s_r = sqrt(d);

@@ -123,7 +123,7 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
     PW_CHECK(plans[i] != nullptr, PW_EINVAL, "NULL plan in batch");
     PW_CHECK(plans[i]->ctx == ctx, PW_EINVAL, "plan of another context in batch");
     PW_CHECK(plans[i]->dav != nullptr, PW_EINVAL, "plan without Davidson workspace in batch");
-    pmax = std::max(pmax, ceil_div((int64_t)o.ndim * nb[i], 16));
+    pmax = std::max(pmax, pw::coop_workgroups(o.ndim * nb[i]));
   }
   PW_HIP(hipSetDevice(ctx->device));
   const int nw = std::max(1, std::min({n, nworkers > 0 ? (int)nworkers : 8, kMaxWorkers}));

@@ -654,6 +654,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     }
   }
   stats.nconv = f.nconv;
+  stats.nlocked = S.nl;
   if (stats_out) *stats_out = stats;
   return result;
 }

@@ -270,20 +270,29 @@ __global__ void k_isolate(int n, c128* __restrict__ A, int ld, const int* __rest
 }
 
 // gamma = max_k || C[:, k] ||_2  (growth factor of the Ritz rotation)
-__global__ void k_colnorm_max(int n, int nev, const c128* __restrict__ C, int ldc, double* __restrict__ gamma,
-                              const int* __restrict__ info) {
-  __shared__ double red[16];
-  double mx = 0.0;
-  if (*info == 0) {
-    for (int k = threadIdx.x; k < nev; k += blockDim.x) {
-      double s = 0.0;
-      for (int i = 0; i < n; ++i) {
-        const c128 v = C[(size_t)k * ldc + i];
-        s += v.x * v.x + v.y * v.y;
-      }
-      mx = fmax(mx, sqrt(s));
-    }
+// largest column norm of C[n][nev]: one wave per column (coalesced rows) into
+// part[nev], then k_max_of over them
+__global__ void __launch_bounds__(256) k_colnorms(int n, int nev, const c128* __restrict__ C, int ldc,
+                                                  double* __restrict__ part, const int* __restrict__ info) {
+  if (*info != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (k >= nev) return;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) {
+    const c128 v = C[(size_t)k * ldc + i];
+    s += v.x * v.x + v.y * v.y;
   }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+  if (lane == 0) part[k] = sqrt(s);
+}
+
+__global__ void k_max_of(int nev, const double* __restrict__ part, double* __restrict__ gamma,
+                         const int* __restrict__ info) {
+  __shared__ double red[4];
+  double mx = 0.0;
+  if (*info == 0)
+    for (int k = threadIdx.x; k < nev; k += blockDim.x) mx = fmax(mx, part[k]);
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
@@ -596,6 +605,7 @@ constexpr int CB = 256;     // columns covered by one pass of the threads
 constexpr int kCoopMinN = 64, kCoopMaxN = 2048;
 constexpr int kCoopMaxP = kCoopMaxN / CR;
 constexpr long kCoopSpin = 1l << 22;   // polls of a barrier before giving up
+constexpr int kCoopSmallN = 2 * CB;     // up to here, 8 rows per workgroup
 
 struct CoopBuf {
   c128* p;         // [2][kCoopMaxN]   p_r of every row, by step parity
@@ -730,18 +740,18 @@ __device__ __forceinline__ Refl householder(c128 al, double xn2) {
   return r;
 }
 
-template <int NC>
+template <int NC, int CRT>
 __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A, int ld, double* __restrict__ d,
                                                      double* __restrict__ e, c128* __restrict__ tau,
                                                      int* __restrict__ info, CoopBuf cb) {
   constexpr int NW = CT / 64;             // waves
   constexpr int NH = CT / CB;             // row halves (threads t and t + CB share columns)
-  constexpr int RH = CR / NH;             // rows per thread
+  constexpr int RH = CRT / NH;            // rows per thread
   constexpr int WH = CB / 64;             // waves per half
   if (*info != 0) return;
   __shared__ c128 s_rowbuf[kCoopMaxN];    // owned row k+1 (for publication)
   __shared__ double s_red[NW][2 * RH];    // per-wave row sums of B v (re, then im)
-  __shared__ c128 s_rv[2][CR], s_rw[CR];  // v_k (by step parity) and w on the own rows
+  __shared__ c128 s_rv[2][CRT], s_rw[CRT];  // v_k (by step parity) and w on the own rows
   __shared__ double s_xn2[NW];
   __shared__ c128 s_alx;
   __shared__ int s_fail;
@@ -753,7 +763,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
   // the same number of live rows as the reduction proceeds)
   auto row_of = [&](int i) { return q + P * i; };
   // local index of row r if it is an own row, else -1
-  auto local_of = [&](int r) { return (r >= q && (r - q) % P == 0 && (r - q) / P < CR) ? (r - q) / P : -1; };
+  auto local_of = [&](int r) { return (r >= q && (r - q) % P == 0 && (r - q) / P < CRT) ? (r - q) / P : -1; };
   int jc[NC];
   bool ok[NC];
 #pragma unroll
@@ -771,7 +781,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     }
   if (tid == 0) s_fail = 0;
   // own rows past the end of the matrix are never written: start from zeros
-  if (tid < CR) { s_rv[0][tid] = s_rv[1][tid] = s_rw[tid] = c128{0.0, 0.0}; }
+  if (tid < CRT) { s_rv[0][tid] = s_rv[1][tid] = s_rw[tid] = c128{0.0, 0.0}; }
   __syncthreads();
 
   // own-row values of a column vector to LDS (one copy: the first half writes)
@@ -840,8 +850,8 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     //    partial sum of conj(p_r) v_r, and (owner) row k+1; then the barrier
     if (wid == 0) {
       c128 p{0.0, 0.0};
-      const int R = (lane < CR) ? row_of(lane) : n;
-      if (lane < CR && R >= k + 1 && R < n) {
+      const int R = (lane < CRT) ? row_of(lane) : n;
+      if (lane < CRT && R >= k + 1 && R < n) {
         const int hh = lane / RH, ii = lane % RH;
         double re = 0.0, im = 0.0;
 #pragma unroll
@@ -849,9 +859,9 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
         p = cmul(tk, c128{re, im});
       }
       // rows outside [k+1, n) contribute nothing (and their v entries are not read)
-      const c128 t = (lane < CR && R >= k + 1 && R < n) ? cmulc(p, s_rv[par][lane]) : c128{0.0, 0.0};
+      const c128 t = (lane < CRT && R >= k + 1 && R < n) ? cmulc(p, s_rv[par][lane]) : c128{0.0, 0.0};
       const double sre = wave_sum(t.x), sim = wave_sum(t.y);
-      if (lane < CR && R < n) xstore(&cb.p[par * kCoopMaxN + R], p);
+      if (lane < CRT && R < n) xstore(&cb.p[par * kCoopMaxN + R], p);
       if (lane == 0) xstore(&cb.s[par * kCoopMaxP + q], c128{sre, sim});
       if ((k + 1) % P == q)
         for (int c = k + 1 + lane; c < n; c += 64) xstore(&cb.row[par * kCoopMaxN + c], s_rowbuf[c]);
@@ -1367,6 +1377,8 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
 
 }  // namespace
 
+int pw::coop_workgroups(int n) { return ceil_div(n, n <= kCoopSmallN ? 8 : CR); }
+
 namespace {
 size_t coop_bytes() { return sizeof(c128) * (4 * kCoopMaxN + 2 * kCoopMaxP) + 2 * 256; }
 CoopBuf coop_buf(const pw::HeigWork& hw) {
@@ -1488,12 +1500,14 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
     if (hw.coop_ok && n >= kCoopMinN && n <= kCoopMaxN) {
       const CoopBuf cb = coop_buf(hw);
-      const int P = ceil_div(n, CR);
+      const int P = pw::coop_workgroups(n);
       k_coop_reset<<<1, 64, 0, st>>>(cb);
-      if (n <= CB) k_tridiag_coop<1><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
-      else if (n <= 2 * CB) k_tridiag_coop<2><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
-      else if (n <= 4 * CB) k_tridiag_coop<4><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
-      else k_tridiag_coop<8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      // up to 512 rows: 8 rows per workgroup (twice the workgroups, half the
+      // update work per step on each); beyond, 16
+      if (n <= CB) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 2 * CB) k_tridiag_coop<2, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 4 * CB) k_tridiag_coop<4, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else k_tridiag_coop<8, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
     } else if (n <= kPanelMinN) {
       k_tridiag<<<1, NTL, sizeof(c128) * (2 * n + std::max(n, NTL)), st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau,
                                                                           hw.info);
@@ -1546,7 +1560,9 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   // C = X Y
   PW_TRY((pw::zgemm_nn<double, double, double>(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, st)));
-  k_colnorm_max<<<1, 256, 0, st>>>(n, nev, C, ldc, hw.gamma, hw.info);
+  // hw.Z (eigenvectors of T) is free once the back-transform has run
+  k_colnorms<<<ceil_div(nev, 4), 256, 0, st>>>(n, nev, C, ldc, hw.Z, hw.info);
+  k_max_of<<<1, 256, 0, st>>>(nev, hw.Z, hw.gamma, hw.info);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

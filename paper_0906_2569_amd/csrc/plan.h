@@ -127,8 +127,10 @@ pw_status dav_alloc(pw_plan p);
 bool dav_set_coop(pw_plan p, bool ok);
 // workgroups that cooperative launches of concurrent solves may keep
 // spinning at once (half of the device's 256 compute units): concurrent
-// solves use them only while workers x ceil(ndim nb / 16) stays within it
+// solves use them only while workers x (workgroups of one launch) stays within it
 constexpr int kCoopWgBudget = 128;
+// workgroups (all resident at once) of the cooperative tridiagonalization of n rows
+int coop_workgroups(int n);
 bool dav_get_coop(pw_plan p);
 // destroy the context's worker streams (pw_ctx_destroy)
 void ctx_release_pool(pw_ctx ctx);

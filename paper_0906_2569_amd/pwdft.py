@@ -59,7 +59,7 @@ class ServerOpts(C.Structure):
 class DavStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("n_hpsi_fp32", C.c_int32),
                 ("n_hpsi_fp64", C.c_int32), ("nconv", C.c_int32), ("iters_fp32", C.c_int32),
-                ("fresh_starts", C.c_int32), ("max_resid", C.c_double)]
+                ("fresh_starts", C.c_int32), ("nlocked", C.c_int32), ("max_resid", C.c_double)]
 
     def asdict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

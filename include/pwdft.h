@@ -120,6 +120,7 @@ typedef struct {
   int32_t nconv;             /* converged bands at exit                                              */
   int32_t iters_fp32;        /* iterations done with float32 H.psi (mixed precision)                 */
   int32_t fresh_starts;      /* rebuilds of the basis with a fresh H.psi (growth budget, ladder)     */
+  int32_t nlocked;           /* bands locked when the solve ended (opts.lock)                        */
   double  max_resid;         /* max_i ||g_i||_2 of the final float64 verification                    */
 } pw_david_stats;
 

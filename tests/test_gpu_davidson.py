@@ -118,3 +118,27 @@ def test_max_iter_gives_notconv_with_valid_outputs(ctx):
     np.testing.assert_allclose(np.conj(psi) @ psi.T, np.eye(p.nb), atol=1e-10)
     w, _ = oracle.eigh_lowest(oracle.dense_h_of(p), p.nb)
     assert np.all(eig >= w - 1e-10)         # Rayleigh quotients bound from above
+
+
+@pytest.mark.parametrize("lock", [0, 1])
+def test_locking_against_dense(ctx, lock):
+    # a basis of 2 nb collapses every few iterations: with locking on, bands
+    # converged by then are fixed and projected out of later corrections;
+    # either way the result is the dense spectrum, sorted, orthonormal, with
+    # the residuals of the returned vectors
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, p.nb)
+    st, eig, resid, psi, stats = _solve(ctx, p, ndim=2, max_iter=400, lock=lock)
+    print("lock", lock, "stats", stats, "max |err|", np.abs(eig - w).max())
+    assert st == 0
+    if lock:
+        assert stats["nlocked"] > 0
+    else:
+        assert stats["nlocked"] == 0
+    assert np.all(np.diff(eig) >= 0)
+    np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+    np.testing.assert_allclose(np.conj(psi) @ psi.T, np.eye(p.nb), atol=1e-10)
+    r = np.linalg.norm(oracle.hpsi(h, psi) - eig[:, None] * psi, axis=1)
+    np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)
+    assert resid.max() <= 1e-6

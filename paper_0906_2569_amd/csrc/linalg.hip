@@ -1485,13 +1485,13 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   if (n0 > 0) {
     // X12 = -X11 (U12 X22)
-    PW_TRY((pw::zgemm_nn<double, double, double>(n0, m, m, 1.0, hw.T1, ldw, X22, ldw, 0.0, hw.Y, ldw, st)));
-    PW_TRY((pw::zgemm_nn<double, double, double>(n0, m, n0, -1.0, hw.X, ldw, hw.Y, ldw, 0.0,
-                                                 hw.X + (size_t)n0 * ldw, ldw, st)));
+    PW_TRY(pw::zgemm_nn_sk(n0, m, m, 1.0, hw.T1, ldw, X22, ldw, 0.0, hw.Y, ldw, part, part_bytes, st));
+    PW_TRY(pw::zgemm_nn_sk(n0, m, n0, -1.0, hw.X, ldw, hw.Y, ldw, 0.0, hw.X + (size_t)n0 * ldw, ldw, part,
+                           part_bytes, st));
     k_zero_block<<<std::min(1024, ceil_div(m * n0, 256)), 256, 0, st>>>(n0, n, n0, hw.X, ldw);
   }
   // A = X^H (H X)
-  PW_TRY((pw::zgemm_nn<double, double, double>(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, st)));
+  PW_TRY(pw::zgemm_nn_sk(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, part, part_bytes, st));
   PW_TRY((pw::zgemm_cn<double, double, double>(n, n, n, hw.X, ldw, hw.T1, ldw, hw.A, ldw, part,
                                                part_bytes, st)));
   k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.A, ldw, hw.drop, hw.info);
@@ -1559,7 +1559,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     else return pw::fail(PW_EINVAL, "reduced problem larger than 4096");
   }
   // C = X Y
-  PW_TRY((pw::zgemm_nn<double, double, double>(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, st)));
+  PW_TRY(pw::zgemm_nn_sk(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, part, part_bytes, st));
   // hw.Z (eigenvectors of T) is free once the back-transform has run
   k_colnorms<<<ceil_div(nev, 4), 256, 0, st>>>(n, nev, C, ldc, hw.Z, hw.info);
   k_max_of<<<1, 256, 0, st>>>(nev, hw.Z, hw.gamma, hw.info);

@@ -111,6 +111,13 @@ pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
                    const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream,
                    const int* guard = nullptr);
 
+// zgemm_nn in float64 for products with few output tiles: K is split over
+// workgroups and the partials summed in a fixed order (part: workspace of
+// splitk_part_bytes(M, N, K, 16) bytes); plain zgemm_nn when the product has
+// tiles enough or the workspace is too small
+pw_status zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int lda, const c128* B, int ldb,
+                      double beta, c128* C, int ldc, void* part, size_t part_bytes, hipStream_t stream);
+
 // C0 = A^H B0 and C1 = A^H B1 (float64, as zgemm_cn with alpha 1, beta 0) in one launch
 pw_status zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c128* B0, const c128* B1, int ldb,
                         c128* C0, c128* C1, int ldc, void* part, size_t part_bytes, hipStream_t stream);

@@ -51,6 +51,9 @@ template <>
 __device__ __forceinline__ int mrow<double>(int lane, int q) { return 4 * q + (lane >> 4); }
 __device__ __forceinline__ int mcol(int lane) { return lane & 15; }
 
+// The GEMM kernels are built for at least three waves per SIMD (at most 168
+// registers, spill-free): three 64x64 tiles then share a CU, and a product
+// of 18277 x 128 rows and columns (572 tiles) is resident in one round.
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
 template <typename T>
@@ -92,7 +95,7 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, typename Mma<T>::v4 (
 // gridDim.z = 2 nsplit for two products of one launch: z >= nsplit takes B1
 // and writes the partials after those of the first product
 template <typename T, typename TA, typename TB>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict__ A, int lda,
           const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
   __shared__ Tile<T> t;
@@ -156,15 +159,20 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
 
 // C[n*ldc + m] = alpha sum_k A[k*lda + m] B[n*ldb + k] + beta C[n*ldc + m]
 // blockIdx.z selects the product: (A0, C0) or (A1, C1), same B (two products of
-// one launch fill the device better than two launches)
-template <typename T, typename TA, typename TB>
-__global__ void __launch_bounds__(NT)
+// one launch fill the device better than two launches).
+// SPLIT: blockIdx.z is instead the K chunk [z kchunk, (z + 1) kchunk) of the one
+// product (A0), whose partial tile goes to P[z][n][m] unscaled, for k_reduce.
+template <typename T, typename TA, typename TB, bool SPLIT = false>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, const cpx<TA>* __restrict__ A1,
           int lda, const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C0,
-          c128* __restrict__ C1, int ldc, const int* __restrict__ guard) {
+          c128* __restrict__ C1, int ldc, const int* __restrict__ guard, int kchunk = 0,
+          cpx<T>* __restrict__ P = nullptr) {
   if (guard != nullptr && *guard != 0) return;
-  const cpx<TA>* __restrict__ A = blockIdx.z ? A1 : A0;
-  c128* __restrict__ C = blockIdx.z ? C1 : C0;
+  const cpx<TA>* __restrict__ A = (!SPLIT && blockIdx.z) ? A1 : A0;
+  c128* __restrict__ C = (!SPLIT && blockIdx.z) ? C1 : C0;
+  const int kbeg = SPLIT ? (int)blockIdx.z * kchunk : 0;
+  const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
   const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
@@ -186,17 +194,17 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
       {
         const int mi = idx % BM, kk = idx / BM;
         const int m = m0 + mi, k = k0 + kk;
-        ra[it] = (m < M && k < K) ? A[(size_t)k * lda + m] : cpx<TA>{TA(0), TA(0)};
+        ra[it] = (m < M && k < kend) ? A[(size_t)k * lda + m] : cpx<TA>{TA(0), TA(0)};
       }
       {
         const int kk = idx % BK, ni = idx / BK;
         const int n = n0 + ni, k = k0 + kk;
-        rb[it] = (n < N && k < K) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
+        rb[it] = (n < N && k < kend) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
       }
     }
   };
-  if (K > 0) load(0);
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  if (kbeg < kend) load(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
     for (int it = 0; it < PER; ++it) {
       const int idx = threadIdx.x + it * NT;
@@ -212,9 +220,23 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
       }
     }
     __syncthreads();
-    if (k0 + BK < K) load(k0 + BK);
+    if (k0 + BK < kend) load(k0 + BK);
     tile_mma<T>(t, cr, ci, wm, wn, lane);
     __syncthreads();
+  }
+  if constexpr (SPLIT) {
+    cpx<T>* out = P + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+          const int n = n0 + wn * 32 + j * 16 + mcol(lane);
+          if (m < M && n < N) out[(size_t)n * M + m] = cpx<T>{cr[i][j][q], ci[i][j][q]};
+        }
+    return;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -237,22 +259,29 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
       }
 }
 
-// sum_z P[z * stride + off] for z < nsplit, in increasing z (the order is
-// fixed, so results are reproducible); the loads of eight partials are
-// issued before they are added
+// In k_reduce the split-K partials of one output element are summed by RZ
+// thread groups:
+// group y adds the partials z in [y nsplit / RZ, (y + 1) nsplit / RZ) in
+// increasing z, then the RZ group sums are added in increasing y.  The order
+// is fixed, so results are reproducible, and the groups keep RZ times more
+// loads in flight than one thread per element would.
+constexpr int RZ = 4;
+
+// sum_z P[z * stride + off] for z0 <= z < z1 in increasing z; the loads of
+// eight partials are issued before they are added
 template <typename T>
-__device__ __forceinline__ cpx<T> sum_partials(const cpx<T>* __restrict__ P, int nsplit, size_t stride,
+__device__ __forceinline__ cpx<T> sum_partials(const cpx<T>* __restrict__ P, int z0, int z1, size_t stride,
                                                size_t off) {
   T re = 0, im = 0;
-  int z = 0;
-  for (; z + 8 <= nsplit; z += 8) {
+  int z = z0;
+  for (; z + 8 <= z1; z += 8) {
     cpx<T> v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) v[u] = P[(size_t)(z + u) * stride + off];
 #pragma unroll
     for (int u = 0; u < 8; ++u) { re += v[u].x; im += v[u].y; }
   }
-  for (; z < nsplit; ++z) {
+  for (; z < z1; ++z) {
     const cpx<T> v = P[(size_t)z * stride + off];
     re += v.x;
     im += v.y;
@@ -260,28 +289,46 @@ __device__ __forceinline__ cpx<T> sum_partials(const cpx<T>* __restrict__ P, int
   return cpx<T>{re, im};
 }
 
-// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]   (fixed summation order)
 template <typename T>
-__global__ void k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
-                         c128* __restrict__ C, int ldc, double alpha, double beta) {
+__device__ __forceinline__ cpx<T> add_groups(const cpx<T> (*s)[64], int x) {
+  cpx<T> v = s[0][x];
+#pragma unroll
+  for (int y = 1; y < RZ; ++y) v = cpx<T>{v.x + s[y][x].x, v.y + s[y][x].y};
+  return v;
+}
+
+// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]; block (64, RZ)
+template <typename T>
+__global__ void __launch_bounds__(64 * RZ) k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
+                                                    c128* __restrict__ C, int ldc, double alpha, double beta) {
+  __shared__ cpx<T> s[RZ][64];
   const size_t total = (size_t)M * N;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int m = (int)(idx % M), n = (int)(idx / M);
-    const cpx<T> sum = sum_partials(P, nsplit, total, idx);
-    const T re = sum.x, im = sum.y;
-    c128* c = C + (size_t)n * ldc + m;
-    double r = alpha * (double)re, i = alpha * (double)im;
-    if (beta != 0.0) {
-      r += beta * c->x;
-      i += beta * c->y;
+  const int x = threadIdx.x, y = threadIdx.y;
+  const int z0 = y * nsplit / RZ, z1 = (y + 1) * nsplit / RZ;
+  // the loop bound depends on the block only, so every thread reaches the barriers
+  for (size_t base = (size_t)blockIdx.x * 64; base < total; base += (size_t)gridDim.x * 64) {
+    const size_t idx = base + x;
+    if (idx < total) s[y][x] = sum_partials(P, z0, z1, total, idx);
+    __syncthreads();
+    if (y == 0 && idx < total) {
+      const cpx<T> sum = add_groups<T>(s, x);
+      const int m = (int)(idx % M), n = (int)(idx / M);
+      c128* c = C + (size_t)n * ldc + m;
+      double r = alpha * (double)sum.x, i = alpha * (double)sum.y;
+      if (beta != 0.0) {
+        r += beta * c->x;
+        i += beta * c->y;
+      }
+      *c = c128{r, i};
     }
-    *c = c128{r, i};
+    __syncthreads();
   }
 }
 
 // One workgroup per band n: becp[j] = sum_z P[z][n][j] into LDS, then
-// out[n][j] = sum_{t < dlen_j} drow[j][t] becp[dstart_j + t].
+// out[n][j] = sum_{t < dlen_j} drow[j][t] becp[dstart_j + t].  It runs beside
+// the transform passes, so its workgroups stay small (256 threads) to find
+// room on CUs those passes occupy.
 template <typename T>
 __global__ void k_reduce_dapply(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
                                 const int* __restrict__ dstart, const int* __restrict__ dlen,
@@ -291,7 +338,8 @@ __global__ void k_reduce_dapply(int M, int N, int nsplit, const cpx<T>* __restri
   cpx<T>* red = reinterpret_cast<cpx<T>*>(smem_raw);
   const int n = blockIdx.x;
   const size_t total = (size_t)M * N;
-  for (int j = threadIdx.x; j < M; j += blockDim.x) red[j] = sum_partials(P, nsplit, total, (size_t)n * M + j);
+  for (int j = threadIdx.x; j < M; j += blockDim.x)
+    red[j] = sum_partials(P, 0, nsplit, total, (size_t)n * M + j);
   __syncthreads();
   for (int j = threadIdx.x; j < M; j += blockDim.x) {
     const int j0 = dstart[j], nh = dlen[j];
@@ -335,8 +383,9 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   PW_CHECK(need <= part_bytes, PW_ENOMEM, "split-K workspace too small");
   cpx<T>* P = static_cast<cpx<T>*>(part);
   if (K <= 0) {
-    PW_HIP(hipMemsetAsync(P, 0, (size_t)M * N * sizeof(cpx<T>), s));
-    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, 1, P, C, ldc, alpha, beta);
+    // a sum over no partials is zero: C = beta C
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, 0, P, C, ldc, alpha,
+                                                                                   beta);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
@@ -347,8 +396,8 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + 16.0 * M * N);
-    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 256)), 256, 0, s>>>(M, N, sp.nsplit, P, C, ldc, alpha,
-                                                                          beta);
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, sp.nsplit, P, C, ldc,
+                                                                                   alpha, beta);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -375,9 +424,9 @@ pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, 2.0 * ((double)nsplit * M * N * sizeof(c128) + 16.0 * M * N));
-    const int g = std::min(4096, ceil_div((size_t)M * N, 256));
-    k_reduce<double><<<g, 256, 0, s>>>(M, N, nsplit, P, C0, ldc, 1.0, 0.0);
-    k_reduce<double><<<g, 256, 0, s>>>(M, N, nsplit, P + (size_t)nsplit * M * N, C1, ldc, 1.0, 0.0);
+    const int g = std::min(4096, ceil_div((size_t)M * N, 64));
+    k_reduce<double><<<g, dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C0, ldc, 1.0, 0.0);
+    k_reduce<double><<<g, dim3(64, RZ), 0, s>>>(M, N, nsplit, P + (size_t)nsplit * M * N, C1, ldc, 1.0, 0.0);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -414,6 +463,32 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
   k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 1), NT, 0, s>>>(
       M, N, K, alpha, A, A, lda, B, ldb, beta, C, C, ldc, guard);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+pw_status pw::zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int lda, const c128* B, int ldb,
+                          double beta, c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s) {
+  if (M <= 0 || N <= 0) return PW_OK;
+  const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  // chunks of at least two K slices, up to about 512 workgroups in all
+  const int ns = std::min(ceil_div(512, tiles), ceil_div(K, 2 * BK));
+  const int kchunk = std::max(BK, ceil_div(ceil_div(K, std::max(ns, 1)), BK) * BK);
+  const int nsplit = ceil_div(K, kchunk);
+  const size_t need = (size_t)nsplit * M * N * sizeof(c128);
+  if (tiles >= 128 || nsplit < 2 || need > part_bytes)
+    return zgemm_nn<double, double, double>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, s);
+  c128* P = static_cast<c128*>(part);
+  {
+    pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
+    k_gemm_nn<double, double, double, true><<<dim3(ceil_div(M, BM), ceil_div(N, BN), nsplit), NT, 0, s>>>(
+        M, N, K, 1.0, A, A, lda, B, ldb, 0.0, nullptr, nullptr, ldc, nullptr, kchunk, P);
+  }
+  {
+    pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)nsplit * M * N * sizeof(c128) + 16.0 * M * N);
+    k_reduce<double><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C, ldc,
+                                                                                         alpha, beta);
+  }
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

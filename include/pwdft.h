@@ -273,10 +273,14 @@ pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, 
  * summed elapsed milliseconds and the summed algorithmic work of class k
  * (0 <= k < pw_profile_count(); bytes for the transform passes and vector
  * kernels, flops for matrix products and factorizations); pw_profile_name(k)
- * names the class.  Process-wide; not for concurrent use
- * from several host threads while enabled.
+ * names the class.  pw_profile_only(k) resets and enables timing of class k
+ * alone (k = -1: every class), so that a measurement of one kernel adds no
+ * events around the others; PW_EINVAL for k outside [-1, pw_profile_count()).
+ * Process-wide; not for concurrent use from several host threads while
+ * enabled.
  */
 pw_status   pw_profile_enable(int on);
+pw_status   pw_profile_only(int32_t k);
 int32_t     pw_profile_count(void);
 const char* pw_profile_name(int32_t k);
 pw_status   pw_profile_read(int32_t k, int64_t* launches, double* total_ms, double* units);

@@ -19,6 +19,7 @@ struct Rec {
 };
 std::mutex g_mu;
 bool g_on = false;
+int g_only = -1;                            // the one class timed, or -1 for all
 uint64_t g_next = 1;
 std::unordered_map<uint64_t, Rec> g_open;   // scopes whose end event is not yet recorded
 std::vector<Rec> g_recs;                    // closed scopes, not yet summed
@@ -53,7 +54,7 @@ void drain() {
 }
 }  // namespace
 
-bool pw::prof_on() { return g_on; }
+bool pw::prof_on(int kernel) { return g_on && (g_only < 0 || g_only == kernel); }
 
 uint64_t pw::prof_begin(int k, hipStream_t s, double units) {
   std::lock_guard<std::mutex> l(g_mu);
@@ -84,7 +85,16 @@ extern "C" pw_status pw_profile_enable(int on) {
   g_open.clear();
   for (int k = 0; k < pw::PK_COUNT; ++k) { g_ms[k] = 0.0; g_n[k] = 0; g_units[k] = 0.0; }
   g_on = on != 0;
+  g_only = -1;
   return PW_OK;
+}
+
+extern "C" pw_status pw_profile_only(int32_t k) {
+  PW_CHECK(k >= -1 && k < pw::PK_COUNT, PW_EINVAL, "bad profile class");
+  const pw_status st = pw_profile_enable(1);
+  std::lock_guard<std::mutex> l(g_mu);
+  g_only = k;
+  return st;
 }
 
 extern "C" int32_t pw_profile_count(void) { return pw::PK_COUNT; }

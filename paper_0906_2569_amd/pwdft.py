@@ -26,7 +26,7 @@ EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_de
            "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
            "pw_reduced_eigh", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
-           "pw_profile_count", "pw_profile_name", "pw_profile_read"]
+           "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
 
 class PwError(RuntimeError):
@@ -110,13 +110,14 @@ def load(path: str = LIB_PATH):
     lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     lib.pw_profile_enable.argtypes = [C.c_int]
+    lib.pw_profile_only.argtypes = [C.c_int32]
     lib.pw_profile_count.restype = C.c_int32
     lib.pw_profile_name.argtypes = [C.c_int32]
     lib.pw_profile_name.restype = C.c_char_p
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
                  "pw_plan_info", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-                 "pw_reduced_eigh", "pw_profile_enable", "pw_profile_read", "pw_server_create",
+                 "pw_reduced_eigh", "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
                  "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -205,6 +206,16 @@ def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0) -> 
 
 def profile_enable(on=True):
     _check(load().pw_profile_enable(1 if on else 0))
+
+
+def profile_only(name):
+    """Reset and time only the kernel class `name` (None: every class)."""
+    lib = load()
+    k = -1
+    if name is not None:
+        names = [lib.pw_profile_name(i).decode() for i in range(lib.pw_profile_count())]
+        k = names.index(name)
+    _check(lib.pw_profile_only(k))
 
 
 def profile_read():
@@ -305,6 +316,25 @@ class Plan:
         _check(self.lib.hpsi_apply(self.h, prec, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
                                    C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
         return out
+
+    def hpsi_graph(self, psi, out, prec=PW_FP64):
+        """A torch.cuda.CUDAGraph whose replay() recomputes out = H psi for these
+        buffers: hpsi_apply captured once (transform passes, projector products
+        on the plan's side stream, and the join), then relaunched with no host
+        work per kernel.  psi and out must stay allocated, in place, while the
+        graph is used; their contents may change between replays."""
+        import torch
+        assert psi.shape == out.shape and psi.stride(1) == 1 and out.stride(1) == 1
+        side = torch.cuda.Stream(device=psi.device)   # default priority
+        side.wait_stream(torch.cuda.current_stream(psi.device))
+        with torch.cuda.stream(side):
+            self.hpsi(psi, out, prec=prec)            # warm-up launch outside the capture
+        torch.cuda.current_stream(psi.device).wait_stream(side)
+        torch.cuda.synchronize(psi.device)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.hpsi(psi, out, prec=prec)
+        return g
 
     def davidson(self, psi, eig=None, resid=None, opts=None, stream=None, history=None):
         """In-place block Davidson on psi [nb][>=npw]; returns (status, eig, resid, stats).

@@ -123,10 +123,12 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
     PW_CHECK(plans[i] != nullptr, PW_EINVAL, "NULL plan in batch");
     PW_CHECK(plans[i]->ctx == ctx, PW_EINVAL, "plan of another context in batch");
     PW_CHECK(plans[i]->dav != nullptr, PW_EINVAL, "plan without Davidson workspace in batch");
-    pmax = std::max(pmax, pw::coop_workgroups(o.ndim * nb[i]));
   }
-  PW_HIP(hipSetDevice(ctx->device));
   const int nw = std::max(1, std::min({n, nworkers > 0 ? (int)nworkers : 8, kMaxWorkers}));
+  // concurrent solves take the cooperative form with fewer workgroups per launch
+  const bool wide = nw > 1;
+  for (int i = 0; i < n; ++i) pmax = std::max(pmax, pw::coop_workgroups(o.ndim * nb[i], wide));
+  PW_HIP(hipSetDevice(ctx->device));
   PW_TRY(ensure_pool(ctx, nw));
   hipStream_t caller = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> l(ctx->mu);
@@ -135,7 +137,7 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
   // cooperative kernels only while every concurrently spinning launch fits
   const bool coop = nw == 1 || nw * pmax <= pw::kCoopWgBudget;
   std::vector<char> prev(n);
-  for (int i = 0; i < n; ++i) prev[i] = pw::dav_set_coop(plans[i], coop && pw::dav_get_coop(plans[i]));
+  for (int i = 0; i < n; ++i) prev[i] = pw::dav_set_coop(plans[i], coop && pw::dav_get_coop(plans[i]), wide);
 
   std::vector<pw_status> st(n, PW_OK);
   std::vector<std::string> msg(n);

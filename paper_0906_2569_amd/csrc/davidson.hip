@@ -347,10 +347,11 @@ pw_status pw::dav_alloc(pw_plan p) {
   return PW_OK;
 }
 
-bool pw::dav_set_coop(pw_plan p, bool ok) {
+bool pw::dav_set_coop(pw_plan p, bool ok, bool wide) {
   if (!p || !p->dav) return false;
   const bool prev = p->dav->hw.coop_ok;
   p->dav->hw.coop_ok = ok;
+  p->dav->hw.coop_wide = wide;
   return prev;
 }
 

@@ -21,6 +21,9 @@ struct HeigWork {
   bool coop_ok = true;     // cooperative (multi-workgroup) kernels allowed: every workgroup of a
                            // launch must be resident at once, so callers that run several
                            // solves concurrently on one device switch them off
+  bool coop_wide = false;  // cooperative tridiagonalization with 16 rows per workgroup at every
+                           // size (half the workgroups of the 8-row form used up to 512 rows):
+                           // the form for solves that run concurrently
 };
 
 size_t heig_work_bytes(int nmax);

@@ -1377,7 +1377,7 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
 
 }  // namespace
 
-int pw::coop_workgroups(int n) { return ceil_div(n, n <= kCoopSmallN ? 8 : CR); }
+int pw::coop_workgroups(int n, bool wide) { return ceil_div(n, (n <= kCoopSmallN && !wide) ? 8 : CR); }
 
 namespace {
 size_t coop_bytes() { return sizeof(c128) * (4 * kCoopMaxN + 2 * kCoopMaxP) + 2 * 256; }
@@ -1441,6 +1441,10 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
            "reduced problem larger than its workspace");
   const int ldw = hw.nmax;
   const int m = n - n0;
+  // split-K workspace for the small products; none when solves run
+  // concurrently (they fill the device already, and splitting K would only
+  // add partial-sum traffic and launches)
+  const size_t skb = hw.coop_wide ? 0 : part_bytes;
   c128* L22 = hw.L + (size_t)n0 * ldw + n0;
   c128* X22 = hw.X + (size_t)n0 * ldw + n0;
   if (n0 > 0) {
@@ -1485,13 +1489,13 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   if (n0 > 0) {
     // X12 = -X11 (U12 X22)
-    PW_TRY(pw::zgemm_nn_sk(n0, m, m, 1.0, hw.T1, ldw, X22, ldw, 0.0, hw.Y, ldw, part, part_bytes, st));
+    PW_TRY(pw::zgemm_nn_sk(n0, m, m, 1.0, hw.T1, ldw, X22, ldw, 0.0, hw.Y, ldw, part, skb, st));
     PW_TRY(pw::zgemm_nn_sk(n0, m, n0, -1.0, hw.X, ldw, hw.Y, ldw, 0.0, hw.X + (size_t)n0 * ldw, ldw, part,
-                           part_bytes, st));
+                           skb, st));
     k_zero_block<<<std::min(1024, ceil_div(m * n0, 256)), 256, 0, st>>>(n0, n, n0, hw.X, ldw);
   }
   // A = X^H (H X)
-  PW_TRY(pw::zgemm_nn_sk(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, part, part_bytes, st));
+  PW_TRY(pw::zgemm_nn_sk(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, part, skb, st));
   PW_TRY((pw::zgemm_cn<double, double, double>(n, n, n, hw.X, ldw, hw.T1, ldw, hw.A, ldw, part,
                                                part_bytes, st)));
   k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.A, ldw, hw.drop, hw.info);
@@ -1500,12 +1504,16 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
     if (hw.coop_ok && n >= kCoopMinN && n <= kCoopMaxN) {
       const CoopBuf cb = coop_buf(hw);
-      const int P = pw::coop_workgroups(n);
+      const bool wide = hw.coop_wide;
+      const int P = pw::coop_workgroups(n, wide);
       k_coop_reset<<<1, 64, 0, st>>>(cb);
       // up to 512 rows: 8 rows per workgroup (twice the workgroups, half the
-      // update work per step on each); beyond, 16
-      if (n <= CB) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
-      else if (n <= 2 * CB) k_tridiag_coop<2, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      // update work per step on each) unless the wide form is asked for; beyond, 16
+      if (n <= CB && !wide) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= CB) k_tridiag_coop<1, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 2 * CB && !wide)
+        k_tridiag_coop<2, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= 2 * CB) k_tridiag_coop<2, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
       else if (n <= 4 * CB) k_tridiag_coop<4, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
       else k_tridiag_coop<8, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
     } else if (n <= kPanelMinN) {
@@ -1559,7 +1567,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     else return pw::fail(PW_EINVAL, "reduced problem larger than 4096");
   }
   // C = X Y
-  PW_TRY(pw::zgemm_nn_sk(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, part, part_bytes, st));
+  PW_TRY(pw::zgemm_nn_sk(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, part, skb, st));
   // hw.Z (eigenvectors of T) is free once the back-transform has run
   k_colnorms<<<ceil_div(nev, 4), 256, 0, st>>>(n, nev, C, ldc, hw.Z, hw.info);
   k_max_of<<<1, 256, 0, st>>>(nev, hw.Z, hw.gamma, hw.info);

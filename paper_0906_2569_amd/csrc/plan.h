@@ -131,13 +131,15 @@ size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
 pw_status dav_alloc(pw_plan p);
 // allow or forbid the cooperative (multi-workgroup) kernels of the plan's
 // reduced eigensolver; returns the previous setting
-bool dav_set_coop(pw_plan p, bool ok);
+// (wide: the form with fewer workgroups per launch, for concurrent solves)
+bool dav_set_coop(pw_plan p, bool ok, bool wide = false);
 // workgroups that cooperative launches of concurrent solves may keep
 // spinning at once (half of the device's 256 compute units): concurrent
 // solves use them only while workers x (workgroups of one launch) stays within it
 constexpr int kCoopWgBudget = 128;
 // workgroups (all resident at once) of the cooperative tridiagonalization of n rows
-int coop_workgroups(int n);
+// (wide: 16 rows per workgroup at every size)
+int coop_workgroups(int n, bool wide = false);
 bool dav_get_coop(pw_plan p);
 // destroy the context's worker streams (pw_ctx_destroy)
 void ctx_release_pool(pw_ctx ctx);

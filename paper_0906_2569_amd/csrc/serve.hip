@@ -69,8 +69,9 @@ struct pw_server_s {
       if (st == PW_OK) {
         // cooperative reduced-eigensolver kernels only while every worker's
         // launch can be resident at once
-        const int pmax = pw::coop_workgroups(r->dopts.ndim * r->nb);
-        (void)pw::dav_set_coop(plan, opts.nworkers * pmax <= pw::kCoopWgBudget);
+        const bool wide = opts.nworkers > 1;
+        const int pmax = pw::coop_workgroups(r->dopts.ndim * r->nb, wide);
+        (void)pw::dav_set_coop(plan, opts.nworkers * pmax <= pw::kCoopWgBudget, wide);
         st = davidson_solve(plan, r->nb, r->psi, r->ldpsi, r->eig, r->resid, &r->dopts, &r->stats, streams[w]);
         if (st != PW_OK) r->msg = pw_last_error();
         (void)hipStreamSynchronize(streams[w]);

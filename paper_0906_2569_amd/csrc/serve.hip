@@ -21,7 +21,8 @@ struct pw_server_s {
   pw_server_opts opts{};
   std::chrono::steady_clock::time_point t0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
+  std::condition_variable cv_work, cv_done, cv_coop;
+  int coop_units = 0;   // cooperative workgroups reserved by running requests
   struct Req {
     int64_t id;
     pw_problem prob;
@@ -67,14 +68,32 @@ struct pw_server_s {
       pw_plan plan = nullptr;
       pw_status st = pw_plan_create(ctx, &r->prob, &po, &plan);
       if (st == PW_OK) {
-        // cooperative reduced-eigensolver kernels only while every worker's
-        // launch can be resident at once
+        // Cooperative reduced-eigensolver kernels need every workgroup of a
+        // launch resident at once.  The request reserves the workgroups of its
+        // launch from the device budget for its whole solve (waiting while
+        // other requests hold theirs), so the launches that can spin at one
+        // time never exceed the budget; a launch larger than the whole budget
+        // runs without them.
         const bool wide = opts.nworkers > 1;
-        const int pmax = pw::coop_workgroups(r->dopts.ndim * r->nb, wide);
-        (void)pw::dav_set_coop(plan, opts.nworkers * pmax <= pw::kCoopWgBudget, wide);
+        const int pcoop = pw::coop_workgroups(r->dopts.ndim * r->nb, wide);
+        int reserved = 0;
+        if (pcoop <= pw::kCoopWgBudget) {
+          std::unique_lock<std::mutex> l(mu);
+          cv_coop.wait(l, [&] { return coop_units + pcoop <= pw::kCoopWgBudget; });
+          coop_units += pcoop;
+          reserved = pcoop;
+        }
+        (void)pw::dav_set_coop(plan, reserved > 0, wide);
         st = davidson_solve(plan, r->nb, r->psi, r->ldpsi, r->eig, r->resid, &r->dopts, &r->stats, streams[w]);
         if (st != PW_OK) r->msg = pw_last_error();
         (void)hipStreamSynchronize(streams[w]);
+        if (reserved > 0) {
+          {
+            std::lock_guard<std::mutex> l(mu);
+            coop_units -= reserved;
+          }
+          cv_coop.notify_all();
+        }
         (void)pw_plan_destroy(plan);
       } else {
         r->msg = pw_last_error();

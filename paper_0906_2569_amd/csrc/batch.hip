@@ -11,6 +11,7 @@
 // and small transforms of different problems share the device.
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
 #include <string>
 #include <thread>
 #include <vector>
@@ -118,7 +119,6 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
     PW_CHECK(std::adjacent_find(seen.begin(), seen.end()) == seen.end(), PW_EINVAL,
              "a plan appears twice in the batch (its workspace cannot serve two solves at once)");
   }
-  int pmax = 0;
   for (int i = 0; i < n; ++i) {
     PW_CHECK(plans[i] != nullptr, PW_EINVAL, "NULL plan in batch");
     PW_CHECK(plans[i]->ctx == ctx, PW_EINVAL, "plan of another context in batch");
@@ -127,17 +127,20 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
   const int nw = std::max(1, std::min({n, nworkers > 0 ? (int)nworkers : 8, kMaxWorkers}));
   // concurrent solves take the cooperative form with fewer workgroups per launch
   const bool wide = nw > 1;
-  for (int i = 0; i < n; ++i) pmax = std::max(pmax, pw::coop_workgroups(o.ndim * nb[i], wide));
   PW_HIP(hipSetDevice(ctx->device));
   PW_TRY(ensure_pool(ctx, nw));
   hipStream_t caller = static_cast<hipStream_t>(stream);
   std::lock_guard<std::mutex> l(ctx->mu);
   PW_TRY(fork_from(ctx, caller, nw));
 
-  // cooperative kernels only while every concurrently spinning launch fits
-  const bool coop = nw == 1 || nw * pmax <= pw::kCoopWgBudget;
-  std::vector<char> prev(n);
-  for (int i = 0; i < n; ++i) prev[i] = pw::dav_set_coop(plans[i], coop && pw::dav_get_coop(plans[i]), wide);
+  // Cooperative kernels need every workgroup of a launch resident at once:
+  // each solve reserves the workgroups of its launch from the device budget
+  // while it runs (waiting while other solves hold theirs), so the launches
+  // that can spin at one time stay within the budget.  A solve whose launch
+  // is larger than the whole budget runs without them.
+  std::mutex cmu;
+  std::condition_variable ccv;
+  int coop_units = 0;
 
   std::vector<pw_status> st(n, PW_OK);
   std::vector<std::string> msg(n);
@@ -147,10 +150,29 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
     for (;;) {
       const int i = next.fetch_add(1);
       if (i >= n) break;
+      const bool allowed = pw::dav_get_coop(plans[i]);
+      const int pcoop = pw::coop_workgroups(o.ndim * nb[i], wide);
+      int reserved = 0;
+      if (allowed && (nw == 1 || pcoop <= pw::kCoopWgBudget)) {
+        std::unique_lock<std::mutex> cl(cmu);
+        ccv.wait(cl, [&] { return nw == 1 || coop_units + pcoop <= pw::kCoopWgBudget; });
+        coop_units += pcoop;
+        reserved = pcoop;
+      }
+      (void)pw::dav_set_coop(plans[i], reserved > 0, wide);
       pw_david_stats one{};
       st[i] = davidson_solve(plans[i], nb[i], psi[i], ldpsi[i], eig[i], resid[i], &o, &one, ctx->pool[w]);
       if (stats) stats[i] = one;
       if (st[i] != PW_OK) msg[i] = pw_last_error();
+      (void)hipStreamSynchronize(ctx->pool[w]);
+      (void)pw::dav_set_coop(plans[i], allowed);
+      if (reserved > 0) {
+        {
+          std::lock_guard<std::mutex> cl(cmu);
+          coop_units -= reserved;
+        }
+        ccv.notify_all();
+      }
     }
   };
   std::vector<std::thread> threads;
@@ -158,7 +180,6 @@ extern "C" pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan
   for (int w = 1; w < nw; ++w) threads.emplace_back(work, w);
   work(0);
   for (auto& t : threads) t.join();
-  for (int i = 0; i < n; ++i) (void)pw::dav_set_coop(plans[i], prev[i]);
   if (status)
     for (int i = 0; i < n; ++i) status[i] = st[i];
   PW_TRY(join_into(ctx, caller, nw));

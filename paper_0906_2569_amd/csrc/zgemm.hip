@@ -56,6 +56,28 @@ __device__ __forceinline__ int mcol(int lane) { return lane & 15; }
 // of 18277 x 128 rows and columns (572 tiles) is resident in one round.
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
 
+// Workgroups go to the 8 XCDs round-robin in linear launch order.  Each XCD is
+// given one contiguous range of a work order in which tile y (YFAST) or tile x
+// runs fastest, then the other, then z: the workgroups that read the same
+// operand strips then run on one XCD at about the same time and share its L2.
+template <bool YFAST>
+__device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int T = gx * gy * gridDim.z;
+  const int L = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int x = L & 7, s = L >> 3, per = T >> 3, rem = T & 7;
+  // XCD x holds slots s < per + (x < rem): a bijection onto [0, T)
+  const int w = x < rem ? x * (per + 1) + s : rem * (per + 1) + (x - rem) * per + s;
+  if (YFAST) {
+    by = w % gy;
+    bx = (w / gy) % gx;
+  } else {
+    bx = w % gx;
+    by = (w / gx) % gy;
+  }
+  bz = w / (gx * gy);
+}
+
 template <typename T>
 struct Tile {
   T ar[BK][BM + 1], ai[BK][BM + 1], br[BK][BN + 1], bi[BK][BN + 1];
@@ -100,9 +122,11 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
           const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
-  const int zs = (int)blockIdx.z % nsplit;
-  const cpx<TB>* __restrict__ B = (int)blockIdx.z >= nsplit ? B1 : B0;
+  int bx, by, bz;
+  xcd_block<false>(bx, by, bz);   // the output tiles of one K chunk share an XCD
+  const int m0 = bx * BM, n0 = by * BN;
+  const int zs = bz % nsplit;
+  const cpx<TB>* __restrict__ B = bz >= nsplit ? B1 : B0;
   const int kbeg = zs * kchunk, kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -144,7 +168,7 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
     tile_mma<T>(t, cr, ci, wm, wn, lane);
     __syncthreads();
   }
-  cpx<T>* out = P + (size_t)blockIdx.z * M * N;
+  cpx<T>* out = P + (size_t)bz * M * N;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -158,9 +182,9 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
 }
 
 // C[n*ldc + m] = alpha sum_k A[k*lda + m] B[n*ldb + k] + beta C[n*ldc + m]
-// blockIdx.z selects the product: (A0, C0) or (A1, C1), same B (two products of
+// The z index of the grid selects the product: (A0, C0) or (A1, C1), same B (two products of
 // one launch fill the device better than two launches).
-// SPLIT: blockIdx.z is instead the K chunk [z kchunk, (z + 1) kchunk) of the one
+// SPLIT: the z index is instead the K chunk [z kchunk, (z + 1) kchunk) of the one
 // product (A0), whose partial tile goes to P[z][n][m] unscaled, for k_reduce.
 template <typename T, typename TA, typename TB, bool SPLIT = false>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
@@ -169,13 +193,15 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
           c128* __restrict__ C1, int ldc, const int* __restrict__ guard, int kchunk = 0,
           cpx<T>* __restrict__ P = nullptr) {
   if (guard != nullptr && *guard != 0) return;
-  const cpx<TA>* __restrict__ A = (!SPLIT && blockIdx.z) ? A1 : A0;
-  c128* __restrict__ C = (!SPLIT && blockIdx.z) ? C1 : C0;
-  const int kbeg = SPLIT ? (int)blockIdx.z * kchunk : 0;
+  int bx, by, bz;
+  xcd_block<true>(bx, by, bz);    // the column tiles of one row strip of A share an XCD
+  const cpx<TA>* __restrict__ A = (!SPLIT && bz) ? A1 : A0;
+  c128* __restrict__ C = (!SPLIT && bz) ? C1 : C0;
+  const int kbeg = SPLIT ? bz * kchunk : 0;
   const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
   __shared__ Tile<T> t;
   typedef typename Mma<T>::v4 v4;
-  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int m0 = bx * BM, n0 = by * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   v4 cr[2][2], ci[2][2];
@@ -225,7 +251,7 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
     __syncthreads();
   }
   if constexpr (SPLIT) {
-    cpx<T>* out = P + (size_t)blockIdx.z * M * N;
+    cpx<T>* out = P + (size_t)bz * M * N;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll

@@ -139,6 +139,118 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
   }
 }
 
+// The same factorization with the matrix in registers, for n <= 128: the
+// 32 x 32 threads of one workgroup each hold a 4 x 4 set of entries (rows
+// tr + 32 p, columns tc + 32 q), so the rank-1 updates touch no memory.  Step
+// j reads column j as published (unscaled) by its owners at the end of step
+// j - 1 through LDS (two buffers by parity, one barrier per column); every
+// thread takes the same pivot decision from the same values.  Operations
+// and their order per entry are those of k_chol.
+constexpr int kChRegSlots = 4;
+constexpr int kChRegN = 32 * kChRegSlots;
+__global__ void __launch_bounds__(1024) k_chol_reg(int n, int nev, double drop_tol, c128* __restrict__ L, int ld,
+                                                  int* __restrict__ drop, int* __restrict__ info) {
+  constexpr int S = kChRegSlots;
+  __shared__ c128 s_col[2][kChRegN];
+  __shared__ double s_diag0[kChRegN];
+  const int tr = threadIdx.x & 31, tc = threadIdx.x >> 5;
+  c128 a[S][S];
+#pragma unroll
+  for (int p = 0; p < S; ++p)
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int i = tr + 32 * p, k = tc + 32 * q;
+      a[p][q] = (i < n && k < n) ? L[(size_t)k * ld + i] : c128{0.0, 0.0};
+    }
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s_diag0[i] = L[(size_t)i * ld + i].x;
+  if (tc == 0) {
+#pragma unroll
+    for (int p = 0; p < S; ++p)
+      if (tr + 32 * p < n) s_col[0][tr + 32 * p] = a[p][0];
+  }
+  __syncthreads();
+  bool bad = false;
+  int ndrop = 0;
+  // column j = 32 qj + jj: the slot qj of its entries is a compile-time
+  // index in each unrolled copy (no selects over the register array)
+#pragma unroll
+  for (int qj = 0; qj < S; ++qj) {
+    if (bad) break;
+    for (int jj = 0; jj < 32; ++jj) {
+      const int j = 32 * qj + jj;
+      if (j >= n) break;
+      const int b = j & 1;
+      const double d = s_col[b][j].x;
+      const double d0 = s_diag0[j];
+      if (!isfinite(d) || !(d0 >= 0.0) || d < -drop_tol * d0) {
+        bad = true;   // the same decision in every thread
+        break;
+      }
+      const bool keep = d > drop_tol * d0;
+      const double r = keep ? sqrt(d) : 1.0;
+      const double inv = keep ? 1.0 / r : 0.0;
+      ndrop += keep ? 0 : 1;
+      if (threadIdx.x == 0) drop[j] = keep ? 0 : 1;
+      // column j of L in its owners' registers: r on the diagonal, a / r below
+      // (a dropped direction: 1 and zeros)
+      if (tc == jj) {
+#pragma unroll
+        for (int p = 0; p < S; ++p) {
+          const int i = tr + 32 * p;
+          if (i == j) a[p][qj] = c128{r, 0.0};
+          else if (i > j) a[p][qj] = c128{a[p][qj].x * inv, a[p][qj].y * inv};
+        }
+      }
+      // trailing update L22 -= l l^H on the lower triangle, l_i = col_i / r
+      if (keep) {
+#pragma unroll
+        for (int q = qj; q < S; ++q) {
+          const int k = tc + 32 * q;
+          if (k <= j || k >= n) continue;
+          const c128 ck = s_col[b][k];
+          const c128 lk = c128{ck.x * inv, ck.y * inv};
+#pragma unroll
+          for (int p = q; p < S; ++p) {
+            const int i = tr + 32 * p;
+            if (i < k || i >= n) continue;
+            const c128 ci = s_col[b][i];
+            const c128 li = c128{ci.x * inv, ci.y * inv};
+            const c128 u = cmulc(lk, li);   // l_i conj(l_k)
+            a[p][q] = c128{a[p][q].x - u.x, a[p][q].y - u.y};
+          }
+        }
+      }
+      // publish column j + 1 (updated, unscaled) for the next step
+      const int j1 = j + 1;
+      if (j1 < n && tc == (j1 & 31)) {
+        if (jj < 31) {
+#pragma unroll
+          for (int p = 0; p < S; ++p) {
+            const int i = tr + 32 * p;
+            if (i >= j1 && i < n) s_col[b ^ 1][i] = a[p][qj];
+          }
+        } else if (qj + 1 < S) {
+#pragma unroll
+          for (int p = 0; p < S; ++p) {
+            const int i = tr + 32 * p;
+            if (i >= j1 && i < n) s_col[b ^ 1][i] = a[p][qj + 1];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) *info = (bad || n - ndrop < nev) ? 1 : 0;
+  // the factor, with the strict upper triangle cleared (it is used as a full matrix)
+#pragma unroll
+  for (int p = 0; p < S; ++p)
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      const int i = tr + 32 * p, k = tc + 32 * q;
+      if (i < n && k < n) L[(size_t)k * ld + i] = (i >= k) ? a[p][q] : c128{0.0, 0.0};
+    }
+}
+
 // Blocked form of the same factorization for large n (right-looking): a
 // workgroup factors a panel of kChPanel columns with the rule above (only
 // the panel's own columns are updated), the trailing matrix then receives
@@ -1459,7 +1571,9 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);
-    if (m < kChBlockedMinN) {
+    if (m <= kChRegN) {
+      k_chol_reg<<<1, 1024, 0, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+    } else if (m < kChBlockedMinN) {
       k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
     } else {
       double* diag0 = hw.scratch;   // free until the eigenvector step

@@ -14,6 +14,7 @@
 // rounding), Vt being the discrete Fourier coefficients of V(r) on the grid;
 // with n_d >= 4 max|m_d| + 1 no wrapped term reaches the sphere.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -154,11 +155,13 @@ k_plane(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
 
 // ---------------------------------------------------------------------------
 // pass 2, register-resident variant for n1 = n2 = 4 LS: one workgroup per
-// (z plane, band); each 1D transform runs on one quad of lanes in VGPRs
-// (see fft_reg.h); LDS only holds the plane's x columns Y[nxr][n2 + 1] as
-// the transpose between the y and x transforms.
+// (PP consecutive z planes, band); each 1D transform runs on one quad of lanes
+// in VGPRs (see fft_reg.h); LDS only holds the planes' x columns
+// Y[PP][nxr][n2 + 1] as the transpose between the y and x transforms.  The
+// columns (rows) of the PP planes form one index space per phase, so a
+// workgroup's last pass over them is fuller than with one plane.
 // ---------------------------------------------------------------------------
-template <typename T, int LS>
+template <typename T, int LS, int PP>
 __global__ void __launch_bounds__(512)
 k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
             const cpx<T>* __restrict__ tw1g, const cpx<T>* __restrict__ tw2g) {
@@ -168,25 +171,28 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   const int nxr = m.nxr, nst = m.nst;
   cpx<T>* tw1 = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw2 = tw1 + N;
-  cpx<T>* Y = tw2 + N;                                   // [nxr][YS]
-  int* hx_of = reinterpret_cast<int*>(Y + nxr * YS);     // [N]
-  const int z = blockIdx.x, band = blockIdx.y;
-  cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
-  const T* vz = vr + (size_t)z * N * N;
+  cpx<T>* Y = tw2 + N;                                        // [PP][nxr][YS]
+  int* hx_of = reinterpret_cast<int*>(Y + PP * nxr * YS);     // [N]
+  const int z0 = blockIdx.x * PP, band = blockIdx.y;
+  const int np = min(PP, m.n3 - z0);                          // planes of this workgroup
+  cpx<T>* st = sticks + ((size_t)band * m.n3 + z0) * m.ldst;   // plane pz at st + pz ldst
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     tw1[i] = tw1g[i];
     tw2[i] = tw2g[i];
     hx_of[i] = m.i1_hx[i];
   }
-  for (int i = threadIdx.x; i < nxr * YS; i += blockDim.x) Y[i] = cpx<T>{T(0), T(0)};
+  for (int i = threadIdx.x; i < np * nxr * YS; i += blockDim.x) Y[i] = cpx<T>{T(0), T(0)};
   __syncthreads();
-  for (int s = threadIdx.x; s < nst; s += blockDim.x) Y[m.st_hx[s] * YS + m.st_i2[s]] = st[s];
+  for (int e = threadIdx.x; e < np * nst; e += blockDim.x) {
+    const int pz = e / nst, s = e - pz * nst;
+    Y[(pz * nxr + m.st_hx[s]) * YS + m.st_i2[s]] = st[(size_t)pz * m.ldst + s];
+  }
   __syncthreads();
   const int q = threadIdx.x & 3, nquads = blockDim.x >> 2;
   const int pb = regfft::quad_block(q);   // block of the transform held after inv_dit
   const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
-  // inverse y transforms of the x columns
-  for (int c = threadIdx.x >> 2; c < nxr; c += nquads) {
+  // inverse y transforms of the x columns (column c = pz nxr + x)
+  for (int c = threadIdx.x >> 2; c < np * nxr; c += nquads) {
     cpx<T> x[LS];
     cpx<T>* col = Y + c * YS;
 #pragma unroll
@@ -196,28 +202,32 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
     for (int k = 0; k < LS; ++k) col[k + LS * pb] = x[k];
   }
   __syncthreads();
-  // rows: inverse x, V(r), forward x; only the x columns of the sphere are read and written
-  for (int r = threadIdx.x >> 2; r < N; r += nquads) {
+  // rows (row index pz N + r): inverse x, V(r), forward x; only the x columns
+  // of the sphere are read and written
+  for (int rr = threadIdx.x >> 2; rr < np * N; rr += nquads) {
+    const int pz = rr / N, r = rr - pz * N;
+    const cpx<T>* Yp = Y + pz * nxr * YS;
     cpx<T> x[LS];
 #pragma unroll
     for (int j = 0; j < LS; ++j) {
       const int hx = hx_of[q + 4 * j];
-      x[j] = hx >= 0 ? Y[hx * YS + r] : cpx<T>{T(0), T(0)};
+      x[j] = hx >= 0 ? Yp[hx * YS + r] : cpx<T>{T(0), T(0)};
     }
     regfft::inv_dit<LS, T>(x, q, ql, tw1);
-    const T* vrow = vz + (size_t)r * N + LS * pb;
+    const T* vrow = vr + ((size_t)(z0 + pz) * N + r) * N + LS * pb;
 #pragma unroll
     for (int k = 0; k < LS; ++k) x[k] = x[k] * vrow[k];
     regfft::fwd_dif<LS, T>(x, q, ql, tw1);
+    cpx<T>* Yw = Y + pz * nxr * YS;
 #pragma unroll
     for (int j = 0; j < LS; ++j) {
       const int hx = hx_of[q + 4 * j];
-      if (hx >= 0) Y[hx * YS + r] = x[j];
+      if (hx >= 0) Yw[hx * YS + r] = x[j];
     }
   }
   __syncthreads();
   // forward y transforms
-  for (int c = threadIdx.x >> 2; c < nxr; c += nquads) {
+  for (int c = threadIdx.x >> 2; c < np * nxr; c += nquads) {
     cpx<T> x[LS];
     cpx<T>* col = Y + c * YS;
 #pragma unroll
@@ -227,11 +237,21 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
     for (int j = 0; j < LS; ++j) col[q + 4 * j] = x[j];
   }
   __syncthreads();
-  for (int s = threadIdx.x; s < nst; s += blockDim.x) st[s] = Y[m.st_hx[s] * YS + m.st_i2[s]];
+  for (int e = threadIdx.x; e < np * nst; e += blockDim.x) {
+    const int pz = e / nst, s = e - pz * nst;
+    st[(size_t)pz * m.ldst + s] = Y[(pz * nxr + m.st_hx[s]) * YS + m.st_i2[s]];
+  }
 }
 
 template <typename T>
 using PlaneRegFn = void (*)(SphereMap, cpx<T>*, const T*, const cpx<T>*, const cpx<T>*);
+
+// z planes per workgroup of the register plane kernel: two in float64 (a
+// 256-thread workgroup then fills its last passes over columns and rows
+// better; 78 KB of LDS at n = 72 keeps two workgroups per CU), one in
+// float32 (up to 512 threads cover every row in one pass)
+template <typename T>
+constexpr int plane_reg_pp() { return sizeof(T) == 8 ? 2 : 1; }
 
 // register-resident plane kernel for n1 = n2 = 4 LS, or nullptr
 template <typename T>
@@ -239,28 +259,32 @@ PlaneRegFn<T> plane_reg_kernel(int n1, int n2) {
   if (n1 != n2 || n1 % 4 != 0) return nullptr;
   const int ls = n1 / 4;
   const bool f64 = sizeof(T) == 8;
+  constexpr int PP = plane_reg_pp<T>();
   switch (ls) {
-    case 8: return k_plane_reg<T, 8>;
-    case 9: return k_plane_reg<T, 9>;
-    case 10: return k_plane_reg<T, 10>;
-    case 12: return k_plane_reg<T, 12>;
-    case 15: return k_plane_reg<T, 15>;
-    case 16: return k_plane_reg<T, 16>;
-    case 18: return k_plane_reg<T, 18>;
-    case 20: return f64 ? nullptr : k_plane_reg<T, 20>;
-    case 24: return f64 ? nullptr : k_plane_reg<T, 24>;
-    case 25: return f64 ? nullptr : k_plane_reg<T, 25>;
-    case 27: return f64 ? nullptr : k_plane_reg<T, 27>;
-    case 30: return f64 ? nullptr : k_plane_reg<T, 30>;
-    case 32: return f64 ? nullptr : k_plane_reg<T, 32>;
-    case 36: return f64 ? nullptr : k_plane_reg<T, 36>;
+    case 8: return k_plane_reg<T, 8, PP>;
+    case 9: return k_plane_reg<T, 9, PP>;
+    case 10: return k_plane_reg<T, 10, PP>;
+    case 12: return k_plane_reg<T, 12, PP>;
+    case 15: return k_plane_reg<T, 15, PP>;
+    case 16: return k_plane_reg<T, 16, PP>;
+    case 18: return k_plane_reg<T, 18, PP>;
+    case 20: return f64 ? nullptr : k_plane_reg<T, 20, PP>;
+    case 24: return f64 ? nullptr : k_plane_reg<T, 24, PP>;
+    case 25: return f64 ? nullptr : k_plane_reg<T, 25, PP>;
+    case 27: return f64 ? nullptr : k_plane_reg<T, 27, PP>;
+    case 30: return f64 ? nullptr : k_plane_reg<T, 30, PP>;
+    case 32: return f64 ? nullptr : k_plane_reg<T, 32, PP>;
+    case 36: return f64 ? nullptr : k_plane_reg<T, 36, PP>;
     default: return nullptr;
   }
 }
 
+// largest LDS of the register plane kernel: two workgroups per CU (160 KB)
+constexpr size_t kPlaneRegMaxLds = 80 * 1024;
+
 template <typename T>
 size_t plane_reg_lds_bytes(int n, int nxr) {
-  return sizeof(cpx<T>) * (2 * (size_t)n + (size_t)nxr * (n + 1)) + sizeof(int) * (size_t)n;
+  return sizeof(cpx<T>) * (2 * (size_t)n + (size_t)plane_reg_pp<T>() * nxr * (n + 1)) + sizeof(int) * (size_t)n;
 }
 
 // float64 transforms use ~240 VGPRs (2 waves per SIMD): 256-thread groups
@@ -870,7 +894,16 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const size_t zl = z_lds_bytes<T>(p->n3);
   const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
   PlaneRegFn<T> preg = p->use_reg_plane ? plane_reg_kernel<T>(p->n1, p->n2) : nullptr;
-  if (preg && plane_reg_lds_bytes<T>(p->n1, p->nxr) > 64 * 1024) preg = nullptr;
+  const size_t plds = plane_reg_lds_bytes<T>(p->n1, p->nxr);
+  if (preg && plds > kPlaneRegMaxLds) preg = nullptr;
+  if (preg && plds > 64 * 1024) {
+    // above the default per-workgroup limit: raised once per kernel
+    static std::atomic<const void*> raised_for{nullptr};
+    if (raised_for.load() != (const void*)preg) {
+      PW_HIP(hipFuncSetAttribute((const void*)preg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneRegMaxLds));
+      raised_for.store((const void*)preg);
+    }
+  }
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
   const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
@@ -892,7 +925,7 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
       if (preg)
-        preg<<<dim3(p->n3, nbc), plane_reg_threads<T>(p->n1, p->nxr), plane_reg_lds_bytes<T>(p->n1, p->nxr), s>>>(
+        preg<<<dim3(ceil_div(p->n3, plane_reg_pp<T>()), nbc), plane_reg_threads<T>(p->n1, p->nxr), plds, s>>>(
             m, st, vr, tw1, tw2);
       else
         k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);

@@ -246,20 +246,13 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
 template <typename T>
 using PlaneRegFn = void (*)(SphereMap, cpx<T>*, const T*, const cpx<T>*, const cpx<T>*);
 
-// z planes per workgroup of the register plane kernel: two in float64 (a
-// 256-thread workgroup then fills its last passes over columns and rows
-// better; 78 KB of LDS at n = 72 keeps two workgroups per CU), one in
-// float32 (up to 512 threads cover every row in one pass)
-template <typename T>
-constexpr int plane_reg_pp() { return sizeof(T) == 8 ? 2 : 1; }
-
-// register-resident plane kernel for n1 = n2 = 4 LS, or nullptr
-template <typename T>
+// register-resident plane kernel for n1 = n2 = 4 LS with PP z planes per
+// workgroup, or nullptr
+template <typename T, int PP>
 PlaneRegFn<T> plane_reg_kernel(int n1, int n2) {
   if (n1 != n2 || n1 % 4 != 0) return nullptr;
   const int ls = n1 / 4;
   const bool f64 = sizeof(T) == 8;
-  constexpr int PP = plane_reg_pp<T>();
   switch (ls) {
     case 8: return k_plane_reg<T, 8, PP>;
     case 9: return k_plane_reg<T, 9, PP>;
@@ -279,12 +272,12 @@ PlaneRegFn<T> plane_reg_kernel(int n1, int n2) {
   }
 }
 
-// largest LDS of the register plane kernel: two workgroups per CU (160 KB)
+// largest LDS of the two-plane register kernel: two workgroups per CU (160 KB)
 constexpr size_t kPlaneRegMaxLds = 80 * 1024;
 
 template <typename T>
-size_t plane_reg_lds_bytes(int n, int nxr) {
-  return sizeof(cpx<T>) * (2 * (size_t)n + (size_t)plane_reg_pp<T>() * nxr * (n + 1)) + sizeof(int) * (size_t)n;
+size_t plane_reg_lds_bytes(int n, int nxr, int pp) {
+  return sizeof(cpx<T>) * (2 * (size_t)n + (size_t)pp * nxr * (n + 1)) + sizeof(int) * (size_t)n;
 }
 
 // float64 transforms use ~240 VGPRs (2 waves per SIMD): 256-thread groups
@@ -893,9 +886,20 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   PW_CHECK(cb > 0, PW_EINVAL, "grid too large for this precision's plane pass");
   const size_t zl = z_lds_bytes<T>(p->n3);
   const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
-  PlaneRegFn<T> preg = p->use_reg_plane ? plane_reg_kernel<T>(p->n1, p->n2) : nullptr;
-  const size_t plds = plane_reg_lds_bytes<T>(p->n1, p->nxr);
-  if (preg && plds > kPlaneRegMaxLds) preg = nullptr;
+  // two z planes per workgroup where their LDS fits (the last passes over
+  // columns and rows are fuller), else one
+  PlaneRegFn<T> preg = nullptr;
+  int ppw = 0;
+  if (p->use_reg_plane) {
+    if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 2) <= kPlaneRegMaxLds) {
+      preg = plane_reg_kernel<T, 2>(p->n1, p->n2);
+      ppw = 2;
+    } else if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 1) <= 64 * 1024) {
+      preg = plane_reg_kernel<T, 1>(p->n1, p->n2);
+      ppw = 1;
+    }
+  }
+  const size_t plds = preg ? plane_reg_lds_bytes<T>(p->n1, p->nxr, ppw) : 0;
   if (preg && plds > 64 * 1024) {
     // above the default per-workgroup limit: raised once per kernel
     static std::atomic<const void*> raised_for{nullptr};
@@ -925,7 +929,7 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
       if (preg)
-        preg<<<dim3(ceil_div(p->n3, plane_reg_pp<T>()), nbc), plane_reg_threads<T>(p->n1, p->nxr), plds, s>>>(
+        preg<<<dim3(ceil_div(p->n3, ppw), nbc), plane_reg_threads<T>(p->n1, p->nxr), plds, s>>>(
             m, st, vr, tw1, tw2);
       else
         k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);

@@ -161,3 +161,16 @@ def test_register_plane_pass_sizes(ctx, n, prec):
         got, ref = got[:, rows], ref_rows
     err = _rel_err(got, ref)
     assert err <= (1e-11 if prec == 0 else 2e-6), err
+
+
+@pytest.mark.parametrize("n,n3,prec", [(32, 27, 0), (32, 27, 1), (72, 45, 0), (72, 45, 1)])
+def test_register_plane_pass_odd_planes(ctx, n, n3, prec):
+    # n1 = n2 = 4 LS with an odd number of z planes: the plane pass takes two
+    # planes per workgroup, and its last workgroup holds a single plane
+    p = pwgen.tiny_cell(40 + n, a=6.0, ecut_ry=6.0 if n == 32 else 12.0, natoms=2, nb=5,
+                        kfrac=(0.25, -0.25, 0.0), nr=(n, n, n3))
+    assert max(pwgen.min_grid(p.miller)) <= n3
+    got = _hpsi(ctx, p, p.psi0, prec=prec)
+    ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
+    err = _rel_err(got, ref)
+    assert err <= (1e-11 if prec == 0 else 2e-6), err

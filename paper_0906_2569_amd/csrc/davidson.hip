@@ -196,7 +196,9 @@ __global__ void k_restart(int nb, const double* __restrict__ eps, c128* __restri
 
 // columns [c0, c1) were computed for rows [0, c1): mirror them into rows
 // [c0, c1) of columns [0, c0), and make the new diagonal block exactly Hermitian
-__global__ void k_herm_fill(int c0, int c1, c128* __restrict__ m, int ldm) {
+// (blockIdx.y selects the matrix: m0 or m1, one launch for H and S)
+__global__ void k_herm_fill(int c0, int c1, c128* __restrict__ m0, c128* __restrict__ m1, int ldm) {
+  c128* __restrict__ m = blockIdx.y ? m1 : m0;
   const int nn = c1 - c0;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < nn * c1; idx += gridDim.x * blockDim.x) {
     const int i = c0 + idx % nn;   // new row
@@ -400,8 +402,7 @@ struct Solver {
                              W.ld, W.hred + (size_t)c0 * ldm, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes,
                              st));
     const int blocks = std::min(1024, ceil_div((size_t)(c1 - c0) * c1, 256));
-    k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.hred, ldm);
-    k_herm_fill<<<blocks, 256, 0, st>>>(c0, c1, W.sred, ldm);
+    k_herm_fill<<<dim3(blocks, 2), 256, 0, st>>>(c0, c1, W.hred, W.sred, ldm);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }

@@ -148,8 +148,12 @@ __global__ void __launch_bounds__(NTL) k_chol(int n, int nev, double drop_tol, c
 // and their order per entry are those of k_chol.
 constexpr int kChRegSlots = 4;
 constexpr int kChRegN = 32 * kChRegSlots;
+// It also does the rank check over all n_all directions of the basis (this
+// block is the last n of them; drop_all holds the flags of the earlier rows):
+// info = 1 when fewer than nev_all remain.
 __global__ void __launch_bounds__(1024) k_chol_reg(int n, int nev, double drop_tol, c128* __restrict__ L, int ld,
-                                                  int* __restrict__ drop, int* __restrict__ info) {
+                                                  int* __restrict__ drop, int* __restrict__ info,
+                                                  const int* __restrict__ drop_all, int n_all, int nev_all) {
   constexpr int S = kChRegSlots;
   __shared__ c128 s_col[2][kChRegN];
   __shared__ double s_diag0[kChRegN];
@@ -240,7 +244,16 @@ __global__ void __launch_bounds__(1024) k_chol_reg(int n, int nev, double drop_t
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) *info = (bad || n - ndrop < nev) ? 1 : 0;
+  // rank check: the rows before this block (drop_all[0, n_all - n), from
+  // earlier factorizations) plus this block's n - ndrop kept directions
+  __shared__ int s_kept;
+  if (threadIdx.x == 0) s_kept = 0;
+  __syncthreads();
+  int kept = 0;
+  for (int i = threadIdx.x; i < n_all - n; i += blockDim.x) kept += drop_all[i] ? 0 : 1;
+  atomicAdd(&s_kept, kept);
+  __syncthreads();
+  if (threadIdx.x == 0) *info = (bad || n - ndrop < nev || s_kept + (n - ndrop) < nev_all) ? 1 : 0;
   // the factor, with the strict upper triangle cleared (it is used as a full matrix)
 #pragma unroll
   for (int p = 0; p < S; ++p)
@@ -371,9 +384,20 @@ __global__ void k_zero_block(int r0, int r1, int c1, c128* __restrict__ X, int l
 }
 
 // Dropped directions are decoupled from the transformed matrix and moved far
-// above the spectrum, so they never enter the lowest nev eigenpairs.
+// above the spectrum, so they never enter the lowest nev eigenpairs.  The
+// launch also clears gamma and, when the cooperative tridiagonalization
+// follows, its barrier counter and failure flag (coop_count, coop_fail; null
+// otherwise).
 __global__ void k_isolate(int n, c128* __restrict__ A, int ld, const int* __restrict__ drop,
-                          const int* __restrict__ info) {
+                          const int* __restrict__ info, unsigned* __restrict__ coop_count,
+                          unsigned* __restrict__ coop_fail, double* __restrict__ gamma) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *gamma = 0.0;   // maximum taken by k_colnorms at the end of the solve
+    if (coop_count != nullptr) {
+      *coop_count = 0u;
+      *coop_fail = 0u;
+    }
+  }
   if (*info != 0) return;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * n; idx += gridDim.x * blockDim.x) {
     const int i = idx % n, j = idx / n;
@@ -381,11 +405,13 @@ __global__ void k_isolate(int n, c128* __restrict__ A, int ld, const int* __rest
   }
 }
 
-// gamma = max_k || C[:, k] ||_2  (growth factor of the Ritz rotation)
-// largest column norm of C[n][nev]: one wave per column (coalesced rows) into
-// part[nev], then k_max_of over them
+// gamma = max_k || C[:, k] ||_2  (growth factor of the Ritz rotation): one
+// wave per column (coalesced rows), then an atomic maximum over the bit
+// patterns of the norms (non-negative doubles order as unsigned integers; the
+// maximum does not depend on the order).  gamma is cleared by k_isolate
+// earlier in the same solve; a NaN norm is left out, as fmax would.
 __global__ void __launch_bounds__(256) k_colnorms(int n, int nev, const c128* __restrict__ C, int ldc,
-                                                  double* __restrict__ part, const int* __restrict__ info) {
+                                                  double* __restrict__ gamma, const int* __restrict__ info) {
   if (*info != 0) return;
   const int lane = threadIdx.x & 63;
   const int k = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
@@ -396,22 +422,10 @@ __global__ void __launch_bounds__(256) k_colnorms(int n, int nev, const c128* __
     s += v.x * v.x + v.y * v.y;
   }
   for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-  if (lane == 0) part[k] = sqrt(s);
-}
-
-__global__ void k_max_of(int nev, const double* __restrict__ part, double* __restrict__ gamma,
-                         const int* __restrict__ info) {
-  __shared__ double red[4];
-  double mx = 0.0;
-  if (*info == 0)
-    for (int k = threadIdx.x; k < nev; k += blockDim.x) mx = fmax(mx, part[k]);
-  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double m = 0.0;
-    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) m = fmax(m, red[w]);
-    *gamma = m;
+  if (lane == 0) {
+    const double v = sqrt(s);
+    if (v == v)
+      atomicMax(reinterpret_cast<unsigned long long*>(gamma), (unsigned long long)__double_as_longlong(v));
   }
 }
 
@@ -742,10 +756,6 @@ __device__ __forceinline__ c128 xload(const c128* p) {
   const unsigned long long lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   const unsigned long long hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   return c128{__longlong_as_double((long long)lo), __longlong_as_double((long long)hi)};
-}
-
-__global__ void k_coop_reset(CoopBuf cb) {
-  if (threadIdx.x == 0) { *cb.count = 0u; *cb.fail = 0u; }
 }
 
 // Cross-lane moves of a double through DPP (no LDS traffic).  The four row
@@ -1572,7 +1582,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   {
     pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);
     if (m <= kChRegN) {
-      k_chol_reg<<<1, 1024, 0, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+      k_chol_reg<<<1, 1024, 0, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info, hw.drop, n, nev);
     } else if (m < kChBlockedMinN) {
       k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
     } else {
@@ -1596,7 +1606,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
                                                                                 hw.info);
     }
   }
-  k_rank_check<<<1, 256, 0, st>>>(n, nev, hw.drop, hw.info);
+  if (m > kChRegN) k_rank_check<<<1, 256, 0, st>>>(n, nev, hw.drop, hw.info);   // else done by k_chol_reg
   {
     pw::ProfScope ps(pw::PK_TRINV, st, 8.0 / 3.0 * m * m * (double)m);
     k_trinv<<<m, 256, sizeof(c128) * m, st>>>(m, L22, ldw, X22, ldw, hw.info);
@@ -1612,15 +1622,17 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   PW_TRY(pw::zgemm_nn_sk(n, n, n, 1.0, H, ld, hw.X, ldw, 0.0, hw.T1, ldw, part, skb, st));
   PW_TRY((pw::zgemm_cn<double, double, double>(n, n, n, hw.X, ldw, hw.T1, ldw, hw.A, ldw, part,
                                                part_bytes, st)));
-  k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(n, hw.A, ldw, hw.drop, hw.info);
+  const bool coop_tri = hw.coop_ok && n >= kCoopMinN && n <= kCoopMaxN;
+  k_isolate<<<std::min(1024, ceil_div(n * n, 256)), 256, 0, st>>>(
+      n, hw.A, ldw, hw.drop, hw.info, coop_tri ? coop_buf(hw).count : nullptr, coop_tri ? coop_buf(hw).fail : nullptr,
+      hw.gamma);
   // tridiagonalize, eigenvalues, eigenvectors of T, back-transform
   {
     pw::ProfScope ps(pw::PK_TRIDIAG, st, 16.0 / 3.0 * n * n * (double)n);
-    if (hw.coop_ok && n >= kCoopMinN && n <= kCoopMaxN) {
-      const CoopBuf cb = coop_buf(hw);
+    if (coop_tri) {
+      const CoopBuf cb = coop_buf(hw);   // counter and flag cleared by k_isolate
       const bool wide = hw.coop_wide;
       const int P = pw::coop_workgroups(n, wide);
-      k_coop_reset<<<1, 64, 0, st>>>(cb);
       // up to 512 rows: 8 rows per workgroup (twice the workgroups, half the
       // update work per step on each) unless the wide form is asked for; beyond, 16
       if (n <= CB && !wide) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
@@ -1683,8 +1695,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   // C = X Y
   PW_TRY(pw::zgemm_nn_sk(n, nev, n, 1.0, hw.X, ldw, hw.Y, ldw, 0.0, C, ldc, part, skb, st));
   // hw.Z (eigenvectors of T) is free once the back-transform has run
-  k_colnorms<<<ceil_div(nev, 4), 256, 0, st>>>(n, nev, C, ldc, hw.Z, hw.info);
-  k_max_of<<<1, 256, 0, st>>>(nev, hw.Z, hw.gamma, hw.info);
+  k_colnorms<<<ceil_div(nev, 4), 256, 0, st>>>(n, nev, C, ldc, hw.gamma, hw.info);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }

@@ -323,11 +323,16 @@ __device__ __forceinline__ cpx<T> add_groups(const cpx<T> (*s)[64], int x) {
   return v;
 }
 
-// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]; block (64, RZ)
+// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]; block (64, RZ).
+// gridDim.y = 2 sums two products in one launch: blockIdx.y = 1 takes the
+// partials after the first product's (nsplit M N of them) into C1.
 template <typename T>
-__global__ void __launch_bounds__(64 * RZ) k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P,
-                                                    c128* __restrict__ C, int ldc, double alpha, double beta) {
+__global__ void __launch_bounds__(64 * RZ) k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P0,
+                                                    c128* __restrict__ C0, c128* __restrict__ C1, int ldc,
+                                                    double alpha, double beta) {
   __shared__ cpx<T> s[RZ][64];
+  const cpx<T>* __restrict__ P = P0 + (size_t)blockIdx.y * nsplit * M * N;
+  c128* __restrict__ C = blockIdx.y ? C1 : C0;
   const size_t total = (size_t)M * N;
   const int x = threadIdx.x, y = threadIdx.y;
   const int z0 = y * nsplit / RZ, z1 = (y + 1) * nsplit / RZ;
@@ -410,8 +415,8 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   cpx<T>* P = static_cast<cpx<T>*>(part);
   if (K <= 0) {
     // a sum over no partials is zero: C = beta C
-    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, 0, P, C, ldc, alpha,
-                                                                                   beta);
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, 0, P, C, C, ldc,
+                                                                                   alpha, beta);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
@@ -422,8 +427,8 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + 16.0 * M * N);
-    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, sp.nsplit, P, C, ldc,
-                                                                                   alpha, beta);
+    k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, sp.nsplit, P, C, C,
+                                                                                   ldc, alpha, beta);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -451,8 +456,7 @@ pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, 2.0 * ((double)nsplit * M * N * sizeof(c128) + 16.0 * M * N));
     const int g = std::min(4096, ceil_div((size_t)M * N, 64));
-    k_reduce<double><<<g, dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C0, ldc, 1.0, 0.0);
-    k_reduce<double><<<g, dim3(64, RZ), 0, s>>>(M, N, nsplit, P + (size_t)nsplit * M * N, C1, ldc, 1.0, 0.0);
+    k_reduce<double><<<dim3(g, 2), dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C0, C1, ldc, 1.0, 0.0);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -512,8 +516,8 @@ pw_status pw::zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int 
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)nsplit * M * N * sizeof(c128) + 16.0 * M * N);
-    k_reduce<double><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C, ldc,
-                                                                                         alpha, beta);
+    k_reduce<double><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, nsplit, P, C, C,
+                                                                                         ldc, alpha, beta);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;

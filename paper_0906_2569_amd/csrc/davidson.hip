@@ -470,6 +470,9 @@ struct Solver {
   // pass followed by a normalization when `normalize` is set (a vector mostly
   // inside the locked span keeps, after one pass, rounding-level components
   // along it): no locked direction re-enters the basis
+  // x -= Psi_l (Psi_l^H x) over `passes` passes (classical Gram-Schmidt
+  // repeated: the second pass removes what rounding left after the first; it
+  // needs no normalization in between), then unit columns if `normalize`
   pw_status project_out_locked(int c0, int n, int passes = 2, bool normalize = true) {
     if (nl == 0 || n == 0) return PW_OK;
     c128* x = W.phi + (size_t)c0 * W.ld;
@@ -478,9 +481,9 @@ struct Solver {
                                                    W.part_bytes, st)));
       PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, n, nl, -1.0, W.psi, W.ld, W.lockc, nl, 1.0, x, W.ld,
                                                    st)));
-      if (normalize) k_normalize<<<n, 256, 0, st>>>(p->npw, x, W.ld);
-      PW_HIP(hipGetLastError());
     }
+    if (normalize) k_normalize<<<n, 256, 0, st>>>(p->npw, x, W.ld);
+    PW_HIP(hipGetLastError());
     return PW_OK;
   }
 

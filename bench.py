@@ -52,7 +52,8 @@ def parse():
                     help="cell64: the 64-atom cell (default line); batch: 32 cells x 4 k-points solved "
                          "concurrently vs one at a time in FP64; serve: Poisson request trace through the "
                          "serving loop (p50/p99 latency)")
-    ap.add_argument("--workers", type=int, default=8, help="batch/serve: concurrent solves")
+    ap.add_argument("--workers", type=int, default=None,
+                    help="batch/serve: concurrent solves (default 12 for batch, 8 for serve)")
     ap.add_argument("--requests", type=int, default=48, help="serve: timed requests")
     ap.add_argument("--max-atoms", type=int, default=128, help="serve: largest request (atoms)")
     ap.add_argument("--ecut", type=float, default=30.0, help="serve: cutoff in Ry")
@@ -310,6 +311,7 @@ def bench_batch(args):
         "data": "synthetic (32 seeded cells a~U[10,20] bohr, 8-64 atoms, 25 Ry, k=(+-1/4,+-1/4,0))",
         "config": {"workload": "batch of 128 problems: 32 cells x 4 k-points, npw 2157-16382, nb 20-128, "
                                "Davidson to 1e-8 Ry", "problems": len(ps), "workers": args.workers,
+                               "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
                    "ndim": args.ndim, "precision": args.precision},
         "sequential_fp64_solves_per_s": len(ps) / t_seq,
         "speedup_vs_sequential_fp64": t_seq / t_b,
@@ -369,7 +371,8 @@ def bench_serve(args):
         "data": "synthetic requests: atoms log-uniform 8..max, a = 41 (n/512)^(1/3) bohr, k = t b1",
         "config": {"workload": f"served requests, {args.ecut:g} Ry, 8-{args.max_atoms} atoms (nb = 2 atoms), "
                                f"Poisson arrivals at 0.7 x measured capacity", "requests": nreq,
-                   "workers": args.workers, "ndim": args.ndim, "precision": args.precision},
+                   "workers": args.workers, "hw_queues": int(os.environ.get("GPU_MAX_HW_QUEUES", "4")),
+                   "ndim": args.ndim, "precision": args.precision},
         "latency_s": {"p50": percentile(lat, 50), "p99": percentile(lat, 99), "max": max(lat)},
         "offered_load_req_per_s": lam,
         "capacity_solves_per_s": capacity,
@@ -387,6 +390,14 @@ def main():
         print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               f"(independent cells and k-points would shard one group per GPU)", file=sys.stderr)
         return 2
+    if args.workload in ("batch", "serve"):
+        # every solve drives two streams (transforms and the projector side
+        # stream): 16 hardware queues keep 8 and more workers from sharing
+        # them (HIP's default is 4).  Set before the GPU runtime starts.
+        if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+            os.environ["GPU_MAX_HW_QUEUES"] = "16"
+        if args.workers is None:
+            args.workers = 12 if args.workload == "batch" else 8
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "serve":

@@ -1573,11 +1573,13 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     PW_TRY((pw::zgemm_cn<double, double, double>(n0, m, n0, hw.X, ldw, S + (size_t)n0 * ld, ld, hw.T1, ldw,
                                                  part, part_bytes, st)));
   }
-  PW_HIP(hipMemcpy2DAsync(L22, sizeof(c128) * ldw, S + (size_t)n0 * ld + n0, sizeof(c128) * ld,
-                          sizeof(c128) * m, m, hipMemcpyDeviceToDevice, st));
   if (n0 > 0) {
+    // L22 = S22 - U12^H U12, reading S22 in place of a copy
     PW_TRY((pw::zgemm_cn<double, double, double>(m, m, n0, hw.T1, ldw, hw.T1, ldw, L22, ldw, part, part_bytes,
-                                                 st, -1.0, 1.0)));
+                                                 st, -1.0, 1.0, S + (size_t)n0 * ld + n0, ld)));
+  } else {
+    PW_HIP(hipMemcpy2DAsync(L22, sizeof(c128) * ldw, S + (size_t)n0 * ld + n0, sizeof(c128) * ld,
+                            sizeof(c128) * m, m, hipMemcpyDeviceToDevice, st));
   }
   {
     pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);

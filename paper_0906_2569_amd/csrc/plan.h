@@ -92,12 +92,13 @@ namespace pw {
 pw_status hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
                       c128* hpsi, int ldhpsi, hipStream_t stream);
 
-// C[m, n] = alpha sum_k conj(A[k, m]) B[k, n] + beta C[m, n]  (A, B K-contiguous columns),
-// C col-major ldc, complex128.  Deterministic split-K.  T = compute type.
+// C[m, n] = alpha sum_k conj(A[k, m]) B[k, n] + beta Cin[m, n]  (A, B K-contiguous columns),
+// C col-major ldc, complex128; Cin = C unless given (col-major, ldcin).
+// Deterministic split-K.  T = compute type.
 template <typename T, typename TA, typename TB>
 pw_status zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>* B, int ldb,
                    c128* C, int ldc, void* part, size_t part_bytes, hipStream_t stream,
-                   double alpha = 1.0, double beta = 0.0);
+                   double alpha = 1.0, double beta = 0.0, const c128* Cin = nullptr, int ldcin = 0);
 
 // calbec with the D blocks applied: out[n][j] = sum_{j' in blk(j)} D_jj' sum_k conj(beta[j'][k]) psi[n][k]
 template <typename T>

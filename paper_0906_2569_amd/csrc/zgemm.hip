@@ -323,13 +323,15 @@ __device__ __forceinline__ cpx<T> add_groups(const cpx<T> (*s)[64], int x) {
   return v;
 }
 
-// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta C[n*ldc + m]; block (64, RZ).
-// gridDim.y = 2 sums two products in one launch: blockIdx.y = 1 takes the
-// partials after the first product's (nsplit M N of them) into C1.
+// C[n*ldc + m] = alpha sum_z P[z][n][m] + beta Cin[n*ldcin + m]; block (64, RZ).
+// Cin = C (in place) unless another matrix is given.  gridDim.y = 2 sums two
+// products in one launch: blockIdx.y = 1 takes the partials after the first
+// product's (nsplit M N of them) into C1.
 template <typename T>
 __global__ void __launch_bounds__(64 * RZ) k_reduce(int M, int N, int nsplit, const cpx<T>* __restrict__ P0,
                                                     c128* __restrict__ C0, c128* __restrict__ C1, int ldc,
-                                                    double alpha, double beta) {
+                                                    double alpha, double beta, const c128* __restrict__ Cin = nullptr,
+                                                    int ldcin = 0) {
   __shared__ cpx<T> s[RZ][64];
   const cpx<T>* __restrict__ P = P0 + (size_t)blockIdx.y * nsplit * M * N;
   c128* __restrict__ C = blockIdx.y ? C1 : C0;
@@ -347,8 +349,9 @@ __global__ void __launch_bounds__(64 * RZ) k_reduce(int M, int N, int nsplit, co
       c128* c = C + (size_t)n * ldc + m;
       double r = alpha * (double)sum.x, i = alpha * (double)sum.y;
       if (beta != 0.0) {
-        r += beta * c->x;
-        i += beta * c->y;
+        const c128 cin = Cin ? Cin[(size_t)n * ldcin + m] : *c;
+        r += beta * cin.x;
+        i += beta * cin.y;
       }
       *c = c128{r, i};
     }
@@ -407,7 +410,7 @@ size_t pw::splitk_part_bytes(int M, int N, int K, int elem_bytes) {
 template <typename T, typename TA, typename TB>
 pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>* B, int ldb,
                        c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s, double alpha,
-                       double beta) {
+                       double beta, const c128* Cin, int ldcin) {
   if (M <= 0 || N <= 0) return PW_OK;
   const Split sp = choose_split(M, N, K);
   const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
@@ -416,7 +419,7 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   if (K <= 0) {
     // a sum over no partials is zero: C = beta C
     k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, 0, P, C, C, ldc,
-                                                                                   alpha, beta);
+                                                                                   alpha, beta, Cin, ldcin);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
@@ -428,7 +431,7 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   {
     pw::ProfScope ps(pw::PK_GEMM_RED, s, (double)sp.nsplit * M * N * sizeof(cpx<T>) + 16.0 * M * N);
     k_reduce<T><<<std::min(4096, ceil_div((size_t)M * N, 64)), dim3(64, RZ), 0, s>>>(M, N, sp.nsplit, P, C, C,
-                                                                                   ldc, alpha, beta);
+                                                                                   ldc, alpha, beta, Cin, ldcin);
   }
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -535,10 +538,10 @@ pw_status pw::zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1,
 
 template pw_status pw::zgemm_cn<double, double, double>(int, int, int, const c128*, int, const c128*,
                                                         int, c128*, int, void*, size_t, hipStream_t,
-                                                        double, double);
+                                                        double, double, const c128*, int);
 template pw_status pw::zgemm_cn<float, double, double>(int, int, int, const c128*, int, const c128*,
                                                        int, c128*, int, void*, size_t, hipStream_t,
-                                                       double, double);
+                                                       double, double, const c128*, int);
 template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, hipStream_t);
 template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t);
 template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,

@@ -53,7 +53,12 @@ struct DavWork {
 
 namespace {
 
-__device__ double block_sum256(double v, double* red) {
+// threads per workgroup of the per-band vector kernels (one workgroup per
+// band streams npw entries: more waves keep more loads in flight)
+constexpr int kVecThreads = 1024;
+
+// sum over the workgroup (any size up to 1024; red[] holds one value per wave)
+__device__ double block_sum(double v, double* red) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   __syncthreads();
@@ -66,10 +71,10 @@ __device__ double block_sum256(double v, double* red) {
 }
 
 // rn[b] = || hpsi_b - eps_b psi_b ||_2
-__global__ void __launch_bounds__(256) k_resid(int npw, const c128* __restrict__ psi,
+__global__ void __launch_bounds__(kVecThreads) k_resid(int npw, const c128* __restrict__ psi,
                                                const c128* __restrict__ hpsi, int ld,
                                                const double* __restrict__ eps, double* __restrict__ rn) {
-  __shared__ double red[4];
+  __shared__ double red[16];
   const int b = blockIdx.x;
   const double e = eps[b];
   const c128* x = psi + (size_t)b * ld;
@@ -79,7 +84,7 @@ __global__ void __launch_bounds__(256) k_resid(int npw, const c128* __restrict__
     const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
     s += re * re + im * im;
   }
-  s = block_sum256(s, red);
+  s = block_sum(s, red);
   if (threadIdx.x == 0) rn[b] = sqrt(s);
 }
 
@@ -111,12 +116,12 @@ __global__ void k_select(int nb, const double* __restrict__ rn, const double* __
 }
 
 // out_t = (hpsi_b - eps_b psi_b) / smax(h_diag - eps_b, floor), normalized; b = idx[t]
-__global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict__ idx,
+__global__ void __launch_bounds__(kVecThreads) k_correct(int npw, const int* __restrict__ idx,
                                                  const c128* __restrict__ psi, const c128* __restrict__ hpsi,
                                                  int ld, const double* __restrict__ eps,
                                                  const double* __restrict__ hdiag, double floor_,
                                                  c128* __restrict__ out, int ldo) {
-  __shared__ double red[4];
+  __shared__ double red[16];
   const int t = blockIdx.x;
   const int b = idx[t];
   const double e = eps[b];
@@ -134,13 +139,13 @@ __global__ void __launch_bounds__(256) k_correct(int npw, const int* __restrict_
     o[g] = r;
     s += r.x * r.x + r.y * r.y;
   }
-  s = block_sum256(s, red);
+  s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
 }
 
 // out_t = hpsi_b - eps_b psi_b, b = idx[t] (residual vectors, for projection before preconditioning)
-__global__ void __launch_bounds__(256) k_residvec(int npw, const int* __restrict__ idx,
+__global__ void __launch_bounds__(kVecThreads) k_residvec(int npw, const int* __restrict__ idx,
                                                   const c128* __restrict__ psi, const c128* __restrict__ hpsi,
                                                   int ld, const double* __restrict__ eps, c128* __restrict__ out,
                                                   int ldo) {
@@ -153,10 +158,10 @@ __global__ void __launch_bounds__(256) k_residvec(int npw, const int* __restrict
 }
 
 // column t of x <- x_t / smax(h_diag - eps_b, floor), b = idx[t], normalized (as k_correct)
-__global__ void __launch_bounds__(256) k_precond(int npw, const int* __restrict__ idx,
+__global__ void __launch_bounds__(kVecThreads) k_precond(int npw, const int* __restrict__ idx,
                                                  const double* __restrict__ eps, const double* __restrict__ hdiag,
                                                  double floor_, c128* __restrict__ x, int ldx) {
-  __shared__ double red[4];
+  __shared__ double red[16];
   const double e = eps[idx[blockIdx.x]];
   c128* o = x + (size_t)blockIdx.x * ldx;
   double s = 0.0;
@@ -168,18 +173,18 @@ __global__ void __launch_bounds__(256) k_precond(int npw, const int* __restrict_
     o[g] = r;
     s += r.x * r.x + r.y * r.y;
   }
-  s = block_sum256(s, red);
+  s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
 }
 
 // columns of x scaled to unit norm (a zero column stays zero)
-__global__ void __launch_bounds__(256) k_normalize(int npw, c128* __restrict__ x, int ld) {
-  __shared__ double red[4];
+__global__ void __launch_bounds__(kVecThreads) k_normalize(int npw, c128* __restrict__ x, int ld) {
+  __shared__ double red[16];
   c128* o = x + (size_t)blockIdx.x * ld;
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) s += o[g].x * o[g].x + o[g].y * o[g].y;
-  s = block_sum256(s, red);
+  s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
 }
@@ -261,7 +266,7 @@ __global__ void k_permute_vals(int n, const int* __restrict__ perm, double* __re
 __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__ psi, int ldpsi,
                                                const c128* __restrict__ hpsi, int ldh,
                                                double* __restrict__ eig, double* __restrict__ resid) {
-  __shared__ double red[4];
+  __shared__ double red[16];
   const int b = blockIdx.x;
   const c128* x = psi + (size_t)b * ldpsi;
   const c128* hx = hpsi + (size_t)b * ldh;
@@ -270,15 +275,15 @@ __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__
     num += x[g].x * hx[g].x + x[g].y * hx[g].y;
     den += x[g].x * x[g].x + x[g].y * x[g].y;
   }
-  num = block_sum256(num, red);
-  den = block_sum256(den, red);
+  num = block_sum(num, red);
+  den = block_sum(den, red);
   const double e = num / den;
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
     s += re * re + im * im;
   }
-  s = block_sum256(s, red);
+  s = block_sum(s, red);
   if (threadIdx.x == 0) {
     eig[b] = e;
     resid[b] = sqrt(s);
@@ -482,7 +487,7 @@ struct Solver {
       PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, n, nl, -1.0, W.psi, W.ld, W.lockc, nl, 1.0, x, W.ld,
                                                    st)));
     }
-    if (normalize) k_normalize<<<n, 256, 0, st>>>(p->npw, x, W.ld);
+    if (normalize) k_normalize<<<n, kVecThreads, 0, st>>>(p->npw, x, W.ld);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
@@ -495,13 +500,13 @@ struct Solver {
   pw_status corrections(int c0, int n, double floor_) {
     c128* x = W.phi + (size_t)c0 * W.ld;
     if (nl == 0) {
-      k_correct<<<n, 256, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, floor_, x, W.ld);
+      k_correct<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, floor_, x, W.ld);
       PW_HIP(hipGetLastError());
       return PW_OK;
     }
-    k_residvec<<<n, 256, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, x, W.ld);
+    k_residvec<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, x, W.ld);
     PW_TRY(project_out_locked(c0, n, 1, false));
-    k_precond<<<n, 256, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, floor_, x, W.ld);
+    k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, floor_, x, W.ld);
     PW_HIP(hipGetLastError());
     return project_out_locked(c0, n);
   }
@@ -544,7 +549,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   pw_status result = PW_OK;
   DavFlags f{};
   for (;;) {
-    k_resid<<<nb, 256, 0, st>>>(npw, W.psi, W.hpsi, W.ld, W.eps, W.rn);
+    k_resid<<<nb, kVecThreads, 0, st>>>(npw, W.psi, W.hpsi, W.ld, W.eps, W.rn);
     // float32 stage: a band needs no more corrections once its residual is
     // below the switch threshold (its eigenvalue change is float32 noise)
     const bool fp32_stage = prec == PW_MIXED;

@@ -89,30 +89,44 @@ __global__ void __launch_bounds__(kVecThreads) k_resid(int npw, const c128* __re
 }
 
 // convergence flags, compaction of the unconverged bands (band order), NaN
-// guard, and the reduced-solver status, gathered for one host read.
-__global__ void k_select(int nb, const double* __restrict__ rn, const double* __restrict__ eps,
-                         const double* __restrict__ eps_prev, double tol_r, double tol_e,
-                         int* __restrict__ idx, const int* __restrict__ info, const double* __restrict__ gamma,
-                         DavFlags* __restrict__ f) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int n = 0, nan = 0, nconv = 0;
+// guard, and the reduced-solver status, gathered for one host read.  One
+// wave takes the bands 64 at a time in order; the unconverged ones of a chunk
+// get consecutive idx positions from a ballot prefix count.
+__global__ void __launch_bounds__(64) k_select(int nb, const double* __restrict__ rn,
+                                               const double* __restrict__ eps,
+                                               const double* __restrict__ eps_prev, double tol_r, double tol_e,
+                                               int* __restrict__ idx, const int* __restrict__ info,
+                                               const double* __restrict__ gamma, DavFlags* __restrict__ f) {
+  const int lane = threadIdx.x;
+  if (blockIdx.x != 0 || lane >= 64) return;
+  int n = 0, nconv = 0;
+  bool nan = false;
   double maxr = 0.0;
-  for (int b = 0; b < nb; ++b) {
-    const double r = rn[b], de = fabs(eps[b] - eps_prev[b]);
-    if (!isfinite(r) || !isfinite(eps[b])) nan = 1;
-    maxr = fmax(maxr, r);
-    if (r <= tol_r && de <= tol_e) {
-      ++nconv;
-    } else {
-      idx[n++] = b;
+  for (int b0 = 0; b0 < nb; b0 += 64) {
+    const int b = b0 + lane;
+    const bool act = b < nb;
+    bool conv = false, bad = false;
+    if (act) {
+      const double r = rn[b], de = fabs(eps[b] - eps_prev[b]);
+      bad = !isfinite(r) || !isfinite(eps[b]);
+      maxr = fmax(maxr, r);
+      conv = r <= tol_r && de <= tol_e;
     }
+    const unsigned long long open = __ballot(act && !conv);
+    if (act && !conv) idx[n + __popcll(open & ((1ull << lane) - 1ull))] = b;
+    n += __popcll(open);
+    nconv += __popcll(__ballot(act && conv));
+    nan = nan || __ballot(bad) != 0ull;
   }
-  f->n_new = n;
-  f->nan = nan;
-  f->info = *info;
-  f->nconv = nconv;
-  f->maxr = maxr;
-  f->gamma = *gamma;
+  for (int o = 32; o > 0; o >>= 1) maxr = fmax(maxr, __shfl_xor(maxr, o, 64));
+  if (lane == 0) {
+    f->n_new = n;
+    f->nan = nan ? 1 : 0;
+    f->info = *info;
+    f->nconv = nconv;
+    f->maxr = maxr;
+    f->gamma = *gamma;
+  }
 }
 
 // out_t = (hpsi_b - eps_b psi_b) / smax(h_diag - eps_b, floor), normalized; b = idx[t]

@@ -84,11 +84,19 @@ typedef struct {
   const pw_c128* dmat;       /* [host] concatenated Hermitian nh x nh blocks, column-major, in Ha   */
 } pw_problem;
 
-/* Capacity of a plan: workspace is allocated once, at plan creation. */
+/* Capacity of a plan: workspace is allocated once, at plan creation.  Fields
+   past ndim_max may be left zero (defaults). */
 typedef struct {
   pw_precision precision;    /* PW_FP64 or PW_MIXED                                                 */
   int32_t      nb_max;       /* largest number of bands passed to hpsi_apply / davidson_solve      */
   int32_t      ndim_max;     /* largest Davidson basis factor (basis <= ndim*nb); 0 = no solver ws  */
+  int32_t      plane_mode;   /* 0: the plane pass (y, x, V(r), x, y of one z plane) runs in one
+                                kernel per plane where the plane fits in LDS, else in three kernels
+                                through an HBM copy of the plane's x columns (large grids, e.g. 144^2
+                                in float64); 1: always three kernels                                */
+  size_t       fft_ws_bytes; /* transform workspace cap (sticks, plus the plane copies of the
+                                three-kernel pass); bands are transformed in chunks that fit it;
+                                0 = 2 GiB                                                          */
 } pw_plan_opts;
 
 typedef struct {
@@ -150,7 +158,9 @@ pw_status pw_plan_create(pw_ctx ctx, const pw_problem* problem, const pw_plan_op
                          pw_plan* out);
 pw_status pw_plan_destroy(pw_plan plan);
 
-/* Plan sizes: out[0]=npw, out[1]=n_sticks, out[2]=x columns, out[3]=N, out[4]=nbeta. */
+/* Plan sizes: out[0]=npw, out[1]=n_sticks, out[2]=x columns, out[3]=N, out[4]=nbeta,
+   out[5]=bands per transform chunk, out[6]/out[7]=1 when the float64/float32 plane pass
+   takes the three-kernel form, else 0. */
 pw_status pw_plan_info(pw_plan plan, int64_t out[8]);
 
 /*

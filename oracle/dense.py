@@ -134,7 +134,9 @@ def hpsi_brute(miller, kpg, vloc_r, beta, blk_off, dmat, psi) -> np.ndarray:
     """H.psi through real space by explicit sums (no H matrix, no FFT).
 
     psi(r_j) = sum_G psi_G exp(+2 pi i m_G.j/n); (V psi)(r) = V(r) psi(r);
-    (V psi)_G = (1/N) sum_j exp(-2 pi i m_G.j/n) (V psi)(r_j).  For tiny cells.
+    (V psi)_G = (1/N) sum_j exp(-2 pi i m_G.j/n) (V psi)(r_j); the projector
+    term sum_ij beta_i D_ij <beta_j|psi> reads D from the flat block list
+    itself (it does not go through dense_d).  For tiny cells.
     """
     miller = np.asarray(miller, dtype=np.int64)
     v = np.asarray(vloc_r, dtype=np.float64)
@@ -147,16 +149,25 @@ def hpsi_brute(miller, kpg, vloc_r, beta, blk_off, dmat, psi) -> np.ndarray:
     t = kinetic(kpg)
     vflat = v.ravel()
     beta = np.asarray(beta, dtype=np.complex128)
-    d = dense_d(beta.shape[0], blk_off, dmat) if beta.shape[0] else None
+    dflat = np.asarray(dmat, dtype=np.complex128).ravel()
     for b in range(psi.shape[0]):
         pr = psi[b] @ phase                                     # psi(r_j)
         vg = (np.conj(phase) @ (vflat * pr)) / vflat.size       # (V psi)_G
         acc = t * psi[b] + vg
-        if d is not None:
-            for i in range(beta.shape[0]):
-                for j in range(beta.shape[0]):
-                    if d[i, j] != 0:
-                        acc = acc + beta[i] * d[i, j] * np.vdot(beta[j], psi[b])
+        # nonlocal term walked block by block straight from the flat input:
+        # block I starts at sum_{J<I} nh_J^2, and its element (i, j) (row i,
+        # column j, column-major) sits at i + j*nh inside the block
+        pos = 0
+        for blk in range(len(blk_off) - 1):
+            o0, o1 = int(blk_off[blk]), int(blk_off[blk + 1])
+            nh = o1 - o0
+            for j in range(nh):
+                proj = np.vdot(beta[o0 + j], psi[b])              # <beta_j|psi>
+                for i in range(nh):
+                    dij = dflat[pos + i + j * nh]
+                    if dij != 0:
+                        acc = acc + beta[o0 + i] * dij * proj
+            pos += nh * nh
         out[b] = acc
     return out
 

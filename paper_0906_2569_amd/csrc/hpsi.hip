@@ -243,6 +243,114 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   }
 }
 
+// ---------------------------------------------------------------------------
+// pass 2, three-kernel form for planes whose x columns do not fit in LDS
+// (float64 at 144^2 and above): the y transforms and the x transforms of a
+// plane run in separate kernels and meet in an HBM copy of the plane's x
+// columns, rows[band][z][n2][nxr] (y major, the x columns of one row
+// contiguous).  Each workgroup holds only CB columns or CB rows.
+// ---------------------------------------------------------------------------
+constexpr int SPLIT_CB = 16;        // columns / rows per workgroup
+constexpr int SPLIT_THREADS = 256;
+
+template <typename T>
+size_t split_lds_bytes(int n1, int n2) {
+  const int lmax = std::max(n1, n2);
+  return 2 * sizeof(cpx<T>) * (size_t)SPLIT_CB * lmax + sizeof(int) * (size_t)SPLIT_CB * n2 +
+         sizeof(int) * (size_t)n1;
+}
+
+// sticks of x columns [c0, c0+CB) -> inverse y -> rows
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_plane_yinv(SphereMap m, const cpx<T>* __restrict__ sticks, cpx<T>* __restrict__ rows,
+             const cpx<T>* __restrict__ tw2) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n2 = m.n2, nxr = m.nxr, lmax = max(m.n1, n2);
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* B = A + SPLIT_CB * lmax;
+  int* sidx = reinterpret_cast<int*>(B + SPLIT_CB * lmax);   // [CB][n2] stick at (column, y) or -1
+  const int z = blockIdx.x, band = blockIdx.y, c0 = blockIdx.z * SPLIT_CB;
+  const int nc = min(SPLIT_CB, nxr - c0);
+  for (int i = threadIdx.x; i < SPLIT_CB * n2; i += blockDim.x) sidx[i] = -1;
+  __syncthreads();
+  for (int s = m.col_ptr[c0] + threadIdx.x; s < m.col_ptr[c0 + nc]; s += blockDim.x)
+    sidx[(m.st_hx[s] - c0) * n2 + m.st_i2[s]] = s;
+  __syncthreads();
+  const cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
+  cpx<T>* out = rows + ((size_t)band * m.n3 + z) * n2 * nxr + c0;
+  fft_run<T>(
+      m.f2, nc, T(1), tw2, A, B, lmax, false, true,
+      [&](int b, int i) {
+        const int s = sidx[b * n2 + i];
+        return s >= 0 ? st[s] : cpx<T>{T(0), T(0)};
+      },
+      [&](int b, int i, cpx<T> v) { out[(size_t)i * nxr + b] = v; });
+}
+
+// rows [r0, r0+CB) of one plane: inverse x, times V(r), forward x; the x
+// columns of the sphere are read and written back in place
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_plane_x(SphereMap m, cpx<T>* __restrict__ rows, const T* __restrict__ vr, const cpx<T>* __restrict__ tw1) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n1 = m.n1, n2 = m.n2, nxr = m.nxr, lmax = max(n1, n2);
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* B = A + SPLIT_CB * lmax;
+  int* hx_of = reinterpret_cast<int*>(B + SPLIT_CB * lmax) + SPLIT_CB * n2;   // [n1]
+  const int z = blockIdx.x, band = blockIdx.y, r0 = blockIdx.z * SPLIT_CB;
+  const int nr = min(SPLIT_CB, n2 - r0);
+  for (int i = threadIdx.x; i < n1; i += blockDim.x) hx_of[i] = m.i1_hx[i];
+  __syncthreads();
+  cpx<T>* rw = rows + (((size_t)band * m.n3 + z) * n2 + r0) * nxr;
+  const T* vz = vr + ((size_t)z * n2 + r0) * n1;
+  const int lr = fft_last_read(m.f1);
+  cpx<T>* X = (lr == 0) ? B : A;
+  cpx<T>* P0 = (X == A) ? B : A;
+  fft_run<T>(
+      m.f1, nr, T(1), tw1, A, B, lmax, false, false,
+      [&](int b, int i) {
+        const int hx = hx_of[i];
+        return hx >= 0 ? rw[(size_t)b * nxr + hx] : cpx<T>{T(0), T(0)};
+      },
+      [&](int b, int i, cpx<T> v) { X[b * lmax + i] = v * vz[(size_t)b * n1 + i]; });
+  fft_run<T>(
+      m.f1, nr, T(-1), tw1, P0, X, lmax, false, false,
+      [&](int b, int i) { return X[b * lmax + i]; },
+      [&](int b, int i, cpx<T> v) {
+        const int hx = hx_of[i];
+        if (hx >= 0) rw[(size_t)b * nxr + hx] = v;
+      });
+}
+
+// rows -> forward y of x columns [c0, c0+CB) -> stick positions only
+template <typename T>
+__global__ void __launch_bounds__(SPLIT_THREADS)
+k_plane_yfwd(SphereMap m, cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ rows,
+             const cpx<T>* __restrict__ tw2) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n2 = m.n2, nxr = m.nxr, lmax = max(m.n1, n2);
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* B = A + SPLIT_CB * lmax;
+  int* sidx = reinterpret_cast<int*>(B + SPLIT_CB * lmax);
+  const int z = blockIdx.x, band = blockIdx.y, c0 = blockIdx.z * SPLIT_CB;
+  const int nc = min(SPLIT_CB, nxr - c0);
+  for (int i = threadIdx.x; i < SPLIT_CB * n2; i += blockDim.x) sidx[i] = -1;
+  __syncthreads();
+  for (int s = m.col_ptr[c0] + threadIdx.x; s < m.col_ptr[c0 + nc]; s += blockDim.x)
+    sidx[(m.st_hx[s] - c0) * n2 + m.st_i2[s]] = s;
+  __syncthreads();
+  cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
+  const cpx<T>* in = rows + ((size_t)band * m.n3 + z) * n2 * nxr + c0;
+  fft_run<T>(
+      m.f2, nc, T(-1), tw2, A, B, lmax, true, false,
+      [&](int b, int i) { return in[(size_t)i * nxr + b]; },
+      [&](int b, int i, cpx<T> v) {
+        const int s = sidx[b * n2 + i];
+        if (s >= 0) st[s] = v;
+      });
+}
+
 template <typename T>
 using PlaneRegFn = void (*)(SphereMap, cpx<T>*, const T*, const cpx<T>*, const cpx<T>*);
 
@@ -516,6 +624,9 @@ pw_status set_lds_limits() {
   PW_TRY(set_lds_limit<T>((const void*)k_plane<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_zinv<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_zfwd<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_plane_yinv<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_plane_x<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_plane_yfwd<T>));
   done = true;
   return PW_OK;
 }
@@ -553,17 +664,26 @@ void twiddles(int L, std::vector<c128>& t64, std::vector<c64>& t32) {
   }
 }
 
-int band_chunk_for(const pw_plan_opts& o, int n3, int ldst) {
-  // bound the stick workspace to ~2 GiB
-  const size_t per_band = (size_t)n3 * ldst * sizeof(c128);
-  size_t cap = ((size_t)2 << 30) / std::max<size_t>(per_band, 1);
+struct Geometry {
+  int n1, n2, n3, nst, nxr, ldst, nhmax;
+  bool split64, split32;   // three-kernel plane pass per precision
+};
+
+// transform workspace per band: the sticks, plus the plane copies of the
+// three-kernel plane pass when a precision of the plan takes it
+size_t fft_ws_per_band(const Geometry& g) {
+  size_t b = (size_t)g.n3 * g.ldst * sizeof(c128);
+  if (g.split64 || g.split32) b += (size_t)g.n3 * g.n2 * g.nxr * sizeof(c128);
+  return b;
+}
+
+// bands per transform chunk: the workspace of a chunk stays within the cap
+int band_chunk_for(const pw_plan_opts& o, const Geometry& g) {
+  const size_t cap_bytes = o.fft_ws_bytes ? o.fft_ws_bytes : ((size_t)2 << 30);
+  size_t cap = cap_bytes / std::max<size_t>(fft_ws_per_band(g), 1);
   cap = std::max<size_t>(cap, 1);
   return (int)std::min<size_t>((size_t)std::max(o.nb_max, 1), cap);
 }
-
-struct Geometry {
-  int n1, n2, n3, nst, nxr, ldst, nhmax;
-};
 
 pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* geo) {
   PW_CHECK(pr != nullptr && o != nullptr, PW_EINVAL, "NULL problem or options");
@@ -613,9 +733,10 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
     geo->nhmax = std::max(geo->nhmax, nh);
   }
   const bool mixed = o->precision == PW_MIXED;
-  PW_CHECK(plane_batch<double>(geo->n1, geo->n2, geo->nxr) > 0 || mixed, PW_EINVAL,
-           "grid too large for the float64 plane pass");
-  PW_CHECK(plane_batch<float>(geo->n1, geo->n2, geo->nxr) > 0, PW_EINVAL, "grid too large for the plane pass");
+  PW_CHECK(o->plane_mode == 0 || o->plane_mode == 1, PW_EINVAL, "plane_mode must be 0 or 1");
+  geo->split64 = o->plane_mode == 1 || plane_batch<double>(geo->n1, geo->n2, geo->nxr) == 0;
+  geo->split32 = mixed && (o->plane_mode == 1 || plane_batch<float>(geo->n1, geo->n2, geo->nxr) == 0);
+  PW_CHECK(split_lds_bytes<double>(geo->n1, geo->n2) <= 160 * 1024, PW_EINVAL, "grid too large for the plane pass");
   PW_CHECK(z_lds_bytes<double>(geo->n3) <= 160 * 1024, PW_EINVAL, "n3 too large");
   return PW_OK;
 }
@@ -638,8 +759,8 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
   b += N * (sizeof(double) + (mixed ? sizeof(float) : 0));
   b += (size_t)pr->nbeta * ldb * (sizeof(c128) + (mixed ? sizeof(c64) : 0));
   b += (size_t)pr->nbeta * (2 * sizeof(int) + geo.nhmax * (sizeof(c128) + sizeof(c64)));
-  const int chunk = band_chunk_for(*o, geo.n3, geo.ldst);
-  b += (size_t)chunk * geo.n3 * geo.ldst * sizeof(c128);
+  const int chunk = band_chunk_for(*o, geo);
+  b += (size_t)chunk * fft_ws_per_band(geo);
   b += 2 * (size_t)o->nb_max * std::max(pr->nbeta, 1) * sizeof(c128);
   b += pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128));
   if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max);
@@ -723,6 +844,9 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
     ent_s[e] = (int)st_hx.size() - 1;
   }
   st_ptr.push_back(npw);
+  std::vector<int> col_ptr(nxr + 1, 0);
+  for (size_t s2 = 0; s2 < st_hx.size(); ++s2) col_ptr[st_hx[s2] + 1]++;
+  for (int c = 0; c < nxr; ++c) col_ptr[c + 1] += col_ptr[c];
   std::vector<int> zidx((size_t)n3 * st_hx.size(), -1);
   for (int e = 0; e < npw; ++e) zidx[(size_t)ent_z[e] * st_hx.size() + ent_s[e]] = ent_g[e];
   std::vector<double> kin(npw);
@@ -745,7 +869,9 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   p->nblk = pr->nbeta > 0 ? pr->nblk : 0;
   p->nhmax = geo.nhmax;
   p->ldb = (npw + 15) / 16 * 16;
-  p->band_chunk = band_chunk_for(*o, n3, geo.ldst);
+  p->band_chunk = band_chunk_for(*o, geo);
+  p->split64 = geo.split64;
+  p->split32 = geo.split32;
   fft_factor(n1, p->f1);
   fft_factor(n2, p->f2);
   fft_factor(n3, p->f3);
@@ -769,6 +895,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(upload(p, &p->ent_s, ent_s));
   PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
   PLAN_TRY(upload(p, &p->zidx, zidx));
+  PLAN_TRY(upload(p, &p->col_ptr, col_ptr));
   PLAN_TRY(upload(p, &p->kin, kin));
   {
     std::vector<c128> t64;
@@ -826,6 +953,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
                                        p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
   // workspace
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->sticks), (size_t)p->band_chunk * n3 * p->ldst));
+  if (p->split64 || p->split32)
+    PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->rows), (size_t)p->band_chunk * n3 * n2 * nxr));
   const int nbeta1 = std::max(p->nbeta, 1);
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becp), (size_t)o->nb_max * nbeta1));
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
@@ -866,8 +995,8 @@ extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
   out[3] = p->N;
   out[4] = p->nbeta;
   out[5] = p->band_chunk;
-  out[6] = plane_batch<double>(p->n1, p->n2, p->nxr);
-  out[7] = plane_batch<float>(p->n1, p->n2, p->nxr);
+  out[6] = p->split64 ? 1 : 0;
+  out[7] = p->split32 ? 1 : 0;
   return PW_OK;
 }
 
@@ -882,15 +1011,16 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const cpx<T>* tw3 = f64 ? (const cpx<T>*)p->tw64_3 : (const cpx<T>*)p->tw32_3;
   const T* vr = f64 ? (const T*)p->vr64 : (const T*)p->vr32;
   PW_CHECK(vr != nullptr, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
+  const bool split = f64 ? p->split64 : p->split32;
   const int cb = plane_batch<T>(p->n1, p->n2, p->nxr);
-  PW_CHECK(cb > 0, PW_EINVAL, "grid too large for this precision's plane pass");
+  PW_CHECK(cb > 0 || split, PW_EINVAL, "grid too large for this precision's plane pass");
   const size_t zl = z_lds_bytes<T>(p->n3);
-  const size_t pl = plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
+  const size_t pl = split ? split_lds_bytes<T>(p->n1, p->n2) : plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
   // two z planes per workgroup where their LDS fits (the last passes over
   // columns and rows are fuller), else one
   PlaneRegFn<T> preg = nullptr;
   int ppw = 0;
-  if (p->use_reg_plane) {
+  if (p->use_reg_plane && !split) {
     if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 2) <= kPlaneRegMaxLds) {
       preg = plane_reg_kernel<T, 2>(p->n1, p->n2);
       ppw = 2;
@@ -928,11 +1058,17 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     }
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
-      if (preg)
+      if (split) {
+        cpx<T>* rows = static_cast<cpx<T>*>(p->rows);
+        k_plane_yinv<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, st, rows, tw2);
+        k_plane_x<T><<<dim3(p->n3, nbc, ceil_div(p->n2, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, rows, vr, tw1);
+        k_plane_yfwd<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, st, rows, tw2);
+      } else if (preg) {
         preg<<<dim3(ceil_div(p->n3, ppw), nbc), plane_reg_threads<T>(p->n1, p->nxr), plds, s>>>(
             m, st, vr, tw1, tw2);
-      else
+      } else {
         k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
+      }
     }
     if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
     {

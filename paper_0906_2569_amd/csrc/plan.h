@@ -27,6 +27,7 @@ struct SphereMap {
   const int* st_i2;    // [nst]     y grid index (k mod n2) of stick s
   const int* i1_hx;    // [n1]      x-column index at x grid index i1, or -1
   const int* zidx;     // [n3][nst] sphere index of (z, stick), or -1
+  const int* col_ptr;  // [nxr+1]   first stick of each x column (sticks are column-major)
   const double* kin;   // [npw]     |k+G|^2 / 2
   FftDesc f1, f2, f3;  // transforms along x, y, z
 };
@@ -44,10 +45,11 @@ struct pw_plan_s {
   int ldb = 0;              // leading dimension of the plan's beta copies
   int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
   bool use_reg_plane = true;  // register-resident plane pass where the grid allows
+  bool split64 = false, split32 = false;  // three-kernel plane pass (float64 / float32)
 
   // maps (device)
   int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
-      *st_i2 = nullptr, *i1_hx = nullptr, *zidx = nullptr;
+      *st_i2 = nullptr, *i1_hx = nullptr, *zidx = nullptr, *col_ptr = nullptr;
   double* kin = nullptr;     // [npw]
   double* hdiag = nullptr;   // [npw] exact diagonal of H
   FftDesc f1{}, f2{}, f3{};
@@ -66,6 +68,7 @@ struct pw_plan_s {
 
   // H.psi workspace (device)
   void* sticks = nullptr;    // [band_chunk][n3][ldst] complex (FP64 size)
+  void* rows = nullptr;      // [band_chunk][n3][n2][nxr] complex (FP64 size), three-kernel plane pass only
   void* part = nullptr;      // split-K partials
   size_t part_bytes = 0;
   void* becp = nullptr;      // [nb_max][nbeta] complex128 (or complex64)
@@ -81,7 +84,7 @@ struct pw_plan_s {
     m.npw = npw; m.n1 = n1; m.n2 = n2; m.n3 = n3;
     m.nst = nst; m.nxr = nxr; m.ldst = ldst;
     m.st_ptr = st_ptr; m.ent_g = ent_g; m.ent_z = ent_z; m.ent_s = ent_s;
-    m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.zidx = zidx; m.kin = kin;
+    m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.zidx = zidx; m.col_ptr = col_ptr; m.kin = kin;
     m.f1 = f1; m.f2 = f2; m.f3 = f3;
     return m;
   }

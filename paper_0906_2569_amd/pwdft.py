@@ -43,7 +43,8 @@ class Problem(C.Structure):
 
 
 class PlanOpts(C.Structure):
-    _fields_ = [("precision", C.c_int), ("nb_max", C.c_int32), ("ndim_max", C.c_int32)]
+    _fields_ = [("precision", C.c_int), ("nb_max", C.c_int32), ("ndim_max", C.c_int32),
+                ("plane_mode", C.c_int32), ("fft_ws_bytes", C.c_size_t)]
 
 
 class DavOpts(C.Structure):
@@ -197,10 +198,11 @@ def _problem_struct(p, dev):
     return s, (miller, kpg, vr, beta, blk, dmat)
 
 
-def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0) -> int:
+def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0, plane_mode=0,
+                    fft_ws_bytes=0) -> int:
     import torch
     s, keep = _problem_struct(p, torch.device("cuda", device))
-    o = PlanOpts(precision, nb_max or p.nb, ndim_max)
+    o = PlanOpts(precision, nb_max or p.nb, ndim_max, plane_mode, fft_ws_bytes)
     return int(load().pw_footprint_bytes(C.byref(s), C.byref(o)))
 
 
@@ -286,13 +288,14 @@ def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):
 class Plan:
     """A problem's maps, operator copies and workspace on one device."""
 
-    def __init__(self, ctx: Context, p, precision=PW_FP64, nb_max=None, ndim_max=4):
+    def __init__(self, ctx: Context, p, precision=PW_FP64, nb_max=None, ndim_max=4, plane_mode=0,
+                 fft_ws_bytes=0):
         import torch
         self.ctx = ctx
         self.lib = ctx.lib
         self.dev = torch.device("cuda", ctx.device)
         s, keep = _problem_struct(p, self.dev)
-        self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max))
+        self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max), int(plane_mode), int(fft_ws_bytes))
         self.h = C.c_void_p()
         _check(self.lib.pw_plan_create(ctx.h, C.byref(s), C.byref(self.opts), C.byref(self.h)))
         ctx._adopt(self)
@@ -303,7 +306,7 @@ class Plan:
     def info(self):
         out = (C.c_int64 * 8)()
         _check(self.lib.pw_plan_info(self.h, out))
-        keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "plane_batch64", "plane_batch32"]
+        keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "split_plane64", "split_plane32"]
         return dict(zip(keys, list(out)))
 
     def hpsi(self, psi, out=None, prec=PW_FP64, stream=None):

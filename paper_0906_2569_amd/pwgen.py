@@ -66,19 +66,6 @@ class Problem:
     def natoms(self) -> int:
         return int(self.tau.shape[0])
 
-    def dense_d(self) -> np.ndarray:
-        """D as a dense block-diagonal nbeta x nbeta matrix (input layout helper)."""
-        nbeta = self.nbeta
-        d = np.zeros((nbeta, nbeta), dtype=np.complex128)
-        pos = 0
-        for i in range(len(self.blk_off) - 1):
-            o0, o1 = int(self.blk_off[i]), int(self.blk_off[i + 1])
-            nh = o1 - o0
-            blk = self.dmat[pos:pos + nh * nh].reshape(nh, nh).T  # col-major
-            d[o0:o1, o0:o1] = blk
-            pos += nh * nh
-        return d
-
 
 # ----------------------------------------------------------------------------
 # geometry helpers
@@ -185,6 +172,23 @@ def random_psi(rng, nb, npw):
     psi = (z[..., 0] + 1j * z[..., 1]) / math.sqrt(2.0)
     psi /= np.linalg.norm(psi, axis=1, keepdims=True)
     return np.ascontiguousarray(psi)
+
+
+def hermitian_blocks(rng, blk_off, scale=0.5):
+    """Random complex Hermitian D blocks (one per atom), concatenated column-major.
+
+    Block I is nh x nh with nh = blk_off[I+1] - blk_off[I]; entry (i, j) of a
+    block is stored at offset i + j*nh inside it.  Diagonal U[0.25, 1] Ha,
+    off-diagonal complex normal times ``scale``/2, Hermitian by construction.
+    """
+    out = []
+    for i in range(len(blk_off) - 1):
+        nh = int(blk_off[i + 1] - blk_off[i])
+        z = rng.standard_normal((nh, nh)) + 1j * rng.standard_normal((nh, nh))
+        a = 0.25 * scale * (z + np.conj(z.T))
+        a[np.diag_indices(nh)] = rng.uniform(0.25, 1.0, size=nh)
+        out.append(np.ascontiguousarray(a.T).ravel())     # column-major
+    return np.concatenate(out) if out else np.zeros((0,), dtype=np.complex128)
 
 
 def make_cell(a, ecut_ry, natoms, nb, seed, kfrac=(0.0, 0.0, 0.0), nr=None,

@@ -246,3 +246,63 @@ def test_reduced_eigh_drops_dependent_directions():
 def scipy_eigh(h, s):
     import scipy.linalg
     return scipy.linalg.eigh(h, s, eigvals_only=True)
+
+
+def _random_unitary(rng, n):
+    z = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    q, r = np.linalg.qr(z)
+    return q * (np.diag(r) / np.abs(np.diag(r)))[None, :]
+
+
+def test_projector_rotation_invariance_pins_d_layout():
+    # Rotating one atom's projectors, beta' = beta U (beta' as npw x nh columns),
+    # with D' = U^H D U leaves sum_ij beta_i D_ij beta_j^H, hence H, unchanged.
+    # D' is complex and not diagonal; reading its column-major block transposed
+    # gives conj(D') and breaks the identity.  Both routes to H.psi are pinned:
+    # the dense matrix and the real-space brute force.
+    p = pwgen.tiny_cell(91, a=6.0, ecut_ry=8.0, natoms=3, nb=4, kfrac=(0.1, 0.2, -0.3))
+    rng = np.random.default_rng(91)
+    p.dmat = pwgen.hermitian_blocks(rng, p.blk_off)
+    h0 = oracle.dense_h_of(p)
+    atom = 1
+    o0, o1 = int(p.blk_off[atom]), int(p.blk_off[atom + 1])
+    nh = o1 - o0
+    u = _random_unitary(rng, nh)
+    beta2 = p.beta.copy()
+    beta2[o0:o1] = (p.beta[o0:o1].T @ u).T
+    d_blk = p.dmat[o0 * nh:(o0 + nh) * nh].reshape(nh, nh).T     # col-major block (nh = 4 for all atoms)
+    assert np.abs(d_blk - np.conj(d_blk.T)).max() < 1e-15
+    assert np.abs(d_blk - d_blk.T).max() > 1e-2                    # really complex off-diagonal
+    d2 = np.conj(u.T) @ d_blk @ u
+    dmat2 = p.dmat.copy()
+    dmat2[o0 * nh:(o0 + nh) * nh] = d2.T.ravel()                   # write back column-major
+    h1 = oracle.dense_h(p.miller, p.kpg, p.vloc_r, beta2, p.blk_off, dmat2)
+    np.testing.assert_allclose(h1, h0, atol=1e-13, rtol=0)
+    # the transposed reading is not invariant (the test can fail)
+    dmat_t = p.dmat.copy()
+    dmat_t[o0 * nh:(o0 + nh) * nh] = d2.ravel()
+    h_bad = oracle.dense_h(p.miller, p.kpg, p.vloc_r, beta2, p.blk_off, dmat_t)
+    assert np.abs(h_bad - h0).max() > 1e-3
+    # brute-force route reads the flat blocks itself
+    ref = oracle.hpsi(h0, p.psi0)
+    got = oracle.hpsi_brute(p.miller, p.kpg, p.vloc_r, beta2, p.blk_off, dmat2, p.psi0)
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+def test_general_d_on_orthonormal_projectors():
+    # V = 0, one atom at Gamma: its s, px, py, pz projectors are orthonormal on
+    # the inversion-symmetric sphere, so H beta_k = T beta_k + sum_i beta_i D_ik
+    # for a general Hermitian D (column k of D, not row k).
+    p = pwgen.make_cell(10.0, 15.0, 1, 4, 5, nr=(30, 30, 30), with_vloc=False)
+    gram = np.conj(p.beta) @ p.beta.T
+    np.testing.assert_allclose(gram, np.eye(4), atol=1e-14)
+    rng = np.random.default_rng(5)
+    dmat = pwgen.hermitian_blocks(rng, p.blk_off)
+    d = dmat.reshape(4, 4).T                                        # d[i, k] = D_ik
+    h = oracle.dense_h(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, dmat)
+    out = oracle.hpsi(h, p.beta)
+    t = oracle.kinetic(p.kpg)
+    expect = t[None, :] * p.beta + d.T @ p.beta                     # row k: sum_i D_ik beta_i
+    np.testing.assert_allclose(out, expect, atol=1e-14)
+    out_b = oracle.hpsi_brute(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, dmat, p.beta)
+    np.testing.assert_allclose(out_b, expect, atol=1e-13)

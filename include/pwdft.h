@@ -276,6 +276,19 @@ pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, 
                           int32_t ld, double* w, pw_c128* C, int32_t ldc, double* debug, void* stream);
 
 /*
+ * pw_reduced_eigh without any device allocation, for callers that cannot
+ * allocate (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, results and errors as pw_reduced_eigh,
+ * plus PW_EINVAL for n > 256.  The workspace is a static 48 MiB device array,
+ * one per GPU, set up by pw_ctx_create and held until the process ends; no
+ * hipMalloc or hipFree is called.  Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on the same GPU (other host threads,
+ * other streams) race and must be serialized by the caller.  Synchronous.
+ */
+pw_status pw_reduced_eigh_noalloc(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H, const pw_c128* S,
+                                  int32_t ld, double* w, pw_c128* C, int32_t ldc, double* debug, void* stream);
+
+/*
  * Per-kernel timing for measurement: when enabled, each library launch of a
  * timed kernel class is bracketed by HIP events on its stream.
  * pw_profile_enable(on) resets the accumulators; pw_profile_read(k, ...)

@@ -1,7 +1,7 @@
 // Context, error reporting and option defaults of the C ABI.
 #include <string>
 
-#include "plan.h"
+#include "linalg.h"
 
 namespace {
 thread_local std::string g_last_error;
@@ -23,6 +23,8 @@ extern "C" pw_status pw_ctx_create(int device, pw_ctx* out) {
   PW_HIP(hipGetDeviceCount(&n));
   PW_CHECK(device >= 0 && device < n, PW_EINVAL, "no such HIP device");
   PW_HIP(hipSetDevice(device));
+  // this device's copy of the static workspace of the allocation-free entry point
+  PW_TRY(pw::noalloc_scratch_init(device));
   pw_ctx c = new pw_ctx_s();
   c->device = device;
   *out = c;

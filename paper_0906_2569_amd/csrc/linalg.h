@@ -33,6 +33,9 @@ pw_status heig_set_limits();
 // the Cholesky factor of S[0:n0, 0:n0] from the previous call is reused
 pw_status heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, const c128* S, int ld, double* w,
                      c128* C, int ldc, void* part, size_t part_bytes, hipStream_t st);
+// device address of this device's static workspace of pw_reduced_eigh_noalloc,
+// looked up once per device (the device must be current)
+pw_status noalloc_scratch_init(int device);
 // factor of an orthonormal leading block of size n: L = X = I
 pw_status heig_reset(HeigWork& hw, int n, hipStream_t st);
 

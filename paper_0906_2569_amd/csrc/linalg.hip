@@ -14,6 +14,9 @@
 #include <cfloat>
 #include <cmath>
 
+#include <mutex>
+#include <string>
+
 #include "linalg.h"
 #include "profile.h"
 
@@ -1763,5 +1766,74 @@ extern "C" pw_status pw_reduced_eigh(pw_ctx ctx, int32_t n, int32_t nev, const p
   (void)hipStreamSynchronize(st);
   (void)hipFree(base);
   (void)hipFree(part);
+  return stt;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant of pw_reduced_eigh: the workspace is a file-scope
+// device array (one copy per GPU, held until the process ends) instead of
+// hipMalloc'd memory.  Host code never passes the array's name to a kernel:
+// it uses the device address hipGetSymbolAddress returns for each device.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocMaxN = 256;
+constexpr size_t kNoAllocBytes = (size_t)48 << 20;   // 48 MiB per device
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) char scratch[kNoAllocBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Looks up this device's copy of the array; `device` must be current.
+pw_status pw::noalloc_scratch_init(int device) {
+  PW_CHECK(device >= 0 && device < kMaxDevices, PW_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return PW_OK;
+  const size_t need = (heig_work_bytes(kNoAllocMaxN) + 255) / 256 * 256 +
+                      splitk_part_bytes(kNoAllocMaxN, kNoAllocMaxN, kNoAllocMaxN, sizeof(c128));
+  PW_CHECK(need <= kNoAllocBytes, PW_EDEVICE, "static scratch array smaller than its stated capacity");
+  void* ptr = nullptr;
+  PW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  PW_CHECK(ptr != nullptr, PW_EDEVICE, "no device address for the static scratch array");
+  g_scratch_ptr[device] = ptr;
+  return PW_OK;
+}
+
+extern "C" pw_status pw_reduced_eigh_noalloc(pw_ctx ctx, int32_t n, int32_t nev, const pw_c128* H,
+                                             const pw_c128* S, int32_t ld, double* w, pw_c128* C, int32_t ldc,
+                                             double* debug, void* stream) {
+  PW_CHECK(ctx != nullptr, PW_EINVAL, "NULL context");
+  PW_CHECK(n >= 1 && nev >= 1 && nev <= n && ld >= n && ldc >= n, PW_EINVAL, "bad sizes");
+  PW_CHECK(n <= kNoAllocMaxN, PW_EINVAL,
+           "n = " + std::to_string(n) + " exceeds the static workspace (n <= " + std::to_string(kNoAllocMaxN) + ")");
+  PW_CHECK(H && S && w && C, PW_EINVAL, "NULL pointer");
+  PW_HIP(hipSetDevice(ctx->device));
+  PW_TRY(pw::heig_set_limits());
+  PW_TRY(pw::noalloc_scratch_init(ctx->device));   // set at context creation; a no-op here
+  void* base = g_scratch_ptr[ctx->device];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t hb = (pw::heig_work_bytes(n) + 255) / 256 * 256;
+  const size_t pb = pw::splitk_part_bytes(n, n, n, sizeof(c128));
+  void* part = static_cast<char*>(base) + hb;
+  pw::HeigWork hw;
+  pw::heig_setup(hw, base, n);
+  pw_status stt = pw::heig_solve(hw, 0, n, nev, reinterpret_cast<const c128*>(H), reinterpret_cast<const c128*>(S),
+                                 ld, w, reinterpret_cast<c128*>(C), ldc, part, pb, st);
+  if (stt == PW_OK && debug) {
+    if (hipMemcpyAsync(debug, hw.d, sizeof(double) * n, hipMemcpyDeviceToDevice, st) != hipSuccess ||
+        (n > 1 && hipMemcpyAsync(debug + n, hw.e, sizeof(double) * (n - 1), hipMemcpyDeviceToDevice, st) != hipSuccess))
+      stt = pw::fail(PW_EDEVICE, "copy of the tridiagonal failed");
+  }
+  int info = 0;
+  if (stt == PW_OK) {
+    if (hipMemcpyAsync(&info, hw.info, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      stt = pw::fail(PW_EDEVICE, "reduced eigensolver failed");
+    else if (info == 2)
+      stt = pw::fail(PW_EDEVICE, "workgroups of the cooperative tridiagonalization were not co-resident");
+    else if (info != 0)
+      stt = pw::fail(PW_EBREAKDOWN, "S is not positive definite or has rank < nev");
+  }
+  (void)hipStreamSynchronize(st);
   return stt;
 }

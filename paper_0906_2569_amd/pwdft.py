@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
            "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-           "pw_reduced_eigh", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
+           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
            "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
@@ -110,6 +110,7 @@ def load(path: str = LIB_PATH):
     lib.pw_server_destroy.argtypes = [C.c_void_p]
     lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
+    lib.pw_reduced_eigh_noalloc.argtypes = lib.pw_reduced_eigh.argtypes
     lib.pw_profile_enable.argtypes = [C.c_int]
     lib.pw_profile_only.argtypes = [C.c_int32]
     lib.pw_profile_count.restype = C.c_int32
@@ -118,7 +119,7 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
                  "pw_plan_info", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-                 "pw_reduced_eigh", "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
+                 "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
                  "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -267,7 +268,7 @@ def davidson_batched(ctx, plans, psis, opts=None, nworkers=0, stream=None):
     return st, list(status), eigs, res, [stats[i] for i in range(n)]
 
 
-def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):
+def reduced_eigh(ctx, h, s, nev, debug=False, stream=None, noalloc=False):
     """Lowest nev eigenpairs of h c = w s c (torch complex128 n x n on the device).
 
     The matrices are read column-major: pass the transpose-free torch tensors
@@ -279,7 +280,8 @@ def reduced_eigh(ctx, h, s, nev, debug=False, stream=None):
     w = torch.empty(nev, dtype=torch.float64, device=h.device)
     c = torch.empty((nev, n), dtype=torch.complex128, device=h.device)
     dbg = torch.empty(2 * n, dtype=torch.float64, device=h.device) if debug else None
-    _check(load().pw_reduced_eigh(ctx.h, n, nev, C.c_void_p(h.data_ptr()), C.c_void_p(s.data_ptr()), n,
+    fn = load().pw_reduced_eigh_noalloc if noalloc else load().pw_reduced_eigh
+    _check(fn(ctx.h, n, nev, C.c_void_p(h.data_ptr()), C.c_void_p(s.data_ptr()), n,
                                   C.c_void_p(w.data_ptr()), C.c_void_p(c.data_ptr()), n,
                                   C.c_void_p(dbg.data_ptr()) if debug else None, _stream_ptr(stream)))
     return w, c, dbg

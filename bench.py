@@ -1,16 +1,21 @@
 #!/usr/bin/env python3
 """Benchmark of the plane-wave H.psi / block-Davidson hot path on one MI355X.
 
-A step is one complete Davidson solve (float64 unless --precision mixed) of
-the 64-atom cubic cell: a = 20.5 bohr, Gamma, ecutwfc 25 Ry (18,277 plane
-waves), FFT grid 72^3, 256 s/p projectors, 128 bands, converged to 1e-8 Ry
-(||g_i|| <= 1e-6 Ha and |d eps_i| <= 5e-9 Ha) from the seeded random trial
-block.  Inputs are synthetic and resident in HBM before timing starts.
+Default workload (cell512): the largest served cell -- cubic a = 41 bohr,
+Gamma, ecutwfc 30 Ry (191,471 plane waves), FFT grid 144^3, 512 atoms with
+2048 s/p projectors, 1024 bands.  A step is one mixed-precision hpsi_apply of
+the 1024-band block (float32 transforms and projector products with float32
+accumulation; complex128 in and out); value = band-H.psi/s.  The same
+product in plain float64 on the same GPU is the metric's baseline
+(vs_baseline = mixed / float64).  Beside it: the 64-atom cell's Davidson
+solves (float64 and mixed, solves/s and the largest eigenvalue error against
+the dense oracle's golden values), the live roofline of the dominant kernel,
+and the CPU baselines (dense oracle rows, and the CPU FFT method), whose
+sampled rows also give the GPU products' parity on this cell.
 
-Prints one JSON line (rank 0): value = Davidson solves/s; band-H.psi/s of
-hpsi_apply (float64 and mixed) is reported beside it, with the live roofline
-of the dominant kernel of the timed solves and the CPU oracle timed on a
-bounded sample of the same workload.
+Other workloads: cell64 (a step is one Davidson solve of the 64-atom cell),
+batch (32 cells x 4 k-points), serve (Poisson request trace, p50/p99).
+Inputs are synthetic and resident in HBM before timing starts.
 """
 from __future__ import annotations
 
@@ -37,8 +42,9 @@ ALU_KERNELS = {"k_chol", "k_trinv", "k_tridiag", "k_backtr", "k_bisect", "k_invi
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20 for cell512, 3 otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default 3 for cell512, 1 otherwise)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--ndim", type=int, default=None,
                     help="Davidson basis cap (x nb); default: 3 for the float64 cell solve, 2 otherwise "
@@ -48,10 +54,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the per-stage H.psi measurement (keeps kernel profiles to the timed steps)")
-    ap.add_argument("--workload", choices=["cell64", "batch", "serve"], default="cell64",
-                    help="cell64: the 64-atom cell (default line); batch: 32 cells x 4 k-points solved "
+    ap.add_argument("--workload", choices=["cell512", "cell64", "batch", "serve"], default="cell512",
+                    help="cell512: mixed H.psi of the 512-atom 144^3 cell vs plain float64 (default line); "
+                         "cell64: Davidson solves of the 64-atom cell; batch: 32 cells x 4 k-points solved "
                          "concurrently vs one at a time in FP64; serve: Poisson request trace through the "
                          "serving loop (p50/p99 latency)")
+    ap.add_argument("--nbands", type=int, default=1024, help="cell512: bands of the H.psi block")
+    ap.add_argument("--solves", type=int, default=3,
+                    help="cell512: Davidson solves of the 64-atom cell per precision (0: skip)")
     ap.add_argument("--workers", type=int, default=None,
                     help="batch/serve: concurrent solves (default 12 for batch, 8 for serve)")
     ap.add_argument("--requests", type=int, default=48, help="serve: timed requests")
@@ -64,6 +74,10 @@ def parse():
                     help="solve: a step is one Davidson solve; hpsi: a step is one hpsi_apply of the "
                          "128-band block (for kernel profiles of H.psi alone)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 20 if args.workload == "cell512" else 3
+    if args.warmup is None:
+        args.warmup = 3 if args.workload == "cell512" else 1
     if args.ndim is None:
         args.ndim = 3 if (args.workload == "cell64" and args.precision == "fp64") else 2
     return args
@@ -138,7 +152,7 @@ def hpsi_graph_rates(ctx, p, plan, psi0, prec, reps):
 
 
 def hpsi_stages(ctx, p, plan, psi0, prec, reps):
-    """Per-stage rates of one 128-band H.psi: the transform stage (sphere -> sticks ->
+    """Per-stage rates of one H.psi of the band block: the transform stage (sphere -> sticks ->
     planes -> sticks -> sphere) against HBM, the projector products against the
     matrix cores.  "in_hpsi": the full product, where the projector products run on
     a side stream beside the transforms; "fft_alone": the same transforms of a plan
@@ -163,7 +177,7 @@ def hpsi_stages(ctx, p, plan, psi0, prec, reps):
 
     def summarize(prof, pr):
         out = {}
-        calls = max(prof.get("k_zinv", (0, 0, 0))[0], 1)
+        calls = reps   # H.psi calls (a call launches each pass once per band chunk)
         t_fft = sum(prof[k][1] for k in FFT_KERNELS if k in prof) / calls * 1e-3
         b_fft = sum(prof[k][2] for k in FFT_KERNELS if k in prof) / calls
         if t_fft > 0:
@@ -384,6 +398,222 @@ def bench_serve(args):
     return 0
 
 
+# HBM bytes per launch of a kernel class, from the rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters (each scaled by a device-to-device copy of known size:
+# fetched bytes = 2.0 x FETCH_SIZE KiB x 1024, written = 1.0 x WRITE_SIZE KiB
+# x 1024), keyed by (workload, kernel class).  Summaries under profiles/.
+# An entry is removed whenever its kernel changes.
+TRAFFIC_BYTES = {}
+
+
+def golden_config2():
+    """Lowest 128 eigenvalues of the 64-atom cell's dense Hamiltonian, as the
+    CPU oracle wrote them (tests/golden/make_config2_eigenvalues.py)."""
+    return np.loadtxt(os.path.join(ROOT, "tests", "golden", "config2_eigenvalues.txt"))
+
+
+def cell64_solves(ctx, nsolves):
+    """Davidson solves of the 64-atom cell (npw 18277, 72^3, 256 beta, 128 bands)
+    in float64 (basis 3 nb) and in mixed precision (basis 2 nb, the ladder);
+    locking on, to 1e-8 Ry; every solve's eigenvalues against the golden
+    dense-oracle values."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    p = pwgen.config2()
+    w = golden_config2()
+    dev = torch.device("cuda", 0)
+    psi0 = torch.from_numpy(p.psi0).to(dev)
+    out = {}
+    for key, prec, ndim in (("fp64", pwdft.PW_FP64, 3), ("mixed", pwdft.PW_MIXED, 2)):
+        plan = pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=ndim)
+        try:
+            psi = torch.empty_like(psi0)
+            eig = torch.empty(p.nb, dtype=torch.float64, device=dev)
+            resid = torch.empty_like(eig)
+            opts = pwdft.default_opts(ndim=ndim, max_iter=400)
+            psi.copy_(psi0)
+            plan.davidson(psi, eig, resid, opts=opts)        # untimed
+            torch.cuda.synchronize()
+            t_tot, errs, sts, stats, rmax = 0.0, [], [], None, 0.0
+            for _ in range(nsolves):
+                psi.copy_(psi0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st, _, _, stats = plan.davidson(psi, eig, resid, opts=opts)
+                torch.cuda.synchronize()
+                t_tot += time.perf_counter() - t0
+                e = np.abs(eig.cpu().numpy() - w)
+                errs.append(e)
+                sts.append(st)
+                rmax = max(rmax, float(resid.max()))
+            out[key] = {
+                "solves_per_s": nsolves / t_tot, "ms_per_solve": t_tot * 1e3 / nsolves, "ndim": ndim,
+                "max_abs_eig_err_ha": float(max(e.max() for e in errs)),
+                "eig_err_ha_last_solve": [float(f"{x:.2e}") for x in errs[-1]],
+                "max_resid_ha": rmax, "status": sts, "stats": stats.asdict(),
+                "band_hpsi_per_solve": stats.n_hpsi_fp64 + stats.n_hpsi_fp32,
+            }
+        finally:
+            plan.close()
+    out["mixed_over_fp64_solves"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    out["reference"] = ("lowest 128 eigenvalues of the dense 18277^2 oracle Hamiltonian "
+                        "(tests/golden/config2_eigenvalues.txt); target 5e-9 Ha = 1e-8 Ry")
+    return out
+
+
+def cpu_baseline_rows(p, got, seconds):
+    """The CPU oracle on a bounded sample of the workload: dense rows of H
+    (kinetic + direct-DFT V + projector term) built and applied to the whole
+    band block, 32 rows at a time for about `seconds`.  The same rows are the
+    parity sample of the GPU products `got` ({name: [nb][npw] device tensor}):
+    per band, ||(H psi)_gpu - (H psi)_oracle|| / ||(H psi)_oracle|| over the
+    sampled rows.  Then the CPU FFT method (3D FFTs + BLAS, float64) on a few
+    bands, checked on the same rows."""
+    import torch
+    import oracle
+    from oracle import fft_method
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    rng = np.random.default_rng(0)
+    order = rng.permutation(p.npw)
+    vt = oracle.vtilde_table(p.vloc_r)
+    done, t_rows = 0, 0.0
+    chunk = 32
+    parity = None
+    while (t_rows < seconds or done == 0) and done < p.npw:
+        rows = np.sort(order[done:done + chunk])
+        t0 = time.perf_counter()
+        hr = oracle.h_rows(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, rows, vt=vt)
+        ref = p.psi0 @ hr.T                                   # [nb][rows]
+        t_rows += time.perf_counter() - t0
+        if parity is None:
+            idx = torch.from_numpy(rows).to(next(iter(got.values())).device)
+            parity = {"rows": int(len(rows))}
+            for name, y in got.items():
+                g = y.index_select(1, idx).cpu().numpy()
+                rel = np.linalg.norm(g - ref, axis=1) / np.linalg.norm(ref, axis=1)
+                parity[name] = {"max_band_rel_err": float(rel.max()), "median_band_rel_err": float(np.median(rel))}
+            ref_rows, rows0 = ref, rows
+        done += len(rows)
+    band_hpsi_s = p.nb * done / (t_rows * p.npw)
+    out = {
+        "value": band_hpsi_s, "unit": "band-H·ψ/s", "cores": int(threads), "kind": "oracle",
+        "sample": (f"dense H rows of the oracle built and applied to all {p.nb} bands for {done} of {p.npw} "
+                   f"rows in {t_rows:.1f} s; rate = bands x sampled rows / (time x npw)"),
+    }
+    # CPU FFT method on the first few bands (all host cores)
+    nbf = min(4, p.nb)
+    t0 = time.perf_counter()
+    hf = fft_method.hpsi(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, p.psi0[:nbf])
+    t_fft = time.perf_counter() - t0
+    chk = np.linalg.norm(hf[:, rows0] - ref_rows[:nbf], axis=1) / np.linalg.norm(ref_rows[:nbf], axis=1)
+    fftm = {"value": nbf / t_fft, "unit": "band-H·ψ/s", "cores": int(os.cpu_count() or 1),
+            "kind": "cpu_fft_method_fp64",
+            "sample": f"{nbf} bands through scipy.fft 3D transforms and BLAS products in {t_fft:.1f} s",
+            "max_band_rel_err_vs_oracle_rows": float(chk.max())}
+    return out, fftm, parity
+
+
+def bench_cell512(args):
+    """Mixed-precision H.psi of the 1024-band block of the 512-atom 144^3 cell,
+    against the same product in plain float64."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    p = pwgen.config5_largest(nb=args.nbands)
+    t_gen = time.perf_counter() - t0
+    print(f"bench: cell generated in {t_gen:.1f} s (npw {p.npw}, grid {p.nr}, {p.nbeta} beta, {p.nb} bands)",
+          file=sys.stderr, flush=True)
+    ctx = pwdft.Context(0)
+    plan = pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=0)
+    info = plan.info()
+    psi0 = torch.from_numpy(p.psi0).to(dev)
+    y = torch.empty_like(psi0)
+    torch.cuda.synchronize()
+    # warm-up: every kernel class profiled (the kernel_ms breakdown)
+    pwdft.profile_enable(True)
+    for _ in range(args.warmup):
+        plan.hpsi(psi0, y, prec=pwdft.PW_MIXED)
+    torch.cuda.synchronize()
+    prof_all = {k: v for k, v in pwdft.profile_read().items() if v[0] > 0}
+    dominant = max(prof_all.items(), key=lambda kv: kv[1][1])[0]
+    # timed steps: events around the dominant class only
+    pwdft.profile_only(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.hpsi(psi0, y, prec=pwdft.PW_MIXED)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = {k: v for k, v in pwdft.profile_read().items() if v[0] > 0}
+    pwdft.profile_enable(False)
+    value = p.nb * args.steps / (t1 - t0)
+    print(f"bench: mixed H.psi {value:.4g} band-H.psi/s", file=sys.stderr, flush=True)
+    # plain float64 on the same GPU and plan (the metric's baseline)
+    y64 = torch.empty_like(psi0)
+    plan.hpsi(psi0, y64, prec=pwdft.PW_FP64)
+    torch.cuda.synchronize()
+    reps64 = max(3, args.steps // 4)
+    a = time.perf_counter()
+    for _ in range(reps64):
+        plan.hpsi(psi0, y64, prec=pwdft.PW_FP64)
+    torch.cuda.synchronize()
+    rate64 = p.nb * reps64 / (time.perf_counter() - a)
+    print(f"bench: float64 H.psi {rate64:.4g} band-H.psi/s", file=sys.stderr, flush=True)
+    stages = None
+    if not args.no_stages:
+        stages = hpsi_stages(ctx, p, plan, psi0, pwdft.PW_MIXED, 3)
+    solves = cell64_solves(ctx, args.solves) if args.solves > 0 else None
+    rl = roofline(prof, "f32")
+    tb = TRAFFIC_BYTES.get(("cell512_mixed", rl["kernel"]))
+    rl["traffic"] = tb
+    line = {
+        "metric": "band H·ψ/s and Davidson solves/s vs plain FP64 at 1e-8 Ry; p50/p99 latency",
+        "value": value, "unit": "band-H·ψ/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": (t1 - t0) * 1e3 / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": value / rate64,
+        "vs_baseline_is": "mixed-precision H.psi over plain float64 H.psi of the same cell on the same GPU "
+                          "(the metric's baseline; the paper reports no number for this path)",
+        "dtype": "f32 (transforms, projector GEMMs; complex128 in/out)",
+        "data": "synthetic (seeded cell, V(G), projectors, D, trial block)",
+        "config": {"workload": f"largest served cell: cubic a=41 bohr, Gamma, ecutwfc 30 Ry (npw {p.npw}), "
+                               f"FFT {p.nr[0]}^3, 512 atoms, {p.nbeta} beta, {p.nb} bands; one mixed-precision "
+                               f"hpsi_apply per step",
+                   "npw": p.npw, "fft": list(p.nr), "nbeta": p.nbeta, "nbands": p.nb, "precision": "mixed",
+                   "band_chunk": info["band_chunk"], "float64_plane_pass_three_kernels": bool(info["split_plane64"])},
+        "band_hpsi_per_s_mixed": value,
+        "band_hpsi_per_s_fp64": rate64,
+        "ms_per_hpsi": {"mixed": 1e3 * p.nb / value, "fp64": 1e3 * p.nb / rate64},
+        "roofline": rl,
+        "hpsi_stages": stages,
+        "cell64_solves": solves,
+        "kernel_ms": {k: round(v[1] / max(args.warmup, 1), 3)
+                      for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1][1])},
+        "kernel_ms_from": "the warm-up steps, every kernel class timed (per step)",
+        "input_generation_s": t_gen,
+    }
+    if not args.no_cpu_baseline:
+        cpu, fftm, parity = cpu_baseline_rows(p, {"mixed": y, "fp64": y64}, args.cpu_seconds)
+        line["cpu_baseline"] = cpu
+        line["cpu_fft_method"] = fftm
+        line["parity_sampled_rows"] = parity
+        line["speedup_vs_cpu_fft_method"] = value / fftm["value"]
+    if args.calibrate_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = 2 * src.numel() * 8
+    print(json.dumps(line), flush=True)
+    plan.close()
+    return 0
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -402,6 +632,8 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "cell512":
+        return bench_cell512(args)
     import torch
     from paper_0906_2569_amd import pwdft, pwgen
 

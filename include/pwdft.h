@@ -97,6 +97,9 @@ typedef struct {
   size_t       fft_ws_bytes; /* transform workspace cap (sticks, plus the plane copies of the
                                 three-kernel pass); bands are transformed in chunks that fit it;
                                 0 = 2 GiB                                                          */
+  int32_t      nl_overlap;   /* projector term of H.psi: 0 = on a side stream beside the transforms
+                                except where a transform workgroup fills a CU's LDS (then after
+                                them on the caller's stream); 1 = always beside; 2 = always after */
 } pw_plan_opts;
 
 typedef struct {

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -382,6 +383,20 @@ PlaneRegFn<T> plane_reg_kernel(int n1, int n2) {
 
 // largest LDS of the two-plane register kernel: two workgroups per CU (160 KB)
 constexpr size_t kPlaneRegMaxLds = 80 * 1024;
+// largest LDS of the one-plane register kernel (static LDS of the kernel is nil)
+constexpr size_t kPlaneRegMaxLds1 = 156 * 1024;
+
+// raise a kernel's dynamic LDS limit (above the default 64 KB) once per kernel
+pw_status raise_lds_limit(const void* fn, int bytes) {
+  static std::mutex mu;
+  static std::map<const void*, int> raised;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = raised.find(fn);
+  if (it != raised.end() && it->second >= bytes) return PW_OK;
+  PW_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  raised[fn] = bytes;
+  return PW_OK;
+}
 
 template <typename T>
 size_t plane_reg_lds_bytes(int n, int nxr, int pp) {
@@ -734,6 +749,7 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
   }
   const bool mixed = o->precision == PW_MIXED;
   PW_CHECK(o->plane_mode == 0 || o->plane_mode == 1, PW_EINVAL, "plane_mode must be 0 or 1");
+  PW_CHECK(o->nl_overlap >= 0 && o->nl_overlap <= 2, PW_EINVAL, "nl_overlap must be 0, 1 or 2");
   geo->split64 = o->plane_mode == 1 || plane_batch<double>(geo->n1, geo->n2, geo->nxr) == 0;
   geo->split32 = mixed && (o->plane_mode == 1 || plane_batch<float>(geo->n1, geo->n2, geo->nxr) == 0);
   PW_CHECK(split_lds_bytes<double>(geo->n1, geo->n2) <= 160 * 1024, PW_EINVAL, "grid too large for the plane pass");
@@ -1024,20 +1040,15 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 2) <= kPlaneRegMaxLds) {
       preg = plane_reg_kernel<T, 2>(p->n1, p->n2);
       ppw = 2;
-    } else if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 1) <= 64 * 1024) {
+    } else if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 1) <= kPlaneRegMaxLds1) {
+      // one plane per workgroup; above 80 KB a single workgroup fills the
+      // CU's LDS (float32 at 144^2: 85 KB, 512 threads, 8 waves per CU)
       preg = plane_reg_kernel<T, 1>(p->n1, p->n2);
       ppw = 1;
     }
   }
   const size_t plds = preg ? plane_reg_lds_bytes<T>(p->n1, p->nxr, ppw) : 0;
-  if (preg && plds > 64 * 1024) {
-    // above the default per-workgroup limit: raised once per kernel
-    static std::atomic<const void*> raised_for{nullptr};
-    if (raised_for.load() != (const void*)preg) {
-      PW_HIP(hipFuncSetAttribute((const void*)preg, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPlaneRegMaxLds));
-      raised_for.store((const void*)preg);
-    }
-  }
+  if (preg && plds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)preg, (int)plds));
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
   const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
@@ -1102,13 +1113,32 @@ pw_status nonlocal_side(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hps
   return PW_OK;
 }
 
+// Does the projector term run on the side stream, beside the transforms?  By
+// default yes, unless the plane pass of this precision holds a whole CU's LDS
+// with one workgroup (no room for the GEMM waves beside it: they only slow
+// each other down) or takes the three-kernel form.
+bool nl_beside(pw_plan p, bool f64) {
+  if (p->opts.nl_overlap == 1) return true;
+  if (p->opts.nl_overlap == 2) return false;
+  if (f64 ? p->split64 : p->split32) return false;
+  const size_t one = f64 ? plane_reg_lds_bytes<double>(p->n1, p->nxr, 1) : plane_reg_lds_bytes<float>(p->n1, p->nxr, 1);
+  const bool reg = p->use_reg_plane && p->n1 == p->n2 && p->n1 % 4 == 0 &&
+                   (f64 ? plane_reg_kernel<double, 1>(p->n1, p->n2) != nullptr
+                        : plane_reg_kernel<float, 1>(p->n1, p->n2) != nullptr);
+  return !(reg && one > kPlaneRegMaxLds);
+}
+
 pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
                           c128* hpsi, int ldhpsi, hipStream_t s) {
   if (nb == 0) return PW_OK;
   const bool f64 = prec == PW_FP64;
   if (!f64) PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
   hipEvent_t join = nullptr;
-  if (p->nbeta > 0) {
+  if (p->nbeta > 0 && !nl_beside(p, f64)) {
+    // projector term first, on the caller's stream; the transforms add to it
+    if (f64) PW_TRY(nonlocal_side<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
+    else PW_TRY(nonlocal_side<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
+  } else if (p->nbeta > 0) {
     // fork: the side stream starts once psi is ready on s
     PW_HIP(hipEventRecord(p->ev_fork, s));
     PW_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));

@@ -306,4 +306,11 @@ def tiny_cell(seed, a=5.0, ecut_ry=6.0, natoms=2, nb=4, kfrac=(0.0, 0.0, 0.0), n
     return make_cell(a, ecut_ry, natoms, nb, seed, kfrac=kfrac, nr=nr, name=f"tiny{seed}", **kw)
 
 
+def config5_largest(nb=1024, **kw):
+    """The largest served request at Gamma: a = 41 bohr, 30 Ry (npw 191471),
+    grid 144^3, 512 atoms, 2048 beta, 1024 bands (fewer with ``nb``: the
+    first nb bands of the same draw)."""
+    return make_cell(41.0, 30.0, 512, nb, SEED_BASE + 5, name=f"cfg5_a41_30Ry_nat512_nb{nb}", **kw)
+
+
 CONFIGS = {1: config1, 2: config2, 3: config3}

@@ -293,3 +293,20 @@ def test_band_chunks(ctx, prec, plane_mode):
         np.testing.assert_array_equal(got, ref)
     h = oracle.dense_h_of(p)
     assert _rel_err(got, oracle.hpsi(h, p.psi0)) <= (1e-11 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_config5_largest_cell_sampled_rows(ctx, prec):
+    # the largest served cell (a = 41 bohr, 30 Ry, npw 191471, 144^3, 512 atoms,
+    # 2048 projectors) with 16 bands: float64 takes the three-kernel plane
+    # pass, float32 the one-plane register pass; rows of the dense H from the oracle
+    p = pwgen.config5_largest(nb=16)
+    info = {}
+    got = _hpsi(ctx, p, p.psi0, prec=prec, info=info)
+    assert info["split_plane64"] == 1 and info["split_plane32"] == 0
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(p.npw, 64, replace=False))
+    ref = oracle.hpsi_rows_of(p, p.psi0, rows)
+    err = _sampled_rel_err(got[:, rows], ref)
+    print("config-5 cell, precision", prec, "max per-band relative error on 64 rows", err)
+    assert err <= (1e-11 if prec == 0 else 2e-6)

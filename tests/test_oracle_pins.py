@@ -306,3 +306,13 @@ def test_general_d_on_orthonormal_projectors():
     np.testing.assert_allclose(out, expect, atol=1e-14)
     out_b = oracle.hpsi_brute(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, dmat, p.beta)
     np.testing.assert_allclose(out_b, expect, atol=1e-13)
+
+
+def test_cpu_fft_method_baseline_matches_dense():
+    # the timed CPU FFT-method baseline computes the oracle's product
+    from oracle import fft_method
+    p = pwgen.tiny_cell(95, a=7.0, ecut_ry=9.0, natoms=3, nb=5, kfrac=(0.25, -0.25, 0.0), nr=(36, 30, 40))
+    p.dmat = pwgen.hermitian_blocks(np.random.default_rng(95), p.blk_off)
+    ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
+    got = fft_method.hpsi(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, p.psi0)
+    np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)

@@ -100,6 +100,8 @@ typedef struct {
   int32_t      nl_overlap;   /* projector term of H.psi: 0 = on a side stream beside the transforms
                                 except where a transform workgroup fills a CU's LDS (then after
                                 them on the caller's stream); 1 = always beside; 2 = always after */
+  int32_t      density;      /* 1: also allocate the workspace of pw_density and pw_scf_norm
+                                (the plane copies of the three-kernel pass and one complex grid)   */
 } pw_plan_opts;
 
 typedef struct {
@@ -196,6 +198,66 @@ pw_status hpsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128*
 pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, double* eig,
                          double* resid, const pw_david_opts* opts, pw_david_stats* stats,
                          void* stream);
+
+/*
+ * Band-by-band preconditioned conjugate gradient for the nb lowest
+ * eigenpairs (the iterative-diagonalization appendix, "Conjugate-Gradient"):
+ * band i minimizes the Rayleigh quotient under orthogonality to bands
+ * 0..i-1, along Polak-Ribiere conjugate directions of the preconditioned
+ * gradient, with the exact line minimization psi cos(theta) + n sin(theta);
+ * kinetic-only preconditioner P^2(G) = 1 / smax(T_G, precond_floor),
+ * smax as in pw_david_opts.  One single-band float64 H.psi per iteration.
+ * Same arguments and outputs as davidson_solve (psi [dev] in: trial vectors,
+ * out: orthonormal eigenvectors; eig, resid [dev] from a final float64
+ * H.psi); needs a plan with ndim_max >= 2 (its workspace).  Returns PW_OK,
+ * PW_ENOTCONV (a band reached max_iter; outputs valid), PW_ENAN, PW_EINVAL,
+ * PW_EDEVICE.  The host reads one small result per iteration.
+ */
+typedef struct {
+  int32_t max_iter;          /* iterations per band (default 400)                                    */
+  double  tol_resid;         /* Ha, band done when ||H psi - eps psi|| <= tol_resid (default 1e-6) ... */
+  double  tol_deig;          /* ... and |d eps| <= tol_deig over the last step (default 5e-9 Ha)     */
+  double  precond_floor;     /* Ha, tau of the kinetic preconditioner (default 0.2)                 */
+} pw_cg_opts;
+typedef struct {
+  int32_t iters;             /* iterations summed over bands                                          */
+  int32_t max_band_iters;    /* largest iteration count of one band                                   */
+  int32_t nconv;             /* bands that met the tolerances                                         */
+  double  max_resid;         /* max_i ||g_i|| of the final float64 verification                       */
+} pw_cg_stats;
+void      pw_cg_opts_default(pw_cg_opts* opts);
+pw_status pcg_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, double* eig, double* resid,
+                    const pw_cg_opts* opts, pw_cg_stats* stats, void* stream);
+
+/*
+ * Output charge density of a block of bands (the rho_out equation of the
+ * self-consistency appendix, with occupation weights):
+ *   rho(r_j) = (1/omega) sum_b w_b |psi_b(r_j)|^2,   psi_b(r_j) = sum_G psi_b(G) exp(+i G.r_j),
+ * on the plan's FFT grid r_j (x fastest).  psi [dev] [nb][ldpsi] complex128;
+ * w [dev] double[nb]; omega = cell volume in bohr^3; rho [dev]
+ * double[n3][n2][n1], overwritten (accumulate = 0) or added to (accumulate = 1).
+ * The grid holds the density without aliasing when n_d >= 4 max|m_d| + 1
+ * (checked at plan creation).  float64, deterministic (bands are summed in
+ * order); asynchronous on `stream`, no allocation.  Needs a plan created with
+ * opts.density = 1.  Errors: PW_EINVAL.
+ */
+pw_status pw_density(pw_plan plan, int32_t nb, const pw_c128* psi, int32_t ldpsi, const double* w,
+                     double omega, int32_t accumulate, double* rho, void* stream);
+
+/*
+ * Squared scf norm of the density change (the self-consistency appendix's
+ * estimate of the self-consistency error, its Hartree-energy form):
+ *   ||rho_out - rho_in||^2 = 4 pi omega sum_{G != 0} |drho(G)|^2 / |G|^2,
+ *   drho(G) = (1/N) sum_j (rho_out - rho_in)(r_j) exp(-i G.r_j)
+ * (Hartree units, e^2 = 1; with these Fourier coefficients this equals
+ * the integral of drho times the Hartree potential it generates), summed
+ * over every G = m1 b1 + m2 b2 + m3 b3 of the grid with grid index i_d -> m_d
+ * = i_d for i_d <= n_d/2, else i_d - n_d.  rho_out, rho_in [dev]
+ * double[n3][n2][n1]; bvec [host] 9 doubles, row d = b_d in bohr^-1;
+ * norm2 [host].  Synchronous on `stream`.  Needs opts.density = 1.
+ */
+pw_status pw_scf_norm(pw_plan plan, const double* rho_out, const double* rho_in, const double* bvec,
+                      double omega, double* norm2, void* stream);
 
 /*
  * Batches of independent problems (cells x k-points; the paper's pool level,

@@ -184,6 +184,61 @@ def h_diag(miller, kpg, vloc_r, beta, blk_off, dmat) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# output density and scf norm (self-consistency appendix)
+# ----------------------------------------------------------------------------
+
+def density(miller, nr, psi, w, omega) -> np.ndarray:
+    """rho(r_j) = (1/omega) sum_b w_b |psi_b(r_j)|^2 on the grid, [n3][n2][n1].
+
+    psi_b(r_j) = sum_G psi_b(G) exp(+2 pi i m_G.j / n) by explicit phase sums
+    (no FFT); the output-density equation of the self-consistency appendix
+    with occupation weights w_b.  For small cells.
+    """
+    miller = np.asarray(miller, dtype=np.int64)
+    n1, n2, n3 = (int(x) for x in nr)
+    j3, j2, j1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    frac = np.stack([j1.ravel() / n1, j2.ravel() / n2, j3.ravel() / n3], axis=1)
+    phase = np.exp(2j * math.pi * (miller @ frac.T))            # [npw][N]
+    psi = np.asarray(psi, dtype=np.complex128)
+    rho = np.zeros(n1 * n2 * n3)
+    for b in range(psi.shape[0]):
+        pr = psi[b] @ phase
+        rho += float(w[b]) * (pr.real ** 2 + pr.imag ** 2)
+    return (rho / omega).reshape(n3, n2, n1)
+
+
+def scf_norm2(drho, bvec, omega) -> float:
+    """Squared scf norm 4 pi omega sum_{G != 0} |drho(G)|^2 / |G|^2.
+
+    drho(G) = (1/N) sum_j drho(r_j) exp(-i G.r_j) by three explicit DFT
+    matrices (no FFT); G = sum_d m_d b_d with b_d = bvec[d] and the grid index
+    i_d -> m_d = i_d for i_d <= n_d/2, else i_d - n_d.  The Hartree-energy
+    form of the self-consistency error estimate of the self-consistency
+    appendix, in Hartree units (e^2 = 1).
+    """
+    d = np.asarray(drho, dtype=np.float64)
+    n3, n2, n1 = d.shape
+    f1, f2, f3 = dft_matrix(n1, -1), dft_matrix(n2, -1), dft_matrix(n3, -1)
+    t = np.einsum("mj,abj->abm", f1, d.astype(np.complex128))
+    t = np.einsum("mj,ajc->amc", f2, t)
+    t = np.einsum("mj,jbc->mbc", f3, t)
+    c = t / float(n1 * n2 * n3)
+    b = np.asarray(bvec, dtype=np.float64).reshape(3, 3)
+    total = 0.0
+    for i3 in range(n3):
+        m3 = i3 if i3 <= n3 // 2 else i3 - n3
+        for i2 in range(n2):
+            m2 = i2 if i2 <= n2 // 2 else i2 - n2
+            for i1 in range(n1):
+                m1 = i1 if i1 <= n1 // 2 else i1 - n1
+                if m1 == 0 and m2 == 0 and m3 == 0:
+                    continue
+                g = m1 * b[0] + m2 * b[1] + m3 * b[2]
+                total += abs(c[i3, i2, i1]) ** 2 / float(g @ g)
+    return 4.0 * math.pi * omega * total
+
+
+# ----------------------------------------------------------------------------
 # spectra
 # ----------------------------------------------------------------------------
 
@@ -254,6 +309,80 @@ def davidson(h: np.ndarray, psi0: np.ndarray, nb: int, hdiag: np.ndarray | None 
         eps = np.real(np.einsum("bg,bg->b", np.conj(psi), hpsi_))
         it += 1
     return eps, psi, it, rn
+
+
+def pcg(h: np.ndarray, psi0: np.ndarray, nb: int, kin: np.ndarray, tol_resid: float = 1e-6,
+        tol_deig: float = 5e-9, max_iter: int = 400, precond_floor: float = 0.2):
+    """Band-by-band preconditioned conjugate gradient (the iterative-
+    diagonalization appendix, "Conjugate-Gradient"), S = 1, on a dense H.
+
+    Band i minimizes <y|H~|y> - lambda(<y|S~|y> - 1) with H~ = PHP, S~ = PSP,
+    y = P^-1 psi, orthogonal to the bands already found; written here in the
+    psi variables (P g and P h of the appendix are the vectors kept):
+      lambda = <y|S~H~|y> / <y|S~^2|y> = Re <psi|P^2|H psi> / <psi|P^2|psi>,
+      P g = P^2 (H - lambda) psi, made orthogonal to psi_j (j < i);
+      P h = P g + gamma P h_prev, gamma = Re <g - g_prev|S~|g> / <g_prev|S~|g_prev>
+            (Polak-Ribiere; <g|S~|g'> = <P g|P g'>), P h made orthogonal to psi;
+      n = P h / ||P h||;  psi <- psi cos(theta) + n sin(theta),
+      theta = (1/2) atan(a / (eps - b)), a = 2 Re <psi|H|n>, b = <n|H|n>,
+      eps = <psi|H|psi>, taking of the two stationary angles theta and
+      theta + pi/2 the one with the lower energy.
+    P^2 is kinetic-only: P^2(G) = 1 / smax(T_G, tau), the smooth maximum of
+    T_G = |k+G|^2/2 and tau (the appendix's 2m / (hbar^2 |k+G|^2) up to a
+    constant factor, which the iteration does not see, kept finite at k+G = 0).
+    Band i stops when ||H psi - eps psi|| <= tol_resid and |d eps| <= tol_deig,
+    or after max_iter iterations.  Returns (eps, psi [nb][npw], iterations per band).
+    """
+    x = kin
+    p2 = 1.0 / (0.5 * (x + precond_floor + np.sqrt((x - precond_floor) ** 2 + precond_floor ** 2)))
+    npw = h.shape[0]
+    out = np.zeros((nb, npw), dtype=np.complex128)
+    eps_out = np.zeros(nb)
+    iters = []
+    for i in range(nb):
+        psi = np.asarray(psi0[i], dtype=np.complex128).copy()
+        for _ in range(2):                                   # orthonormalize to the bands found
+            psi -= out[:i].T @ (np.conj(out[:i]) @ psi)
+        psi /= np.linalg.norm(psi)
+        hpsi_ = h @ psi
+        eps = float(np.real(np.vdot(psi, hpsi_)))
+        g_prev = d_prev = None
+        gg_prev = 0.0
+        it = 0
+        while True:
+            lam = float(np.real(np.vdot(psi, p2 * hpsi_)) / np.real(np.vdot(psi, p2 * psi)))
+            g = p2 * (hpsi_ - lam * psi)
+            g -= out[:i].T @ (np.conj(out[:i]) @ g)
+            gg = float(np.real(np.vdot(g, g)))
+            if g_prev is None:
+                d = g.copy()
+            else:
+                gamma = float(np.real(np.vdot(g - g_prev, g))) / gg_prev
+                d = g + gamma * d_prev
+            d -= psi * np.vdot(psi, d)
+            n = d / np.linalg.norm(d)
+            hn = h @ n
+            a = 2.0 * float(np.real(np.vdot(psi, hn)))
+            b = float(np.real(np.vdot(n, hn)))
+            theta = 0.5 * math.atan(a / (eps - b)) if eps != b else math.pi / 4
+            def energy(t):
+                return eps * math.cos(t) ** 2 + b * math.sin(t) ** 2 + a * math.sin(t) * math.cos(t)
+            if energy(theta + 0.5 * math.pi) < energy(theta):
+                theta += 0.5 * math.pi
+            psi = psi * math.cos(theta) + n * math.sin(theta)
+            hpsi_ = hpsi_ * math.cos(theta) + hn * math.sin(theta)
+            eps_new = float(np.real(np.vdot(psi, hpsi_)))
+            it += 1
+            r = float(np.linalg.norm(hpsi_ - eps_new * psi))
+            done = r <= tol_resid and abs(eps_new - eps) <= tol_deig
+            eps = eps_new
+            g_prev, d_prev, gg_prev = g, d, gg
+            if done or it >= max_iter:
+                break
+        out[i] = psi
+        eps_out[i] = eps
+        iters.append(it)
+    return eps_out, out, iters
 
 
 def reduced_eigh(hred: np.ndarray, sred: np.ndarray, nev: int, drop: float = 1e-10):

@@ -528,6 +528,17 @@ struct Solver {
 
 }  // namespace
 
+pw_status pw::final_check(pw_plan p, int nb, const c128* psi, int ldpsi, double* eig, double* resid,
+                          hipStream_t st) {
+  PW_CHECK(p->dav != nullptr, PW_EINVAL, "plan was created without solver workspace (ndim_max = 0)");
+  DavWork& W = *p->dav;
+  PW_CHECK(nb <= W.nbmax, PW_EINVAL, "nb > nb_max");
+  PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
+  k_final<<<nb, 256, 0, st>>>(p->npw, psi, ldpsi, W.hpsi, W.ld, eig, resid);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
 extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ldpsi, double* eig,
                                     double* resid, const pw_david_opts* o_, pw_david_stats* stats_out,
                                     void* stream) {

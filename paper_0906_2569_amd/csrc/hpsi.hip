@@ -682,13 +682,14 @@ void twiddles(int L, std::vector<c128>& t64, std::vector<c64>& t32) {
 struct Geometry {
   int n1, n2, n3, nst, nxr, ldst, nhmax;
   bool split64, split32;   // three-kernel plane pass per precision
+  bool density;            // workspace of pw_density / pw_scf_norm
 };
 
 // transform workspace per band: the sticks, plus the plane copies of the
 // three-kernel plane pass when a precision of the plan takes it
 size_t fft_ws_per_band(const Geometry& g) {
   size_t b = (size_t)g.n3 * g.ldst * sizeof(c128);
-  if (g.split64 || g.split32) b += (size_t)g.n3 * g.n2 * g.nxr * sizeof(c128);
+  if (g.split64 || g.split32 || g.density) b += (size_t)g.n3 * g.n2 * g.nxr * sizeof(c128);
   return b;
 }
 
@@ -752,6 +753,8 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
   PW_CHECK(o->nl_overlap >= 0 && o->nl_overlap <= 2, PW_EINVAL, "nl_overlap must be 0, 1 or 2");
   geo->split64 = o->plane_mode == 1 || plane_batch<double>(geo->n1, geo->n2, geo->nxr) == 0;
   geo->split32 = mixed && (o->plane_mode == 1 || plane_batch<float>(geo->n1, geo->n2, geo->nxr) == 0);
+  PW_CHECK(o->density == 0 || o->density == 1, PW_EINVAL, "density must be 0 or 1");
+  geo->density = o->density == 1;
   PW_CHECK(split_lds_bytes<double>(geo->n1, geo->n2) <= 160 * 1024, PW_EINVAL, "grid too large for the plane pass");
   PW_CHECK(z_lds_bytes<double>(geo->n3) <= 160 * 1024, PW_EINVAL, "n3 too large");
   return PW_OK;
@@ -777,9 +780,10 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
   b += (size_t)pr->nbeta * (2 * sizeof(int) + geo.nhmax * (sizeof(c128) + sizeof(c64)));
   const int chunk = band_chunk_for(*o, geo);
   b += (size_t)chunk * fft_ws_per_band(geo);
+  if (geo.density) b += N * sizeof(c128) + kDensityPart * sizeof(double);
   b += 2 * (size_t)o->nb_max * std::max(pr->nbeta, 1) * sizeof(c128);
   b += pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128));
-  if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max);
+  if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max) + pw::cg_bytes(pr->npw, o->nb_max);
   return b;
 }
 
@@ -969,8 +973,12 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
                                        p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
   // workspace
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->sticks), (size_t)p->band_chunk * n3 * p->ldst));
-  if (p->split64 || p->split32)
+  if (p->split64 || p->split32 || geo.density)
     PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->rows), (size_t)p->band_chunk * n3 * n2 * nxr));
+  if (geo.density) {
+    PLAN_TRY(dalloc(p, &p->dgrid, (size_t)p->N));
+    PLAN_TRY(dalloc(p, &p->dpart, (size_t)kDensityPart));
+  }
   const int nbeta1 = std::max(p->nbeta, 1);
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becp), (size_t)o->nb_max * nbeta1));
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
@@ -980,7 +988,10 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming) != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "stream/event creation failed"));
-  if (o->ndim_max > 0) PLAN_TRY(pw::dav_alloc(p));
+  if (o->ndim_max > 0) {
+    PLAN_TRY(pw::dav_alloc(p));
+    PLAN_TRY(pw::cg_alloc(p));
+  }
   if (hipDeviceSynchronize() != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "plan initialisation kernels failed"));
 #undef PLAN_TRY
@@ -993,6 +1004,7 @@ extern "C" pw_status pw_plan_destroy(pw_plan p) {
   (void)hipSetDevice(p->device);
   (void)hipDeviceSynchronize();
   pw::dav_free(p);
+  pw::cg_free(p);
   for (void* q : p->allocs)
     if (q) (void)hipFree(q);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
@@ -1098,6 +1110,29 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   return PW_OK;
 }
 }  // namespace
+
+pw_status pw::psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStream_t s) {
+  PW_CHECK(p->rows != nullptr, PW_EINVAL, "plan has no plane-copy workspace (create it with opts.density = 1)");
+  PW_CHECK(nb >= 0 && nb <= p->band_chunk, PW_EINVAL, "more bands than one transform chunk");
+  if (nb == 0) return PW_OK;
+  const SphereMap m = p->map();
+  const cpx<double>* tw2 = (const cpx<double>*)p->tw64_2;
+  const cpx<double>* tw3 = (const cpx<double>*)p->tw64_3;
+  cpx<double>* st = static_cast<cpx<double>*>(p->sticks);
+  const ZRegFns<double> zr = p->use_reg_plane ? zreg_kernels<double>(p->n3) : ZRegFns<double>{};
+  const int nb8 = ceil_div(nb, 8) * 8;
+  if (zr.inv) {
+    const int gzr = ceil_div(p->nst, ZRSTICKS);
+    zr.inv<<<gzr * nb8, ZRTHREADS, 0, s>>>(m, psi, ldpsi, st, tw3, gzr, nb);
+  } else {
+    const int gz = ceil_div(p->nst, ZSB);
+    k_zinv<double><<<gz * nb8, ZTHREADS, z_lds_bytes<double>(p->n3), s>>>(m, psi, ldpsi, st, tw3, gz, nb);
+  }
+  k_plane_yinv<double><<<dim3(p->n3, nb, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS,
+                         split_lds_bytes<double>(p->n1, p->n2), s>>>(m, st, static_cast<cpx<double>*>(p->rows), tw2);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
 
 // Projector term on the plan's side stream, written into hpsi (overwrite):
 // hpsi = beta (D <beta|psi>).  Runs concurrently with the transform passes

@@ -33,6 +33,10 @@ struct SphereMap {
 };
 
 struct DavWork;  // Davidson workspace (davidson.hip)
+struct CgWork;   // conjugate-gradient workspace (pcg.hip)
+
+// partial sums of pw_scf_norm (one per workgroup of its last transform pass, plus the total)
+constexpr int kDensityPart = 16384;
 
 struct pw_plan_s {
   pw_ctx ctx = nullptr;
@@ -68,13 +72,17 @@ struct pw_plan_s {
 
   // H.psi workspace (device)
   void* sticks = nullptr;    // [band_chunk][n3][ldst] complex (FP64 size)
-  void* rows = nullptr;      // [band_chunk][n3][n2][nxr] complex (FP64 size), three-kernel plane pass only
+  void* rows = nullptr;      // [band_chunk][n3][n2][nxr] complex (FP64 size), three-kernel plane pass
+                             // and density only
+  c128* dgrid = nullptr;     // [N] complex grid of pw_scf_norm (density plans)
+  double* dpart = nullptr;   // partial sums of pw_scf_norm
   void* part = nullptr;      // split-K partials
   size_t part_bytes = 0;
   void* becp = nullptr;      // [nb_max][nbeta] complex128 (or complex64)
   void* becpd = nullptr;     // D-applied becp
 
   DavWork* dav = nullptr;
+  CgWork* cg = nullptr;
   std::vector<void*> allocs;
   hipStream_t side = nullptr;          // projector term runs here, beside the transforms
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -91,6 +99,9 @@ struct pw_plan_s {
 };
 
 namespace pw {
+// sphere -> sticks -> rows for nb <= band_chunk bands in float64: inverse z
+// and inverse y transforms into p->rows ([band][z][y][x column])
+pw_status psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStream_t stream);
 // H.psi for nb bands (nb <= opts.nb_max) on `stream`.
 pw_status hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
                       c128* hpsi, int ldhpsi, hipStream_t stream);
@@ -149,4 +160,10 @@ bool dav_get_coop(pw_plan p);
 void ctx_release_pool(pw_ctx ctx);
 void dav_free(pw_plan p);
 size_t dav_bytes(int npw, int nb_max, int ndim_max);
+// float64 H psi of the block (into the Davidson workspace), then
+// eig_b = <psi_b|H psi_b> / <psi_b|psi_b> and resid_b = ||H psi_b - eig_b psi_b||
+pw_status final_check(pw_plan p, int nb, const c128* psi, int ldpsi, double* eig, double* resid, hipStream_t st);
+pw_status cg_alloc(pw_plan p);
+void cg_free(pw_plan p);
+size_t cg_bytes(int npw, int nb_max);
 }  // namespace pw

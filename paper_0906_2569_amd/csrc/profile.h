@@ -6,7 +6,7 @@
 namespace pw {
 enum ProfKernel {
   PK_ZINV = 0, PK_PLANE, PK_ZFWD, PK_CALBEC, PK_CALBEC_RED, PK_ADDNL, PK_GEMM_CN, PK_GEMM_RED, PK_GEMM_NN,
-  PK_CHOL, PK_TRINV, PK_TRIDIAG, PK_BISECT, PK_INVIT, PK_BACKTR, PK_VECTOR, PK_COUNT
+  PK_CHOL, PK_TRINV, PK_TRIDIAG, PK_BISECT, PK_INVIT, PK_BACKTR, PK_VECTOR, PK_DENSITY, PK_COUNT
 };
 // timing is enabled for kernel class `kernel`
 bool prof_on(int kernel);

@@ -11,7 +11,8 @@
 namespace {
 const char* kNames[pw::PK_COUNT] = {"k_zinv", "k_plane", "k_zfwd", "calbec_gemm", "calbec_reduce_dapply",
                                     "add_nl_gemm", "zgemm_cn", "zgemm_cn_reduce", "zgemm_nn", "k_chol",
-                                    "k_trinv", "k_tridiag", "k_bisect", "k_invit", "k_backtr", "vector_ops"};
+                                    "k_trinv", "k_tridiag", "k_bisect", "k_invit", "k_backtr", "vector_ops",
+                                    "density"};
 struct Rec {
   int k;
   double units;

@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
            "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
+           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
            "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
@@ -44,13 +44,27 @@ class Problem(C.Structure):
 
 class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("nb_max", C.c_int32), ("ndim_max", C.c_int32),
-                ("plane_mode", C.c_int32), ("fft_ws_bytes", C.c_size_t), ("nl_overlap", C.c_int32)]
+                ("plane_mode", C.c_int32), ("fft_ws_bytes", C.c_size_t), ("nl_overlap", C.c_int32),
+                ("density", C.c_int32)]
 
 
 class DavOpts(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("max_iter", C.c_int32), ("tol_resid", C.c_double),
                 ("tol_deig", C.c_double), ("precond_floor", C.c_double),
                 ("ladder_switch", C.c_double), ("history", C.POINTER(C.c_double)), ("lock", C.c_int32)]
+
+
+class CgOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int32), ("tol_resid", C.c_double), ("tol_deig", C.c_double),
+                ("precond_floor", C.c_double)]
+
+
+class CgStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("max_band_iters", C.c_int32), ("nconv", C.c_int32),
+                ("max_resid", C.c_double)]
+
+    def asdict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class ServerOpts(C.Structure):
@@ -111,6 +125,14 @@ def load(path: str = LIB_PATH):
     lib.pw_reduced_eigh.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
                                     C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]
     lib.pw_reduced_eigh_noalloc.argtypes = lib.pw_reduced_eigh.argtypes
+    lib.pw_cg_opts_default.argtypes = [P(CgOpts)]
+    lib.pw_cg_opts_default.restype = None
+    lib.pcg_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, P(CgOpts),
+                              P(CgStats), C.c_void_p]
+    lib.pw_density.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_double, C.c_int32,
+                               C.c_void_p, C.c_void_p]
+    lib.pw_scf_norm.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_double,
+                                C.POINTER(C.c_double), C.c_void_p]
     lib.pw_profile_enable.argtypes = [C.c_int]
     lib.pw_profile_only.argtypes = [C.c_int32]
     lib.pw_profile_count.restype = C.c_int32
@@ -119,7 +141,8 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
                  "pw_plan_info", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-                 "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
+                 "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve",
+                 "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
                  "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
@@ -291,19 +314,20 @@ class Plan:
     """A problem's maps, operator copies and workspace on one device."""
 
     def __init__(self, ctx: Context, p, precision=PW_FP64, nb_max=None, ndim_max=4, plane_mode=0,
-                 fft_ws_bytes=0, nl_overlap=0):
+                 fft_ws_bytes=0, nl_overlap=0, density=0):
         import torch
         self.ctx = ctx
         self.lib = ctx.lib
         self.dev = torch.device("cuda", ctx.device)
         s, keep = _problem_struct(p, self.dev)
         self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max), int(plane_mode), int(fft_ws_bytes),
-                             int(nl_overlap))
+                             int(nl_overlap), int(density))
         self.h = C.c_void_p()
         _check(self.lib.pw_plan_create(ctx.h, C.byref(s), C.byref(self.opts), C.byref(self.h)))
         ctx._adopt(self)
         del keep
         self.npw = int(s.npw)
+        self.nr = tuple(int(x) for x in p.nr)
         self.precision = precision
 
     def info(self):
@@ -365,6 +389,48 @@ class Plan:
         if st not in (PW_OK, PW_ENOTCONV):
             _check(st)
         return st, eig, resid, stats
+
+    def pcg(self, psi, eig=None, resid=None, opts=None, stream=None, **kw):
+        """In-place band-by-band conjugate gradient on psi [nb][>=npw]; returns (status, eig, resid, stats)."""
+        import torch
+        nb = psi.shape[0]
+        if eig is None:
+            eig = torch.empty(nb, dtype=torch.float64, device=psi.device)
+        if resid is None:
+            resid = torch.empty(nb, dtype=torch.float64, device=psi.device)
+        if opts is None:
+            opts = CgOpts()
+            self.lib.pw_cg_opts_default(C.byref(opts))
+            for k, v in kw.items():
+                setattr(opts, k, v)
+        stats = CgStats()
+        st = self.lib.pcg_solve(self.h, nb, C.c_void_p(psi.data_ptr()), psi.stride(0), C.c_void_p(eig.data_ptr()),
+                                C.c_void_p(resid.data_ptr()), C.byref(opts), C.byref(stats), _stream_ptr(stream))
+        if st not in (PW_OK, PW_ENOTCONV):
+            _check(st)
+        return st, eig, resid, stats
+
+    def density(self, psi, w, omega, rho=None, accumulate=False, stream=None):
+        """rho (+)= (1/omega) sum_b w_b |psi_b(r)|^2 on the plan's grid; returns rho
+        (torch float64 [n3][n2][n1]).  Needs a plan created with density=1."""
+        import torch
+        assert psi.dtype == torch.complex128 and psi.stride(1) == 1
+        w = torch.as_tensor(w, dtype=torch.float64, device=psi.device).contiguous()
+        if rho is None:
+            rho = torch.empty((self.nr[2], self.nr[1], self.nr[0]), dtype=torch.float64, device=psi.device)
+        _check(self.lib.pw_density(self.h, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                   C.c_void_p(w.data_ptr()), float(omega), 1 if accumulate else 0,
+                                   C.c_void_p(rho.data_ptr()), _stream_ptr(stream)))
+        return rho
+
+    def scf_norm2(self, rho_out, rho_in, bvec, omega, stream=None):
+        """4 pi omega sum_{G != 0} |drho(G)|^2 / |G|^2 of drho = rho_out - rho_in (device grids);
+        bvec: 3x3 reciprocal vectors (rows, bohr^-1)."""
+        bv = (C.c_double * 9)(*[float(x) for x in np.asarray(bvec, dtype=np.float64).ravel()])
+        out = C.c_double()
+        _check(self.lib.pw_scf_norm(self.h, C.c_void_p(rho_out.data_ptr()), C.c_void_p(rho_in.data_ptr()), bv,
+                                    float(omega), C.byref(out), _stream_ptr(stream)))
+        return float(out.value)
 
     def close(self):
         if self.h:

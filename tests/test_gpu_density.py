@@ -1,0 +1,127 @@
+"""Output density and scf norm on the GPU (through the C ABI) against the CPU oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0906_2569_amd import pwgen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0906_2569_amd import pwdft
+    return pwdft.Context(0)
+
+
+def _plan(ctx, p, nb, **kw):
+    from paper_0906_2569_amd import pwdft
+    return pwdft.Plan(ctx, p, precision=0, nb_max=nb, ndim_max=0, density=1, **kw)
+
+
+@pytest.mark.parametrize("seed,a,ecut,kfrac,nr", [
+    (81, 5.0, 6.0, (0, 0, 0), None),
+    (82, 6.0, 8.0, (0.25, -0.25, 0.0), (20, 18, 24)),
+    (83, 7.0, 9.0, (0.1, 0.2, -0.3), (36, 30, 40)),
+])
+def test_density_against_oracle(ctx, seed, a, ecut, kfrac, nr):
+    p = pwgen.tiny_cell(seed, a=a, ecut_ry=ecut, natoms=2, nb=6, kfrac=kfrac, nr=nr)
+    w = np.linspace(2.0, 0.5, p.nb)
+    omega = p.a ** 3
+    ref = oracle.density(p.miller, p.nr, p.psi0, w, omega)
+    plan = _plan(ctx, p, p.nb)
+    try:
+        x = torch.from_numpy(p.psi0).cuda()
+        got = plan.density(x, w, omega).cpu().numpy()
+        np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max(), rtol=0)
+        # accumulate: a second call adds the same density again
+        rho = torch.from_numpy(ref.copy()).cuda()
+        plan.density(x, w, omega, rho=rho, accumulate=True)
+        np.testing.assert_allclose(rho.cpu().numpy(), 2 * ref, atol=2e-12 * np.abs(ref).max(), rtol=0)
+    finally:
+        plan.close()
+
+
+def test_density_band_chunks_are_deterministic(ctx):
+    # 16 bands in chunks of 3 (small workspace cap) equal one chunk bit for bit
+    # only up to the grouping of the band sum; both match the oracle
+    p = pwgen.config1()
+    w = np.linspace(1.0, 2.0, p.nb)
+    omega = p.a ** 3
+    x = torch.from_numpy(p.psi0).cuda()
+    one = _plan(ctx, p, p.nb)
+    got1 = one.density(x, w, omega).cpu().numpy()
+    again = one.density(x, w, omega).cpu().numpy()
+    info = one.info()
+    one.close()
+    np.testing.assert_array_equal(got1, again)            # reproducible run to run
+    per_band = 16 * p.nr[2] * ((info["nsticks"] + 3) // 4 * 4) + 16 * p.nr[2] * p.nr[1] * info["ncols"]
+    chunked = _plan(ctx, p, p.nb, fft_ws_bytes=3 * per_band + 100)
+    assert chunked.info()["band_chunk"] == 3
+    got3 = chunked.density(x, w, omega).cpu().numpy()
+    chunked.close()
+    np.testing.assert_allclose(got3, got1, rtol=1e-14, atol=0)
+    # charge: (omega/N) sum rho = sum_b w_b ||psi_b||^2
+    n = np.prod(p.nr)
+    charge = got1.sum() * omega / n
+    assert abs(charge - w.sum()) <= 1e-12 * w.sum()
+
+
+def test_density_config2_charge(ctx):
+    # the 64-atom cell (72^3): charge of 128 unit-norm bands with unit weights
+    p = pwgen.config2()
+    omega = p.a ** 3
+    plan = _plan(ctx, p, p.nb)
+    try:
+        x = torch.from_numpy(p.psi0).cuda()
+        rho = plan.density(x, np.ones(p.nb), omega)
+        charge = float(rho.sum()) * omega / np.prod(p.nr)
+        assert abs(charge - p.nb) <= 1e-11 * p.nb
+        assert float(rho.min()) >= 0.0
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("nr", [(12, 10, 15), (30, 30, 30), (36, 30, 40)])
+def test_scf_norm_against_oracle(ctx, nr):
+    rng = np.random.default_rng(sum(nr))
+    a = 7.0
+    p = pwgen.tiny_cell(84, a=a, ecut_ry=3.0, natoms=1, nb=1, nr=nr)
+    bvec = np.eye(3) * (2 * math.pi / a)
+    omega = a ** 3
+    ro = rng.standard_normal((nr[2], nr[1], nr[0])) * 0.1 + 1.0
+    ri = rng.standard_normal((nr[2], nr[1], nr[0])) * 0.1 + 1.0
+    ref = oracle.scf_norm2(ro - ri, bvec, omega)
+    plan = _plan(ctx, p, 1)
+    try:
+        got = plan.scf_norm2(torch.from_numpy(ro).cuda(), torch.from_numpy(ri).cuda(), bvec, omega)
+        assert abs(got - ref) <= 1e-12 * ref
+        assert plan.scf_norm2(torch.from_numpy(ro).cuda(), torch.from_numpy(ro).cuda(), bvec, omega) == 0.0
+    finally:
+        plan.close()
+
+
+def test_scf_norm_of_two_densities(ctx):
+    # the norm between the output densities of two different band blocks
+    p = pwgen.tiny_cell(85, a=6.0, ecut_ry=8.0, natoms=2, nb=6, nr=(20, 18, 24))
+    omega = p.a ** 3
+    bvec = np.eye(3) * (2 * math.pi / p.a)
+    rng = np.random.default_rng(85)
+    psi2 = pwgen.random_psi(rng, p.nb, p.npw)
+    w = np.full(p.nb, 2.0)
+    plan = _plan(ctx, p, p.nb)
+    try:
+        r1 = plan.density(torch.from_numpy(p.psi0).cuda(), w, omega)
+        r2 = plan.density(torch.from_numpy(psi2).cuda(), w, omega)
+        got = plan.scf_norm2(r1, r2, bvec, omega)
+    finally:
+        plan.close()
+    ref = oracle.scf_norm2(oracle.density(p.miller, p.nr, p.psi0, w, omega) -
+                           oracle.density(p.miller, p.nr, psi2, w, omega), bvec, omega)
+    assert abs(got - ref) <= 1e-11 * ref

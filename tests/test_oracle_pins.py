@@ -316,3 +316,70 @@ def test_cpu_fft_method_baseline_matches_dense():
     ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
     got = fft_method.hpsi(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat, p.psi0)
     np.testing.assert_allclose(got, ref, atol=1e-12, rtol=0)
+
+
+def test_density_charge_equals_weighted_norms():
+    # (omega/N) sum_j rho(r_j) = sum_b w_b ||psi_b||^2 (Parseval on a grid that
+    # holds the sphere without aliasing)
+    p = pwgen.tiny_cell(96, a=6.0, ecut_ry=8.0, natoms=2, nb=4, kfrac=(0.25, 0.0, -0.25), nr=(20, 18, 24))
+    w = np.array([2.0, 1.5, 0.5, 0.25])
+    omega = p.a ** 3
+    rho = oracle.density(p.miller, p.nr, p.psi0 * np.array([1, 2, 3, 4])[:, None], w, omega)
+    n = np.prod(p.nr)
+    assert abs(rho.sum() * omega / n - float(np.sum(w * np.array([1, 4, 9, 16])))) <= 1e-12
+    assert rho.min() >= 0.0
+
+
+def test_density_of_plane_waves_closed_form():
+    # one plane wave: uniform w/omega; two plane waves a e^{iG1 r} + b e^{iG2 r}:
+    # (|a|^2 + |b|^2 + 2 Re(a conj(b) e^{i(G1-G2).r})) / omega
+    p = pwgen.tiny_cell(97, a=5.0, ecut_ry=6.0, natoms=1, nb=1, nr=(12, 10, 15))
+    omega = p.a ** 3
+    g1, g2 = 3, 7
+    psi = np.zeros((2, p.npw), dtype=np.complex128)
+    psi[0, g1] = 0.8 - 0.6j
+    a, b = 0.3 + 0.4j, -0.5 + 0.2j
+    psi[1, g1], psi[1, g2] = a, b
+    rho1 = oracle.density(p.miller, p.nr, psi[:1], [1.7], omega)
+    np.testing.assert_allclose(rho1, 1.7 / omega, rtol=1e-13)
+    rho2 = oracle.density(p.miller, p.nr, psi[1:], [1.0], omega)
+    n1, n2, n3 = p.nr
+    j3, j2, j1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    dm = p.miller[g1] - p.miller[g2]
+    ph = np.exp(2j * math.pi * (dm[0] * j1 / n1 + dm[1] * j2 / n2 + dm[2] * j3 / n3))
+    expect = (abs(a) ** 2 + abs(b) ** 2 + 2 * np.real(a * np.conj(b) * ph)) / omega
+    np.testing.assert_allclose(rho2, expect, atol=1e-15)
+
+
+@pytest.mark.parametrize("m0", [(1, 0, 0), (0, 2, 1), (-2, 1, 3)])
+def test_scf_norm_of_a_cosine(m0):
+    # drho(r) = c cos(G0.r) has coefficients c/2 at +-G0:
+    # ||drho||^2 = 4 pi omega 2 (c/2)^2 / |G0|^2 = 2 pi omega c^2 / |G0|^2
+    nr = (12, 10, 15)
+    bvec = np.array([[0.7, 0.1, 0.0], [0.0, 0.9, 0.2], [0.1, 0.0, 0.8]])
+    omega = (2 * math.pi) ** 3 / abs(np.linalg.det(bvec))
+    n1, n2, n3 = nr
+    j3, j2, j1 = np.meshgrid(np.arange(n3), np.arange(n2), np.arange(n1), indexing="ij")
+    c = 0.37
+    d = c * np.cos(2 * math.pi * (m0[0] * j1 / n1 + m0[1] * j2 / n2 + m0[2] * j3 / n3))
+    g0 = m0[0] * bvec[0] + m0[1] * bvec[1] + m0[2] * bvec[2]
+    got = oracle.scf_norm2(d, bvec, omega)
+    assert abs(got - 2 * math.pi * omega * c * c / float(g0 @ g0)) <= 1e-12 * got
+    # a constant has no G != 0 component; the norm is quadratic
+    assert abs(oracle.scf_norm2(d + 5.0, bvec, omega) - got) <= 1e-12 * got
+    assert abs(oracle.scf_norm2(3.0 * d, bvec, omega) - 9.0 * got) <= 1e-12 * got
+
+
+def test_pcg_converges_to_dense_spectrum():
+    # band-by-band preconditioned CG: the lowest nb eigenvalues of the dense H
+    p = pwgen.config1()
+    h = oracle.dense_h_of(p)
+    w, _ = oracle.eigh_lowest(h, 8)
+    eps, psi, iters = oracle.pcg(h, p.psi0[:8], 8, oracle.kinetic(p.kpg), max_iter=600)
+    print("pcg iterations per band", iters)
+    np.testing.assert_allclose(eps, w, atol=5e-9)
+    np.testing.assert_allclose(np.conj(psi) @ psi.T, np.eye(8), atol=1e-10)
+    assert max(iters) < 600
+    # the returned vectors are eigenvectors: residuals at the tolerance
+    r = np.linalg.norm(psi @ h.T - eps[:, None] * psi, axis=1)
+    assert r.max() <= 1e-6

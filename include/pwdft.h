@@ -82,6 +82,8 @@ typedef struct {
   int32_t        nblk;       /* number of D blocks (atoms)                                         */
   const int32_t* blk_off;    /* [host] [nblk+1], 0 = blk_off[0] < ... < blk_off[nblk] = nbeta       */
   const pw_c128* dmat;       /* [host] concatenated Hermitian nh x nh blocks, column-major, in Ha   */
+  const pw_c128* qmat;       /* [host] ultrasoft augmentation: S = 1 + sum_I beta_I q_I beta_I^H,
+                                blocks laid out as dmat; NULL: norm-conserving, S = 1             */
 } pw_problem;
 
 /* Capacity of a plan: workspace is allocated once, at plan creation.  Fields
@@ -180,9 +182,22 @@ pw_status hpsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128*
                      int32_t ldpsi, pw_c128* hpsi, int32_t ldhpsi, void* stream);
 
 /*
+ * spsi = S psi = psi + sum_I beta_I q_I <beta_I|psi> (overwrite), the overlap
+ * operator of the generalized problem H psi = eps S psi (ultrasoft form; S = 1
+ * when the problem has no qmat).  Layout, precision and errors as hpsi_apply.
+ */
+pw_status spsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128* psi, int32_t ldpsi,
+                     pw_c128* spsi, int32_t ldspsi, void* stream);
+
+/*
  * Block Davidson for the nb lowest eigenpairs.
  *   psi   [dev] [nb][ldpsi]: in = trial vectors (any linearly independent set),
- *         out = orthonormal eigenvector estimates.
+ *         out = eigenvector estimates, orthonormal in the S metric
+ *         (<psi_i|S|psi_j> = delta_ij; S = 1 without qmat).
+ * With an ultrasoft problem (qmat) the generalized problem H psi = eps S psi
+ * is solved: residuals (H - eps_i S) psi_i, reduced overlap phi^H S phi, the
+ * preconditioner's diagonal h_diag(G) - eps_i s_diag(G), and S phi carried
+ * through every Ritz rotation; opts->lock is ignored (no locking).
  *   eig   [dev] double[nb], ascending Rayleigh quotients of the output psi.
  *   resid [dev] double[nb], ||H psi_i - eps_i psi_i||_2 of the output psi.
  * Both are recomputed by a final float64 H.psi.  opts may be NULL (defaults);

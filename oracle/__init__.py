@@ -6,4 +6,4 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 from .dense import (kinetic, dft_matrix, vtilde_table, vtilde_lookup, dense_d, h_rows,
                     dense_h, dense_h_of, hpsi, hpsi_rows_of, hpsi_brute, h_diag,
                     eigh_lowest, davidson, reduced_eigh, secular_roots, kato_temple, density, scf_norm2,
-                    pcg)
+                    pcg, dense_s, dense_s_of, eigh_lowest_gen)

@@ -119,6 +119,29 @@ def dense_h_of(p) -> np.ndarray:
     return dense_h(p.miller, p.kpg, p.vloc_r, p.beta, p.blk_off, p.dmat)
 
 
+def dense_s(npw, beta, blk_off, qmat) -> np.ndarray:
+    """Overlap S = 1 + sum_I sum_ij beta_i q^I_ij beta_j^H of the ultrasoft form
+    (the generalized problem H psi = eps S psi of the iterative-diagonalization
+    appendix); q blocks laid out as the D blocks.  qmat None: S = 1."""
+    s = np.eye(npw, dtype=np.complex128)
+    beta = np.asarray(beta, dtype=np.complex128)
+    if qmat is not None and beta.shape[0] > 0:
+        q = dense_d(beta.shape[0], blk_off, qmat)
+        s += beta.T @ q @ np.conj(beta)
+    return s
+
+
+def dense_s_of(p) -> np.ndarray:
+    return dense_s(p.npw, p.beta, p.blk_off, getattr(p, "qmat", None))
+
+
+def eigh_lowest_gen(h: np.ndarray, s: np.ndarray, nb: int):
+    """Lowest nb solutions of H c = eps S c (S positive definite), ascending;
+    eigenvectors S-orthonormal, as [nb][npw]."""
+    w, v = scipy.linalg.eigh(h, s, subset_by_index=[0, nb - 1])
+    return w, v.T.copy()
+
+
 def hpsi(h: np.ndarray, psi: np.ndarray) -> np.ndarray:
     """H.psi for bands stored [nb][npw]: (H psi_b)_G = sum_G' H_GG' psi_b(G')."""
     return np.asarray(psi) @ h.T

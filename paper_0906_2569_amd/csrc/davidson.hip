@@ -37,6 +37,7 @@ struct DavFlags {
 struct DavWork {
   int nbmax = 0, ndim = 0, nbasis = 0, ld = 0;
   c128 *phi = nullptr, *hphi = nullptr, *psi = nullptr, *hpsi = nullptr;
+  c128 *sphi = nullptr, *spsi = nullptr;   // S phi, S psi (ultrasoft plans only)
   c128 *hred = nullptr, *sred = nullptr, *cvec = nullptr;
   double *eps = nullptr, *eps_prev = nullptr, *rn = nullptr;
   int* idx = nullptr;
@@ -70,7 +71,7 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// rn[b] = || hpsi_b - eps_b psi_b ||_2
+// rn[b] = || hpsi_b - eps_b spsi_b ||_2  (spsi = psi when S = 1)
 __global__ void __launch_bounds__(kVecThreads) k_resid(int npw, const c128* __restrict__ psi,
                                                const c128* __restrict__ hpsi, int ld,
                                                const double* __restrict__ eps, double* __restrict__ rn) {
@@ -129,12 +130,13 @@ __global__ void __launch_bounds__(64) k_select(int nb, const double* __restrict_
   }
 }
 
-// out_t = (hpsi_b - eps_b psi_b) / smax(h_diag - eps_b, floor), normalized; b = idx[t]
+// out_t = (hpsi_b - eps_b spsi_b) / smax(h_diag - eps_b s_diag, floor), normalized; b = idx[t]
+// (spsi: S psi, or psi when S = 1; sdiag: diagonal of S, or nullptr for 1)
 __global__ void __launch_bounds__(kVecThreads) k_correct(int npw, const int* __restrict__ idx,
                                                  const c128* __restrict__ psi, const c128* __restrict__ hpsi,
                                                  int ld, const double* __restrict__ eps,
-                                                 const double* __restrict__ hdiag, double floor_,
-                                                 c128* __restrict__ out, int ldo) {
+                                                 const double* __restrict__ hdiag, const double* __restrict__ sdiag,
+                                                 double floor_, c128* __restrict__ out, int ldo) {
   __shared__ double red[16];
   const int t = blockIdx.x;
   const int b = idx[t];
@@ -146,7 +148,7 @@ __global__ void __launch_bounds__(kVecThreads) k_correct(int npw, const int* __r
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     // diagonal of H - eps, replaced by its smooth maximum with floor_: equal
     // to it far above floor_, positive and >= floor_/2 everywhere
-    const double dg = hdiag[g] - e;
+    const double dg = hdiag[g] - e * (sdiag ? sdiag[g] : 1.0);
     const double den = 0.5 * (dg + floor_ + sqrt((dg - floor_) * (dg - floor_) + floor_ * floor_));
     const double inv = 1.0 / den;
     const c128 r = c128{(hx[g].x - e * x[g].x) * inv, (hx[g].y - e * x[g].y) * inv};
@@ -174,13 +176,14 @@ __global__ void __launch_bounds__(kVecThreads) k_residvec(int npw, const int* __
 // column t of x <- x_t / smax(h_diag - eps_b, floor), b = idx[t], normalized (as k_correct)
 __global__ void __launch_bounds__(kVecThreads) k_precond(int npw, const int* __restrict__ idx,
                                                  const double* __restrict__ eps, const double* __restrict__ hdiag,
-                                                 double floor_, c128* __restrict__ x, int ldx) {
+                                                 const double* __restrict__ sdiag, double floor_,
+                                                 c128* __restrict__ x, int ldx) {
   __shared__ double red[16];
   const double e = eps[idx[blockIdx.x]];
   c128* o = x + (size_t)blockIdx.x * ldx;
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double dg = hdiag[g] - e;
+    const double dg = hdiag[g] - e * (sdiag ? sdiag[g] : 1.0);
     const double den = 0.5 * (dg + floor_ + sqrt((dg - floor_) * (dg - floor_) + floor_ * floor_));
     const double inv = 1.0 / den;
     const c128 r = c128{o[g].x * inv, o[g].y * inv};
@@ -276,25 +279,28 @@ __global__ void k_permute_vals(int n, const int* __restrict__ perm, double* __re
   for (int j = 0; j < n; ++j) x[j] = tmp[j];
 }
 
-// eig_b = Re <psi_b|H psi_b> / <psi_b|psi_b>,  resid_b = || H psi_b - eig_b psi_b ||
+// eig_b = Re <psi_b|H psi_b> / <psi_b|S psi_b>,  resid_b = || H psi_b - eig_b S psi_b ||
+// (spsi = nullptr: S = 1)
 __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__ psi, int ldpsi,
                                                const c128* __restrict__ hpsi, int ldh,
-                                               double* __restrict__ eig, double* __restrict__ resid) {
+                                               double* __restrict__ eig, double* __restrict__ resid,
+                                               const c128* __restrict__ spsi = nullptr) {
   __shared__ double red[16];
   const int b = blockIdx.x;
   const c128* x = psi + (size_t)b * ldpsi;
   const c128* hx = hpsi + (size_t)b * ldh;
+  const c128* sx = spsi ? spsi + (size_t)b * ldh : x;
   double num = 0.0, den = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     num += x[g].x * hx[g].x + x[g].y * hx[g].y;
-    den += x[g].x * x[g].x + x[g].y * x[g].y;
+    den += x[g].x * sx[g].x + x[g].y * sx[g].y;
   }
   num = block_sum(num, red);
   den = block_sum(den, red);
   const double e = num / den;
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
+    const double re = hx[g].x - e * sx[g].x, im = hx[g].y - e * sx[g].y;
     s += re * re + im * im;
   }
   s = block_sum(s, red);
@@ -312,6 +318,7 @@ size_t pw::dav_bytes(int npw, int nb_max, int ndim_max) {
   size_t b = 0;
   b += 2 * nbasis * ld * sizeof(c128);                  // phi, hphi
   b += 2 * (size_t)nb_max * ld * sizeof(c128);          // psi, hpsi
+  b += (nbasis + nb_max) * ld * sizeof(c128);           // S phi, S psi (upper bound: ultrasoft plans)
   b += 2 * nbasis * nbasis * sizeof(c128);              // hred, sred
   b += nbasis * nb_max * sizeof(c128);                  // cvec
   b += 5 * (size_t)nb_max * sizeof(double) + 2 * nb_max * sizeof(int) + 256;
@@ -343,6 +350,10 @@ pw_status pw::dav_alloc(pw_plan p) {
   PW_TRY(get(nbx * ld * sizeof(c128), (void**)&W->hphi));
   PW_TRY(get(nb * ld * sizeof(c128), (void**)&W->psi));
   PW_TRY(get(nb * ld * sizeof(c128), (void**)&W->hpsi));
+  if (p->us) {
+    PW_TRY(get(nbx * ld * sizeof(c128), (void**)&W->sphi));
+    PW_TRY(get(nb * ld * sizeof(c128), (void**)&W->spsi));
+  }
   PW_TRY(get(nbx * nbx * sizeof(c128), (void**)&W->hred));
   PW_TRY(get(nbx * nbx * sizeof(c128), (void**)&W->sred));
   PW_TRY(get(nbx * nb * sizeof(c128), (void**)&W->cvec));
@@ -407,17 +418,23 @@ struct Solver {
   int nfact = 0;   // leading basis size whose overlap factor is current
   int nl = 0;      // locked bands: psi[0:nl), hpsi[0:nl), eps[0:nl) stay fixed
 
-  pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx) {
+  // H x and, for ultrasoft plans, S x (columns at the same offsets in sphi)
+  pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx, c128* sx = nullptr) {
     PW_TRY(pw::hpsi_launch(p, prec, n, x, W.ld, hx, W.ld, st));
+    if (p->us && sx) PW_TRY(pw::spsi_launch(p, prec, n, x, W.ld, sx, W.ld, st));
     if (prec == PW_FP64) stats.n_hpsi_fp64 += n; else stats.n_hpsi_fp32 += n;
     return PW_OK;
   }
+
+  // the vector the eigenvalue multiplies in the residual: S psi, or psi when S = 1
+  const c128* spsi_or_psi() const { return p->us ? W.spsi : W.psi; }
 
   // reduced columns [c0, c1) of H and S over the basis phi[0:c1)
   pw_status project(int c0, int c1) {
     const int npw = p->npw, ldm = W.nbasis;
     // phi^H (H phi_new) and phi^H phi_new in one launch
-    PW_TRY(pw::zgemm_cn_pair(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld, W.phi + (size_t)c0 * W.ld,
+    const c128* sb = (p->us ? W.sphi : W.phi) + (size_t)c0 * W.ld;
+    PW_TRY(pw::zgemm_cn_pair(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld, sb,
                              W.ld, W.hred + (size_t)c0 * ldm, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes,
                              st));
     const int blocks = std::min(1024, ceil_div((size_t)(c1 - c0) * c1, 256));
@@ -437,6 +454,9 @@ struct Solver {
     // psi = phi c and hpsi = (H phi) c in one launch
     PW_TRY(pw::zgemm_nn_pair(p->npw, nact, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi + (size_t)nl * W.ld,
                              W.hpsi + (size_t)nl * W.ld, W.ld, st, W.hw.info));
+    if (p->us)   // S psi = (S phi) c
+      PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nact, nbase, 1.0, W.sphi, W.ld, W.cvec, ldm, 0.0,
+                                                   W.spsi + (size_t)nl * W.ld, W.ld, st, W.hw.info)));
     return PW_OK;
   }
 
@@ -447,6 +467,9 @@ struct Solver {
                             hipMemcpyDeviceToDevice, st));
     PW_HIP(hipMemcpy2DAsync(W.hphi, pitch, W.hpsi + (size_t)nl * W.ld, pitch, sizeof(c128) * p->npw, nact,
                             hipMemcpyDeviceToDevice, st));
+    if (p->us)
+      PW_HIP(hipMemcpy2DAsync(W.sphi, pitch, W.spsi + (size_t)nl * W.ld, pitch, sizeof(c128) * p->npw, nact,
+                              hipMemcpyDeviceToDevice, st));
     k_restart<<<std::min(1024, ceil_div(nact * nact, 256)), 256, 0, st>>>(nact, W.eps + nl, W.hred, W.sred,
                                                                           W.nbasis);
     PW_HIP(hipGetLastError());
@@ -458,7 +481,7 @@ struct Solver {
   // full Rayleigh-Ritz on a block already in phi[0:nact) (start, precision switch, rebuild)
   pw_status start_block(pw_precision prec, int nact) {
     nfact = 0;
-    PW_TRY(hpsi(prec, nact, W.phi, W.hphi));
+    PW_TRY(hpsi(prec, nact, W.phi, W.hphi, W.sphi));
     PW_TRY(project(0, nact));
     PW_TRY(rayleigh_ritz(nact, nact));
     return PW_OK;
@@ -514,13 +537,14 @@ struct Solver {
   pw_status corrections(int c0, int n, double floor_) {
     c128* x = W.phi + (size_t)c0 * W.ld;
     if (nl == 0) {
-      k_correct<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, p->hdiag, floor_, x, W.ld);
+      k_correct<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, spsi_or_psi(), W.hpsi, W.ld, W.eps, p->hdiag, p->sdiag,
+                                           floor_, x, W.ld);
       PW_HIP(hipGetLastError());
       return PW_OK;
     }
-    k_residvec<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.psi, W.hpsi, W.ld, W.eps, x, W.ld);
+    k_residvec<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, spsi_or_psi(), W.hpsi, W.ld, W.eps, x, W.ld);
     PW_TRY(project_out_locked(c0, n, 1, false));
-    k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, floor_, x, W.ld);
+    k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, p->sdiag, floor_, x, W.ld);
     PW_HIP(hipGetLastError());
     return project_out_locked(c0, n);
   }
@@ -534,7 +558,8 @@ pw_status pw::final_check(pw_plan p, int nb, const c128* psi, int ldpsi, double*
   DavWork& W = *p->dav;
   PW_CHECK(nb <= W.nbmax, PW_EINVAL, "nb > nb_max");
   PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
-  k_final<<<nb, 256, 0, st>>>(p->npw, psi, ldpsi, W.hpsi, W.ld, eig, resid);
+  if (p->us) PW_TRY(pw::spsi_launch(p, PW_FP64, nb, psi, ldpsi, W.spsi, W.ld, st));
+  k_final<<<nb, 256, 0, st>>>(p->npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -546,6 +571,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_CHECK(p->dav != nullptr, PW_EINVAL, "plan was created without Davidson workspace (ndim_max = 0)");
   pw_david_opts o;
   if (o_) o = *o_; else pw_david_opts_default(&o);
+  if (p->us) o.lock = 0;   // locked bands would need S-orthogonal projections: not done
   DavWork& W = *p->dav;
   PW_CHECK(nb >= 1 && nb <= W.nbmax, PW_EINVAL, "nb out of range [1, nb_max]");
   PW_CHECK(nb <= p->npw, PW_EINVAL, "nb > npw");
@@ -574,7 +600,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   pw_status result = PW_OK;
   DavFlags f{};
   for (;;) {
-    k_resid<<<nb, kVecThreads, 0, st>>>(npw, W.psi, W.hpsi, W.ld, W.eps, W.rn);
+    k_resid<<<nb, kVecThreads, 0, st>>>(npw, S.spsi_or_psi(), W.hpsi, W.ld, W.eps, W.rn);
     // float32 stage: a band needs no more corrections once its residual is
     // below the switch threshold (its eigenvalue change is float32 noise)
     const bool fp32_stage = prec == PW_MIXED;
@@ -648,7 +674,8 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       stats.restarts++;
     }
     PW_TRY(S.corrections(nbase, n_new, o.precond_floor));
-    PW_TRY(S.hpsi(prec, n_new, W.phi + (size_t)nbase * W.ld, W.hphi + (size_t)nbase * W.ld));
+    PW_TRY(S.hpsi(prec, n_new, W.phi + (size_t)nbase * W.ld, W.hphi + (size_t)nbase * W.ld,
+                  W.sphi ? W.sphi + (size_t)nbase * W.ld : nullptr));
     PW_TRY(S.project(nbase, nbase + n_new));
     nbase += n_new;
     PW_HIP(hipMemcpyAsync(W.eps_prev, W.eps, sizeof(double) * nb, hipMemcpyDeviceToDevice, st));
@@ -660,8 +687,9 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_HIP(hipMemcpy2DAsync(psi, sizeof(c128) * ldpsi, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
                           hipMemcpyDeviceToDevice, st));
   PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
+  if (p->us) PW_TRY(pw::spsi_launch(p, PW_FP64, nb, psi, ldpsi, W.spsi, W.ld, st));
   stats.n_hpsi_fp64 += nb;
-  k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid);
+  k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr);
   PW_HIP(hipGetLastError());
   std::vector<double> hr(nb), he(nb);
   PW_HIP(hipMemcpyAsync(hr.data(), resid, sizeof(double) * nb, hipMemcpyDeviceToHost, st));

@@ -602,7 +602,7 @@ __global__ void k_hdiag(int npw, int nbeta, const c128* __restrict__ beta, int l
       acc += bi.x * dbj.x - bi.y * dbj.y;
     }
   }
-  hdiag[g] = kin[g] + v0 + acc;
+  hdiag[g] = (kin ? kin[g] : 0.0) + v0 + acc;
 }
 
 template <typename T>
@@ -782,6 +782,9 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
   b += (size_t)chunk * fft_ws_per_band(geo);
   if (geo.density) b += N * sizeof(c128) + kDensityPart * sizeof(double);
   b += 2 * (size_t)o->nb_max * std::max(pr->nbeta, 1) * sizeof(c128);
+  if (pr->nbeta > 0 && pr->qmat != nullptr)
+    b += (size_t)o->nb_max * pr->nbeta * sizeof(c128) + (size_t)pr->npw * sizeof(double) +
+         (size_t)pr->nbeta * geo.nhmax * (sizeof(c128) + sizeof(c64));
   b += pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128));
   if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max) + pw::cg_bytes(pr->npw, o->nb_max);
   return b;
@@ -818,6 +821,28 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
           drow[(size_t)(o0 + i) * geo.nhmax + j] = c128{dij.re, dij.im};
         }
       for (int i = 0; i < nh; ++i) { dstart[o0 + i] = o0; dlen[o0 + i] = nh; }
+      pos += (size_t)nh * nh;
+    }
+  }
+
+  // q blocks (ultrasoft overlap): Hermitian check, block rows as for D
+  const bool us = pr->nbeta > 0 && pr->qmat != nullptr;
+  std::vector<c128> qrow;
+  if (us) {
+    qrow.assign((size_t)pr->nbeta * geo.nhmax, c128{0, 0});
+    size_t pos = 0;
+    for (int b = 0; b < pr->nblk; ++b) {
+      const int o0 = pr->blk_off[b], nh = pr->blk_off[b + 1] - o0;
+      const pw_c128* blk = pr->qmat + pos;
+      for (int i = 0; i < nh; ++i)
+        for (int j = 0; j < nh; ++j) {
+          const pw_c128 qij = blk[(size_t)j * nh + i], qji = blk[(size_t)i * nh + j];
+          const double scale = std::max(1.0, std::hypot(qij.re, qij.im));
+          PW_CHECK(std::isfinite(qij.re) && std::isfinite(qij.im), PW_ENAN, "non-finite q block entry");
+          PW_CHECK(std::abs(qij.re - qji.re) <= 1e-12 * scale && std::abs(qij.im + qji.im) <= 1e-12 * scale,
+                   PW_EINVAL, "q block " + std::to_string(b) + " is not Hermitian");
+          qrow[(size_t)(o0 + i) * geo.nhmax + j] = c128{qij.re, qij.im};
+        }
       pos += (size_t)nh * nh;
     }
   }
@@ -971,6 +996,17 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(dalloc(p, &p->hdiag, (size_t)npw));
   k_hdiag<<<ceil_div(npw, 256), 256>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen,
                                        p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
+  if (us) {
+    p->us = true;
+    PLAN_TRY(upload(p, &p->qrow64, qrow));
+    std::vector<c64> q32(qrow.size());
+    for (size_t i = 0; i < qrow.size(); ++i) q32[i] = c64{(float)qrow[i].x, (float)qrow[i].y};
+    PLAN_TRY(upload(p, &p->qrow32, q32));
+    PLAN_TRY(dalloc(p, &p->sdiag, (size_t)npw));
+    // diagonal of S: 1 + sum beta_i q_ij conj(beta_j)
+    k_hdiag<<<ceil_div(npw, 256), 256>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen, p->qrow64,
+                                         std::max(p->nhmax, 1), nullptr, 1.0, p->sdiag);
+  }
   // workspace
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->sticks), (size_t)p->band_chunk * n3 * p->ldst));
   if (p->split64 || p->split32 || geo.density)
@@ -982,6 +1018,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   const int nbeta1 = std::max(p->nbeta, 1);
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becp), (size_t)o->nb_max * nbeta1));
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
+  if (us) PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpq), (size_t)o->nb_max * nbeta1));
   p->part_bytes = pw::splitk_part_bytes(nbeta1, o->nb_max, npw, sizeof(c128));
   PLAN_TRY(dalloc(p, reinterpret_cast<char**>(&p->part), p->part_bytes));
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
@@ -1204,4 +1241,46 @@ extern "C" pw_status hpsi_apply(pw_plan p, pw_precision prec, int32_t nb, const 
   PW_HIP(hipSetDevice(p->device));
   return pw::hpsi_launch(p, prec, nb, reinterpret_cast<const c128*>(psi), ldpsi,
                          reinterpret_cast<c128*>(hpsi), ldhpsi, static_cast<hipStream_t>(stream));
+}
+
+pw_status pw::spsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi, c128* spsi,
+                          int ldspsi, hipStream_t s) {
+  if (nb == 0) return PW_OK;
+  const bool f64 = prec == PW_FP64;
+  if (!f64) PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 S.psi needs a PW_MIXED plan");
+  PW_HIP(hipMemcpy2DAsync(spsi, sizeof(c128) * ldspsi, psi, sizeof(c128) * ldpsi, sizeof(c128) * p->npw, nb,
+                          hipMemcpyDeviceToDevice, s));
+  if (!p->us) return PW_OK;
+  if (f64) {
+    c128* bq = static_cast<c128*>(p->becpq);
+    PW_TRY(pw::calbec_d<double>(p, nb, psi, ldpsi, bq, s, p->qrow64));
+    pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
+    PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nb, p->nbeta, 1.0, p->beta64, p->ldb, bq, p->nbeta, 1.0,
+                                                 spsi, ldspsi, s)));
+  } else {
+    c64* bq = static_cast<c64*>(p->becpq);
+    PW_TRY(pw::calbec_d<float>(p, nb, psi, ldpsi, bq, s, p->qrow32));
+    pw::ProfScope ps(pw::PK_ADDNL, s, 8.0 * p->npw * nb * p->nbeta);
+    PW_TRY((pw::zgemm_nn<float, float, float>(p->npw, nb, p->nbeta, 1.0, p->beta32, p->ldb, bq, p->nbeta, 1.0,
+                                              spsi, ldspsi, s)));
+  }
+  return PW_OK;
+}
+
+extern "C" pw_status spsi_apply(pw_plan p, pw_precision prec, int32_t nb, const pw_c128* psi, int32_t ldpsi,
+                                pw_c128* spsi, int32_t ldspsi, void* stream) {
+  PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
+  PW_CHECK(nb >= 0 && nb <= p->opts.nb_max, PW_EINVAL, "nb out of range [0, nb_max]");
+  if (nb == 0) return PW_OK;
+  PW_CHECK(psi != nullptr && spsi != nullptr, PW_EINVAL, "NULL psi or spsi");
+  PW_CHECK(ldpsi >= p->npw && ldspsi >= p->npw, PW_EINVAL, "leading dimension < npw");
+  PW_CHECK(prec == PW_FP64 || prec == PW_MIXED, PW_EINVAL, "bad precision");
+  const char* a0 = reinterpret_cast<const char*>(psi);
+  const char* a1 = a0 + sizeof(pw_c128) * ((size_t)(nb - 1) * ldpsi + p->npw);
+  const char* b0 = reinterpret_cast<const char*>(spsi);
+  const char* b1 = b0 + sizeof(pw_c128) * ((size_t)(nb - 1) * ldspsi + p->npw);
+  PW_CHECK(a1 <= b0 || b1 <= a0, PW_EINVAL, "psi and spsi overlap");
+  PW_HIP(hipSetDevice(p->device));
+  return pw::spsi_launch(p, prec, nb, reinterpret_cast<const c128*>(psi), ldpsi, reinterpret_cast<c128*>(spsi),
+                         ldspsi, static_cast<hipStream_t>(stream));
 }

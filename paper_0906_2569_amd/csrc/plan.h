@@ -69,6 +69,10 @@ struct pw_plan_s {
   int* dlen = nullptr;       // [nbeta] size of that block
   c128* drow64 = nullptr;    // [nbeta][nhmax] row j of D restricted to its block
   c64* drow32 = nullptr;
+  bool us = false;           // ultrasoft: S = 1 + beta q beta^H
+  c128* qrow64 = nullptr;    // [nbeta][nhmax] row j of q restricted to its block
+  c64* qrow32 = nullptr;
+  double* sdiag = nullptr;   // [npw] diagonal of S (ultrasoft plans)
 
   // H.psi workspace (device)
   void* sticks = nullptr;    // [band_chunk][n3][ldst] complex (FP64 size)
@@ -80,6 +84,7 @@ struct pw_plan_s {
   size_t part_bytes = 0;
   void* becp = nullptr;      // [nb_max][nbeta] complex128 (or complex64)
   void* becpd = nullptr;     // D-applied becp
+  void* becpq = nullptr;     // q-applied becp (S psi of ultrasoft plans)
 
   DavWork* dav = nullptr;
   CgWork* cg = nullptr;
@@ -115,8 +120,13 @@ pw_status zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx<TB>
                    double alpha = 1.0, double beta = 0.0, const c128* Cin = nullptr, int ldcin = 0);
 
 // calbec with the D blocks applied: out[n][j] = sum_{j' in blk(j)} D_jj' sum_k conj(beta[j'][k]) psi[n][k]
+// (rows: the block rows of another block-diagonal matrix in the layout of drow, e.g. q)
 template <typename T>
-pw_status calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t stream);
+pw_status calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t stream,
+                   const cpx<T>* rows = nullptr);
+// spsi = S psi = psi + beta (q <beta|psi>) (a copy of psi when the plan has no q)
+pw_status spsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi, c128* spsi, int ldspsi,
+                      hipStream_t stream);
 
 // C[m, n] = alpha sum_k A[m, k] B[k, n] + beta C[m, n];  A M-contiguous (A[k*lda + m]),
 // B K-contiguous (B[n*ldb + k]), C M-contiguous complex128 (C[n*ldc + m]).

@@ -466,14 +466,15 @@ pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c
 }
 
 template <typename T>
-pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t s) {
+pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t s,
+                       const cpx<T>* rows) {
   const int M = p->nbeta, N = nb, K = p->npw;
   const Split sp = choose_split(M, N, K);
   const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
   PW_CHECK(need <= p->part_bytes, PW_ENOMEM, "split-K workspace too small");
   cpx<T>* P = static_cast<cpx<T>*>(p->part);
   const cpx<T>* beta = sizeof(T) == 8 ? (const cpx<T>*)p->beta64 : (const cpx<T>*)p->beta32;
-  const cpx<T>* drow = sizeof(T) == 8 ? (const cpx<T>*)p->drow64 : (const cpx<T>*)p->drow32;
+  const cpx<T>* drow = rows ? rows : (sizeof(T) == 8 ? (const cpx<T>*)p->drow64 : (const cpx<T>*)p->drow32);
   {
     pw::ProfScope ps(pw::PK_CALBEC, s, 8.0 * M * N * K);
     k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
@@ -542,8 +543,8 @@ template pw_status pw::zgemm_cn<double, double, double>(int, int, int, const c12
 template pw_status pw::zgemm_cn<float, double, double>(int, int, int, const c128*, int, const c128*,
                                                        int, c128*, int, void*, size_t, hipStream_t,
                                                        double, double, const c128*, int);
-template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, hipStream_t);
-template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t);
+template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, hipStream_t, const c128*);
+template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t, const c64*);
 template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,
                                                         const c128*, int, double, c128*, int,
                                                         hipStream_t, const int*);

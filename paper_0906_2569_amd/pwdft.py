@@ -24,7 +24,7 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
            "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
+           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "spsi_apply", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
            "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
@@ -39,7 +39,7 @@ class Problem(C.Structure):
     _fields_ = [("npw", C.c_int32), ("miller", C.c_void_p), ("kpg", C.c_void_p),
                 ("nr", C.c_int32 * 3), ("vloc_r", C.c_void_p), ("nbeta", C.c_int32),
                 ("beta", C.c_void_p), ("ld_beta", C.c_int32), ("nblk", C.c_int32),
-                ("blk_off", C.c_void_p), ("dmat", C.c_void_p)]
+                ("blk_off", C.c_void_p), ("dmat", C.c_void_p), ("qmat", C.c_void_p)]
 
 
 class PlanOpts(C.Structure):
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.pw_plan_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
     lib.hpsi_apply.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p]
+    lib.spsi_apply.argtypes = lib.hpsi_apply.argtypes
     lib.davidson_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
     P = C.POINTER
@@ -140,7 +141,7 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_name.restype = C.c_char_p
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
+                 "pw_plan_info", "hpsi_apply", "spsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
                  "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve",
                  "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
                  "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
@@ -219,7 +220,10 @@ def _problem_struct(p, dev):
     s.nblk = len(blk) - 1
     s.blk_off = blk.ctypes.data
     s.dmat = dmat.ctypes.data if dmat.size else None
-    return s, (miller, kpg, vr, beta, blk, dmat)
+    qm = getattr(p, "qmat", None)
+    qmat = np.ascontiguousarray(qm, dtype=np.complex128) if qm is not None else None
+    s.qmat = qmat.ctypes.data if (qmat is not None and qmat.size) else None
+    return s, (miller, kpg, vr, beta, blk, dmat, qmat)
 
 
 def footprint_bytes(p, precision=PW_FP64, nb_max=None, ndim_max=4, device=0, plane_mode=0,
@@ -344,6 +348,16 @@ class Plan:
         if out is None:
             out = torch.empty_like(psi)
         _check(self.lib.hpsi_apply(self.h, prec, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                   C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
+        return out
+
+    def spsi(self, psi, out=None, prec=PW_FP64, stream=None):
+        """out = S psi (the ultrasoft overlap; psi itself for norm-conserving problems)."""
+        import torch
+        assert psi.dtype == torch.complex128 and psi.is_cuda and psi.dim() == 2 and psi.stride(1) == 1
+        if out is None:
+            out = torch.empty_like(psi)
+        _check(self.lib.spsi_apply(self.h, prec, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
                                    C.c_void_p(out.data_ptr()), out.stride(0), _stream_ptr(stream)))
         return out
 

@@ -53,6 +53,7 @@ class Problem:
     psi0: np.ndarray              # complex128 [nb][npw] trial wavefunctions
     name: str = ""
     meta: dict = field(default_factory=dict)
+    qmat: np.ndarray | None = None  # complex128 augmentation blocks q (col-major, like dmat); None: S = 1
 
     @property
     def npw(self) -> int:
@@ -189,6 +190,18 @@ def hermitian_blocks(rng, blk_off, scale=0.5):
         a[np.diag_indices(nh)] = rng.uniform(0.25, 1.0, size=nh)
         out.append(np.ascontiguousarray(a.T).ravel())     # column-major
     return np.concatenate(out) if out else np.zeros((0,), dtype=np.complex128)
+
+
+def ultrasoft_q(problem, seed, lo=0.1, hi=0.5):
+    """Diagonal augmentation blocks q (one per atom, U[lo, hi] on the diagonal,
+    concatenated column-major like dmat), drawn from their own stream, so that
+    S = 1 + sum_I beta_I q_I beta_I^H is Hermitian and positive definite."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), 77])))
+    blocks = []
+    for i in range(len(problem.blk_off) - 1):
+        nh = int(problem.blk_off[i + 1] - problem.blk_off[i])
+        blocks.append(np.diag(rng.uniform(lo, hi, size=nh)).astype(np.complex128).T.ravel())
+    return np.concatenate(blocks) if blocks else np.zeros((0,), dtype=np.complex128)
 
 
 def make_cell(a, ecut_ry, natoms, nb, seed, kfrac=(0.0, 0.0, 0.0), nr=None,

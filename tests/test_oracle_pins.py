@@ -383,3 +383,40 @@ def test_pcg_converges_to_dense_spectrum():
     # the returned vectors are eigenvectors: residuals at the tolerance
     r = np.linalg.norm(psi @ h.T - eps[:, None] * psi, axis=1)
     assert r.max() <= 1e-6
+
+
+def test_ultrasoft_single_plane_wave_projector_closed_form():
+    # V = 0 and one projector that is a single plane wave e_G0, with D = d and
+    # q: H and S are diagonal; the generalized eigenvalues are T_G for G != G0
+    # and (T_G0 + d) / (1 + q) at G0
+    p = pwgen.make_cell(10.0, 15.0, 0, 8, 7, nr=(30, 30, 30), with_vloc=False, with_beta=False)
+    g0 = 40
+    beta = np.zeros((1, p.npw), dtype=np.complex128)
+    beta[0, g0] = np.exp(0.7j)
+    d, q = 0.9, 0.6
+    blk = np.array([0, 1], dtype=np.int32)
+    h = oracle.dense_h(p.miller, p.kpg, p.vloc_r, beta, blk, np.array([d], dtype=np.complex128))
+    s = oracle.dense_s(p.npw, beta, blk, np.array([q], dtype=np.complex128))
+    t = oracle.kinetic(p.kpg)
+    expect = np.sort(np.concatenate([np.delete(t, g0), [(t[g0] + d) / (1 + q)]]))[:30]
+    w, v = oracle.eigh_lowest_gen(h, s, 30)
+    np.testing.assert_allclose(w, expect, atol=1e-12)
+    np.testing.assert_allclose(np.conj(v) @ s @ v.T, np.eye(30), atol=1e-12)
+
+
+def test_ultrasoft_rotation_invariance_and_q_zero():
+    # beta' = beta U, q' = U^H q U leaves S unchanged (a transposed reading of the
+    # q blocks fails); q = 0 gives S = 1
+    p = pwgen.tiny_cell(98, a=6.0, ecut_ry=8.0, natoms=2, nb=4)
+    rng = np.random.default_rng(98)
+    qmat = pwgen.hermitian_blocks(rng, p.blk_off, scale=0.2)
+    s0 = oracle.dense_s(p.npw, p.beta, p.blk_off, qmat)
+    u = _random_unitary(rng, 4)
+    beta2 = p.beta.copy()
+    beta2[4:8] = (p.beta[4:8].T @ u).T
+    qb = qmat[16:32].reshape(4, 4).T
+    q2 = qmat.copy()
+    q2[16:32] = (np.conj(u.T) @ qb @ u).T.ravel()
+    np.testing.assert_allclose(oracle.dense_s(p.npw, beta2, p.blk_off, q2), s0, atol=1e-14)
+    assert np.abs(s0 - np.eye(p.npw)).max() > 1e-3
+    np.testing.assert_allclose(oracle.dense_s(p.npw, p.beta, p.blk_off, np.zeros_like(qmat)), np.eye(p.npw))

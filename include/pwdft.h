@@ -104,6 +104,14 @@ typedef struct {
                                 them on the caller's stream); 1 = always beside; 2 = always after */
   int32_t      density;      /* 1: also allocate the workspace of pw_density and pw_scf_norm
                                 (the plane copies of the three-kernel pass and one complex grid)   */
+  int32_t      gamma;        /* 1: Gamma point with real wavefunctions.  The problem lists the half
+                                sphere: G = 0 first, then one of each pair (G, -G); k = 0; beta real
+                                in real space (beta(-G) = conj(beta(G))), D real.  Band vectors hold
+                                the half-sphere coefficients (the -G ones are their conjugates,
+                                psi(0) real; the imaginary part of psi(0) is ignored).  H.psi packs two
+                                bands into one complex transform, and the projector and subspace
+                                products are real products over the interleaved half sphere.
+                                Norm-conserving only; pw_density and pcg_solve are not available. */
 } pw_plan_opts;
 
 typedef struct {

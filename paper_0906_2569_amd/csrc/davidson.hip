@@ -43,6 +43,7 @@ struct DavWork {
   int* idx = nullptr;
   int* perm = nullptr;       // [nb] band order (locking, final sort)
   c128* lockc = nullptr;     // [nb][nb] overlaps of locked bands with new corrections
+  double* creal = nullptr;   // Gamma: real parts of the Ritz coefficients [nb][nbasis]
   double* etmp = nullptr;    // [2 nb] staging of permuted values
   DavFlags* flags = nullptr;     // device
   DavFlags* hflags = nullptr;    // pinned host
@@ -71,10 +72,14 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// Weight of half-sphere entry g in full-sphere sums at Gamma (gam = 1): the
+// entry stands for G and -G, except G = 0 at index 0
+__device__ __forceinline__ double gw(int gam, int g) { return (gam && g > 0) ? 2.0 : 1.0; }
+
 // rn[b] = || hpsi_b - eps_b spsi_b ||_2  (spsi = psi when S = 1)
 __global__ void __launch_bounds__(kVecThreads) k_resid(int npw, const c128* __restrict__ psi,
                                                const c128* __restrict__ hpsi, int ld,
-                                               const double* __restrict__ eps, double* __restrict__ rn) {
+                                               const double* __restrict__ eps, double* __restrict__ rn, int gam = 0) {
   __shared__ double red[16];
   const int b = blockIdx.x;
   const double e = eps[b];
@@ -83,7 +88,7 @@ __global__ void __launch_bounds__(kVecThreads) k_resid(int npw, const c128* __re
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const double re = hx[g].x - e * x[g].x, im = hx[g].y - e * x[g].y;
-    s += re * re + im * im;
+    s += gw(gam, g) * (re * re + im * im);
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) rn[b] = sqrt(s);
@@ -136,7 +141,7 @@ __global__ void __launch_bounds__(kVecThreads) k_correct(int npw, const int* __r
                                                  const c128* __restrict__ psi, const c128* __restrict__ hpsi,
                                                  int ld, const double* __restrict__ eps,
                                                  const double* __restrict__ hdiag, const double* __restrict__ sdiag,
-                                                 double floor_, c128* __restrict__ out, int ldo) {
+                                                 double floor_, c128* __restrict__ out, int ldo, int gam = 0) {
   __shared__ double red[16];
   const int t = blockIdx.x;
   const int b = idx[t];
@@ -153,7 +158,7 @@ __global__ void __launch_bounds__(kVecThreads) k_correct(int npw, const int* __r
     const double inv = 1.0 / den;
     const c128 r = c128{(hx[g].x - e * x[g].x) * inv, (hx[g].y - e * x[g].y) * inv};
     o[g] = r;
-    s += r.x * r.x + r.y * r.y;
+    s += gw(gam, g) * (r.x * r.x + r.y * r.y);
   }
   s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
@@ -177,7 +182,7 @@ __global__ void __launch_bounds__(kVecThreads) k_residvec(int npw, const int* __
 __global__ void __launch_bounds__(kVecThreads) k_precond(int npw, const int* __restrict__ idx,
                                                  const double* __restrict__ eps, const double* __restrict__ hdiag,
                                                  const double* __restrict__ sdiag, double floor_,
-                                                 c128* __restrict__ x, int ldx) {
+                                                 c128* __restrict__ x, int ldx, int gam = 0) {
   __shared__ double red[16];
   const double e = eps[idx[blockIdx.x]];
   c128* o = x + (size_t)blockIdx.x * ldx;
@@ -188,7 +193,7 @@ __global__ void __launch_bounds__(kVecThreads) k_precond(int npw, const int* __r
     const double inv = 1.0 / den;
     const c128 r = c128{o[g].x * inv, o[g].y * inv};
     o[g] = r;
-    s += r.x * r.x + r.y * r.y;
+    s += gw(gam, g) * (r.x * r.x + r.y * r.y);
   }
   s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
@@ -196,11 +201,11 @@ __global__ void __launch_bounds__(kVecThreads) k_precond(int npw, const int* __r
 }
 
 // columns of x scaled to unit norm (a zero column stays zero)
-__global__ void __launch_bounds__(kVecThreads) k_normalize(int npw, c128* __restrict__ x, int ld) {
+__global__ void __launch_bounds__(kVecThreads) k_normalize(int npw, c128* __restrict__ x, int ld, int gam = 0) {
   __shared__ double red[16];
   c128* o = x + (size_t)blockIdx.x * ld;
   double s = 0.0;
-  for (int g = threadIdx.x; g < npw; g += blockDim.x) s += o[g].x * o[g].x + o[g].y * o[g].y;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) s += gw(gam, g) * (o[g].x * o[g].x + o[g].y * o[g].y);
   s = block_sum(s, red);
   const double sc = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) o[g] = c128{o[g].x * sc, o[g].y * sc};
@@ -238,6 +243,19 @@ __global__ void k_herm_fill(int c0, int c1, c128* __restrict__ m0, c128* __restr
       m[(size_t)i * ldm + i].y = 0.0;
     }
   }
+}
+
+// out[j][i] = Re c[j][i] (columns of leading dimension ld), i < n, j < m
+__global__ void k_real_part(int n, int m, const c128* __restrict__ c, int ld, double* __restrict__ out) {
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < n * m; idx += gridDim.x * blockDim.x) {
+    const int i = idx % n, j = idx / n;
+    out[(size_t)j * ld + i] = c[(size_t)j * ld + i].x;
+  }
+}
+
+// Im x_j(G = 0) = 0 for the n columns (Gamma: the coefficient of G = 0 is real)
+__global__ void k_zero_im0(int n, c128* __restrict__ x, int ld) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) x[(size_t)j * ld].y = 0.0;
 }
 
 __global__ void k_fill(int n, double v, double* __restrict__ x) {
@@ -284,7 +302,7 @@ __global__ void k_permute_vals(int n, const int* __restrict__ perm, double* __re
 __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__ psi, int ldpsi,
                                                const c128* __restrict__ hpsi, int ldh,
                                                double* __restrict__ eig, double* __restrict__ resid,
-                                               const c128* __restrict__ spsi = nullptr) {
+                                               const c128* __restrict__ spsi = nullptr, int gam = 0) {
   __shared__ double red[16];
   const int b = blockIdx.x;
   const c128* x = psi + (size_t)b * ldpsi;
@@ -292,8 +310,8 @@ __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__
   const c128* sx = spsi ? spsi + (size_t)b * ldh : x;
   double num = 0.0, den = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    num += x[g].x * hx[g].x + x[g].y * hx[g].y;
-    den += x[g].x * sx[g].x + x[g].y * sx[g].y;
+    num += gw(gam, g) * (x[g].x * hx[g].x + x[g].y * hx[g].y);
+    den += gw(gam, g) * (x[g].x * sx[g].x + x[g].y * sx[g].y);
   }
   num = block_sum(num, red);
   den = block_sum(den, red);
@@ -301,7 +319,7 @@ __global__ void __launch_bounds__(256) k_final(int npw, const c128* __restrict__
   double s = 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const double re = hx[g].x - e * sx[g].x, im = hx[g].y - e * sx[g].y;
-    s += re * re + im * im;
+    s += gw(gam, g) * (re * re + im * im);
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) {
@@ -323,6 +341,7 @@ size_t pw::dav_bytes(int npw, int nb_max, int ndim_max) {
   b += nbasis * nb_max * sizeof(c128);                  // cvec
   b += 5 * (size_t)nb_max * sizeof(double) + 2 * nb_max * sizeof(int) + 256;
   b += (size_t)nb_max * nb_max * sizeof(c128);          // lockc
+  b += nbasis * nb_max * sizeof(double);                // real Ritz coefficients (Gamma)
   b += pw::splitk_part_bytes((int)nbasis, (int)nbasis, npw, sizeof(c128));
   b += pw::heig_work_bytes((int)nbasis);
   return b + 32 * 256;
@@ -363,6 +382,7 @@ pw_status pw::dav_alloc(pw_plan p) {
   PW_TRY(get(nb * sizeof(int), (void**)&W->idx));
   PW_TRY(get(nb * sizeof(int), (void**)&W->perm));
   PW_TRY(get(nb * nb * sizeof(c128), (void**)&W->lockc));
+  if (p->gamma) PW_TRY(get(nbx * nb * sizeof(double), (void**)&W->creal));
   PW_TRY(get(2 * nb * sizeof(double), (void**)&W->etmp));
   PW_TRY(get(sizeof(DavFlags), (void**)&W->flags));
   W->part_bytes = pw::splitk_part_bytes((int)nbx, (int)nbx, p->npw, sizeof(c128));
@@ -434,9 +454,23 @@ struct Solver {
     const int npw = p->npw, ldm = W.nbasis;
     // phi^H (H phi_new) and phi^H phi_new in one launch
     const c128* sb = (p->us ? W.sphi : W.phi) + (size_t)c0 * W.ld;
-    PW_TRY(pw::zgemm_cn_pair(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld, sb,
-                             W.ld, W.hred + (size_t)c0 * ldm, W.sred + (size_t)c0 * ldm, ldm, W.part, W.part_bytes,
-                             st));
+    if (p->gamma) {
+      // real products over the interleaved half sphere: 2 sum - (G = 0 term)
+      const double* ph = reinterpret_cast<const double*>(W.phi);
+      const long l2 = 2L * W.ld;
+      PW_TRY((pw::dgemm_tn<double, double, double>(c1, c1 - c0, 2 * npw, ph, l2,
+                                                   reinterpret_cast<const double*>(W.hphi + (size_t)c0 * W.ld), l2,
+                                                   1.0, 1.0, 0.0, reinterpret_cast<double*>(W.hred + (size_t)c0 * ldm),
+                                                   ldm, true, W.part, W.part_bytes, st)));
+      PW_TRY((pw::dgemm_tn<double, double, double>(c1, c1 - c0, 2 * npw, ph, l2, reinterpret_cast<const double*>(sb),
+                                                   l2, 1.0, 1.0, 0.0,
+                                                   reinterpret_cast<double*>(W.sred + (size_t)c0 * ldm), ldm, true,
+                                                   W.part, W.part_bytes, st)));
+    } else {
+      PW_TRY(pw::zgemm_cn_pair(c1, c1 - c0, npw, W.phi, W.ld, W.hphi + (size_t)c0 * W.ld, sb,
+                               W.ld, W.hred + (size_t)c0 * ldm, W.sred + (size_t)c0 * ldm, ldm, W.part,
+                               W.part_bytes, st));
+    }
     const int blocks = std::min(1024, ceil_div((size_t)(c1 - c0) * c1, 256));
     k_herm_fill<<<dim3(blocks, 2), 256, 0, st>>>(c0, c1, W.hred, W.sred, ldm);
     PW_HIP(hipGetLastError());
@@ -451,6 +485,21 @@ struct Solver {
     PW_TRY(pw::heig_solve(W.hw, nfact, nbase, nact, W.hred, W.sred, ldm, W.eps + nl, W.cvec, ldm, W.part,
                           W.part_bytes, st));
     nfact = nbase;
+    if (p->gamma) {
+      // real Ritz coefficients: psi = phi c and H psi = (H phi) c as real products of 2 npw rows
+      k_real_part<<<std::min(1024, ceil_div(nbase * nact, 256)), 256, 0, st>>>(nbase, nact, W.cvec, ldm, W.creal);
+      PW_HIP(hipGetLastError());
+      const long l2 = 2L * W.ld;
+      PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, nact, nbase, 1.0,
+                                                   reinterpret_cast<const double*>(W.phi), l2, W.creal, ldm, 0.0,
+                                                   reinterpret_cast<double*>(W.psi + (size_t)nl * W.ld), l2, st,
+                                                   W.hw.info)));
+      PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, nact, nbase, 1.0,
+                                                   reinterpret_cast<const double*>(W.hphi), l2, W.creal, ldm, 0.0,
+                                                   reinterpret_cast<double*>(W.hpsi + (size_t)nl * W.ld), l2, st,
+                                                   W.hw.info)));
+      return PW_OK;
+    }
     // psi = phi c and hpsi = (H phi) c in one launch
     PW_TRY(pw::zgemm_nn_pair(p->npw, nact, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi + (size_t)nl * W.ld,
                              W.hpsi + (size_t)nl * W.ld, W.ld, st, W.hw.info));
@@ -519,12 +568,22 @@ struct Solver {
     if (nl == 0 || n == 0) return PW_OK;
     c128* x = W.phi + (size_t)c0 * W.ld;
     for (int pass = 0; pass < passes; ++pass) {
+      if (p->gamma) {
+        const long l2 = 2L * W.ld;
+        double* lc = reinterpret_cast<double*>(W.lockc);
+        PW_TRY((pw::dgemm_tn<double, double, double>(nl, n, 2 * p->npw, reinterpret_cast<const double*>(W.psi), l2,
+                                                     reinterpret_cast<const double*>(x), l2, 1.0, 1.0, 0.0, lc, nl,
+                                                     false, W.part, W.part_bytes, st)));
+        PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, n, nl, -1.0, reinterpret_cast<const double*>(W.psi),
+                                                     l2, lc, nl, 1.0, reinterpret_cast<double*>(x), l2, st)));
+        continue;
+      }
       PW_TRY((pw::zgemm_cn<double, double, double>(nl, n, p->npw, W.psi, W.ld, x, W.ld, W.lockc, nl, W.part,
                                                    W.part_bytes, st)));
       PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, n, nl, -1.0, W.psi, W.ld, W.lockc, nl, 1.0, x, W.ld,
                                                    st)));
     }
-    if (normalize) k_normalize<<<n, kVecThreads, 0, st>>>(p->npw, x, W.ld);
+    if (normalize) k_normalize<<<n, kVecThreads, 0, st>>>(p->npw, x, W.ld, p->gamma ? 1 : 0);
     PW_HIP(hipGetLastError());
     return PW_OK;
   }
@@ -538,13 +597,13 @@ struct Solver {
     c128* x = W.phi + (size_t)c0 * W.ld;
     if (nl == 0) {
       k_correct<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, spsi_or_psi(), W.hpsi, W.ld, W.eps, p->hdiag, p->sdiag,
-                                           floor_, x, W.ld);
+                                           floor_, x, W.ld, p->gamma ? 1 : 0);
       PW_HIP(hipGetLastError());
       return PW_OK;
     }
     k_residvec<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, spsi_or_psi(), W.hpsi, W.ld, W.eps, x, W.ld);
     PW_TRY(project_out_locked(c0, n, 1, false));
-    k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, p->sdiag, floor_, x, W.ld);
+    k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, p->sdiag, floor_, x, W.ld, p->gamma ? 1 : 0);
     PW_HIP(hipGetLastError());
     return project_out_locked(c0, n);
   }
@@ -559,7 +618,7 @@ pw_status pw::final_check(pw_plan p, int nb, const c128* psi, int ldpsi, double*
   PW_CHECK(nb <= W.nbmax, PW_EINVAL, "nb > nb_max");
   PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
   if (p->us) PW_TRY(pw::spsi_launch(p, PW_FP64, nb, psi, ldpsi, W.spsi, W.ld, st));
-  k_final<<<nb, 256, 0, st>>>(p->npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr);
+  k_final<<<nb, 256, 0, st>>>(p->npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr, p->gamma ? 1 : 0);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -590,6 +649,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
 
   PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, psi, sizeof(c128) * ldpsi, sizeof(c128) * npw, nb,
                           hipMemcpyDeviceToDevice, st));
+  if (p->gamma) k_zero_im0<<<1, 256, 0, st>>>(nb, W.phi, W.ld);
   PW_TRY(S.start_block(prec, nb));
   k_fill<<<1, 256, 0, st>>>(nb, INFINITY, W.eps_prev);
   int nbase = nb;
@@ -600,7 +660,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   pw_status result = PW_OK;
   DavFlags f{};
   for (;;) {
-    k_resid<<<nb, kVecThreads, 0, st>>>(npw, S.spsi_or_psi(), W.hpsi, W.ld, W.eps, W.rn);
+    k_resid<<<nb, kVecThreads, 0, st>>>(npw, S.spsi_or_psi(), W.hpsi, W.ld, W.eps, W.rn, p->gamma ? 1 : 0);
     // float32 stage: a band needs no more corrections once its residual is
     // below the switch threshold (its eigenvalue change is float32 noise)
     const bool fp32_stage = prec == PW_MIXED;
@@ -689,7 +749,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_TRY(pw::hpsi_launch(p, PW_FP64, nb, psi, ldpsi, W.hpsi, W.ld, st));
   if (p->us) PW_TRY(pw::spsi_launch(p, PW_FP64, nb, psi, ldpsi, W.spsi, W.ld, st));
   stats.n_hpsi_fp64 += nb;
-  k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr);
+  k_final<<<nb, 256, 0, st>>>(npw, psi, ldpsi, W.hpsi, W.ld, eig, resid, p->us ? W.spsi : nullptr, p->gamma ? 1 : 0);
   PW_HIP(hipGetLastError());
   std::vector<double> hr(nb), he(nb);
   PW_HIP(hipMemcpyAsync(hr.data(), resid, sizeof(double) * nb, hipMemcpyDeviceToHost, st));

@@ -180,6 +180,7 @@ extern "C" pw_status pw_density(pw_plan p, int32_t nb, const pw_c128* psi, int32
                                 double omega, int32_t accumulate, double* rho, void* stream) {
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
   PW_CHECK(p->dgrid != nullptr, PW_EINVAL, "plan was created without density workspace (opts.density = 0)");
+  PW_CHECK(!p->gamma, PW_EINVAL, "pw_density works on full-sphere plans (no Gamma plans)");
   PW_CHECK(nb >= 0 && nb <= p->opts.nb_max, PW_EINVAL, "nb out of range [0, nb_max]");
   PW_CHECK(ldpsi >= p->npw, PW_EINVAL, "ldpsi < npw");
   PW_CHECK(omega > 0.0 && std::isfinite(omega), PW_EINVAL, "omega must be positive");

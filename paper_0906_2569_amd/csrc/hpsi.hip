@@ -537,10 +537,166 @@ k_zfwd_reg(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gamma point (real wavefunctions on the half sphere): bands a = 2t and
+// b = 2t + 1 share transform t.  The inverse z pass packs a + i b onto the
+// sticks of the whole sphere (conj(a) + i conj(b) at the mirror -G), so the
+// real-space grid holds psi_a(r) + i psi_b(r); after V(r) and the forward
+// transform f(G) = (V psi_a)(G) + i (V psi_b)(G), and the gather separates
+// (V psi_a)(G) = (f(G) + conj f(-G)) / 2, (V psi_b)(G) = (f(G) - conj f(-G)) / 2i.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ c128 gamma_pack(const c128* __restrict__ pa, const c128* __restrict__ pb, int enc) {
+  const int g = enc >> 1;
+  c128 a = pa[g];
+  c128 b = pb ? pb[g] : c128{0.0, 0.0};
+  if (g == 0) { a.y = 0.0; b.y = 0.0; }   // psi(0) is real
+  return (enc & 1) ? c128{a.x + b.y, b.x - a.y} : c128{a.x - b.y, a.y + b.x};
+}
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZRTHREADS)
+k_zinv_reg_g(SphereMap m, const c128* __restrict__ psi, int ldpsi, cpx<T>* __restrict__ sticks,
+             const cpx<T>* __restrict__ twg, int gz, int npair, int nbands) {
+  constexpr int N3 = 4 * LS;
+  __shared__ cpx<T> tw[N3];
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const int s = chunk * ZRSTICKS + (threadIdx.x >> 2);
+  if (s >= m.nst) return;
+  const int q = threadIdx.x & 3, nst = m.nst;
+  const c128* pa = psi + (size_t)(2 * pair) * ldpsi;
+  const c128* pb = 2 * pair + 1 < nbands ? pa + ldpsi : nullptr;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int j = 0; j < LS; ++j) {
+    const int enc = m.zidx[(size_t)(q + 4 * j) * nst + s];
+    x[j] = enc >= 0 ? to_t<T>(gamma_pack(pa, pb, enc)) : cpx<T>{T(0), T(0)};
+  }
+  const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
+  regfft::inv_dit<LS, T>(x, q, ql, tw);
+  const int blk = regfft::quad_block(q);
+  cpx<T>* out = sticks + (size_t)pair * N3 * m.ldst + s;
+#pragma unroll
+  for (int k = 0; k < LS; ++k) out[(size_t)(k + LS * blk) * m.ldst] = x[k];
+}
+
+// forward z transform of each stick, in place (the gather follows)
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZRTHREADS)
+k_zfwd_reg_g(SphereMap m, cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ twg, int gz, int npair) {
+  constexpr int N3 = 4 * LS;
+  __shared__ cpx<T> tw[N3];
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  for (int i = threadIdx.x; i < N3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  const int s = chunk * ZRSTICKS + (threadIdx.x >> 2);
+  if (s >= m.nst) return;
+  const int q = threadIdx.x & 3;
+  const int blk = regfft::quad_block(q);
+  cpx<T>* io = sticks + (size_t)pair * N3 * m.ldst + s;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int k = 0; k < LS; ++k) x[k] = io[(size_t)(k + LS * blk) * m.ldst];
+  const regfft::QuadLane<T> ql = regfft::quad_lane<T>(q);
+  regfft::fwd_dif<LS, T>(x, q, ql, tw);
+#pragma unroll
+  for (int j = 0; j < LS; ++j) io[(size_t)(q + 4 * j) * m.ldst] = x[j];
+}
+
+// LDS Stockham forms of the two Gamma z passes (other lengths)
+template <typename T>
+__global__ void __launch_bounds__(ZTHREADS)
+k_zinv_g(SphereMap m, const c128* __restrict__ psi, int ldpsi, cpx<T>* __restrict__ sticks,
+         const cpx<T>* __restrict__ twg, int gz, int npair, int nbands) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n3 = m.n3;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n3;
+  cpx<T>* B = A + ZSB * n3;
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  const int s0 = chunk * ZSB;
+  const int ns = min(ZSB, m.nst - s0);
+  const c128* pa = psi + (size_t)(2 * pair) * ldpsi;
+  const c128* pb = 2 * pair + 1 < nbands ? pa + ldpsi : nullptr;
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < ZSB * n3; i += blockDim.x) B[i] = cpx<T>{T(0), T(0)};
+  __syncthreads();
+  const int e0 = m.st_ptr[s0], e1 = m.st_ptr[s0 + ns];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+    B[(m.ent_s[e] - s0) * n3 + m.ent_z[e]] = to_t<T>(gamma_pack(pa, pb, m.ent_g[e]));
+  __syncthreads();
+  cpx<T>* out = sticks + (size_t)pair * n3 * m.ldst + s0;
+  const int ldst = m.ldst;
+  fft_run<T>(
+      m.f3, ns, T(1), tw, A, B, n3, false, true,
+      [&](int b, int i) { return B[b * n3 + i]; },
+      [&](int b, int i, cpx<T> v) { out[(size_t)i * ldst + b] = v; });
+}
+
+template <typename T>
+__global__ void __launch_bounds__(ZTHREADS)
+k_zfwd_g(SphereMap m, cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ twg, int gz, int npair) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const int n3 = m.n3;
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* A = tw + n3;
+  cpx<T>* B = A + ZSB * n3;
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  const int s0 = chunk * ZSB;
+  const int ns = min(ZSB, m.nst - s0);
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) tw[i] = twg[i];
+  __syncthreads();
+  cpx<T>* io = sticks + (size_t)pair * n3 * m.ldst + s0;
+  const int ldst = m.ldst;
+  fft_run<T>(
+      m.f3, ns, T(-1), tw, A, B, n3, true, true,
+      [&](int b, int i) { return io[(size_t)i * ldst + b]; },
+      [&](int b, int i, cpx<T> v) { io[(size_t)i * ldst + b] = v; });
+}
+
+// H psi(G) for the half sphere: kinetic + the separated local terms of the
+// two bands of each transform (+ the projector term already in hpsi)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gamma_gather(int npw, const int* __restrict__ gpos_p, const int* __restrict__ gpos_m,
+               const cpx<T>* __restrict__ sticks, size_t pair_stride, const double* __restrict__ kin,
+               const c128* __restrict__ psi, int ldpsi, c128* __restrict__ hpsi, int ldhpsi, double inv_n,
+               int accumulate, int nbands) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pair = blockIdx.y;
+  if (g >= npw) return;
+  const cpx<T>* st = sticks + (size_t)pair * pair_stride;
+  const cpx<T> fp = st[gpos_p[g]], fm = st[gpos_m[g]];
+  const double f1x = (double)fp.x, f1y = (double)fp.y, f2x = (double)fm.x, f2y = -(double)fm.y;   // f(G), conj f(-G)
+  // (f1 + f2) / 2 and (f1 - f2) / (2 i)
+  double va_x = 0.5 * (f1x + f2x), va_y = 0.5 * (f1y + f2y);
+  double vb_x = 0.5 * (f1y - f2y), vb_y = -0.5 * (f1x - f2x);
+  if (g == 0) { va_y = 0.0; vb_y = 0.0; }
+  const double t = kin[g];
+  for (int h = 0; h < 2; ++h) {
+    const int band = 2 * pair + h;
+    if (band >= nbands) break;
+    const c128 p = psi[(size_t)band * ldpsi + g];
+    const double px = p.x, py = g == 0 ? 0.0 : p.y;
+    c128 r = h == 0 ? c128{t * px + va_x * inv_n, t * py + va_y * inv_n}
+                    : c128{t * px + vb_x * inv_n, t * py + vb_y * inv_n};
+    c128* o = hpsi + (size_t)band * ldhpsi + g;
+    if (accumulate) r = c128{r.x + o->x, r.y + o->y};
+    *o = r;
+  }
+}
+
 template <typename T>
 struct ZRegFns {
   void (*inv)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int) = nullptr;
   void (*fwd)(SphereMap, const cpx<T>*, const c128*, int, c128*, int, const cpx<T>*, double, int, int, int) = nullptr;
+  void (*inv_g)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int, int) = nullptr;
+  void (*fwd_g)(SphereMap, cpx<T>*, const cpx<T>*, int, int) = nullptr;
 };
 
 template <typename T, int LS>
@@ -548,6 +704,8 @@ ZRegFns<T> zreg_pair() {
   ZRegFns<T> f;
   f.inv = k_zinv_reg<T, LS>;
   f.fwd = k_zfwd_reg<T, LS>;
+  f.inv_g = k_zinv_reg_g<T, LS>;
+  f.fwd_g = k_zfwd_reg_g<T, LS>;
   return f;
 }
 
@@ -639,6 +797,8 @@ pw_status set_lds_limits() {
   PW_TRY(set_lds_limit<T>((const void*)k_plane<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_zinv<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_zfwd<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_zinv_g<T>));
+  PW_TRY(set_lds_limit<T>((const void*)k_zfwd_g<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_plane_yinv<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_plane_x<T>));
   PW_TRY(set_lds_limit<T>((const void*)k_plane_yfwd<T>));
@@ -683,7 +843,33 @@ struct Geometry {
   int n1, n2, n3, nst, nxr, ldst, nhmax;
   bool split64, split32;   // three-kernel plane pass per precision
   bool density;            // workspace of pw_density / pw_scf_norm
+  bool gamma;              // Gamma point, real wavefunctions on the half sphere
+  std::vector<int> mfull;  // Miller indices of the whole sphere, [nfull][3]
+  std::vector<int> enc;    // for each G of mfull: its vector index (2 g + mirror at Gamma)
 };
+
+// The whole sphere the transforms cover.  Without gamma it is the problem's
+// list and enc[g] = g.  With gamma the problem lists the half sphere, G = 0
+// first; G = (k, l, m) and -G fill the sphere, enc = 2 g for G and 2 g + 1
+// for the mirror -G of half-sphere entry g (g >= 1).
+pw_status full_sphere(const pw_problem* pr, bool gamma, Geometry* geo) {
+  geo->mfull.assign(pr->miller, pr->miller + 3 * (size_t)pr->npw);
+  geo->enc.resize(pr->npw);
+  if (!gamma) {
+    for (int g = 0; g < pr->npw; ++g) geo->enc[g] = g;
+    return PW_OK;
+  }
+  PW_CHECK(pr->miller[0] == 0 && pr->miller[1] == 0 && pr->miller[2] == 0, PW_EINVAL,
+           "a Gamma-point problem lists G = 0 first");
+  PW_CHECK(pr->kpg[0] == 0.0 && pr->kpg[1] == 0.0 && pr->kpg[2] == 0.0, PW_EINVAL,
+           "a Gamma-point problem needs k = 0");
+  for (int g = 0; g < pr->npw; ++g) geo->enc[g] = 2 * g;
+  for (int g = 1; g < pr->npw; ++g) {
+    for (int d = 0; d < 3; ++d) geo->mfull.push_back(-pr->miller[3 * g + d]);
+    geo->enc.push_back(2 * g + 1);
+  }
+  return PW_OK;
+}
 
 // transform workspace per band: the sticks, plus the plane copies of the
 // three-kernel plane pass when a precision of the plan takes it
@@ -716,9 +902,16 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
     PW_CHECK(pr->nblk > 0, PW_EINVAL, "nblk must be positive when nbeta > 0");
     PW_CHECK(pr->blk_off[0] == 0 && pr->blk_off[pr->nblk] == pr->nbeta, PW_EINVAL, "D blocks must cover [0, nbeta)");
   }
+  PW_CHECK(o->gamma == 0 || o->gamma == 1, PW_EINVAL, "gamma must be 0 or 1");
+  geo->gamma = o->gamma == 1;
+  if (geo->gamma) PW_CHECK(pr->qmat == nullptr || pr->nbeta == 0, PW_EINVAL,
+                           "the Gamma-point path handles norm-conserving (S = 1) problems only");
+  PW_TRY(full_sphere(pr, geo->gamma, geo));
+  const int nfull = (int)geo->enc.size();
+  const int* mf = geo->mfull.data();
   int hmax[3] = {0, 0, 0};
-  for (int g = 0; g < pr->npw; ++g)
-    for (int d = 0; d < 3; ++d) hmax[d] = std::max(hmax[d], std::abs(pr->miller[3 * g + d]));
+  for (int g = 0; g < nfull; ++g)
+    for (int d = 0; d < 3; ++d) hmax[d] = std::max(hmax[d], std::abs(mf[3 * g + d]));
   for (int d = 0; d < 3; ++d) {
     PW_CHECK(pr->nr[d] >= 4 * hmax[d] + 1, PW_EINVAL,
              "FFT grid too small along axis " + std::to_string(d) + ": need >= " + std::to_string(4 * hmax[d] + 1));
@@ -732,9 +925,9 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
   std::vector<char> col(geo->n1, 0);
   std::vector<char> stk((size_t)geo->n1 * geo->n2, 0);
   int nst = 0;
-  for (int g = 0; g < pr->npw; ++g) {
-    const int i1 = ((pr->miller[3 * g] % geo->n1) + geo->n1) % geo->n1;
-    const int i2 = ((pr->miller[3 * g + 1] % geo->n2) + geo->n2) % geo->n2;
+  for (int g = 0; g < nfull; ++g) {
+    const int i1 = ((mf[3 * g] % geo->n1) + geo->n1) % geo->n1;
+    const int i2 = ((mf[3 * g + 1] % geo->n2) + geo->n2) % geo->n2;
     col[i1] = 1;
     if (!stk[(size_t)i1 * geo->n2 + i2]) { stk[(size_t)i1 * geo->n2 + i2] = 1; ++nst; }
   }
@@ -801,6 +994,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PW_TRY(set_lds_limits<float>());
 
   const int npw = pr->npw, n1 = geo.n1, n2 = geo.n2, n3 = geo.n3;
+  const int nfull = (int)geo.enc.size();   // entries of the whole sphere (npw without gamma)
+  const int* mfull = geo.mfull.data();
   // D blocks: Hermitian check
   std::vector<int> dstart, dlen;
   std::vector<c128> drow;
@@ -818,6 +1013,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
           const double scale = std::max(1.0, std::hypot(dij.re, dij.im));
           PW_CHECK(std::abs(dij.re - dji.re) <= 1e-12 * scale && std::abs(dij.im + dji.im) <= 1e-12 * scale,
                    PW_EINVAL, "D block " + std::to_string(b) + " is not Hermitian");
+          PW_CHECK(!geo.gamma || std::abs(dij.im) <= 1e-12 * scale, PW_EINVAL,
+                   "a Gamma-point problem needs real D blocks (real-space-real projectors)");
           drow[(size_t)(o0 + i) * geo.nhmax + j] = c128{dij.re, dij.im};
         }
       for (int i = 0; i < nh; ++i) { dstart[o0 + i] = o0; dlen[o0 + i] = nh; }
@@ -848,15 +1045,18 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   }
 
   // sphere -> grid maps
-  std::vector<int> i1v(npw), i2v(npw), i3v(npw);
+  std::vector<int> i1v(nfull), i2v(nfull), i3v(nfull);
   {
     std::vector<char> seen((size_t)n1 * n2 * n3, 0);
-    for (int g = 0; g < npw; ++g) {
-      i1v[g] = ((pr->miller[3 * g] % n1) + n1) % n1;
-      i2v[g] = ((pr->miller[3 * g + 1] % n2) + n2) % n2;
-      i3v[g] = ((pr->miller[3 * g + 2] % n3) + n3) % n3;
+    for (int g = 0; g < nfull; ++g) {
+      i1v[g] = ((mfull[3 * g] % n1) + n1) % n1;
+      i2v[g] = ((mfull[3 * g + 1] % n2) + n2) % n2;
+      i3v[g] = ((mfull[3 * g + 2] % n3) + n3) % n3;
       const size_t key = ((size_t)i3v[g] * n2 + i2v[g]) * n1 + i1v[g];
-      PW_CHECK(!seen[key], PW_EINVAL, "duplicate G vector at index " + std::to_string(g));
+      PW_CHECK(!seen[key], PW_EINVAL,
+               geo.gamma ? "a Gamma-point problem lists G or -G twice (half sphere expected): index " +
+                               std::to_string(g < npw ? g : g - npw + 1)
+                         : "duplicate G vector at index " + std::to_string(g));
       seen[key] = 1;
     }
   }
@@ -865,35 +1065,47 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   int nxr = 0;
   {
     std::vector<char> col(n1, 0);
-    for (int g = 0; g < npw; ++g) col[i1v[g]] = 1;
+    for (int g = 0; g < nfull; ++g) col[i1v[g]] = 1;
     for (int i = 0; i < n1; ++i)
       if (col[i]) i1_hx[i] = nxr++;
   }
-  std::vector<int> order(npw);
+  std::vector<int> order(nfull);
   std::iota(order.begin(), order.end(), 0);
   std::sort(order.begin(), order.end(), [&](int a, int b) {
     if (i1_hx[i1v[a]] != i1_hx[i1v[b]]) return i1_hx[i1v[a]] < i1_hx[i1v[b]];
     if (i2v[a] != i2v[b]) return i2v[a] < i2v[b];
     return i3v[a] < i3v[b];
   });
-  std::vector<int> st_ptr, st_hx, st_i2, ent_g(npw), ent_z(npw), ent_s(npw);
-  for (int e = 0; e < npw; ++e) {
+  std::vector<int> st_ptr, st_hx, st_i2, ent_g(nfull), ent_z(nfull), ent_s(nfull);
+  for (int e = 0; e < nfull; ++e) {
     const int g = order[e];
     if (e == 0 || i1v[g] != i1v[order[e - 1]] || i2v[g] != i2v[order[e - 1]]) {
       st_ptr.push_back(e);
       st_hx.push_back(i1_hx[i1v[g]]);
       st_i2.push_back(i2v[g]);
     }
-    ent_g[e] = g;
+    ent_g[e] = geo.enc[g];
     ent_z[e] = i3v[g];
     ent_s[e] = (int)st_hx.size() - 1;
   }
-  st_ptr.push_back(npw);
+  st_ptr.push_back(nfull);
   std::vector<int> col_ptr(nxr + 1, 0);
   for (size_t s2 = 0; s2 < st_hx.size(); ++s2) col_ptr[st_hx[s2] + 1]++;
   for (int c = 0; c < nxr; ++c) col_ptr[c + 1] += col_ptr[c];
   std::vector<int> zidx((size_t)n3 * st_hx.size(), -1);
-  for (int e = 0; e < npw; ++e) zidx[(size_t)ent_z[e] * st_hx.size() + ent_s[e]] = ent_g[e];
+  for (int e = 0; e < nfull; ++e) zidx[(size_t)ent_z[e] * st_hx.size() + ent_s[e]] = ent_g[e];
+  // Gamma: positions (z ldst + stick) of G and of -G for each half-sphere entry
+  const int ldst_h = (int)((st_hx.size() + 3) / 4 * 4);
+  std::vector<int> gpos_p, gpos_m;
+  if (geo.gamma) {
+    gpos_p.assign(npw, -1);
+    gpos_m.assign(npw, -1);
+    for (int e = 0; e < nfull; ++e) {
+      const int enc = ent_g[e], pos = ent_z[e] * ldst_h + ent_s[e];
+      if (enc & 1) gpos_m[enc >> 1] = pos; else gpos_p[enc >> 1] = pos;
+    }
+    gpos_m[0] = gpos_p[0];
+  }
   std::vector<double> kin(npw);
   for (int g = 0; g < npw; ++g) {
     const double* q = pr->kpg + 3 * g;
@@ -941,6 +1153,12 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
   PLAN_TRY(upload(p, &p->zidx, zidx));
   PLAN_TRY(upload(p, &p->col_ptr, col_ptr));
+  p->gamma = geo.gamma;
+  p->nfull = nfull;
+  if (geo.gamma) {
+    PLAN_TRY(upload(p, &p->gpos_p, gpos_p));
+    PLAN_TRY(upload(p, &p->gpos_m, gpos_m));
+  }
   PLAN_TRY(upload(p, &p->kin, kin));
   {
     std::vector<c128> t64;
@@ -1105,11 +1323,22 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   // algorithmic bytes per band: sphere in/out (complex128) and one write plus
   // one read of the stick columns per transform direction; V(r) once per pass
   const double sphere_b = 16.0 * p->npw, stick_b = (double)sizeof(cpx<T>) * p->n3 * p->nst;
-  for (int c0 = 0; c0 < nb; c0 += p->band_chunk) {
-    const int nbc = std::min(p->band_chunk, nb - c0);
+  // transforms: one per band, or one per pair of bands at Gamma
+  const bool gam = p->gamma;
+  const int nt = gam ? ceil_div(nb, 2) : nb;
+  for (int c0 = 0; c0 < nt; c0 += p->band_chunk) {
+    const int nbc = std::min(p->band_chunk, nt - c0);
     const int nbc8 = ceil_div(nbc, 8) * 8;
     const int zgrid = gz * nbc8, zrgrid = gzr * nbc8;
-    {
+    const int b0 = gam ? 2 * c0 : c0;                    // first band of the chunk
+    const int nbb = gam ? std::min(nb - b0, 2 * nbc) : nbc;
+    if (gam) {
+      pw::ProfScope ps(pw::PK_ZINV, s, nbb * sphere_b + nbc * stick_b);
+      if (zr.inv_g)
+        zr.inv_g<<<zrgrid, ZRTHREADS, 0, s>>>(m, psi + (size_t)b0 * ldpsi, ldpsi, st, tw3, gzr, nbc, nbb);
+      else
+        k_zinv_g<T><<<zgrid, ZTHREADS, zl, s>>>(m, psi + (size_t)b0 * ldpsi, ldpsi, st, tw3, gz, nbc, nbb);
+    } else {
       pw::ProfScope ps(pw::PK_ZINV, s, nbc * (sphere_b + stick_b));
       if (zr.inv)
         zr.inv<<<zrgrid, ZRTHREADS, 0, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gzr, nbc);
@@ -1129,6 +1358,18 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
       } else {
         k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
       }
+    }
+    if (gam) {
+      pw::ProfScope ps(pw::PK_ZFWD, s, nbb * sphere_b + nbc * stick_b);
+      if (zr.fwd_g)
+        zr.fwd_g<<<zrgrid, ZRTHREADS, 0, s>>>(m, st, tw3, gzr, nbc);
+      else
+        k_zfwd_g<T><<<zgrid, ZTHREADS, zl, s>>>(m, st, tw3, gz, nbc);
+      if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
+      k_gamma_gather<T><<<dim3(ceil_div(p->npw, 256), nbc), 256, 0, s>>>(
+          p->npw, p->gpos_p, p->gpos_m, st, (size_t)p->n3 * p->ldst, p->kin, psi + (size_t)b0 * ldpsi, ldpsi,
+          hpsi + (size_t)b0 * ldhpsi, ldhpsi, 1.0 / (double)p->N, accumulate ? 1 : 0, nbb);
+      continue;
     }
     if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
     {
@@ -1171,6 +1412,40 @@ pw_status pw::psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStre
   return PW_OK;
 }
 
+// Gamma: out[n][j] = sum_{t < dlen_j} Re D[j][t] becp[n][dstart_j + t] (real D, real projections)
+template <typename T>
+__global__ void k_dapply_real(int nbeta, int nb, const double* __restrict__ becp, const int* __restrict__ dstart,
+                              const int* __restrict__ dlen, const c128* __restrict__ drow, int nhmax,
+                              T* __restrict__ out) {
+  const int n = blockIdx.x;
+  for (int j = threadIdx.x; j < nbeta; j += blockDim.x) {
+    const int j0 = dstart[j], nh = dlen[j];
+    double acc = 0.0;
+    for (int t = 0; t < nh; ++t) acc += drow[(size_t)j * nhmax + t].x * becp[(size_t)n * nbeta + j0 + t];
+    out[(size_t)n * nbeta + j] = (T)acc;
+  }
+}
+
+// Gamma projector term, written into hpsi (overwrite): real projections
+// <beta_j|psi> = 2 sum_k beta_jk psi_k - beta_j(0) psi(0) over the interleaved
+// half sphere, D, then hpsi = beta (D <beta|psi>) as a real product of
+// 2 npw rows
+template <typename T>
+pw_status nonlocal_gamma(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, int ldhpsi, hipStream_t s) {
+  const T* beta = sizeof(T) == 8 ? (const T*)p->beta64 : (const T*)p->beta32;
+  double* becp = static_cast<double*>(p->becp);
+  T* becpd = static_cast<T*>(p->becpd);
+  const int K = 2 * p->npw;
+  PW_TRY((pw::dgemm_tn<T, T, double>(p->nbeta, nb, K, beta, 2L * p->ldb, reinterpret_cast<const double*>(psi),
+                                     2L * ldpsi, 1.0, 1.0, 0.0, becp, p->nbeta, false, p->part, p->part_bytes, s,
+                                     pw::PK_CALBEC)));
+  k_dapply_real<T><<<nb, 256, 0, s>>>(p->nbeta, nb, becp, p->dstart, p->dlen, p->drow64, p->nhmax, becpd);
+  PW_HIP(hipGetLastError());
+  PW_TRY((pw::dgemm_nn<T, T, T>(K, nb, p->nbeta, 1.0, beta, 2L * p->ldb, becpd, p->nbeta, 0.0,
+                                reinterpret_cast<double*>(hpsi), 2L * ldhpsi, s, nullptr, pw::PK_ADDNL)));
+  return PW_OK;
+}
+
 // Projector term on the plan's side stream, written into hpsi (overwrite):
 // hpsi = beta (D <beta|psi>).  Runs concurrently with the transform passes
 // (matrix cores vs vector ALUs); the final transform pass adds to it.
@@ -1206,16 +1481,20 @@ pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi,
   const bool f64 = prec == PW_FP64;
   if (!f64) PW_CHECK(p->opts.precision == PW_MIXED, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
   hipEvent_t join = nullptr;
+  auto nonlocal = [&](hipStream_t ns) -> pw_status {
+    if (p->gamma) return f64 ? nonlocal_gamma<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, ns)
+                             : nonlocal_gamma<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, ns);
+    return f64 ? nonlocal_side<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, ns)
+               : nonlocal_side<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, ns);
+  };
   if (p->nbeta > 0 && !nl_beside(p, f64)) {
     // projector term first, on the caller's stream; the transforms add to it
-    if (f64) PW_TRY(nonlocal_side<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
-    else PW_TRY(nonlocal_side<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, s));
+    PW_TRY(nonlocal(s));
   } else if (p->nbeta > 0) {
     // fork: the side stream starts once psi is ready on s
     PW_HIP(hipEventRecord(p->ev_fork, s));
     PW_HIP(hipStreamWaitEvent(p->side, p->ev_fork, 0));
-    if (f64) PW_TRY(nonlocal_side<double>(p, nb, psi, ldpsi, hpsi, ldhpsi, p->side));
-    else PW_TRY(nonlocal_side<float>(p, nb, psi, ldpsi, hpsi, ldhpsi, p->side));
+    PW_TRY(nonlocal(p->side));
     PW_HIP(hipEventRecord(p->ev_join, p->side));
     join = p->ev_join;
   }

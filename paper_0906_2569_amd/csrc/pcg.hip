@@ -275,6 +275,7 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
   PW_CHECK(p->cg != nullptr, PW_EINVAL, "plan was created without solver workspace (ndim_max = 0)");
   PW_CHECK(!p->us, PW_EINVAL, "the conjugate-gradient solver handles S = 1 (norm-conserving) problems only");
+  PW_CHECK(!p->gamma, PW_EINVAL, "the conjugate-gradient solver works on the full sphere (no Gamma plans)");
   pw_cg_opts o;
   if (o_) o = *o_; else pw_cg_opts_default(&o);
   PW_CHECK(nb >= 1 && nb <= p->opts.nb_max, PW_EINVAL, "nb out of range [1, nb_max]");

@@ -50,6 +50,10 @@ struct pw_plan_s {
   int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
   bool use_reg_plane = true;  // register-resident plane pass where the grid allows
   bool split64 = false, split32 = false;  // three-kernel plane pass (float64 / float32)
+  bool gamma = false;       // Gamma point: bands are real functions stored on the half sphere (npw
+                            // entries, G = 0 first); the transforms cover the whole sphere (nfull)
+  int nfull = 0;
+  int *gpos_p = nullptr, *gpos_m = nullptr;   // Gamma: [npw] stick position of G and of -G
 
   // maps (device)
   int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
@@ -152,6 +156,22 @@ pw_status zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1, int
                         c128* C0, c128* C1, int ldc, hipStream_t stream, const int* guard = nullptr);
 
 size_t splitk_part_bytes(int M, int N, int K, int elem_bytes);
+
+// Real products for the Gamma-point path (dgemm.hip).  Complex half-sphere
+// columns are read as real columns of twice the length.
+// tn: C[m, n] = alpha (2 sum_k A[m*lda + k] B[n*ldb + k] - w0 A[m*lda] B[n*ldb]) + beta C[m, n],
+//     C real (ldc) or, cplx_out, the real parts of a complex matrix (imaginary parts set to 0);
+//     deterministic split K (part: dgemm_part_bytes(M, N) bytes).  T = compute type.
+// (prof: the profiler class the product is timed under, -1 = the generic product class)
+template <typename T, typename TA, typename TB>
+pw_status dgemm_tn(int M, int N, int K, const TA* A, long lda, const TB* B, long ldb, double w0, double alpha,
+                   double beta, double* C, int ldc, bool cplx_out, void* part, size_t part_bytes,
+                   hipStream_t stream, int prof = -1);
+// nn: C[n*ldc + m] = alpha sum_k A[k*lda + m] B[n*ldb + k] + beta C[n*ldc + m] (C double; guard as zgemm_nn)
+template <typename T, typename TA, typename TB>
+pw_status dgemm_nn(int M, int N, int K, double alpha, const TA* A, long lda, const TB* B, long ldb, double beta,
+                   double* C, long ldc, hipStream_t stream, const int* guard = nullptr, int prof = -1);
+size_t dgemm_part_bytes(int M, int N);
 
 pw_status dav_alloc(pw_plan p);
 // allow or forbid the cooperative (multi-workgroup) kernels of the plan's

@@ -45,7 +45,7 @@ class Problem(C.Structure):
 class PlanOpts(C.Structure):
     _fields_ = [("precision", C.c_int), ("nb_max", C.c_int32), ("ndim_max", C.c_int32),
                 ("plane_mode", C.c_int32), ("fft_ws_bytes", C.c_size_t), ("nl_overlap", C.c_int32),
-                ("density", C.c_int32)]
+                ("density", C.c_int32), ("gamma", C.c_int32)]
 
 
 class DavOpts(C.Structure):
@@ -318,14 +318,14 @@ class Plan:
     """A problem's maps, operator copies and workspace on one device."""
 
     def __init__(self, ctx: Context, p, precision=PW_FP64, nb_max=None, ndim_max=4, plane_mode=0,
-                 fft_ws_bytes=0, nl_overlap=0, density=0):
+                 fft_ws_bytes=0, nl_overlap=0, density=0, gamma=0):
         import torch
         self.ctx = ctx
         self.lib = ctx.lib
         self.dev = torch.device("cuda", ctx.device)
         s, keep = _problem_struct(p, self.dev)
         self.opts = PlanOpts(precision, int(nb_max or p.nb), int(ndim_max), int(plane_mode), int(fft_ws_bytes),
-                             int(nl_overlap), int(density))
+                             int(nl_overlap), int(density), int(gamma))
         self.h = C.c_void_p()
         _check(self.lib.pw_plan_create(ctx.h, C.byref(s), C.byref(self.opts), C.byref(self.h)))
         ctx._adopt(self)

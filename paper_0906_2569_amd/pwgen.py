@@ -327,3 +327,85 @@ def config5_largest(nb=1024, **kw):
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3}
+
+
+# ----------------------------------------------------------------------------
+# Gamma point, real wavefunctions: half-sphere storage
+# ----------------------------------------------------------------------------
+
+def half_sphere_index(miller: np.ndarray) -> np.ndarray:
+    """Indices of the half sphere in a full Gamma sphere: G = 0 first, then the
+    G > 0 (lexicographic on (h, k, l)) in the sphere's order.  Their mirrors -G
+    make up the rest of the sphere."""
+    m = np.asarray(miller)
+    zero = np.nonzero((m == 0).all(axis=1))[0]
+    assert len(zero) == 1, "the Gamma sphere holds G = 0 once"
+    pos = (m[:, 0] > 0) | ((m[:, 0] == 0) & (m[:, 1] > 0)) | ((m[:, 0] == 0) & (m[:, 1] == 0) & (m[:, 2] > 0))
+    return np.concatenate([zero, np.nonzero(pos)[0]])
+
+
+def mirror_index(miller: np.ndarray) -> np.ndarray:
+    """For each G of the sphere, the index of -G."""
+    m = np.asarray(miller)
+    key = {tuple(x): i for i, x in enumerate(m.tolist())}
+    return np.array([key[(-x[0], -x[1], -x[2])] for x in m.tolist()], dtype=np.int64)
+
+
+@dataclass
+class GammaProblem:
+    """A Gamma-point cell in two forms: `full` (the complex problem on the whole
+    sphere, its projectors real in real space) and the half-sphere arrays the
+    real-wavefunction path takes (`miller`, `kpg`, `beta`, `psi0`, indices into
+    the full sphere in `half`)."""
+    full: Problem
+    half: np.ndarray
+    miller: np.ndarray
+    kpg: np.ndarray
+    beta: np.ndarray
+    psi0: np.ndarray
+
+    def __getattr__(self, name):     # everything else as in the full problem
+        return getattr(self.full, name)
+
+    @property
+    def npw(self) -> int:
+        return int(self.miller.shape[0])
+
+    def expand(self, x_half: np.ndarray) -> np.ndarray:
+        """Full-sphere coefficients of real functions given on the half sphere:
+        f(-G) = conj(f(G))."""
+        x_half = np.atleast_2d(x_half)
+        out = np.zeros((x_half.shape[0], self.full.npw), dtype=np.complex128)
+        out[:, self.half] = x_half
+        mir = mirror_index(self.full.miller)
+        out[:, mir[self.half]] = np.conj(x_half)
+        return out
+
+
+def gamma_cell(a, ecut_ry, natoms, nb, seed, nr=None, name="", with_vloc=True, with_beta=True):
+    """A Gamma-point cell for the real-wavefunction path.  As make_cell, with
+    the p projectors multiplied by -i (the (-i)^l factor of the structure
+    factor form), so that every projector is real in real space:
+    beta(-G) = conj(beta(G)).  The trial block is real in real space (its
+    half-sphere coefficients, with psi(0) real, and their mirrors)."""
+    p = make_cell(a, ecut_ry, natoms, nb, seed, nr=nr, name=name or f"gamma{seed}",
+                  with_vloc=with_vloc, with_beta=with_beta)
+    if p.nbeta:
+        beta = p.beta.copy()
+        for j in range(p.nbeta):
+            if j % NPROJ_PER_ATOM != 0:
+                beta[j] *= -1j
+        p.beta = beta
+    half = half_sphere_index(p.miller)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed or 0), 78])))
+    z = rng.standard_normal((nb, len(half), 2))
+    ph = (z[..., 0] + 1j * z[..., 1]) / math.sqrt(2.0)
+    ph[:, 0] = ph[:, 0].real
+    g = GammaProblem(full=p, half=half, miller=np.ascontiguousarray(p.miller[half]),
+                     kpg=np.ascontiguousarray(p.kpg[half]), beta=np.ascontiguousarray(p.beta[:, half]),
+                     psi0=None)
+    full_psi = g.expand(ph)
+    full_psi /= np.linalg.norm(full_psi, axis=1, keepdims=True)
+    p.psi0 = full_psi
+    g.psi0 = np.ascontiguousarray(full_psi[:, half])
+    return g

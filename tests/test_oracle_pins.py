@@ -420,3 +420,19 @@ def test_ultrasoft_rotation_invariance_and_q_zero():
     np.testing.assert_allclose(oracle.dense_s(p.npw, beta2, p.blk_off, q2), s0, atol=1e-14)
     assert np.abs(s0 - np.eye(p.npw)).max() > 1e-3
     np.testing.assert_allclose(oracle.dense_s(p.npw, p.beta, p.blk_off, np.zeros_like(qmat)), np.eye(p.npw))
+
+
+def test_gamma_cell_is_real_in_real_space():
+    # with the -i of the p projectors, beta(-G) = conj(beta(G)) and
+    # H(-G, -G') = conj(H(G, G')): H maps real functions to real functions, so
+    # the half sphere carries them; diagonal D leaves H unchanged by the phase
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 4, 31, nr=(30, 30, 30))
+    mir = pwgen.mirror_index(g.full.miller)
+    np.testing.assert_allclose(g.full.beta[:, mir], np.conj(g.full.beta), atol=1e-15)
+    h = oracle.dense_h_of(g.full)
+    np.testing.assert_allclose(h[np.ix_(mir, mir)], np.conj(h), atol=1e-14)
+    ref = pwgen.make_cell(10.0, 15.0, 8, 4, 31, nr=(30, 30, 30))
+    np.testing.assert_allclose(h, oracle.dense_h_of(ref), atol=1e-14)
+    hp = oracle.hpsi(h, g.full.psi0)
+    np.testing.assert_allclose(hp[:, mir], np.conj(hp), atol=1e-14)
+    assert len(g.half) == (g.full.npw + 1) // 2 and g.half[0] == np.nonzero((g.full.miller == 0).all(1))[0][0]

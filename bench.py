@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--hpsi-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gamma", action="store_true", help="cell512: skip the Gamma-point path rates")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the per-stage H.psi measurement (keeps kernel profiles to the timed steps)")
     ap.add_argument("--workload", choices=["cell512", "cell64", "batch", "serve"], default="cell512",
@@ -403,7 +404,11 @@ def bench_serve(args):
 # fetched bytes = 2.0 x FETCH_SIZE KiB x 1024, written = 1.0 x WRITE_SIZE KiB
 # x 1024), keyed by (workload, kernel class).  Summaries under profiles/.
 # An entry is removed whenever its kernel changes.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {
+    # k_gemm_cn<float, float, double>, 8 K chunks: 57.12 GB read + 0.134 GB written
+    # (profiles/hpsi_mixed_512atom_144cubed.md)
+    ("cell512_mixed", "calbec_gemm"): 57.257e9,
+}
 
 
 def golden_config2():
@@ -455,7 +460,37 @@ def cell64_solves(ctx, nsolves):
             }
         finally:
             plan.close()
+    # the same cell on the Gamma-point real-wavefunction path (half sphere; the
+    # -i of its p projectors leaves H unchanged for diagonal D, so the same
+    # golden eigenvalues apply)
+    g = pwgen.gamma_cell(20.5, 25.0, 64, 128, pwgen.SEED_BASE + 2, nr=(72, 72, 72))
+    plan = pwdft.Plan(ctx, g, precision=pwdft.PW_FP64, nb_max=g.nb, ndim_max=3, gamma=1)
+    try:
+        gpsi0 = torch.from_numpy(g.psi0).to(dev)
+        psi = torch.empty_like(gpsi0)
+        eig = torch.empty(g.nb, dtype=torch.float64, device=dev)
+        resid = torch.empty_like(eig)
+        opts = pwdft.default_opts(ndim=3, max_iter=400)
+        psi.copy_(gpsi0)
+        plan.davidson(psi, eig, resid, opts=opts)
+        torch.cuda.synchronize()
+        t_tot, emax, sts = 0.0, 0.0, []
+        for _ in range(nsolves):
+            psi.copy_(gpsi0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st, _, _, stats = plan.davidson(psi, eig, resid, opts=opts)
+            torch.cuda.synchronize()
+            t_tot += time.perf_counter() - t0
+            emax = max(emax, float(np.abs(eig.cpu().numpy() - w).max()))
+            sts.append(st)
+        out["gamma_fp64"] = {"solves_per_s": nsolves / t_tot, "ms_per_solve": t_tot * 1e3 / nsolves, "ndim": 3,
+                             "max_abs_eig_err_ha": emax, "status": sts, "stats": stats.asdict(),
+                             "npw_half": g.npw}
+    finally:
+        plan.close()
     out["mixed_over_fp64_solves"] = out["mixed"]["solves_per_s"] / out["fp64"]["solves_per_s"]
+    out["gamma_over_complex_fp64_solves"] = out["gamma_fp64"]["solves_per_s"] / out["fp64"]["solves_per_s"]
     out["reference"] = ("lowest 128 eigenvalues of the dense 18277^2 oracle Hamiltonian "
                         "(tests/golden/config2_eigenvalues.txt); target 5e-9 Ha = 1e-8 Ry")
     return out
@@ -517,6 +552,34 @@ def cpu_baseline_rows(p, got, seconds):
     return out, fftm, parity
 
 
+def gamma_rates(ctx, p, reps, mixed_complex, fp64_complex):
+    """band-H.psi/s of the same cell on the Gamma-point real-wavefunction path
+    (half sphere, two bands per transform, real projector products), mixed and
+    float64, against the complex path."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    g = pwgen.gamma_cell(p.a, p.ecut_ry, p.natoms, p.nb, p.meta.get("seed") or pwgen.SEED_BASE + 5, nr=p.nr)
+    plan = pwdft.Plan(ctx, g, precision=pwdft.PW_MIXED, nb_max=g.nb, ndim_max=0, gamma=1)
+    try:
+        x = torch.from_numpy(g.psi0).cuda()
+        y = torch.empty_like(x)
+        out = {"npw_half": g.npw}
+        for key, pr in (("mixed", pwdft.PW_MIXED), ("fp64", pwdft.PW_FP64)):
+            plan.hpsi(x, y, prec=pr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                plan.hpsi(x, y, prec=pr)
+            torch.cuda.synchronize()
+            out[key] = g.nb * reps / (time.perf_counter() - t0)
+        out["mixed_over_complex_mixed"] = out["mixed"] / mixed_complex
+        out["fp64_over_complex_fp64"] = out["fp64"] / fp64_complex
+        out["unit"] = "band-H·ψ/s"
+        return out
+    finally:
+        plan.close()
+
+
 def bench_cell512(args):
     """Mixed-precision H.psi of the 1024-band block of the 512-atom 144^3 cell,
     against the same product in plain float64."""
@@ -567,6 +630,7 @@ def bench_cell512(args):
     stages = None
     if not args.no_stages:
         stages = hpsi_stages(ctx, p, plan, psi0, pwdft.PW_MIXED, 3)
+    gamma = None if args.no_gamma else gamma_rates(ctx, p, max(3, args.steps // 4), value, rate64)
     solves = cell64_solves(ctx, args.solves) if args.solves > 0 else None
     rl = roofline(prof, "f32")
     tb = TRAFFIC_BYTES.get(("cell512_mixed", rl["kernel"]))
@@ -590,6 +654,7 @@ def bench_cell512(args):
         "ms_per_hpsi": {"mixed": 1e3 * p.nb / value, "fp64": 1e3 * p.nb / rate64},
         "roofline": rl,
         "hpsi_stages": stages,
+        "gamma_real_path": gamma,
         "cell64_solves": solves,
         "kernel_ms": {k: round(v[1] / max(args.warmup, 1), 3)
                       for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1][1])},

@@ -51,7 +51,7 @@ typedef enum {
   PW_EDEVICE = -3,      /* HIP runtime error                                          */
   PW_EBREAKDOWN = -4,   /* overlap matrix not positive definite after a restart       */
   PW_ENAN = -5,         /* non-finite residual norm                                   */
-  PW_ECANCELLED = -6    /* solve cancelled through pw_cancel                          */
+  PW_ECANCELLED = -6    /* solve cancelled through pw_cancel or pw_server_cancel       */
 } pw_status;
 
 typedef enum {
@@ -283,6 +283,29 @@ pw_status pw_scf_norm(pw_plan plan, const double* rho_out, const double* rho_in,
                       double omega, double* norm2, void* stream);
 
 /*
+ * Ask the solve running on `plan` (davidson_solve or pcg_solve, from another
+ * host thread) to stop: it returns PW_ECANCELLED at its next iteration check,
+ * with the current Ritz vectors, eigenvalues and residuals written as for
+ * PW_ENOTCONV.  With no solve running, the next solve on the plan stops at its
+ * first check.  Thread-safe; returns PW_EINVAL for a NULL plan.
+ */
+pw_status pw_cancel(pw_plan plan);
+
+/*
+ * hpsi_apply captured into a HIP graph: the transform passes, the projector
+ * products and their join, replayed by pw_graph_launch with no host work per
+ * kernel.  The graph is bound to these psi / hpsi buffers (their contents may
+ * change between launches) and to the plan, which must outlive it.  One
+ * eager hpsi_apply runs first on a private stream; capture uses a private
+ * stream too.  Synchronous.  Errors: PW_EINVAL, PW_EDEVICE.
+ */
+typedef struct pw_graph_s* pw_graph;
+pw_status pw_hpsi_graph_create(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128* psi, int32_t ldpsi,
+                               pw_c128* hpsi, int32_t ldhpsi, pw_graph* out);
+pw_status pw_graph_launch(pw_graph graph, void* stream);   /* asynchronous on `stream` */
+pw_status pw_graph_destroy(pw_graph graph);
+
+/*
  * Batches of independent problems (cells x k-points; the paper's pool level,
  * whose problems need no communication).  Item i uses plans[i] (all plans of
  * ctx, each at most once per call) with nb[i] bands and the [dev] blocks
@@ -331,6 +354,11 @@ pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, co
  *     ticket can be waited for once.
  *   pw_server_poll: done = 1 when the request has completed.
  *   pw_server_clock: seconds since pw_server_create.
+ *   pw_server_cancel: a queued request is dropped (its wait returns
+ *     PW_ECANCELLED at once); a running one stops at its solve's next
+ *     iteration check (pw_cancel) and returns PW_ECANCELLED with its current
+ *     Ritz pairs; a finished one is left as it is.  PW_EINVAL for an unknown
+ *     ticket.
  *   pw_server_destroy: finish every submitted request, then stop.
  */
 typedef struct pw_server_s* pw_server;
@@ -346,6 +374,7 @@ pw_status pw_server_submit(pw_server server, const pw_problem* problem, int32_t 
                            int64_t* ticket);
 pw_status pw_server_wait(pw_server server, int64_t ticket, pw_david_stats* stats, double times[3]);
 pw_status pw_server_poll(pw_server server, int64_t ticket, int32_t* done);
+pw_status pw_server_cancel(pw_server server, int64_t ticket);
 double    pw_server_clock(pw_server server);
 pw_status pw_server_destroy(pw_server server);
 

@@ -342,7 +342,8 @@ size_t pw::dav_bytes(int npw, int nb_max, int ndim_max) {
   b += 5 * (size_t)nb_max * sizeof(double) + 2 * nb_max * sizeof(int) + 256;
   b += (size_t)nb_max * nb_max * sizeof(c128);          // lockc
   b += nbasis * nb_max * sizeof(double);                // real Ritz coefficients (Gamma)
-  b += pw::splitk_part_bytes((int)nbasis, (int)nbasis, npw, sizeof(c128));
+  b += std::max(pw::splitk_part_bytes((int)nbasis, (int)nbasis, npw, sizeof(c128)),
+                pw::dgemm_part_bytes((int)nbasis, (int)nbasis));
   b += pw::heig_work_bytes((int)nbasis);
   return b + 32 * 256;
 }
@@ -385,7 +386,8 @@ pw_status pw::dav_alloc(pw_plan p) {
   if (p->gamma) PW_TRY(get(nbx * nb * sizeof(double), (void**)&W->creal));
   PW_TRY(get(2 * nb * sizeof(double), (void**)&W->etmp));
   PW_TRY(get(sizeof(DavFlags), (void**)&W->flags));
-  W->part_bytes = pw::splitk_part_bytes((int)nbx, (int)nbx, p->npw, sizeof(c128));
+  W->part_bytes = std::max(pw::splitk_part_bytes((int)nbx, (int)nbx, p->npw, sizeof(c128)),
+                           pw::dgemm_part_bytes((int)nbx, (int)nbx));
   PW_TRY(get(W->part_bytes, &W->part));
   void* hwb = nullptr;
   PW_TRY(get(pw::heig_work_bytes((int)nbx), &hwb));
@@ -689,6 +691,7 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
       continue;
     }
     if (f.nan) { result = pw::fail(PW_ENAN, "non-finite residual norm"); break; }
+    if (p->cancel.exchange(0)) { result = pw::fail(PW_ECANCELLED, "solve cancelled (pw_cancel)"); break; }
     if (fp32_stage && f.maxr < kStallZone * o.ladder_switch) {
       if (f.maxr < 0.5 * best32) { best32 = f.maxr; stall32 = 0; } else { ++stall32; }
     }
@@ -779,5 +782,12 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   stats.nconv = f.nconv;
   stats.nlocked = S.nl;
   if (stats_out) *stats_out = stats;
+  p->cancel.store(0);   // a cancel asked after the last check does not carry over to the next solve
   return result;
+}
+
+extern "C" pw_status pw_cancel(pw_plan p) {
+  PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
+  p->cancel.store(1);
+  return PW_OK;
 }

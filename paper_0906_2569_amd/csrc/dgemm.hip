@@ -246,6 +246,7 @@ k_dgemm_nn(int M, int N, int K, double alpha, const TA* __restrict__ A, long lda
 int dsplit(int M, int N, int K, int& kchunk) {
   const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
   int ns = std::max(1, ceil_div(512, tiles));
+  if (ns < 8 && K >= 8 * 256 * BK) ns = 8;   // one K range per XCD (see the complex products)
   ns = std::min(ns, std::max(1, ceil_div(K, 4 * BK)));
   kchunk = std::max(BK, ceil_div(ceil_div(K, ns), BK) * BK);
   return std::max(1, ceil_div(K, kchunk));
@@ -254,7 +255,8 @@ int dsplit(int M, int N, int K, int& kchunk) {
 }  // namespace
 
 size_t pw::dgemm_part_bytes(int M, int N) {
-  return ((size_t)512 * BM * BN + (size_t)std::max(M, 1) * std::max(N, 1)) * sizeof(double) + 256;
+  const size_t mn = (size_t)std::max(M, 1) * std::max(N, 1);
+  return std::max((size_t)512 * BM * BN + mn, 8 * mn) * sizeof(double) + 256;
 }
 
 template <typename T, typename TA, typename TB>

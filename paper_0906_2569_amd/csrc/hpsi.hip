@@ -978,7 +978,8 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
   if (pr->nbeta > 0 && pr->qmat != nullptr)
     b += (size_t)o->nb_max * pr->nbeta * sizeof(c128) + (size_t)pr->npw * sizeof(double) +
          (size_t)pr->nbeta * geo.nhmax * (sizeof(c128) + sizeof(c64));
-  b += pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128));
+  b += std::max(pw::splitk_part_bytes(std::max(pr->nbeta, 1), o->nb_max, pr->npw, sizeof(c128)),
+                pw::dgemm_part_bytes(std::max(pr->nbeta, 1), o->nb_max));
   if (o->ndim_max > 0) b += pw::dav_bytes(pr->npw, o->nb_max, o->ndim_max) + pw::cg_bytes(pr->npw, o->nb_max);
   return b;
 }
@@ -1238,6 +1239,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpd), (size_t)o->nb_max * nbeta1));
   if (us) PLAN_TRY(dalloc(p, reinterpret_cast<c128**>(&p->becpq), (size_t)o->nb_max * nbeta1));
   p->part_bytes = pw::splitk_part_bytes(nbeta1, o->nb_max, npw, sizeof(c128));
+  if (geo.gamma) p->part_bytes = std::max(p->part_bytes, pw::dgemm_part_bytes(nbeta1, o->nb_max));
   PLAN_TRY(dalloc(p, reinterpret_cast<char**>(&p->part), p->part_bytes));
   if (hipStreamCreateWithFlags(&p->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming) != hipSuccess ||

@@ -318,6 +318,10 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
         break;
       }
       if (W.hsc->conv == 1) { conv = true; break; }
+      if (p->cancel.exchange(0)) {
+        result = pw::fail(PW_ECANCELLED, "solve cancelled (pw_cancel)");
+        break;
+      }
     }
     if (result != PW_OK) break;
     // the band joins the found ones, orthogonal to them and normalized
@@ -338,5 +342,6 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
     if (stats.nconv < nb) result = PW_ENOTCONV;
   }
   if (stats_out) *stats_out = stats;
+  p->cancel.store(0);
   return result;
 }

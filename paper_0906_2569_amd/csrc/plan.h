@@ -1,5 +1,6 @@
 // Internal plan / context layout shared by the library's translation units.
 #pragma once
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -92,6 +93,7 @@ struct pw_plan_s {
 
   DavWork* dav = nullptr;
   CgWork* cg = nullptr;
+  std::atomic<int> cancel{0};   // set by pw_cancel; read once per iteration by the running solve
   std::vector<void*> allocs;
   hipStream_t side = nullptr;          // projector term runs here, beside the transforms
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;

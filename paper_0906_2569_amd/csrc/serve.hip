@@ -36,6 +36,8 @@ struct pw_server_s {
     std::string msg;
     pw_david_stats stats{};
     bool done = false;
+    bool cancel = false;        // pw_server_cancel was called for it
+    pw_plan plan = nullptr;     // while its solve runs (guarded by mu)
   };
   std::deque<Req*> queue;
   std::map<int64_t, Req*> all;
@@ -84,7 +86,16 @@ struct pw_server_s {
           reserved = pcoop;
         }
         (void)pw::dav_set_coop(plan, reserved > 0, wide);
+        {
+          std::lock_guard<std::mutex> l(mu);
+          r->plan = plan;
+          if (r->cancel) (void)pw_cancel(plan);   // cancelled while its plan was built: stops at the first check
+        }
         st = davidson_solve(plan, r->nb, r->psi, r->ldpsi, r->eig, r->resid, &r->dopts, &r->stats, streams[w]);
+        {
+          std::lock_guard<std::mutex> l(mu);
+          r->plan = nullptr;
+        }
         if (st != PW_OK) r->msg = pw_last_error();
         (void)hipStreamSynchronize(streams[w]);
         if (reserved > 0) {
@@ -224,5 +235,35 @@ extern "C" pw_status pw_server_destroy(pw_server s) {
   for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
   for (auto& kv : s->all) delete kv.second;
   delete s;
+  return PW_OK;
+}
+
+extern "C" pw_status pw_server_cancel(pw_server s, int64_t ticket) {
+  PW_CHECK(s != nullptr, PW_EINVAL, "NULL server");
+  bool dequeued = false;
+  {
+    std::lock_guard<std::mutex> l(s->mu);
+    auto it = s->all.find(ticket);
+    PW_CHECK(it != s->all.end(), PW_EINVAL, "unknown ticket");
+    pw_server_s::Req* r = it->second;
+    if (r->done) return PW_OK;
+    r->cancel = true;
+    for (auto q = s->queue.begin(); q != s->queue.end(); ++q) {
+      if (*q == r) {
+        s->queue.erase(q);
+        r->st = PW_ECANCELLED;
+        r->msg = "request cancelled before it started";
+        r->t_start = r->t_end = s->now();
+        r->done = true;
+        dequeued = true;
+        break;
+      }
+    }
+    if (!dequeued && r->plan) (void)pw_cancel(r->plan);
+  }
+  if (dequeued) {
+    s->cv_done.notify_all();
+    s->cv_work.notify_all();
+  }
   return PW_OK;
 }

@@ -391,6 +391,11 @@ Split choose_split(int M, int N, int K) {
   const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
   const int target = 512;
   int nsplit = std::max(1, ceil_div(target, tiles));
+  // A long K splits into at least one chunk per XCD even when the tiles alone
+  // fill the device: the work order then gives each XCD its own K range, and
+  // every operand element is read from memory once instead of by every tile
+  // row or column (calbec of the 512-atom cell read its operands 9 times)
+  if (nsplit < 8 && K >= 8 * 256 * BK) nsplit = 8;
   nsplit = std::min(nsplit, std::max(1, ceil_div(K, 4 * BK)));
   int kchunk = ceil_div(ceil_div(K, nsplit), BK) * BK;
   kchunk = std::max(kchunk, BK);
@@ -402,9 +407,11 @@ Split choose_split(int M, int N, int K) {
 
 size_t pw::splitk_part_bytes(int M, int N, int K, int elem_bytes) {
   // Upper bound over every M' <= M, N' <= N: nsplit <= 512/tiles + 1, so
-  // nsplit M' N' <= 512 BM BN + M N.
-  (void)K;
-  return ((size_t)512 * BM * BN + (size_t)std::max(M, 1) * std::max(N, 1)) * elem_bytes + 256;
+  // nsplit M' N' <= 512 BM BN + M N; a long K adds the 8-chunk minimum.
+  const size_t mn = (size_t)std::max(M, 1) * std::max(N, 1);
+  size_t e = (size_t)512 * BM * BN + mn;
+  if (K >= 8 * 256 * BK) e = std::max(e, 8 * mn);
+  return e * elem_bytes + 256;
 }
 
 template <typename T, typename TA, typename TB>

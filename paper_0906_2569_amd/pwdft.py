@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
            "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
-           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "spsi_apply", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
+           "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "spsi_apply", "pw_cancel", "pw_hpsi_graph_create",
+           "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
            "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
@@ -104,6 +105,12 @@ def load(path: str = LIB_PATH):
     lib.hpsi_apply.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p]
     lib.spsi_apply.argtypes = lib.hpsi_apply.argtypes
+    lib.pw_cancel.argtypes = [C.c_void_p]
+    lib.pw_hpsi_graph_create.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
+                                         C.c_int32, C.POINTER(C.c_void_p)]
+    lib.pw_graph_launch.argtypes = [C.c_void_p, C.c_void_p]
+    lib.pw_graph_destroy.argtypes = [C.c_void_p]
+    lib.pw_server_cancel.argtypes = [C.c_void_p, C.c_int64]
     lib.davidson_solve.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                    C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavStats), C.c_void_p]
     P = C.POINTER
@@ -141,7 +148,8 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_name.restype = C.c_char_p
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "spsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
+                 "pw_plan_info", "hpsi_apply", "spsi_apply", "davidson_solve", "pw_cancel",
+                 "pw_hpsi_graph_create", "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "hpsi_apply_batched", "davidson_solve_batched",
                  "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve",
                  "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
                  "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
@@ -362,23 +370,19 @@ class Plan:
         return out
 
     def hpsi_graph(self, psi, out, prec=PW_FP64):
-        """A torch.cuda.CUDAGraph whose replay() recomputes out = H psi for these
-        buffers: hpsi_apply captured once (transform passes, projector products
-        on the plan's side stream, and the join), then relaunched with no host
-        work per kernel.  psi and out must stay allocated, in place, while the
-        graph is used; their contents may change between replays."""
-        import torch
+        """A captured hpsi_apply for these buffers (pw_hpsi_graph_create): its
+        replay() relaunches out = H psi on the current torch stream.  psi and
+        out must stay allocated, in place, while the graph is used; their
+        contents may change between replays."""
         assert psi.shape == out.shape and psi.stride(1) == 1 and out.stride(1) == 1
-        side = torch.cuda.Stream(device=psi.device)   # default priority
-        side.wait_stream(torch.cuda.current_stream(psi.device))
-        with torch.cuda.stream(side):
-            self.hpsi(psi, out, prec=prec)            # warm-up launch outside the capture
-        torch.cuda.current_stream(psi.device).wait_stream(side)
-        torch.cuda.synchronize(psi.device)
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            self.hpsi(psi, out, prec=prec)
-        return g
+        h = C.c_void_p()
+        _check(self.lib.pw_hpsi_graph_create(self.h, prec, psi.shape[0], C.c_void_p(psi.data_ptr()), psi.stride(0),
+                                             C.c_void_p(out.data_ptr()), out.stride(0), C.byref(h)))
+        return HpsiGraph(self, h, (psi, out))
+
+    def cancel(self):
+        """Stop the solve running on this plan (from another thread): it returns PW_ECANCELLED."""
+        _check(self.lib.pw_cancel(self.h))
 
     def davidson(self, psi, eig=None, resid=None, opts=None, stream=None, history=None):
         """In-place block Davidson on psi [nb][>=npw]; returns (status, eig, resid, stats).
@@ -458,6 +462,27 @@ class Plan:
             pass
 
 
+class HpsiGraph:
+    """hpsi_apply captured in a HIP graph (see Plan.hpsi_graph)."""
+
+    def __init__(self, plan, h, keep):
+        self.plan, self.lib, self.h, self._keep = plan, plan.lib, h, keep
+
+    def replay(self, stream=None):
+        _check(self.lib.pw_graph_launch(self.h, _stream_ptr(stream)))
+
+    def close(self):
+        if self.h:
+            self.lib.pw_graph_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Serving loop of the library (see pw_server_* in include/pwdft.h)."""
 
@@ -498,6 +523,9 @@ class Server:
         if rc not in (PW_OK, PW_ENOTCONV):
             _check(rc)
         return rc, st.asdict(), (times[0], times[1], times[2])
+
+    def cancel(self, ticket):
+        _check(self.lib.pw_server_cancel(self.h, ticket))
 
     def close(self):
         if self.h:

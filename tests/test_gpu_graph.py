@@ -51,3 +51,24 @@ def test_hpsi_graph_replays_equal_eager(ctx, cfg, prec):
             assert err.max() <= 1e-11
     finally:
         plan.close()
+
+
+def test_graph_of_gamma_and_mixed_plans(ctx):
+    # the C-ABI capture holds the side-stream projector products and their join
+    from paper_0906_2569_amd import pwdft
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 16, 26, nr=(30, 30, 30))
+    plan = pwdft.Plan(ctx, g, precision=1, nb_max=g.nb, ndim_max=0, gamma=1, nl_overlap=1)
+    try:
+        x = torch.from_numpy(g.psi0).cuda()
+        y = torch.empty_like(x)
+        graph = plan.hpsi_graph(x, y, prec=1)
+        for rep in range(3):
+            x.mul_(0.5 + rep)
+            ref = plan.hpsi(x.clone(), prec=1)
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref), rep
+        graph.close()
+    finally:
+        plan.close()

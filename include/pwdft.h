@@ -346,7 +346,9 @@ pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, co
  *     free device memory, PW_MIXED plans).
  *   pw_server_submit: enqueue one request and return its ticket at once.
  *     The problem's arrays (host and device) and psi [dev, in/out], eig and
- *     resid [dev] must stay valid until the request completes.  PW_ENOMEM if
+ *     resid [dev] must stay valid until the request completes, and their
+ *     contents must be complete when submit is called: the worker reads them
+ *     on its own stream, with no ordering against the caller's streams.  PW_ENOMEM if
  *     the request alone exceeds mem_budget; PW_EINVAL for invalid problems.
  *   pw_server_wait: block until the ticket's request is done; returns its
  *     davidson_solve status (message in pw_last_error), its stats, and

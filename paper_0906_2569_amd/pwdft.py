@@ -507,6 +507,9 @@ class Server:
         eig = torch.empty(psi.shape[0], dtype=torch.float64, device=psi.device)
         res = torch.empty_like(eig)
         opts = opts or default_opts()
+        # the worker reads psi, V and beta on its own stream: their uploads
+        # (on torch's stream) must be complete before the request is submitted
+        torch.cuda.current_stream(psi.device).synchronize()
         t = C.c_int64()
         _check(self.lib.pw_server_submit(self.h, C.byref(s), psi.shape[0], C.c_void_p(psi.data_ptr()),
                                          psi.stride(0), C.c_void_p(eig.data_ptr()), C.c_void_p(res.data_ptr()),

@@ -3,9 +3,16 @@
 // (<beta|psi>, then sum_j beta_j (D <beta|psi>)_j) and for the Davidson
 // subspace products (phi^H H phi, phi^H phi, Ritz rotations).
 //
-// Complex products use four real MFMAs per 16x16x4 block:
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B,
-// with Im A negated once, at the LDS store, when A enters conjugated.
+// Complex float64 products use four real MFMAs per 16x16x4 block:
+//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
+// Complex float32 products use three (Gauss's product, as in the 3M complex
+// GEMMs): t1 += Re A Re B, t2 += Im A Im B, t3 += (Re A + Im A)(Re B + Im B),
+// and at the end Re C = t1 - t2, Im C = t3 - t1 - t2.  That is 6 M N K real
+// flops on the matrix cores instead of 8; the error bound of the imaginary
+// part grows from about K u (|Re A||Im B| + |Im A||Re B|) to about
+// K u (|Re A| + |Im A|)(|Re B| + |Im B|) (u the float32 unit roundoff),
+// which the float32 stage of the precision ladder absorbs.  Im A is negated
+// once, at the LDS store, when A enters conjugated.
 //
 // Two shapes:
 //   cn : C[m, n] = sum_k conj(A[k, m]) B[k, n]; A and B are stored as
@@ -83,12 +90,34 @@ struct Tile {
   T ar[BK][BM + 1], ai[BK][BM + 1], br[BK][BN + 1], bi[BK][BN + 1];
 };
 
+// Accumulators of one wave's 32x32 quadrant (2x2 blocks of 16x16): for
+// float64, a = Re C and b = Im C; for float32, a = t1, b = t2, c = t3 of the
+// three-product form.
+template <typename T>
+struct CAcc {
+  typedef typename Mma<T>::v4 v4;
+  static constexpr bool k3 = sizeof(T) == 4;
+  v4 a[2][2], b[2][2], c[2][2];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) a[i][j] = b[i][j] = c[i][j] = v4{0, 0, 0, 0};
+  }
+  __device__ __forceinline__ cpx<T> get(int i, int j, int q) const {
+    if constexpr (k3) {
+      const T t1 = a[i][j][q], t2 = b[i][j][q];
+      return cpx<T>{t1 - t2, (c[i][j][q] - t1) - t2};
+    } else {
+      return cpx<T>{a[i][j][q], b[i][j][q]};
+    }
+  }
+};
+
 // One BK slice of a 64x64 tile product held in LDS; each of the 4 waves owns a
 // 32x32 quadrant (2x2 blocks of 16x16).
 template <typename T>
-__device__ __forceinline__ void tile_mma(const Tile<T>& t, typename Mma<T>::v4 (&cr)[2][2],
-                                         typename Mma<T>::v4 (&ci)[2][2], int wm, int wn,
-                                         int lane) {
+__device__ __forceinline__ void tile_mma(const Tile<T>& t, CAcc<T>& acc, int wm, int wn, int lane) {
   const int r = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int k4 = 0; k4 < BK; k4 += 4) {
@@ -101,15 +130,29 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, typename Mma<T>::v4 (
       br[i] = t.br[kk][wn * 32 + i * 16 + r];
       bi[i] = t.bi[kk][wn * 32 + i * 16 + r];
     }
+    if constexpr (CAcc<T>::k3) {
+      T sa[2], sb[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i) { sa[i] = ar[i] + ai[i]; sb[i] = br[i] + bi[i]; }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        cr[i][j] = Mma<T>::run(ar[i], br[j], cr[i][j]);
-        cr[i][j] = Mma<T>::run(-ai[i], bi[j], cr[i][j]);
-        ci[i][j] = Mma<T>::run(ar[i], bi[j], ci[i][j]);
-        ci[i][j] = Mma<T>::run(ai[i], br[j], ci[i][j]);
-      }
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc.a[i][j] = Mma<T>::run(ar[i], br[j], acc.a[i][j]);
+          acc.b[i][j] = Mma<T>::run(ai[i], bi[j], acc.b[i][j]);
+          acc.c[i][j] = Mma<T>::run(sa[i], sb[j], acc.c[i][j]);
+        }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc.a[i][j] = Mma<T>::run(ar[i], br[j], acc.a[i][j]);
+          acc.a[i][j] = Mma<T>::run(-ai[i], bi[j], acc.a[i][j]);
+          acc.b[i][j] = Mma<T>::run(ar[i], bi[j], acc.b[i][j]);
+          acc.b[i][j] = Mma<T>::run(ai[i], br[j], acc.b[i][j]);
+        }
+    }
   }
 }
 
@@ -121,7 +164,6 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
 k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict__ A, int lda,
           const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
   __shared__ Tile<T> t;
-  typedef typename Mma<T>::v4 v4;
   int bx, by, bz;
   xcd_block<false>(bx, by, bz);   // the output tiles of one K chunk share an XCD
   const int m0 = bx * BM, n0 = by * BN;
@@ -130,11 +172,8 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
   const int kbeg = zs * kchunk, kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  v4 cr[2][2], ci[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
+  CAcc<T> acc;
+  acc.zero();
 
   // the next K slice is loaded into registers while the current one is
   // multiplied out of LDS
@@ -165,7 +204,7 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
     }
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);
-    tile_mma<T>(t, cr, ci, wm, wn, lane);
+    tile_mma<T>(t, acc, wm, wn, lane);
     __syncthreads();
   }
   cpx<T>* out = P + (size_t)bz * M * N;
@@ -177,7 +216,7 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
         const int n = n0 + wn * 32 + j * 16 + mcol(lane);
-        if (m < M && n < N) out[(size_t)n * M + m] = cpx<T>{cr[i][j][q], ci[i][j][q]};
+        if (m < M && n < N) out[(size_t)n * M + m] = acc.get(i, j, q);
       }
 }
 
@@ -200,15 +239,11 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
   const int kbeg = SPLIT ? bz * kchunk : 0;
   const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
   __shared__ Tile<T> t;
-  typedef typename Mma<T>::v4 v4;
   const int m0 = bx * BM, n0 = by * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  v4 cr[2][2], ci[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) { cr[i][j] = v4{0, 0, 0, 0}; ci[i][j] = v4{0, 0, 0, 0}; }
+  CAcc<T> acc;
+  acc.zero();
 
   constexpr int PER = BM * BK / NT;
   cpx<TA> ra[PER];
@@ -247,7 +282,7 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
     }
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);
-    tile_mma<T>(t, cr, ci, wm, wn, lane);
+    tile_mma<T>(t, acc, wm, wn, lane);
     __syncthreads();
   }
   if constexpr (SPLIT) {
@@ -260,7 +295,7 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
         for (int q = 0; q < 4; ++q) {
           const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
           const int n = n0 + wn * 32 + j * 16 + mcol(lane);
-          if (m < M && n < N) out[(size_t)n * M + m] = cpx<T>{cr[i][j][q], ci[i][j][q]};
+          if (m < M && n < N) out[(size_t)n * M + m] = acc.get(i, j, q);
         }
     return;
   }
@@ -274,7 +309,8 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
         const int n = n0 + wn * 32 + j * 16 + mcol(lane);
         if (m < M && n < N) {
           c128* c = C + (size_t)n * ldc + m;
-          double re = alpha * (double)cr[i][j][q], im = alpha * (double)ci[i][j][q];
+          const cpx<T> v = acc.get(i, j, q);
+          double re = alpha * (double)v.x, im = alpha * (double)v.y;
           if (beta != 0.0) {
             const c128 old = *c;
             re += beta * old.x;

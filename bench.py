@@ -69,6 +69,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per trace")
     ap.add_argument("--max-atoms", type=int, default=512, help="serve: largest request (atoms)")
     ap.add_argument("--ecut", type=float, default=30.0, help="serve: cutoff in Ry")
+    ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2],
+                    help="cell512: plane pass form (plan option plane_mode: 0 auto, 1 three kernels, "
+                         "2 the 16-lane-group kernel wherever it applies)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device to device once (reference kernel "
                          "for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -117,6 +120,8 @@ def roofline(prof, dtype):
 
 
 FFT_KERNELS = ("k_zinv", "k_plane", "k_zfwd")
+PLANE_FORMS = {0: "one kernel per plane (register or LDS form)", 1: "three kernels",
+               2: "one kernel per plane, 16-lane groups"}
 COMPLEX3_KERNELS = ("calbec_gemm", "add_nl_gemm", "zgemm_cn", "zgemm_nn")
 NL_KERNELS = ("calbec_gemm", "add_nl_gemm")
 
@@ -617,7 +622,7 @@ def bench_cell512(args):
     print(f"bench: cell generated in {t_gen:.1f} s (npw {p.npw}, grid {p.nr}, {p.nbeta} beta, {p.nb} bands)",
           file=sys.stderr, flush=True)
     ctx = pwdft.Context(0)
-    plan = pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=0)
+    plan = pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=0, plane_mode=args.plane_mode)
     info = plan.info()
     psi0 = torch.from_numpy(p.psi0).to(dev)
     y = torch.empty_like(psi0)
@@ -673,7 +678,8 @@ def bench_cell512(args):
                                f"FFT {p.nr[0]}^3, 512 atoms, {p.nbeta} beta, {p.nb} bands; one mixed-precision "
                                f"hpsi_apply per step",
                    "npw": p.npw, "fft": list(p.nr), "nbeta": p.nbeta, "nbands": p.nb, "precision": "mixed",
-                   "band_chunk": info["band_chunk"], "float64_plane_pass_three_kernels": bool(info["split_plane64"])},
+                   "band_chunk": info["band_chunk"],
+                   "plane_pass": {k: PLANE_FORMS[info[k]] for k in ("plane64", "plane32")}},
         "band_hpsi_per_s_mixed": value,
         "band_hpsi_per_s_fp64": rate64,
         "ms_per_hpsi": {"mixed": 1e3 * p.nb / value, "fp64": 1e3 * p.nb / rate64},

@@ -243,4 +243,175 @@ __device__ __forceinline__ void fwd_dif(cpx<T> (&x)[LS], int q, const QuadLane<T
   RDft<LS, T>::run(x, s);
 }
 
+// ---------------------------------------------------------------------------
+// Groups of G = 8 or 16 lanes: N = G LS, lane g (0..G-1) of a group of G
+// consecutive lanes (inside one DPP row) holds x[g + G j], j < LS.  The same
+// four-step factorization as the quad form: an LS-point DFT in each lane, the
+// twiddle W_N^(s g k), then the G-point DFT across the lanes as log2(G)
+// radix-2 stages (DPP exchanges with lanes g ^ 8, g ^ 4, g ^ 2, g ^ 1).
+// ---------------------------------------------------------------------------
+
+// value of lane g ^ 4: 7 - i within each half row (row_half_mirror), then
+// 3 - i within each quad: (g ^ 7) ^ 3 = g ^ 4
+__device__ __forceinline__ int lx4_b32(int v) {
+  const int a = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
+  return __builtin_amdgcn_mov_dpp(a, 0x1B, 0xF, 0xF, true);
+}
+// value of lane g ^ 8: 15 - i within each row (row_mirror), then 7 - i
+// within each half row: (g ^ 15) ^ 7 = g ^ 8
+__device__ __forceinline__ int lx8_b32(int v) {
+  const int a = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);
+  return __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, true);
+}
+template <int D>
+__device__ __forceinline__ int lx_b32(int v) {
+  if constexpr (D == 8) return lx8_b32(v);
+  else if constexpr (D == 4) return lx4_b32(v);
+  else return __builtin_amdgcn_mov_dpp(v, D == 1 ? 0xB1 : 0x4E, 0xF, 0xF, true);
+}
+template <int D>
+__device__ __forceinline__ float lx(float v) { return __int_as_float(lx_b32<D>(__float_as_int(v))); }
+template <int D>
+__device__ __forceinline__ double lx(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = lx_b32<D>((int)(b & 0xffffffffll));
+  const int hi = lx_b32<D>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// partner + sg * self, partner = lane g ^ D
+template <int D, typename T>
+__device__ __forceinline__ cpx<T> gbfly(cpx<T> self, T sg) {
+  const cpx<T> o{lx<D>(self.x), lx<D>(self.y)};
+  return cpx<T>{tfma(sg, self.x, o.x), tfma(sg, self.y, o.y)};
+}
+
+// per-lane constants of the cross-lane stages (for s = +1; s = -1 conjugates)
+template <typename T>
+struct GLane {
+  T sg1, sg2, sg4, sg8;   // -1 where bit 0, 1, 2, 3 of g is set, else +1
+  T w2r, w2i;             // W_4^(g mod 2) where bit 1 is set, else 1
+  T w4r, w4i;             // W_8^(g mod 4) where bit 2 is set, else 1
+  T w8r, w8i;             // W_16^(g mod 8) where bit 3 is set, else 1
+};
+
+template <typename T>
+__device__ __forceinline__ GLane<T> glane(int g) {
+  // cos(pi m / 8), m = 0..4
+  constexpr double c16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173, 0.0};
+  GLane<T> l;
+  l.sg1 = (g & 1) ? T(-1) : T(1);
+  l.sg2 = (g & 2) ? T(-1) : T(1);
+  l.sg4 = (g & 4) ? T(-1) : T(1);
+  l.sg8 = (g & 8) ? T(-1) : T(1);
+  // W_16^m = (cos(pi m / 8), sin(pi m / 8)), m < 8; sin(pi m / 8) = cos(pi (4 - m) / 8)
+  auto w16 = [&](int m, T& re, T& im) {
+    re = (T)(m <= 4 ? c16[m] : -c16[8 - m]);
+    im = (T)(m <= 4 ? c16[4 - m] : c16[m - 4]);
+  };
+  w16((g & 2) ? 4 * (g & 1) : 0, l.w2r, l.w2i);
+  w16((g & 4) ? 2 * (g & 3) : 0, l.w4r, l.w4i);
+  w16((g & 8) ? (g & 7) : 0, l.w8r, l.w8i);
+  return l;
+}
+
+// b * (wr + i s wi)
+template <typename T>
+__device__ __forceinline__ cpx<T> grot(cpx<T> b, T wr, T wi, T s) {
+  const T si = s * wi;
+  return cpx<T>{tfma(b.x, wr, -b.y * si), tfma(b.x, si, b.y * wr)};
+}
+
+// decimation in frequency across the G lanes: lane g holds b_g; returns
+// X_p = sum_g b_g W_G^(s g p) for p = the bit reversal of g (log2 G bits)
+template <int G, typename T>
+__device__ __forceinline__ cpx<T> g_dif(cpx<T> b, const GLane<T>& l, T s) {
+  if constexpr (G == 16) {
+    b = gbfly<8>(b, l.sg8);
+    b = grot(b, l.w8r, l.w8i, s);
+  }
+  b = gbfly<4>(b, l.sg4);
+  b = grot(b, l.w4r, l.w4i, s);
+  b = gbfly<2>(b, l.sg2);
+  b = grot(b, l.w2r, l.w2i, s);
+  return gbfly<1>(b, l.sg1);
+}
+
+// decimation in time across the G lanes: lane g holds y_p for p = the bit
+// reversal of g; returns Y_g = sum_p y_p W_G^(s p g)
+template <int G, typename T>
+__device__ __forceinline__ cpx<T> g_dit(cpx<T> y, const GLane<T>& l, T s) {
+  y = gbfly<1>(y, l.sg1);
+  y = grot(y, l.w2r, l.w2i, s);
+  y = gbfly<2>(y, l.sg2);
+  y = grot(y, l.w4r, l.w4i, s);
+  y = gbfly<4>(y, l.sg4);
+  if constexpr (G == 16) {
+    y = grot(y, l.w8r, l.w8i, s);
+    y = gbfly<8>(y, l.sg8);
+  }
+  return y;
+}
+
+// block index held by lane g after ginv (bit reversal of g, log2 G bits)
+template <int G>
+__device__ __forceinline__ int g_block(int g) {
+  const int r3 = ((g & 1) << 2) | (g & 2) | ((g >> 2) & 1);
+  return G == 8 ? r3 : ((r3 << 1) | ((g >> 3) & 1));
+}
+
+// Twiddles W_N^(g k), k = 1, 2, ...: float64 forms them by the recurrence
+// w_k = w_(k-1) w_1 from one table entry (rounding grows by about one unit
+// per step, far below float64 tolerances, and no table entries occupy
+// registers); float32 reads each from the table.
+template <typename T>
+struct GTw {
+  cpx<T> w1, w;
+  const cpx<T>* __restrict__ tw;
+  int g;
+  __device__ __forceinline__ GTw(const cpx<T>* __restrict__ t, int gg) : tw(t), g(gg) {
+    if constexpr (sizeof(T) == 8) { w1 = t[gg]; w = w1; }
+  }
+  __device__ __forceinline__ cpx<T> next(int k) {
+    if constexpr (sizeof(T) == 8) {
+      const cpx<T> r = w;
+      w = cmul(w, w1);
+      return r;
+    } else {
+      return tw[g * k];
+    }
+  }
+};
+
+// inverse direction (s = +1): lane g holds x[g + G j]  ->  X[k + LS p], p = g_block<G>(g).
+// tw[m] = exp(+2 pi i m / N) in global memory (g k < N)
+template <int G, int LS, typename T>
+__device__ __forceinline__ void ginv(cpx<T> (&x)[LS], int g, const GLane<T>& l, const cpx<T>* __restrict__ tw) {
+  const T s = T(1);
+  RDft<LS, T>::run(x, s);
+  GTw<T> t(tw, g);
+#pragma unroll
+  for (int k = 0; k < LS; ++k) {
+    if (k != 0) x[k] = cmul(x[k], t.next(k));
+    x[k] = g_dif<G>(x[k], l, s);
+  }
+}
+
+// forward direction (s = -1): lane g holds y[k + LS p], p = g_block<G>(g)  ->  Y[g + G m]
+template <int G, int LS, typename T>
+__device__ __forceinline__ void gfwd(cpx<T> (&x)[LS], int g, const GLane<T>& l, const cpx<T>* __restrict__ tw) {
+  const T s = T(-1);
+  GTw<T> t(tw, g);
+#pragma unroll
+  for (int k = 0; k < LS; ++k) {
+    x[k] = g_dit<G>(x[k], l, s);
+    if (k != 0) {
+      cpx<T> w = t.next(k);
+      w.y = -w.y;
+      x[k] = cmul(x[k], w);
+    }
+  }
+  RDft<LS, T>::run(x, s);
+}
+
 }  // namespace regfft

@@ -245,6 +245,123 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
 }
 
 // ---------------------------------------------------------------------------
+// pass 2, lane-group variant for n1 = n2 = G LS (G = 16 lanes per 1D
+// transform): one workgroup per (z plane, band) holds the plane's x columns
+// Y[nxr][N] in LDS with no padding -- a float64 144 x 71 plane (163,584
+// bytes) fits in the 160 KB of a CU -- and each 1D transform runs on a group
+// of G lanes in VGPRs (fft_reg.h).  The y transforms read their sticks
+// straight from HBM and write them back through the (column, y) -> stick
+// map; twiddles, the x map and V(r) come from global memory (L1/L2), so the
+// plane is the kernel's only LDS.
+// ---------------------------------------------------------------------------
+constexpr int OCT_G = 16;          // lanes per 1D transform
+constexpr int OCT_THREADS = 576;   // 36 groups: a 144^2 plane's 71 columns in two passes, its rows in four
+
+// LDS position of (x column c, y): y ^ 2 sigma(c mod 8), sigma rotating the
+// three bits of c mod 8 right, so bit 3 of the mask is bit 0 of c.  Column
+// accesses (consecutive y of one or two columns per 16 lanes) and row
+// accesses (neighbouring columns at one y) then spread over the banks.  The
+// mask stays below 16 and N is a multiple of 16: a bijection of each column.
+template <int N>
+__device__ __forceinline__ int oct_pos(int c, int y) {
+  const int sg = ((c & 1) << 2) | ((c >> 1) & 3);
+  return c * N + (y ^ (sg << 1));
+}
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(OCT_THREADS)
+k_plane_oct(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr, const cpx<T>* __restrict__ tw) {
+  constexpr int G = OCT_G;
+  constexpr int N = G * LS;
+  static_assert(N % 16 == 0, "the LDS swizzle permutes within aligned blocks of 16");
+  extern __shared__ __align__(16) char smem_raw[];
+  cpx<T>* Y = reinterpret_cast<cpx<T>*>(smem_raw);   // [nxr][N], swizzled
+  const int nxr = m.nxr;
+  const int z = blockIdx.x, band = blockIdx.y;
+  cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
+  const int g = threadIdx.x & (G - 1), grp = threadIdx.x / G, ngrp = blockDim.x / G;
+  const int pb = regfft::g_block<G>(g);   // block of the transform held after ginv
+  const regfft::GLane<T> gl = regfft::glane<T>(g);
+  // inverse y transforms: the sticks of column c -> Y[c][*]
+#pragma unroll 1
+  for (int c = grp; c < nxr; c += ngrp) {
+    const int* cs = m.cy_st + (size_t)c * N;
+    cpx<T> x[LS];
+#pragma unroll
+    for (int j = 0; j < LS; ++j) {
+      const int sidx = cs[g + G * j];
+      x[j] = sidx >= 0 ? st[sidx] : cpx<T>{T(0), T(0)};
+    }
+    regfft::ginv<G, LS, T>(x, g, gl, tw);
+#pragma unroll
+    for (int k = 0; k < LS; ++k) Y[oct_pos<N>(c, k + LS * pb)] = x[k];
+  }
+  __syncthreads();
+  // rows: inverse x, V(r), forward x; only the x columns of the sphere are
+  // read and written
+  int hx[LS];
+#pragma unroll
+  for (int j = 0; j < LS; ++j) hx[j] = m.i1_hx[g + G * j];
+#pragma unroll 1
+  for (int r = grp; r < N; r += ngrp) {
+    const T* vrow = vr + ((size_t)z * N + r) * N + LS * pb;
+    cpx<T> x[LS];
+#pragma unroll
+    for (int j = 0; j < LS; ++j) x[j] = hx[j] >= 0 ? Y[oct_pos<N>(hx[j], r)] : cpx<T>{T(0), T(0)};
+    regfft::ginv<G, LS, T>(x, g, gl, tw);
+    // keep the V(r) loads after the transform: hoisted above it they would
+    // hold LS more registers through it
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = x[k] * vrow[k];
+    regfft::gfwd<G, LS, T>(x, g, gl, tw);
+#pragma unroll
+    for (int j = 0; j < LS; ++j)
+      if (hx[j] >= 0) Y[oct_pos<N>(hx[j], r)] = x[j];
+  }
+  __syncthreads();
+  // forward y transforms: Y[c][*] -> the sticks of column c
+#pragma unroll 1
+  for (int c = grp; c < nxr; c += ngrp) {
+    cpx<T> x[LS];
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = Y[oct_pos<N>(c, k + LS * pb)];
+    regfft::gfwd<G, LS, T>(x, g, gl, tw);
+    const int* cs = m.cy_st + (size_t)c * N;
+#pragma unroll
+    for (int j = 0; j < LS; ++j) {
+      const int sidx = cs[g + G * j];
+      if (sidx >= 0) st[sidx] = x[j];
+    }
+  }
+}
+
+template <typename T>
+using PlaneOctFn = void (*)(SphereMap, cpx<T>*, const T*, const cpx<T>*);
+
+// lane-group plane kernel for n1 = n2 = 16 LS, or nullptr
+template <typename T>
+PlaneOctFn<T> plane_oct_kernel(int n1, int n2) {
+  if (n1 != n2) return nullptr;
+  switch (n1) {
+    case 80: return k_plane_oct<T, 5>;
+    case 96: return k_plane_oct<T, 6>;
+    case 128: return k_plane_oct<T, 8>;
+    case 144: return k_plane_oct<T, 9>;
+    default: return nullptr;
+  }
+}
+
+// the plane is the lane-group kernel's only LDS; a workgroup may take all 160 KB of a CU
+constexpr size_t kPlaneOctMaxLds = 160 * 1024;
+template <typename T>
+size_t plane_oct_lds_bytes(int n, int nxr) { return sizeof(cpx<T>) * (size_t)n * nxr; }
+template <typename T>
+bool plane_oct_fits(int n1, int n2, int nxr) {
+  return plane_oct_kernel<T>(n1, n2) != nullptr && plane_oct_lds_bytes<T>(n1, nxr) <= kPlaneOctMaxLds;
+}
+
+// ---------------------------------------------------------------------------
 // pass 2, three-kernel form for planes whose x columns do not fit in LDS
 // (float64 at 144^2 and above): the y transforms and the x transforms of a
 // plane run in separate kernels and meet in an HBM copy of the plane's x
@@ -410,6 +527,13 @@ int plane_reg_threads(int n, int nxr) {
   const int need = 4 * std::max(n, nxr);
   const int cap = sizeof(T) == 8 ? 256 : 512;
   return std::min(cap, (need + 63) / 64 * 64);
+}
+
+// the register (quad) plane kernel exists for this grid and its LDS fits
+template <typename T>
+bool plane_quad_fits(int n1, int n2, int nxr) {
+  if (plane_reg_kernel<T, 2>(n1, n2) != nullptr && plane_reg_lds_bytes<T>(n1, nxr, 2) <= kPlaneRegMaxLds) return true;
+  return plane_reg_kernel<T, 1>(n1, n2) != nullptr && plane_reg_lds_bytes<T>(n1, nxr, 1) <= kPlaneRegMaxLds1;
 }
 
 // ---------------------------------------------------------------------------
@@ -842,6 +966,7 @@ void twiddles(int L, std::vector<c128>& t64, std::vector<c64>& t32) {
 struct Geometry {
   int n1, n2, n3, nst, nxr, ldst, nhmax;
   bool split64, split32;   // three-kernel plane pass per precision
+  bool oct64, oct32;       // eight-lane one-kernel plane pass per precision
   bool density;            // workspace of pw_density / pw_scf_norm
   bool gamma;              // Gamma point, real wavefunctions on the half sphere
   std::vector<int> mfull;  // Miller indices of the whole sphere, [nfull][3]
@@ -942,10 +1067,19 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
     geo->nhmax = std::max(geo->nhmax, nh);
   }
   const bool mixed = o->precision == PW_MIXED;
-  PW_CHECK(o->plane_mode == 0 || o->plane_mode == 1, PW_EINVAL, "plane_mode must be 0 or 1");
+  PW_CHECK(o->plane_mode >= 0 && o->plane_mode <= 2, PW_EINVAL, "plane_mode must be 0, 1 or 2");
   PW_CHECK(o->nl_overlap >= 0 && o->nl_overlap <= 2, PW_EINVAL, "nl_overlap must be 0, 1 or 2");
-  geo->split64 = o->plane_mode == 1 || plane_batch<double>(geo->n1, geo->n2, geo->nxr) == 0;
-  geo->split32 = mixed && (o->plane_mode == 1 || plane_batch<float>(geo->n1, geo->n2, geo->nxr) == 0);
+  // plane pass form per precision: the register (quad) kernel where it
+  // exists and fits; else the eight-lane kernel where the unpadded plane fits
+  // in LDS (plane_mode 2 takes it wherever it applies); else the generic LDS
+  // kernel; else three kernels (plane_mode 1 forces those)
+  const int n1 = geo->n1, n2 = geo->n2, nxr = geo->nxr;
+  geo->oct64 = o->plane_mode != 1 && plane_oct_fits<double>(n1, n2, nxr) &&
+               (o->plane_mode == 2 || !plane_quad_fits<double>(n1, n2, nxr));
+  geo->oct32 = mixed && o->plane_mode != 1 && plane_oct_fits<float>(n1, n2, nxr) &&
+               (o->plane_mode == 2 || !plane_quad_fits<float>(n1, n2, nxr));
+  geo->split64 = o->plane_mode == 1 || (!geo->oct64 && plane_batch<double>(n1, n2, nxr) == 0);
+  geo->split32 = mixed && (o->plane_mode == 1 || (!geo->oct32 && plane_batch<float>(n1, n2, nxr) == 0));
   PW_CHECK(o->density == 0 || o->density == 1, PW_EINVAL, "density must be 0 or 1");
   geo->density = o->density == 1;
   PW_CHECK(split_lds_bytes<double>(geo->n1, geo->n2) <= 160 * 1024, PW_EINVAL, "grid too large for the plane pass");
@@ -1130,6 +1264,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   p->band_chunk = band_chunk_for(*o, geo);
   p->split64 = geo.split64;
   p->split32 = geo.split32;
+  p->oct64 = geo.oct64;
+  p->oct32 = geo.oct32;
   fft_factor(n1, p->f1);
   fft_factor(n2, p->f2);
   fft_factor(n3, p->f3);
@@ -1154,6 +1290,11 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
   PLAN_TRY(upload(p, &p->zidx, zidx));
   PLAN_TRY(upload(p, &p->col_ptr, col_ptr));
+  if (geo.oct64 || geo.oct32) {
+    std::vector<int> cy_st((size_t)nxr * n2, -1);
+    for (size_t s2 = 0; s2 < st_hx.size(); ++s2) cy_st[(size_t)st_hx[s2] * n2 + st_i2[s2]] = (int)s2;
+    PLAN_TRY(upload(p, &p->cy_st, cy_st));
+  }
   p->gamma = geo.gamma;
   p->nfull = nfull;
   if (geo.gamma) {
@@ -1280,8 +1421,8 @@ extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
   out[3] = p->N;
   out[4] = p->nbeta;
   out[5] = p->band_chunk;
-  out[6] = p->split64 ? 1 : 0;
-  out[7] = p->split32 ? 1 : 0;
+  out[6] = p->split64 ? 1 : (p->oct64 ? 2 : 0);
+  out[7] = p->split32 ? 1 : (p->oct32 ? 2 : 0);
   return PW_OK;
 }
 
@@ -1297,15 +1438,16 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const T* vr = f64 ? (const T*)p->vr64 : (const T*)p->vr32;
   PW_CHECK(vr != nullptr, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
   const bool split = f64 ? p->split64 : p->split32;
+  const bool oct = f64 ? p->oct64 : p->oct32;
   const int cb = plane_batch<T>(p->n1, p->n2, p->nxr);
-  PW_CHECK(cb > 0 || split, PW_EINVAL, "grid too large for this precision's plane pass");
+  PW_CHECK(cb > 0 || split || oct, PW_EINVAL, "grid too large for this precision's plane pass");
   const size_t zl = z_lds_bytes<T>(p->n3);
   const size_t pl = split ? split_lds_bytes<T>(p->n1, p->n2) : plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
   // two z planes per workgroup where their LDS fits (the last passes over
   // columns and rows are fuller), else one
   PlaneRegFn<T> preg = nullptr;
   int ppw = 0;
-  if (p->use_reg_plane && !split) {
+  if (p->use_reg_plane && !split && !oct) {
     if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 2) <= kPlaneRegMaxLds) {
       preg = plane_reg_kernel<T, 2>(p->n1, p->n2);
       ppw = 2;
@@ -1318,6 +1460,10 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   }
   const size_t plds = preg ? plane_reg_lds_bytes<T>(p->n1, p->nxr, ppw) : 0;
   if (preg && plds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)preg, (int)plds));
+  const PlaneOctFn<T> poct = oct ? plane_oct_kernel<T>(p->n1, p->n2) : nullptr;
+  const size_t olds = oct ? plane_oct_lds_bytes<T>(p->n1, p->nxr) : 0;
+  PW_CHECK(!oct || poct != nullptr, PW_EINVAL, "no eight-lane plane kernel for this grid");
+  if (poct && olds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)poct, (int)olds));
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
   const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
@@ -1349,7 +1495,9 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     }
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
-      if (split) {
+      if (oct) {
+        poct<<<dim3(p->n3, nbc), OCT_THREADS, olds, s>>>(m, st, vr, tw1);
+      } else if (split) {
         cpx<T>* rows = static_cast<cpx<T>*>(p->rows);
         k_plane_yinv<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, st, rows, tw2);
         k_plane_x<T><<<dim3(p->n3, nbc, ceil_div(p->n2, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, rows, vr, tw1);
@@ -1470,6 +1618,9 @@ bool nl_beside(pw_plan p, bool f64) {
   if (p->opts.nl_overlap == 1) return true;
   if (p->opts.nl_overlap == 2) return false;
   if (f64 ? p->split64 : p->split32) return false;
+  // an eight-lane plane workgroup holds more than 64 KB of LDS
+  if (f64 ? p->oct64 : p->oct32)
+    return (f64 ? plane_oct_lds_bytes<double>(p->n1, p->nxr) : plane_oct_lds_bytes<float>(p->n1, p->nxr)) <= 64 * 1024;
   const size_t one = f64 ? plane_reg_lds_bytes<double>(p->n1, p->nxr, 1) : plane_reg_lds_bytes<float>(p->n1, p->nxr, 1);
   const bool reg = p->use_reg_plane && p->n1 == p->n2 && p->n1 % 4 == 0 &&
                    (f64 ? plane_reg_kernel<double, 1>(p->n1, p->n2) != nullptr

@@ -29,6 +29,7 @@ struct SphereMap {
   const int* i1_hx;    // [n1]      x-column index at x grid index i1, or -1
   const int* zidx;     // [n3][nst] sphere index of (z, stick), or -1
   const int* col_ptr;  // [nxr+1]   first stick of each x column (sticks are column-major)
+  const int* cy_st;    // [nxr][n2] stick at (x column, y grid index), or -1 (eight-lane plane pass)
   const double* kin;   // [npw]     |k+G|^2 / 2
   FftDesc f1, f2, f3;  // transforms along x, y, z
 };
@@ -51,6 +52,7 @@ struct pw_plan_s {
   int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
   bool use_reg_plane = true;  // register-resident plane pass where the grid allows
   bool split64 = false, split32 = false;  // three-kernel plane pass (float64 / float32)
+  bool oct64 = false, oct32 = false;      // eight-lane one-kernel plane pass (float64 / float32)
   bool gamma = false;       // Gamma point: bands are real functions stored on the half sphere (npw
                             // entries, G = 0 first); the transforms cover the whole sphere (nfull)
   int nfull = 0;
@@ -58,7 +60,7 @@ struct pw_plan_s {
 
   // maps (device)
   int *st_ptr = nullptr, *ent_g = nullptr, *ent_z = nullptr, *ent_s = nullptr, *st_hx = nullptr,
-      *st_i2 = nullptr, *i1_hx = nullptr, *zidx = nullptr, *col_ptr = nullptr;
+      *st_i2 = nullptr, *i1_hx = nullptr, *zidx = nullptr, *col_ptr = nullptr, *cy_st = nullptr;
   double* kin = nullptr;     // [npw]
   double* hdiag = nullptr;   // [npw] exact diagonal of H
   FftDesc f1{}, f2{}, f3{};
@@ -104,6 +106,7 @@ struct pw_plan_s {
     m.nst = nst; m.nxr = nxr; m.ldst = ldst;
     m.st_ptr = st_ptr; m.ent_g = ent_g; m.ent_z = ent_z; m.ent_s = ent_s;
     m.st_hx = st_hx; m.st_i2 = st_i2; m.i1_hx = i1_hx; m.zidx = zidx; m.col_ptr = col_ptr; m.kin = kin;
+    m.cy_st = cy_st;
     m.f1 = f1; m.f2 = f2; m.f3 = f3;
     return m;
   }

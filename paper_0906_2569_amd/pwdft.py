@@ -345,8 +345,12 @@ class Plan:
     def info(self):
         out = (C.c_int64 * 8)()
         _check(self.lib.pw_plan_info(self.h, out))
-        keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "split_plane64", "split_plane32"]
-        return dict(zip(keys, list(out)))
+        keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "plane64", "plane32"]
+        d = dict(zip(keys, list(out)))
+        # plane pass form: 0 one kernel, 1 three kernels, 2 eight-lane one kernel
+        d["split_plane64"] = int(d["plane64"] == 1)
+        d["split_plane32"] = int(d["plane32"] == 1)
+        return d
 
     def hpsi(self, psi, out=None, prec=PW_FP64, stream=None):
         """out = H psi for psi [nb][>=npw] complex128 on the device."""

@@ -295,18 +295,43 @@ def test_band_chunks(ctx, prec, plane_mode):
     assert _rel_err(got, oracle.hpsi(h, p.psi0)) <= (1e-11 if prec == 0 else 2e-6)
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_config5_largest_cell_sampled_rows(ctx, prec):
+@pytest.mark.parametrize("prec,plane_mode", [(0, 0), (1, 0), (0, 1), (1, 2)])
+def test_config5_largest_cell_sampled_rows(ctx, prec, plane_mode):
     # the largest served cell (a = 41 bohr, 30 Ry, npw 191471, 144^3, 512 atoms,
-    # 2048 projectors) with 16 bands: float64 takes the three-kernel plane
-    # pass, float32 the one-plane register pass; rows of the dense H from the oracle
+    # 2048 projectors) with 16 bands.  By default float64 takes the lane-group
+    # plane kernel (its unpadded 144 x 71 plane fills the 160 KB of LDS) and
+    # float32 the one-plane register kernel; plane_mode 1 forces three kernels,
+    # 2 the lane-group kernel for float32 too.  Rows of the dense H from the oracle.
     p = pwgen.config5_largest(nb=16)
     info = {}
-    got = _hpsi(ctx, p, p.psi0, prec=prec, info=info)
-    assert info["split_plane64"] == 1 and info["split_plane32"] == 0
+    got = _hpsi(ctx, p, p.psi0, prec=prec, plane_mode=plane_mode, info=info)
+    expect64 = {0: 2, 1: 1, 2: 2}[plane_mode]
+    expect32 = {0: 0, 1: 1, 2: 2}[plane_mode] if prec == 1 else 0
+    assert (info["plane64"], info["plane32"]) == (expect64, expect32)
     rng = np.random.default_rng(5)
     rows = np.sort(rng.choice(p.npw, 64, replace=False))
     ref = oracle.hpsi_rows_of(p, p.psi0, rows)
     err = _sampled_rel_err(got[:, rows], ref)
     print("config-5 cell, precision", prec, "max per-band relative error on 64 rows", err)
     assert err <= (1e-11 if prec == 0 else 2e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,n3,ecut,kfrac", [
+    (80, 32, 10.0, (0.25, -0.25, 0.0)),
+    (96, 30, 12.0, (0, 0, 0)),
+    (128, 27, 9.0, (0.1, 0.2, -0.3)),
+    (144, 32, 14.0, (0.25, 0.0, 0.5)),
+])
+def test_lane_group_plane_pass(ctx, prec, n, n3, ecut, kfrac):
+    # plane_mode 2: the plane pass of every precision on the lane-group kernel
+    # (16 lanes per 1D transform, unpadded swizzled plane in LDS) for the
+    # n1 = n2 = 16 LS grids it covers; odd and even numbers of z planes
+    p = pwgen.tiny_cell(300 + n, a=8.0, ecut_ry=ecut, natoms=2, nb=5, kfrac=kfrac, nr=(n, n, n3))
+    assert max(pwgen.min_grid(p.miller)) <= n3
+    info = {}
+    got = _hpsi(ctx, p, p.psi0, prec=prec, plane_mode=2, info=info)
+    assert info["plane64"] == 2 and info["plane32"] == (2 if prec == 1 else 0)
+    ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
+    err = _rel_err(got, ref)
+    assert err <= (1e-11 if prec == 0 else 2e-6), err

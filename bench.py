@@ -101,9 +101,9 @@ def roofline(prof, dtype):
         peak = FP32_MFMA_PEAK_TF if dtype == "f32" else FP64_PEAK_TF
         achieved = per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
         out = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
-        if dtype == "f32" and name in COMPLEX3_KERNELS:
-            # the conventional complex count is 8 M N K; the float32 complex
-            # GEMMs run Gauss's three-product form, 6 M N K on the matrix cores
+        if name in COMPLEX3_KERNELS:
+            # the conventional complex count is 8 M N K; the complex GEMMs run
+            # Gauss's three-product form, 6 M N K on the matrix cores
             out["flops_counted_as"] = "8 M N K (conventional complex GEMM count)"
             out["mfma_flops_per_launch"] = 0.75 * per_launch
             out["mfma_pipe_frac"] = 0.75 * achieved / peak

@@ -3,16 +3,16 @@
 // (<beta|psi>, then sum_j beta_j (D <beta|psi>)_j) and for the Davidson
 // subspace products (phi^H H phi, phi^H phi, Ritz rotations).
 //
-// Complex float64 products use four real MFMAs per 16x16x4 block:
-//   Re C += Re A Re B - Im A Im B,   Im C += Re A Im B + Im A Re B.
-// Complex float32 products use three (Gauss's product, as in the 3M complex
-// GEMMs): t1 += Re A Re B, t2 += Im A Im B, t3 += (Re A + Im A)(Re B + Im B),
-// and at the end Re C = t1 - t2, Im C = t3 - t1 - t2.  That is 6 M N K real
-// flops on the matrix cores instead of 8; the error bound of the imaginary
-// part grows from about K u (|Re A||Im B| + |Im A||Re B|) to about
-// K u (|Re A| + |Im A|)(|Re B| + |Im B|) (u the float32 unit roundoff),
-// which the float32 stage of the precision ladder absorbs.  Im A is negated
-// once, at the LDS store, when A enters conjugated.
+// Complex products use three real MFMAs per 16x16x4 block (Gauss's product,
+// as in the 3M complex GEMMs): t1 += Re A Re B, t2 += Im A Im B,
+// t3 += (Re A + Im A)(Re B + Im B), and at the end Re C = t1 - t2,
+// Im C = t3 - t1 - t2.  That is 6 M N K real flops on the matrix cores
+// instead of the 8 of the four-product form.  The error bound of the
+// imaginary part grows from about K u (|Re A||Im B| + |Im A||Re B|) to about
+// K u (|Re A| + |Im A|)(|Re B| + |Im B|) (u the unit roundoff of the
+// precision), a small constant factor on the same order.  Im A is negated
+// once, at the LDS store, when A enters conjugated.  The four-product form
+// is kept (kGauss = false) for comparison.
 //
 // Two shapes:
 //   cn : C[m, n] = sum_k conj(A[k, m]) B[k, n]; A and B are stored as
@@ -58,10 +58,15 @@ template <>
 __device__ __forceinline__ int mrow<double>(int lane, int q) { return 4 * q + (lane >> 4); }
 __device__ __forceinline__ int mcol(int lane) { return lane & 15; }
 
-// The GEMM kernels are built for at least three waves per SIMD (at most 168
-// registers, spill-free): three 64x64 tiles then share a CU, and a product
-// of 18277 x 128 rows and columns (572 tiles) is resident in one round.
+// The float32 GEMM kernels are built for at least three waves per SIMD (at
+// most 168 registers, spill-free): three 64x64 tiles then share a CU, and a
+// product of 18277 x 128 rows and columns (572 tiles) is resident in one
+// round.  The float64 ones hold three float64 accumulator sets (96
+// registers) and are built for two waves per SIMD, each MFMA there taking
+// twice as many cycles.
 constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+template <typename T>
+struct GemmWaves { static constexpr int value = sizeof(T) == 8 ? 2 : 3; };
 
 // Workgroups go to the 8 XCDs round-robin in linear launch order.  Each XCD is
 // given one contiguous range of a work order in which tile y (YFAST) or tile x
@@ -90,13 +95,15 @@ struct Tile {
   T ar[BK][BM + 1], ai[BK][BM + 1], br[BK][BN + 1], bi[BK][BN + 1];
 };
 
-// Accumulators of one wave's 32x32 quadrant (2x2 blocks of 16x16): for
-// float64, a = Re C and b = Im C; for float32, a = t1, b = t2, c = t3 of the
-// three-product form.
+// Accumulators of one wave's 32x32 quadrant (2x2 blocks of 16x16): a = t1,
+// b = t2, c = t3 of the three-product form (a = Re C, b = Im C in the
+// four-product form).
+constexpr bool kGauss = true;
+
 template <typename T>
 struct CAcc {
   typedef typename Mma<T>::v4 v4;
-  static constexpr bool k3 = sizeof(T) == 4;
+  static constexpr bool k3 = kGauss;
   v4 a[2][2], b[2][2], c[2][2];
   __device__ __forceinline__ void zero() {
 #pragma unroll
@@ -160,7 +167,7 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, CAcc<T>& acc, int wm,
 // gridDim.z = 2 nsplit for two products of one launch: z >= nsplit takes B1
 // and writes the partials after those of the first product
 template <typename T, typename TA, typename TB>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value)))
 k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict__ A, int lda,
           const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
   __shared__ Tile<T> t;
@@ -226,7 +233,7 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
 // SPLIT: the z index is instead the K chunk [z kchunk, (z + 1) kchunk) of the one
 // product (A0), whose partial tile goes to P[z][n][m] unscaled, for k_reduce.
 template <typename T, typename TA, typename TB, bool SPLIT = false>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value)))
 k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, const cpx<TA>* __restrict__ A1,
           int lda, const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C0,
           c128* __restrict__ C1, int ldc, const int* __restrict__ guard, int kchunk = 0,

@@ -72,6 +72,9 @@ def parse():
     ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2],
                     help="cell512: plane pass form (plan option plane_mode: 0 auto, 1 three kernels, "
                          "2 the 16-lane-group kernel wherever it applies)")
+    ap.add_argument("--nl-overlap", type=int, default=0, choices=[0, 1, 2],
+                    help="cell512: projector GEMMs beside the transforms (plan option nl_overlap: 0 auto, "
+                         "1 always beside, 2 always after)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device to device once (reference kernel "
                          "for the FETCH_SIZE / WRITE_SIZE counter scale)")
@@ -381,11 +384,14 @@ def bench_serve(args):
             x = torch.from_numpy(p.psi0).to(dev)
             subs.append(srv.submit(p, x, opts=opts))
         res = [srv.wait(t) for t, _, _ in subs]
+        pools.append(srv.info())
         srv.close()
         lat = [r[2][2] - r[2][0] for r in res]
         t_end = max(r[2][2] for r in res) - start
         ok = sum(r[0] == 0 for r in res)
         return lat, t_end, ok, res
+
+    pools = []
 
     def poisson(rate, seed):
         rng = np.random.default_rng(seed)
@@ -423,6 +429,9 @@ def bench_serve(args):
         "capacity_solves_per_s": capacity,
         "burst_latency_s": {"p50": percentile(lat_b, 50), "p99": percentile(lat_b, 99)},
         "atoms": {"min": min(nat), "median": int(np.median(nat)), "max": max(nat)},
+        "memory_pool": {"pool_bytes": pools[-1]["pool_bytes"], "peak_use": max(q["pool_peak"] for q in pools),
+                        "allocations_outside_pool": sum(q["pool_fallbacks"] for q in pools),
+                        "requests_served": sum(q["served"] for q in pools)},
         "input_generation_s": t_gen,
     }
     print(json.dumps(line), flush=True)
@@ -622,7 +631,8 @@ def bench_cell512(args):
     print(f"bench: cell generated in {t_gen:.1f} s (npw {p.npw}, grid {p.nr}, {p.nbeta} beta, {p.nb} bands)",
           file=sys.stderr, flush=True)
     ctx = pwdft.Context(0)
-    plan = pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=0, plane_mode=args.plane_mode)
+    plan = pwdft.Plan(ctx, p, precision=pwdft.PW_MIXED, nb_max=p.nb, ndim_max=0, plane_mode=args.plane_mode,
+                      nl_overlap=args.nl_overlap)
     info = plan.info()
     psi0 = torch.from_numpy(p.psi0).to(dev)
     y = torch.empty_like(psi0)

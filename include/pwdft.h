@@ -346,7 +346,9 @@ pw_status davidson_solve_batched(pw_ctx ctx, int32_t n, const pw_plan* plans, co
  * to the running ones; each runs pw_plan_create, davidson_solve on the
  * worker's stream and pw_plan_destroy.
  *   pw_server_create: opts may be NULL (4 workers, mem_budget 0 = 60% of the
- *     free device memory, PW_MIXED plans).
+ *     free device memory, PW_MIXED plans).  Allocates the whole budget at once
+ *     as the pool the served plans take their memory from (PW_ENOMEM when
+ *     that allocation fails); it is freed by pw_server_destroy.
  *   pw_server_submit: enqueue one request and return its ticket at once.
  *     The problem's arrays (host and device) and psi [dev, in/out], eig and
  *     resid [dev] must stay valid until the request completes, and their
@@ -381,6 +383,12 @@ pw_status pw_server_wait(pw_server server, int64_t ticket, pw_david_stats* stats
 pw_status pw_server_poll(pw_server server, int64_t ticket, int32_t* done);
 pw_status pw_server_cancel(pw_server server, int64_t ticket);
 double    pw_server_clock(pw_server server);
+/* Serving-loop counters: out[0] = requests whose plan was built, out[1] = bytes
+   of the device memory pool (allocated once at pw_server_create: the admission
+   budget), out[2] = largest pool use seen when a plan completed, out[3] =
+   allocations that did not fit a free range of the pool and fell back to
+   hipMalloc / hipHostMalloc (0 in a steady state).  Errors: PW_EINVAL. */
+pw_status pw_server_info(pw_server server, int64_t out[4]);
 pw_status pw_server_destroy(pw_server server);
 
 /*

@@ -357,11 +357,7 @@ pw_status pw::dav_alloc(pw_plan p) {
   W->nbasis = W->nbmax * W->ndim;
   W->ld = (p->npw + 15) / 16 * 16;
   auto get = [&](size_t bytes, void** out) -> pw_status {
-    *out = nullptr;
-    if (hipMalloc(out, std::max<size_t>(bytes, 256)) != hipSuccess) {
-      (void)hipGetLastError();
-      return pw::fail(PW_ENOMEM, "hipMalloc failed for the Davidson workspace");
-    }
+    PW_TRY(pw::dev_alloc(p, std::max<size_t>(bytes, 256), out));
     W->allocs.push_back(*out);
     return PW_OK;
   };
@@ -393,10 +389,7 @@ pw_status pw::dav_alloc(pw_plan p) {
   PW_TRY(get(pw::heig_work_bytes((int)nbx), &hwb));
   PW_TRY(pw::heig_setup(W->hw, hwb, (int)nbx));
   void* hf = nullptr;
-  if (hipHostMalloc(&hf, sizeof(DavFlags), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    return pw::fail(PW_ENOMEM, "hipHostMalloc failed");
-  }
+  PW_TRY(pw::host_alloc(p, sizeof(DavFlags), &hf));
   W->hflags = static_cast<DavFlags*>(hf);
   return PW_OK;
 }
@@ -414,8 +407,8 @@ bool pw::dav_get_coop(pw_plan p) { return p && p->dav && p->dav->hw.coop_ok; }
 void pw::dav_free(pw_plan p) {
   DavWork* W = p->dav;
   if (!W) return;
-  for (void* q : W->allocs) (void)hipFree(q);
-  if (W->hflags) (void)hipHostFree(W->hflags);
+  for (void* q : W->allocs) pw::dev_free(p, q);
+  pw::host_free(p, W->hflags);
   delete W;
   p->dav = nullptr;
 }

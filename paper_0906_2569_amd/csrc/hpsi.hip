@@ -935,11 +935,7 @@ pw_status dalloc(pw_plan p, X** ptr, size_t count) {
   *ptr = nullptr;
   if (count == 0) return PW_OK;
   void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(X));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return pw::fail(PW_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(X)) + " bytes failed");
-  }
+  PW_TRY(pw::dev_alloc(p, count * sizeof(X), &q));
   p->allocs.push_back(q);
   *ptr = static_cast<X*>(q);
   return PW_OK;
@@ -948,7 +944,14 @@ pw_status dalloc(pw_plan p, X** ptr, size_t count) {
 template <typename X>
 pw_status upload(pw_plan p, X** ptr, const std::vector<X>& v) {
   PW_TRY(dalloc(p, ptr, v.size()));
-  if (!v.empty()) PW_HIP(hipMemcpy(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+  if (v.empty()) return PW_OK;
+  if (p->pool) {
+    // on the plan's set-up stream only (a served plan never waits on the device)
+    PW_HIP(hipMemcpyAsync(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice, p->init_stream));
+    PW_HIP(hipStreamSynchronize(p->init_stream));
+  } else {
+    PW_HIP(hipMemcpy(*ptr, v.data(), v.size() * sizeof(X), hipMemcpyHostToDevice));
+  }
   return PW_OK;
 }
 
@@ -1120,6 +1123,11 @@ extern "C" size_t pw_footprint_bytes(const pw_problem* pr, const pw_plan_opts* o
 
 extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* o,
                                     pw_plan* out) {
+  return pw::plan_create(ctx, pr, o, nullptr, nullptr, out);
+}
+
+pw_status pw::plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* o, MemPool* pool,
+                          hipStream_t stream, pw_plan* out) {
   PW_CHECK(ctx != nullptr && out != nullptr, PW_EINVAL, "NULL context or output");
   *out = nullptr;
   Geometry geo;
@@ -1248,6 +1256,8 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   }
 
   pw_plan p = new pw_plan_s();
+  p->pool = pool;
+  p->init_stream = stream;
   p->ctx = ctx;
   p->device = ctx->device;
   p->opts = *o;
@@ -1317,12 +1327,13 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   }
   // V(r): copy, mean for the preconditioner diagonal, float32 copy
   PLAN_TRY(dalloc(p, &p->vr64, (size_t)p->N));
-  if (hipMemcpy(p->vr64, pr->vloc_r, sizeof(double) * p->N, hipMemcpyDeviceToDevice) != hipSuccess)
+  if (hipMemcpyAsync(p->vr64, pr->vloc_r, sizeof(double) * p->N, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "copy of vloc_r failed (is it a device pointer?)"));
   double v0 = 0.0;
   {
     std::vector<double> hv(p->N);
-    if (hipMemcpy(hv.data(), p->vr64, sizeof(double) * p->N, hipMemcpyDeviceToHost) != hipSuccess)
+    if (hipMemcpyAsync(hv.data(), p->vr64, sizeof(double) * p->N, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
       return fail_cleanup(pw::fail(PW_EDEVICE, "readback of vloc_r failed"));
     long double acc = 0.0L;
     for (long i = 0; i < p->N; ++i) {
@@ -1333,18 +1344,19 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
   }
   if (mixed) {
     PLAN_TRY(dalloc(p, &p->vr32, (size_t)p->N));
-    k_f64_to_f32<<<1024, 256>>>(p->vr64, p->vr32, (size_t)p->N);
+    k_f64_to_f32<<<1024, 256, 0, stream>>>(p->vr64, p->vr32, (size_t)p->N);
   }
   // beta, D
   if (p->nbeta > 0) {
     PLAN_TRY(dalloc(p, &p->beta64, (size_t)p->nbeta * p->ldb));
-    if (hipMemset(p->beta64, 0, sizeof(c128) * (size_t)p->nbeta * p->ldb) != hipSuccess ||
-        hipMemcpy2D(p->beta64, sizeof(c128) * p->ldb, pr->beta, sizeof(c128) * pr->ld_beta,
-                    sizeof(c128) * npw, p->nbeta, hipMemcpyDeviceToDevice) != hipSuccess)
+    if (hipMemsetAsync(p->beta64, 0, sizeof(c128) * (size_t)p->nbeta * p->ldb, stream) != hipSuccess ||
+        hipMemcpy2DAsync(p->beta64, sizeof(c128) * p->ldb, pr->beta, sizeof(c128) * pr->ld_beta,
+                         sizeof(c128) * npw, p->nbeta, hipMemcpyDeviceToDevice, stream) != hipSuccess)
       return fail_cleanup(pw::fail(PW_EDEVICE, "copy of beta failed (is it a device pointer?)"));
     if (mixed) {
       PLAN_TRY(dalloc(p, &p->beta32, (size_t)p->nbeta * p->ldb));
-      k_f64_to_f32<<<1024, 256>>>((const double*)p->beta64, (float*)p->beta32, 2 * (size_t)p->nbeta * p->ldb);
+      k_f64_to_f32<<<1024, 256, 0, stream>>>((const double*)p->beta64, (float*)p->beta32,
+                                             2 * (size_t)p->nbeta * p->ldb);
     }
     PLAN_TRY(upload(p, &p->dstart, dstart));
     PLAN_TRY(upload(p, &p->dlen, dlen));
@@ -1354,7 +1366,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
     PLAN_TRY(upload(p, &p->drow32, d32));
   }
   PLAN_TRY(dalloc(p, &p->hdiag, (size_t)npw));
-  k_hdiag<<<ceil_div(npw, 256), 256>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen,
+  k_hdiag<<<ceil_div(npw, 256), 256, 0, stream>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen,
                                        p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
   if (us) {
     p->us = true;
@@ -1364,7 +1376,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
     PLAN_TRY(upload(p, &p->qrow32, q32));
     PLAN_TRY(dalloc(p, &p->sdiag, (size_t)npw));
     // diagonal of S: 1 + sum beta_i q_ij conj(beta_j)
-    k_hdiag<<<ceil_div(npw, 256), 256>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen, p->qrow64,
+    k_hdiag<<<ceil_div(npw, 256), 256, 0, stream>>>(npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen, p->qrow64,
                                          std::max(p->nhmax, 1), nullptr, 1.0, p->sdiag);
   }
   // workspace
@@ -1390,7 +1402,7 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
     PLAN_TRY(pw::dav_alloc(p));
     PLAN_TRY(pw::cg_alloc(p));
   }
-  if (hipDeviceSynchronize() != hipSuccess)
+  if ((pool ? hipStreamSynchronize(stream) : hipDeviceSynchronize()) != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "plan initialisation kernels failed"));
 #undef PLAN_TRY
   *out = p;
@@ -1398,19 +1410,30 @@ extern "C" pw_status pw_plan_create(pw_ctx ctx, const pw_problem* pr, const pw_p
 }
 
 extern "C" pw_status pw_plan_destroy(pw_plan p) {
-  if (!p) return PW_OK;
+  pw::plan_destroy(p);
+  return PW_OK;
+}
+
+// A pooled (served) plan waits only for its own streams: the caller has
+// synchronized the stream its solve ran on, and the memory goes back to the
+// pool.  Any other plan waits for the device, then frees its memory.
+void pw::plan_destroy(pw_plan p) {
+  if (!p) return;
   (void)hipSetDevice(p->device);
-  (void)hipDeviceSynchronize();
+  if (p->pool) {
+    if (p->side) (void)hipStreamSynchronize(p->side);
+    (void)hipStreamSynchronize(p->init_stream);
+  } else {
+    (void)hipDeviceSynchronize();
+  }
   pw::dav_free(p);
   pw::cg_free(p);
-  for (void* q : p->allocs)
-    if (q) (void)hipFree(q);
+  for (void* q : p->allocs) pw::dev_free(p, q);
   if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
   if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   if (p->side) (void)hipStreamDestroy(p->side);
   delete p;
   (void)hipGetLastError();   // leave no error of the teardown behind for other HIP users
-  return PW_OK;
 }
 
 extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {

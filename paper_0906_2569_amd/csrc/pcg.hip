@@ -219,11 +219,7 @@ pw_status pw::cg_alloc(pw_plan p) {
   p->cg = W;
   W->ld = (p->npw + 15) / 16 * 16;
   auto get = [&](size_t bytes, void** out) -> pw_status {
-    *out = nullptr;
-    if (hipMalloc(out, std::max<size_t>(bytes, 256)) != hipSuccess) {
-      (void)hipGetLastError();
-      return pw::fail(PW_ENOMEM, "hipMalloc failed for the conjugate-gradient workspace");
-    }
+    PW_TRY(pw::dev_alloc(p, std::max<size_t>(bytes, 256), out));
     W->allocs.push_back(*out);
     return PW_OK;
   };
@@ -234,10 +230,7 @@ pw_status pw::cg_alloc(pw_plan p) {
   W->part_bytes = pw::splitk_part_bytes(p->opts.nb_max, 1, p->npw, sizeof(c128));
   PW_TRY(get(W->part_bytes, &W->part));
   void* h = nullptr;
-  if (hipHostMalloc(&h, sizeof(CgScalars), hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
-    return pw::fail(PW_ENOMEM, "hipHostMalloc failed");
-  }
+  PW_TRY(pw::host_alloc(p, sizeof(CgScalars), &h));
   W->hsc = static_cast<CgScalars*>(h);
   return PW_OK;
 }
@@ -245,8 +238,8 @@ pw_status pw::cg_alloc(pw_plan p) {
 void pw::cg_free(pw_plan p) {
   CgWork* W = p->cg;
   if (!W) return;
-  for (void* q : W->allocs) (void)hipFree(q);
-  if (W->hsc) (void)hipHostFree(W->hsc);
+  for (void* q : W->allocs) pw::dev_free(p, q);
+  pw::host_free(p, W->hsc);
   delete W;
   p->cg = nullptr;
 }

@@ -1,6 +1,7 @@
 // Internal plan / context layout shared by the library's translation units.
 #pragma once
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -39,6 +40,37 @@ struct CgWork;   // conjugate-gradient workspace (pcg.hip)
 
 // partial sums of pw_scf_norm (one per workgroup of its last transform pass, plus the total)
 constexpr int kDensityPart = 16384;
+
+namespace pw {
+// First-fit sub-allocator over one block (device memory from hipMalloc, or
+// pinned host memory from hipHostMalloc) in 256-byte granules; neighbouring
+// free ranges merge on release.  Thread-safe.  The serving loop gives every
+// plan it builds one of these, so that requests neither call hipMalloc nor
+// hipFree (both of which synchronize with work on other streams).
+class Arena {
+ public:
+  pw_status init(size_t bytes, bool host);
+  void release();
+  void* alloc(size_t bytes);        // nullptr when no free range is large enough
+  bool free(void* p);               // false when p is not a live block of this arena
+  size_t size() const { return size_; }
+  size_t used() const;
+  ~Arena() { release(); }
+
+ private:
+  mutable std::mutex mu_;
+  char* base_ = nullptr;
+  size_t size_ = 0;
+  bool host_ = false;
+  std::map<size_t, size_t> free_;   // offset -> length
+  std::map<size_t, size_t> used_;   // offset -> length
+};
+
+struct MemPool {
+  Arena dev, host;
+  std::atomic<long> fallbacks{0};   // allocations that fell back to hipMalloc / hipHostMalloc
+};
+}  // namespace pw
 
 struct pw_plan_s {
   pw_ctx ctx = nullptr;
@@ -97,6 +129,8 @@ struct pw_plan_s {
   CgWork* cg = nullptr;
   std::atomic<int> cancel{0};   // set by pw_cancel; read once per iteration by the running solve
   std::vector<void*> allocs;
+  pw::MemPool* pool = nullptr;         // device / pinned host memory of a served plan (else hipMalloc)
+  hipStream_t init_stream = nullptr;   // stream of the set-up work of a pooled plan
   hipStream_t side = nullptr;          // projector term runs here, beside the transforms
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
@@ -113,6 +147,19 @@ struct pw_plan_s {
 };
 
 namespace pw {
+// Device and pinned host allocations of a plan and its workspaces: from the
+// plan's pool when it has one (falling back to hipMalloc / hipHostMalloc when
+// the pool has no free range large enough), else hipMalloc / hipHostMalloc.
+pw_status dev_alloc(pw_plan p, size_t bytes, void** out);
+void dev_free(pw_plan p, void* q);
+pw_status host_alloc(pw_plan p, size_t bytes, void** out);
+void host_free(pw_plan p, void* q);
+// pw_plan_create / pw_plan_destroy with a pool: the set-up work runs on
+// `stream` and only that stream is synchronized (not the device)
+pw_status plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* o, MemPool* pool,
+                      hipStream_t stream, pw_plan* out);
+void plan_destroy(pw_plan p);
+
 // sphere -> sticks -> rows for nb <= band_chunk bands in float64: inverse z
 // and inverse y transforms into p->rows ([band][z][y][x column])
 pw_status psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStream_t stream);

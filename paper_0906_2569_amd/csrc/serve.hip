@@ -5,6 +5,10 @@
 // next to the requests already running (continuous batching: no waiting for
 // a batch to fill, no head request overtaken).  The worker builds the plan,
 // runs davidson_solve, frees the plan and records the request's times.
+// Plans take their device and pinned host memory from one pool that the
+// server allocates once (the admission budget), and their set-up and
+// teardown synchronize only the worker's own streams: a request never calls
+// hipMalloc / hipFree nor waits on another request's work.
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -23,6 +27,9 @@ struct pw_server_s {
   std::mutex mu;
   std::condition_variable cv_work, cv_done, cv_coop;
   int coop_units = 0;   // cooperative workgroups reserved by running requests
+  pw::MemPool pool;     // device memory (the budget) and pinned host memory of the plans
+  int64_t served = 0;   // requests whose plan was built
+  size_t pool_peak = 0; // largest pool use seen at a plan's completion
   struct Req {
     int64_t id;
     pw_problem prob;
@@ -68,7 +75,7 @@ struct pw_server_s {
       }
       pw_plan_opts po{opts.precision, r->nb, r->dopts.ndim};
       pw_plan plan = nullptr;
-      pw_status st = pw_plan_create(ctx, &r->prob, &po, &plan);
+      pw_status st = pw::plan_create(ctx, &r->prob, &po, &pool, streams[w], &plan);
       if (st == PW_OK) {
         // Cooperative reduced-eigensolver kernels need every workgroup of a
         // launch resident at once.  The request reserves the workgroups of its
@@ -105,7 +112,12 @@ struct pw_server_s {
           }
           cv_coop.notify_all();
         }
-        (void)pw_plan_destroy(plan);
+        {
+          std::lock_guard<std::mutex> l(mu);
+          ++served;
+          pool_peak = std::max(pool_peak, pool.dev.used());
+        }
+        pw::plan_destroy(plan);
       } else {
         r->msg = pw_last_error();
       }
@@ -146,6 +158,20 @@ extern "C" pw_status pw_server_create(pw_ctx ctx, const pw_server_opts* opts, pw
   s->ctx = ctx;
   s->opts = o;
   s->t0 = std::chrono::steady_clock::now();
+  // one device block of the admission budget, and pinned host memory for
+  // the per-plan flags of the solvers (a few KB per running request)
+  {
+    const pw_status st = s->pool.dev.init(o.mem_budget, false);
+    if (st != PW_OK) {
+      delete s;
+      return st;
+    }
+    const pw_status sh = s->pool.host.init((size_t)o.nworkers * 64 * 1024, true);
+    if (sh != PW_OK) {
+      delete s;
+      return sh;
+    }
+  }
   for (int w = 0; w < o.nworkers; ++w) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -265,5 +291,15 @@ extern "C" pw_status pw_server_cancel(pw_server s, int64_t ticket) {
     s->cv_done.notify_all();
     s->cv_work.notify_all();
   }
+  return PW_OK;
+}
+
+extern "C" pw_status pw_server_info(pw_server s, int64_t out[4]) {
+  PW_CHECK(s != nullptr && out != nullptr, PW_EINVAL, "NULL server or output");
+  std::lock_guard<std::mutex> l(s->mu);
+  out[0] = s->served;
+  out[1] = (int64_t)s->pool.dev.size();
+  out[2] = (int64_t)s->pool_peak;
+  out[3] = s->pool.fallbacks.load();
   return PW_OK;
 }

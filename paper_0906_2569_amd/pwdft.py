@@ -27,7 +27,7 @@ EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_de
            "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "spsi_apply", "pw_cancel", "pw_hpsi_graph_create",
            "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
-           "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
+           "pw_server_info", "pw_profile_count", "pw_profile_name", "pw_profile_read", "pw_profile_only"]
 
 
 class PwError(RuntimeError):
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
                                      C.c_void_p, P(DavOpts), P(C.c_int64)]
     lib.pw_server_wait.argtypes = [C.c_void_p, C.c_int64, P(DavStats), P(C.c_double)]
     lib.pw_server_poll.argtypes = [C.c_void_p, C.c_int64, P(C.c_int32)]
+    lib.pw_server_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
     lib.pw_server_clock.argtypes = [C.c_void_p]
     lib.pw_server_clock.restype = C.c_double
     lib.pw_server_destroy.argtypes = [C.c_void_p]
@@ -152,7 +153,8 @@ def load(path: str = LIB_PATH):
                  "pw_hpsi_graph_create", "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "hpsi_apply_batched", "davidson_solve_batched",
                  "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve",
                  "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
-                 "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy"):
+                 "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_destroy",
+                 "pw_server_info"):
         getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -502,6 +504,12 @@ class Server:
 
     def clock(self) -> float:
         return float(self.lib.pw_server_clock(self.h))
+
+    def info(self):
+        """Requests served, pool bytes, peak pool use, allocations outside the pool."""
+        out = (C.c_int64 * 4)()
+        _check(self.lib.pw_server_info(self.h, out))
+        return dict(zip(["served", "pool_bytes", "pool_peak", "pool_fallbacks"], list(out)))
 
     def submit(self, p, psi, opts=None):
         """Enqueue problem p with trial block psi (torch [nb][npw] on the device, solved in place);

@@ -46,7 +46,11 @@ def test_alone_vs_mix(ctx):
         x = torch.from_numpy(p.psi0).cuda()
         tickets.append(srv.submit(p, x, opts=opts))
     results = [srv.wait(t) for t, _, _ in tickets]
+    info = srv.info()
     srv.close()
+    # every plan took its memory from the server's pool: no hipMalloc per request
+    assert info["served"] == len(reqs) and info["pool_fallbacks"] == 0
+    assert 0 < info["pool_peak"] <= info["pool_bytes"]
     for p, (t, e, r), (st, stats, times), ea in zip(reqs, tickets, results, alone):
         assert st == 0 and stats["max_resid"] <= 1e-6
         assert times[0] <= times[1] <= times[2]
@@ -70,7 +74,10 @@ def test_memory_budget_and_errors(ctx):
     srv = pwdft.Server(ctx, nworkers=2, mem_budget=need + need // 2, precision=pwdft.PW_FP64)
     subs = [srv.submit(p, torch.from_numpy(p.psi0).cuda(), opts=pwdft.default_opts(ndim=2)) for _ in range(3)]
     res = [srv.wait(t) for t, _, _ in subs]
+    info = srv.info()
     srv.close()
+    assert info["served"] == 3 and info["pool_fallbacks"] == 0
+    assert info["pool_bytes"] >= need + need // 2 and info["pool_peak"] <= need + need // 2 + (1 << 20)
     starts = [r[2][1] for r in res]
     ends = [r[2][2] for r in res]
     assert all(r[0] == 0 for r in res)

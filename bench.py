@@ -69,9 +69,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per trace")
     ap.add_argument("--max-atoms", type=int, default=512, help="serve: largest request (atoms)")
     ap.add_argument("--ecut", type=float, default=30.0, help="serve: cutoff in Ry")
-    ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2],
+    ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2, 3],
                     help="cell512: plane pass form (plan option plane_mode: 0 auto, 1 three kernels, "
-                         "2 the 16-lane-group kernel wherever it applies)")
+                         "2 the 16-lane-group kernel wherever it applies, 3 measured at plan creation)")
     ap.add_argument("--nl-overlap", type=int, default=0, choices=[0, 1, 2],
                     help="cell512: projector GEMMs beside the transforms (plan option nl_overlap: 0 auto, "
                          "1 always beside, 2 always after)")
@@ -123,8 +123,8 @@ def roofline(prof, dtype):
 
 
 FFT_KERNELS = ("k_zinv", "k_plane", "k_zfwd")
-PLANE_FORMS = {0: "one kernel per plane (register or LDS form)", 1: "three kernels",
-               2: "one kernel per plane, 16-lane groups"}
+PLANE_FORMS = {0: "one kernel per plane, a quad of lanes per 1D transform", 1: "three kernels",
+               2: "one kernel per plane, 16-lane groups", 3: "one kernel per plane, generic LDS FFT"}
 COMPLEX3_KERNELS = ("calbec_gemm", "add_nl_gemm", "zgemm_cn", "zgemm_nn")
 NL_KERNELS = ("calbec_gemm", "add_nl_gemm")
 

@@ -93,11 +93,14 @@ typedef struct {
   int32_t      nb_max;       /* largest number of bands passed to hpsi_apply / davidson_solve      */
   int32_t      ndim_max;     /* largest Davidson basis factor (basis <= ndim*nb); 0 = no solver ws  */
   int32_t      plane_mode;   /* 0: the plane pass (y, x, V(r), x, y of one z plane) runs in one
-                                kernel per plane where the plane fits in LDS (the eight-lane form
+                                kernel per plane where the plane fits in LDS (the lane-group form
                                 where the padded forms do not fit, e.g. 144^2 in float64), else in
                                 three kernels through an HBM copy of the plane's x columns;
-                                1: always three kernels; 2: the eight-lane form wherever it applies
-                                (n1 = n2 in {80, 96, 128, 144}, unpadded plane within 160 KB)       */
+                                1: always three kernels; 2: the lane-group form (16 lanes per 1D
+                                transform) wherever it applies (n1 = n2 in {80, 96, 128, 144},
+                                unpadded plane within 160 KB); 3: measure every form that fits the
+                                grid at plan creation and keep the fastest (cached per precision
+                                and grid shape for the process)                                    */
   size_t       fft_ws_bytes; /* transform workspace cap (sticks, plus the plane copies of the
                                 three-kernel pass); bands are transformed in chunks that fit it;
                                 0 = 2 GiB                                                          */
@@ -177,8 +180,9 @@ pw_status pw_plan_destroy(pw_plan plan);
 
 /* Plan sizes: out[0]=npw, out[1]=n_sticks, out[2]=x columns, out[3]=N, out[4]=nbeta,
    out[5]=bands per transform chunk, out[6]/out[7]=form of the float64/float32 plane pass:
-   0 one kernel per plane (register or generic LDS form), 1 three kernels, 2 one kernel per
-   plane on eight-lane groups (unpadded plane in LDS). */
+   0 register kernel (a quad of lanes per 1D transform), 1 three kernels, 2 lane-group kernel
+   (16 lanes per 1D transform, unpadded plane in LDS), 3 generic LDS kernel; out[7] is 0 for a
+   PW_FP64 plan. */
 pw_status pw_plan_info(pw_plan plan, int64_t out[8]);
 
 /*

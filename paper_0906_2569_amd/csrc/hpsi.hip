@@ -14,6 +14,7 @@
 // rounding), Vt being the discrete Fourier coefficients of V(r) on the grid;
 // with n_d >= 4 max|m_d| + 1 no wrapped term reaches the sphere.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -903,6 +904,33 @@ int plane_batch(int n1, int n2, int nxr) {
   return 0;
 }
 
+// Forms of the plane pass (pw_plan_info reports them).
+enum PlaneForm { kFormQuad = 0, kFormSplit = 1, kFormGroup = 2, kFormLds = 3 };
+
+template <typename T>
+bool plane_form_ok(int form, int n1, int n2, int nxr) {
+  switch (form) {
+    case kFormQuad: return plane_quad_fits<T>(n1, n2, nxr);
+    case kFormGroup: return plane_oct_fits<T>(n1, n2, nxr);
+    case kFormLds: return plane_batch<T>(n1, n2, nxr) > 0;
+    default: return true;   // three kernels fit any grid the plan accepts
+  }
+}
+
+// Form chosen without measurement: plane_mode 1 takes three kernels; 2 the
+// lane-group kernel where it applies; 0 (and 3, before its measurement) the
+// register (quad) kernel where it fits, else the lane-group kernel, else the
+// generic LDS kernel, else three kernels.
+template <typename T>
+int plane_form_for(int mode, int n1, int n2, int nxr) {
+  if (mode == 1) return kFormSplit;
+  if (mode == 2 && plane_form_ok<T>(kFormGroup, n1, n2, nxr)) return kFormGroup;
+  for (int f : {(int)kFormQuad, (int)kFormGroup, (int)kFormLds})
+    if (plane_form_ok<T>(f, n1, n2, nxr)) return f;
+  return kFormSplit;
+}
+
+
 template <typename T>
 size_t z_lds_bytes(int n3) { return sizeof(cpx<T>) * ((size_t)n3 + 2 * (size_t)ZSB * n3); }
 
@@ -968,8 +996,8 @@ void twiddles(int L, std::vector<c128>& t64, std::vector<c64>& t32) {
 
 struct Geometry {
   int n1, n2, n3, nst, nxr, ldst, nhmax;
-  bool split64, split32;   // three-kernel plane pass per precision
-  bool oct64, oct32;       // eight-lane one-kernel plane pass per precision
+  int form64, form32;      // plane pass form per precision (PlaneForm)
+  bool split64, split32;   // three-kernel plane pass per precision (its HBM plane copies are allocated)
   bool density;            // workspace of pw_density / pw_scf_norm
   bool gamma;              // Gamma point, real wavefunctions on the half sphere
   std::vector<int> mfull;  // Miller indices of the whole sphere, [nfull][3]
@@ -1070,25 +1098,22 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
     geo->nhmax = std::max(geo->nhmax, nh);
   }
   const bool mixed = o->precision == PW_MIXED;
-  PW_CHECK(o->plane_mode >= 0 && o->plane_mode <= 2, PW_EINVAL, "plane_mode must be 0, 1 or 2");
+  PW_CHECK(o->plane_mode >= 0 && o->plane_mode <= 3, PW_EINVAL, "plane_mode must be 0, 1, 2 or 3");
   PW_CHECK(o->nl_overlap >= 0 && o->nl_overlap <= 2, PW_EINVAL, "nl_overlap must be 0, 1 or 2");
-  // plane pass form per precision: the register (quad) kernel where it
-  // exists and fits; else the eight-lane kernel where the unpadded plane fits
-  // in LDS (plane_mode 2 takes it wherever it applies); else the generic LDS
-  // kernel; else three kernels (plane_mode 1 forces those)
-  const int n1 = geo->n1, n2 = geo->n2, nxr = geo->nxr;
-  geo->oct64 = o->plane_mode != 1 && plane_oct_fits<double>(n1, n2, nxr) &&
-               (o->plane_mode == 2 || !plane_quad_fits<double>(n1, n2, nxr));
-  geo->oct32 = mixed && o->plane_mode != 1 && plane_oct_fits<float>(n1, n2, nxr) &&
-               (o->plane_mode == 2 || !plane_quad_fits<float>(n1, n2, nxr));
-  geo->split64 = o->plane_mode == 1 || (!geo->oct64 && plane_batch<double>(n1, n2, nxr) == 0);
-  geo->split32 = mixed && (o->plane_mode == 1 || (!geo->oct32 && plane_batch<float>(n1, n2, nxr) == 0));
+  geo->form64 = plane_form_for<double>(o->plane_mode, geo->n1, geo->n2, geo->nxr);
+  geo->form32 = mixed ? plane_form_for<float>(o->plane_mode, geo->n1, geo->n2, geo->nxr) : kFormQuad;
+  geo->split64 = geo->form64 == kFormSplit;
+  geo->split32 = mixed && geo->form32 == kFormSplit;
   PW_CHECK(o->density == 0 || o->density == 1, PW_EINVAL, "density must be 0 or 1");
   geo->density = o->density == 1;
   PW_CHECK(split_lds_bytes<double>(geo->n1, geo->n2) <= 160 * 1024, PW_EINVAL, "grid too large for the plane pass");
   PW_CHECK(z_lds_bytes<double>(geo->n3) <= 160 * 1024, PW_EINVAL, "n3 too large");
   return PW_OK;
 }
+
+// plane_mode 3 measurement (defined with the H.psi launch code below)
+template <typename T>
+pw_status tune_plane(pw_plan p, hipStream_t s);
 
 }  // namespace
 
@@ -1274,8 +1299,8 @@ pw_status pw::plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* 
   p->band_chunk = band_chunk_for(*o, geo);
   p->split64 = geo.split64;
   p->split32 = geo.split32;
-  p->oct64 = geo.oct64;
-  p->oct32 = geo.oct32;
+  p->form64 = geo.form64;
+  p->form32 = geo.form32;
   fft_factor(n1, p->f1);
   fft_factor(n2, p->f2);
   fft_factor(n3, p->f3);
@@ -1300,7 +1325,9 @@ pw_status pw::plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* 
   PLAN_TRY(upload(p, &p->i1_hx, i1_hx));
   PLAN_TRY(upload(p, &p->zidx, zidx));
   PLAN_TRY(upload(p, &p->col_ptr, col_ptr));
-  if (geo.oct64 || geo.oct32) {
+  // the (column, y) -> stick map of the lane-group kernel: built for every
+  // plan whose grid that kernel covers (plane_mode 3 may pick it later)
+  if (plane_oct_kernel<double>(n1, n2) != nullptr) {
     std::vector<int> cy_st((size_t)nxr * n2, -1);
     for (size_t s2 = 0; s2 < st_hx.size(); ++s2) cy_st[(size_t)st_hx[s2] * n2 + st_i2[s2]] = (int)s2;
     PLAN_TRY(upload(p, &p->cy_st, cy_st));
@@ -1402,6 +1429,10 @@ pw_status pw::plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* 
     PLAN_TRY(pw::dav_alloc(p));
     PLAN_TRY(pw::cg_alloc(p));
   }
+  if (o->plane_mode == 3) {
+    PLAN_TRY(tune_plane<double>(p, stream));
+    if (mixed) PLAN_TRY(tune_plane<float>(p, stream));
+  }
   if ((pool ? hipStreamSynchronize(stream) : hipDeviceSynchronize()) != hipSuccess)
     return fail_cleanup(pw::fail(PW_EDEVICE, "plan initialisation kernels failed"));
 #undef PLAN_TRY
@@ -1444,12 +1475,159 @@ extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
   out[3] = p->N;
   out[4] = p->nbeta;
   out[5] = p->band_chunk;
-  out[6] = p->split64 ? 1 : (p->oct64 ? 2 : 0);
-  out[7] = p->split32 ? 1 : (p->oct32 ? 2 : 0);
+  out[6] = p->form64;
+  out[7] = p->opts.precision == PW_MIXED ? p->form32 : 0;
   return PW_OK;
 }
 
 namespace {
+// The kernels and LDS sizes of one plane pass form, resolved once per call.
+template <typename T>
+struct PlaneLaunch {
+  int form = kFormQuad;
+  PlaneRegFn<T> preg = nullptr;   // register (quad) kernel and its planes per workgroup
+  int ppw = 0;
+  size_t plds = 0;
+  PlaneOctFn<T> poct = nullptr;   // lane-group kernel
+  size_t olds = 0;
+  int cb = 0;                     // generic LDS kernel: transforms per batch
+  size_t pl = 0;                  // its LDS (or that of the three-kernel form)
+};
+
+template <typename T>
+pw_status plane_setup(pw_plan p, int form, PlaneLaunch<T>& L) {
+  L = PlaneLaunch<T>{};
+  L.form = form;
+  const int n1 = p->n1, n2 = p->n2, nxr = p->nxr;
+  switch (form) {
+    case kFormQuad:
+      // two z planes per workgroup where their LDS fits (the last passes over
+      // columns and rows are fuller), else one; above 80 KB one workgroup
+      // fills the CU's LDS (float32 at 144^2: 85 KB, 512 threads)
+      if (plane_reg_lds_bytes<T>(n1, nxr, 2) <= kPlaneRegMaxLds) {
+        L.preg = plane_reg_kernel<T, 2>(n1, n2);
+        L.ppw = 2;
+      } else if (plane_reg_lds_bytes<T>(n1, nxr, 1) <= kPlaneRegMaxLds1) {
+        L.preg = plane_reg_kernel<T, 1>(n1, n2);
+        L.ppw = 1;
+      }
+      PW_CHECK(L.preg != nullptr, PW_EINVAL, "no register plane kernel for this grid");
+      L.plds = plane_reg_lds_bytes<T>(n1, nxr, L.ppw);
+      if (L.plds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)L.preg, (int)L.plds));
+      break;
+    case kFormGroup:
+      L.poct = plane_oct_kernel<T>(n1, n2);
+      PW_CHECK(L.poct != nullptr && p->cy_st != nullptr, PW_EINVAL, "no lane-group plane kernel for this grid");
+      L.olds = plane_oct_lds_bytes<T>(n1, nxr);
+      if (L.olds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)L.poct, (int)L.olds));
+      break;
+    case kFormLds:
+      L.cb = plane_batch<T>(n1, n2, nxr);
+      PW_CHECK(L.cb > 0, PW_EINVAL, "grid too large for the generic plane kernel");
+      L.pl = plane_lds_bytes<T>(n1, n2, nxr, L.cb);
+      break;
+    default:
+      PW_CHECK(p->rows != nullptr, PW_EINVAL, "plan has no plane copies for the three-kernel form");
+      L.pl = split_lds_bytes<T>(n1, n2);
+      break;
+  }
+  return PW_OK;
+}
+
+// the plane pass (y, x, V(r), x, y of every z plane) of nbc bands of sticks
+template <typename T>
+void plane_launch(pw_plan p, const PlaneLaunch<T>& L, cpx<T>* st, const T* vr, const cpx<T>* tw1,
+                  const cpx<T>* tw2, int nbc, hipStream_t s) {
+  const SphereMap m = p->map();
+  switch (L.form) {
+    case kFormQuad:
+      L.preg<<<dim3(ceil_div(p->n3, L.ppw), nbc), plane_reg_threads<T>(p->n1, p->nxr), L.plds, s>>>(m, st, vr, tw1,
+                                                                                                 tw2);
+      break;
+    case kFormGroup:
+      L.poct<<<dim3(p->n3, nbc), OCT_THREADS, L.olds, s>>>(m, st, vr, tw1);
+      break;
+    case kFormLds:
+      k_plane<T><<<dim3(p->n3, nbc), PTHREADS, L.pl, s>>>(m, st, vr, tw1, tw2, L.cb);
+      break;
+    default: {
+      cpx<T>* rows = static_cast<cpx<T>*>(p->rows);
+      k_plane_yinv<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, L.pl, s>>>(m, st, rows, tw2);
+      k_plane_x<T><<<dim3(p->n3, nbc, ceil_div(p->n2, SPLIT_CB)), SPLIT_THREADS, L.pl, s>>>(m, rows, vr, tw1);
+      k_plane_yfwd<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, L.pl, s>>>(m, st, rows, tw2);
+      break;
+    }
+  }
+}
+
+// plane_mode 3: time every form of the plane pass that fits this grid (the
+// three-kernel form only when no other does) on one chunk of up to 16 bands
+// of the stick workspace, and keep the fastest.  The choice is cached per
+// precision and grid shape for the rest of the process, so plans of the same
+// shape measure once.
+template <typename T>
+pw_status tune_plane(pw_plan p, hipStream_t s) {
+  int& form = sizeof(T) == 8 ? p->form64 : p->form32;
+  if (form == kFormSplit) return PW_OK;
+  const std::array<int, 6> key{(int)sizeof(T), p->n1, p->n2, p->n3, p->nxr, p->nst};
+  static std::mutex mu;
+  static std::map<std::array<int, 6>, int> cache;
+  {
+    std::lock_guard<std::mutex> l(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      form = it->second;
+      return PW_OK;
+    }
+  }
+  std::vector<int> cand;
+  for (int f : {(int)kFormQuad, (int)kFormGroup, (int)kFormLds})
+    if (plane_form_ok<T>(f, p->n1, p->n2, p->nxr) && (f != kFormGroup || p->cy_st != nullptr)) cand.push_back(f);
+  int best = form;
+  if (cand.size() > 1) {
+    const bool f64 = sizeof(T) == 8;
+    const cpx<T>* tw1 = f64 ? (const cpx<T>*)p->tw64_1 : (const cpx<T>*)p->tw32_1;
+    const cpx<T>* tw2 = f64 ? (const cpx<T>*)p->tw64_2 : (const cpx<T>*)p->tw32_2;
+    const T* vr = f64 ? (const T*)p->vr64 : (const T*)p->vr32;
+    cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
+    const int nbc = std::min(p->band_chunk, 16);
+    PW_HIP(hipMemsetAsync(st, 0, sizeof(cpx<T>) * (size_t)nbc * p->n3 * p->ldst, s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PW_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return pw::fail(PW_EDEVICE, "event creation failed");
+    }
+    float best_ms = 0.0f;
+    pw_status st_out = PW_OK;
+    for (int f : cand) {
+      PlaneLaunch<T> L;
+      st_out = plane_setup<T>(p, f, L);
+      if (st_out != PW_OK) break;
+      plane_launch<T>(p, L, st, vr, tw1, tw2, nbc, s);   // warm-up
+      (void)hipEventRecord(e0, s);
+      for (int r = 0; r < 3; ++r) plane_launch<T>(p, L, st, vr, tw1, tw2, nbc, s);
+      (void)hipEventRecord(e1, s);
+      float ms = 0.0f;
+      if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st_out = pw::fail(PW_EDEVICE, "plane pass timing failed");
+        break;
+      }
+      if (f == cand.front() || ms < best_ms) {
+        best_ms = ms;
+        best = f;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    PW_TRY(st_out);
+  }
+  form = best;
+  std::lock_guard<std::mutex> l(mu);
+  cache[key] = best;
+  return PW_OK;
+}
+
 template <typename T>
 pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, int ldhpsi,
                    hipStream_t s, bool accumulate, hipEvent_t join) {
@@ -1460,33 +1638,9 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const cpx<T>* tw3 = f64 ? (const cpx<T>*)p->tw64_3 : (const cpx<T>*)p->tw32_3;
   const T* vr = f64 ? (const T*)p->vr64 : (const T*)p->vr32;
   PW_CHECK(vr != nullptr, PW_EINVAL, "float32 H.psi needs a PW_MIXED plan");
-  const bool split = f64 ? p->split64 : p->split32;
-  const bool oct = f64 ? p->oct64 : p->oct32;
-  const int cb = plane_batch<T>(p->n1, p->n2, p->nxr);
-  PW_CHECK(cb > 0 || split || oct, PW_EINVAL, "grid too large for this precision's plane pass");
+  PlaneLaunch<T> pln;
+  PW_TRY(plane_setup<T>(p, f64 ? p->form64 : p->form32, pln));
   const size_t zl = z_lds_bytes<T>(p->n3);
-  const size_t pl = split ? split_lds_bytes<T>(p->n1, p->n2) : plane_lds_bytes<T>(p->n1, p->n2, p->nxr, cb);
-  // two z planes per workgroup where their LDS fits (the last passes over
-  // columns and rows are fuller), else one
-  PlaneRegFn<T> preg = nullptr;
-  int ppw = 0;
-  if (p->use_reg_plane && !split && !oct) {
-    if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 2) <= kPlaneRegMaxLds) {
-      preg = plane_reg_kernel<T, 2>(p->n1, p->n2);
-      ppw = 2;
-    } else if (plane_reg_lds_bytes<T>(p->n1, p->nxr, 1) <= kPlaneRegMaxLds1) {
-      // one plane per workgroup; above 80 KB a single workgroup fills the
-      // CU's LDS (float32 at 144^2: 85 KB, 512 threads, 8 waves per CU)
-      preg = plane_reg_kernel<T, 1>(p->n1, p->n2);
-      ppw = 1;
-    }
-  }
-  const size_t plds = preg ? plane_reg_lds_bytes<T>(p->n1, p->nxr, ppw) : 0;
-  if (preg && plds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)preg, (int)plds));
-  const PlaneOctFn<T> poct = oct ? plane_oct_kernel<T>(p->n1, p->n2) : nullptr;
-  const size_t olds = oct ? plane_oct_lds_bytes<T>(p->n1, p->nxr) : 0;
-  PW_CHECK(!oct || poct != nullptr, PW_EINVAL, "no eight-lane plane kernel for this grid");
-  if (poct && olds > 64 * 1024) PW_TRY(raise_lds_limit((const void*)poct, (int)olds));
   cpx<T>* st = static_cast<cpx<T>*>(p->sticks);
   const int gz = ceil_div(p->nst, ZSB);
   const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
@@ -1518,19 +1672,7 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
     }
     {
       pw::ProfScope ps(pw::PK_PLANE, s, nbc * 2.0 * stick_b + (double)sizeof(T) * p->N);
-      if (oct) {
-        poct<<<dim3(p->n3, nbc), OCT_THREADS, olds, s>>>(m, st, vr, tw1);
-      } else if (split) {
-        cpx<T>* rows = static_cast<cpx<T>*>(p->rows);
-        k_plane_yinv<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, st, rows, tw2);
-        k_plane_x<T><<<dim3(p->n3, nbc, ceil_div(p->n2, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, rows, vr, tw1);
-        k_plane_yfwd<T><<<dim3(p->n3, nbc, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS, pl, s>>>(m, st, rows, tw2);
-      } else if (preg) {
-        preg<<<dim3(ceil_div(p->n3, ppw), nbc), plane_reg_threads<T>(p->n1, p->nxr), plds, s>>>(
-            m, st, vr, tw1, tw2);
-      } else {
-        k_plane<T><<<dim3(p->n3, nbc), PTHREADS, pl, s>>>(m, st, vr, tw1, tw2, cb);
-      }
+      plane_launch<T>(p, pln, st, vr, tw1, tw2, nbc, s);
     }
     if (gam) {
       pw::ProfScope ps(pw::PK_ZFWD, s, nbb * sphere_b + nbc * stick_b);
@@ -1640,15 +1782,17 @@ pw_status nonlocal_side(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hps
 bool nl_beside(pw_plan p, bool f64) {
   if (p->opts.nl_overlap == 1) return true;
   if (p->opts.nl_overlap == 2) return false;
-  if (f64 ? p->split64 : p->split32) return false;
-  // an eight-lane plane workgroup holds more than 64 KB of LDS
-  if (f64 ? p->oct64 : p->oct32)
-    return (f64 ? plane_oct_lds_bytes<double>(p->n1, p->nxr) : plane_oct_lds_bytes<float>(p->n1, p->nxr)) <= 64 * 1024;
-  const size_t one = f64 ? plane_reg_lds_bytes<double>(p->n1, p->nxr, 1) : plane_reg_lds_bytes<float>(p->n1, p->nxr, 1);
-  const bool reg = p->use_reg_plane && p->n1 == p->n2 && p->n1 % 4 == 0 &&
-                   (f64 ? plane_reg_kernel<double, 1>(p->n1, p->n2) != nullptr
-                        : plane_reg_kernel<float, 1>(p->n1, p->n2) != nullptr);
-  return !(reg && one > kPlaneRegMaxLds);
+  const int form = f64 ? p->form64 : p->form32;
+  switch (form) {
+    case kFormSplit: return false;
+    case kFormGroup:   // its workgroup holds more than 64 KB of LDS
+      return (f64 ? plane_oct_lds_bytes<double>(p->n1, p->nxr) : plane_oct_lds_bytes<float>(p->n1, p->nxr)) <=
+             64 * 1024;
+    case kFormQuad:
+      return (f64 ? plane_reg_lds_bytes<double>(p->n1, p->nxr, 1) : plane_reg_lds_bytes<float>(p->n1, p->nxr, 1)) <=
+             kPlaneRegMaxLds;
+    default: return true;
+  }
 }
 
 pw_status pw::hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,

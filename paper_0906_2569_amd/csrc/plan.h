@@ -82,9 +82,10 @@ struct pw_plan_s {
   int nbeta = 0, nblk = 0, nhmax = 0;
   int ldb = 0;              // leading dimension of the plan's beta copies
   int band_chunk = 0;       // bands per FFT pass (stick workspace capacity)
-  bool use_reg_plane = true;  // register-resident plane pass where the grid allows
+  bool use_reg_plane = true;  // register-resident z passes where the grid allows
   bool split64 = false, split32 = false;  // three-kernel plane pass (float64 / float32)
-  bool oct64 = false, oct32 = false;      // eight-lane one-kernel plane pass (float64 / float32)
+  int form64 = 0, form32 = 0;   // plane pass form per precision: 0 register (quad) kernel,
+                                // 1 three kernels, 2 lane-group kernel, 3 generic LDS kernel
   bool gamma = false;       // Gamma point: bands are real functions stored on the half sphere (npw
                             // entries, G = 0 first); the transforms cover the whole sphere (nfull)
   int nfull = 0;

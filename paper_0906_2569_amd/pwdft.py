@@ -349,7 +349,7 @@ class Plan:
         _check(self.lib.pw_plan_info(self.h, out))
         keys = ["npw", "nsticks", "ncols", "N", "nbeta", "band_chunk", "plane64", "plane32"]
         d = dict(zip(keys, list(out)))
-        # plane pass form: 0 one kernel, 1 three kernels, 2 eight-lane one kernel
+        # plane pass form: 0 register kernel, 1 three kernels, 2 lane-group kernel, 3 generic LDS kernel
         d["split_plane64"] = int(d["plane64"] == 1)
         d["split_plane32"] = int(d["plane32"] == 1)
         return d

@@ -335,3 +335,32 @@ def test_lane_group_plane_pass(ctx, prec, n, n3, ecut, kfrac):
     ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
     err = _rel_err(got, ref)
     assert err <= (1e-11 if prec == 0 else 2e-6), err
+
+
+@pytest.mark.parametrize("n,n3,ecut,expect_forms", [
+    (96, 30, 40.0, {0, 2, 3}),     # float64: lane-group or generic; float32: any one-kernel form
+    (144, 32, 14.0, {0, 2, 3}),
+])
+def test_plane_form_tuning(ctx, n, n3, ecut, expect_forms):
+    # plane_mode 3 times the one-kernel forms that fit the grid at plan
+    # creation and keeps the fastest; a second plan of the same shape reuses
+    # the choice; both give the oracle's H.psi
+    p = pwgen.tiny_cell(500 + n, a=6.0, ecut_ry=ecut, natoms=2, nb=5, kfrac=(0.25, -0.25, 0.0), nr=(n, n, n3))
+    assert max(pwgen.min_grid(p.miller)) <= n3
+    ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0) if p.npw <= 3000 else None
+    rows = None
+    if ref is None:
+        rows = np.sort(np.random.default_rng(n).choice(p.npw, 300, replace=False))
+        ref = oracle.hpsi_rows_of(p, p.psi0, rows)
+    forms = []
+    for prec in (0, 1, 1):
+        info = {}
+        got = _hpsi(ctx, p, p.psi0, prec=prec, plane_mode=3, info=info)
+        forms.append((info["plane64"], info["plane32"]))
+        assert info["plane64"] in expect_forms and (prec == 0 or info["plane32"] in expect_forms)
+        if rows is not None:
+            got = got[:, rows]
+        err = _rel_err(got, ref)
+        assert err <= (1e-11 if prec == 0 else 2e-6), err
+    assert forms[1] == forms[2]   # cached per shape
+    assert forms[0][0] == forms[1][0]

@@ -98,8 +98,10 @@ k_plane(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   cpx<T>* B = A + cbatch * lmax;     // [cbatch][lmax]
   int* hx_of = reinterpret_cast<int*>(B + cbatch * lmax);   // [n1]
 
-  const int z = blockIdx.x;
-  const int band = blockIdx.y;
+  // band fastest in the launch order: the workgroups in flight share z
+  // planes, so each plane of V(r) is read from HBM about once per XCD
+  const int band = blockIdx.x;
+  const int z = blockIdx.y;
   cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
   const T* vz = vr + (size_t)z * n1 * n2;
 
@@ -175,7 +177,7 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
   cpx<T>* tw2 = tw1 + N;
   cpx<T>* Y = tw2 + N;                                        // [PP][nxr][YS]
   int* hx_of = reinterpret_cast<int*>(Y + PP * nxr * YS);     // [N]
-  const int z0 = blockIdx.x * PP, band = blockIdx.y;
+  const int z0 = blockIdx.y * PP, band = blockIdx.x;   // band fastest (see k_plane)
   const int np = min(PP, m.n3 - z0);                          // planes of this workgroup
   cpx<T>* st = sticks + ((size_t)band * m.n3 + z0) * m.ldst;   // plane pz at st + pz ldst
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
@@ -278,7 +280,7 @@ k_plane_oct(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr, 
   extern __shared__ __align__(16) char smem_raw[];
   cpx<T>* Y = reinterpret_cast<cpx<T>*>(smem_raw);   // [nxr][N], swizzled
   const int nxr = m.nxr;
-  const int z = blockIdx.x, band = blockIdx.y;
+  const int z = blockIdx.y, band = blockIdx.x;   // band fastest (see k_plane)
   cpx<T>* st = sticks + ((size_t)band * m.n3 + z) * m.ldst;
   const int g = threadIdx.x & (G - 1), grp = threadIdx.x / G, ngrp = blockDim.x / G;
   const int pb = regfft::g_block<G>(g);   // block of the transform held after ginv
@@ -1541,14 +1543,14 @@ void plane_launch(pw_plan p, const PlaneLaunch<T>& L, cpx<T>* st, const T* vr, c
   const SphereMap m = p->map();
   switch (L.form) {
     case kFormQuad:
-      L.preg<<<dim3(ceil_div(p->n3, L.ppw), nbc), plane_reg_threads<T>(p->n1, p->nxr), L.plds, s>>>(m, st, vr, tw1,
+      L.preg<<<dim3(nbc, ceil_div(p->n3, L.ppw)), plane_reg_threads<T>(p->n1, p->nxr), L.plds, s>>>(m, st, vr, tw1,
                                                                                                  tw2);
       break;
     case kFormGroup:
-      L.poct<<<dim3(p->n3, nbc), OCT_THREADS, L.olds, s>>>(m, st, vr, tw1);
+      L.poct<<<dim3(nbc, p->n3), OCT_THREADS, L.olds, s>>>(m, st, vr, tw1);
       break;
     case kFormLds:
-      k_plane<T><<<dim3(p->n3, nbc), PTHREADS, L.pl, s>>>(m, st, vr, tw1, tw2, L.cb);
+      k_plane<T><<<dim3(nbc, p->n3), PTHREADS, L.pl, s>>>(m, st, vr, tw1, tw2, L.cb);
       break;
     default: {
       cpx<T>* rows = static_cast<cpx<T>*>(p->rows);

@@ -69,9 +69,10 @@ def parse():
     ap.add_argument("--requests", type=int, default=32, help="serve: requests per trace")
     ap.add_argument("--max-atoms", type=int, default=512, help="serve: largest request (atoms)")
     ap.add_argument("--ecut", type=float, default=30.0, help="serve: cutoff in Ry")
-    ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2, 3],
+    ap.add_argument("--plane-mode", type=int, default=0, choices=[0, 1, 2, 3, 4],
                     help="cell512: plane pass form (plan option plane_mode: 0 auto, 1 three kernels, "
-                         "2 the 16-lane-group kernel wherever it applies, 3 measured at plan creation)")
+                         "2 the 16-lane-group kernel wherever it applies, 3 measured at plan creation, "
+                         "4 the register (quad) kernel wherever it applies)")
     ap.add_argument("--nl-overlap", type=int, default=0, choices=[0, 1, 2],
                     help="cell512: projector GEMMs beside the transforms (plan option nl_overlap: 0 auto, "
                          "1 always beside, 2 always after)")

@@ -93,14 +93,16 @@ typedef struct {
   int32_t      nb_max;       /* largest number of bands passed to hpsi_apply / davidson_solve      */
   int32_t      ndim_max;     /* largest Davidson basis factor (basis <= ndim*nb); 0 = no solver ws  */
   int32_t      plane_mode;   /* 0: the plane pass (y, x, V(r), x, y of one z plane) runs in one
-                                kernel per plane where the plane fits in LDS (the lane-group form
-                                where the padded forms do not fit, e.g. 144^2 in float64), else in
+                                kernel per plane where the plane fits in LDS (the register form
+                                where two planes fit a workgroup, else the lane-group form, e.g.
+                                144^2 in both precisions), else in
                                 three kernels through an HBM copy of the plane's x columns;
                                 1: always three kernels; 2: the lane-group form (16 lanes per 1D
                                 transform) wherever it applies (n1 = n2 in {80, 96, 128, 144},
                                 unpadded plane within 160 KB); 3: measure every form that fits the
                                 grid at plan creation and keep the fastest (cached per precision
-                                and grid shape for the process)                                    */
+                                and grid shape for the process); 4: the register form (a quad of
+                                lanes per 1D transform) wherever it applies                       */
   size_t       fft_ws_bytes; /* transform workspace cap (sticks, plus the plane copies of the
                                 three-kernel pass); bands are transformed in chunks that fit it;
                                 0 = 2 GiB                                                          */

@@ -258,7 +258,15 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
 // plane is the kernel's only LDS.
 // ---------------------------------------------------------------------------
 constexpr int OCT_G = 16;          // lanes per 1D transform
-constexpr int OCT_THREADS = 576;   // 36 groups: a 144^2 plane's 71 columns in two passes, its rows in four
+// float64: 576 threads (36 groups: a 144^2 plane's 71 columns in two passes,
+// its rows in four), one workgroup per CU (the plane fills the LDS);
+// float32: 512 threads and at most 128 registers, so that two workgroups
+// (two 82 KB planes) share a CU
+template <typename T>
+struct OctCfg {
+  static constexpr int threads = sizeof(T) == 8 ? 576 : 512;
+  static constexpr int waves = sizeof(T) == 8 ? 3 : 4;
+};
 
 // LDS position of (x column c, y): y ^ 2 sigma(c mod 8), sigma rotating the
 // three bits of c mod 8 right, so bit 3 of the mask is bit 0 of c.  Column
@@ -272,7 +280,7 @@ __device__ __forceinline__ int oct_pos(int c, int y) {
 }
 
 template <typename T, int LS>
-__global__ void __launch_bounds__(OCT_THREADS)
+__global__ void __launch_bounds__(OctCfg<T>::threads) __attribute__((amdgpu_waves_per_eu(OctCfg<T>::waves)))
 k_plane_oct(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr, const cpx<T>* __restrict__ tw) {
   constexpr int G = OCT_G;
   constexpr int N = G * LS;
@@ -920,14 +928,21 @@ bool plane_form_ok(int form, int n1, int n2, int nxr) {
 }
 
 // Form chosen without measurement: plane_mode 1 takes three kernels; 2 the
-// lane-group kernel where it applies; 0 (and 3, before its measurement) the
-// register (quad) kernel where it fits, else the lane-group kernel, else the
-// generic LDS kernel, else three kernels.
+// lane-group kernel where it applies; 4 the register kernel where it
+// applies; 0 (and 3, before its measurement, and 2 and 4 elsewhere) the
+// register (quad) kernel where two planes fit a workgroup, else the
+// lane-group kernel, else the register kernel with one plane per workgroup,
+// else the generic LDS kernel, else three kernels.  (At 144^2 in float32 the
+// lane-group kernel runs two workgroups per CU where the one-plane register
+// kernel runs one: 12.5 against 18.4 ms per 1024-band H.psi.)
 template <typename T>
 int plane_form_for(int mode, int n1, int n2, int nxr) {
   if (mode == 1) return kFormSplit;
   if (mode == 2 && plane_form_ok<T>(kFormGroup, n1, n2, nxr)) return kFormGroup;
-  for (int f : {(int)kFormQuad, (int)kFormGroup, (int)kFormLds})
+  if (mode == 4 && plane_form_ok<T>(kFormQuad, n1, n2, nxr)) return kFormQuad;
+  if (plane_reg_kernel<T, 2>(n1, n2) != nullptr && plane_reg_lds_bytes<T>(n1, nxr, 2) <= kPlaneRegMaxLds)
+    return kFormQuad;
+  for (int f : {(int)kFormGroup, (int)kFormQuad, (int)kFormLds})
     if (plane_form_ok<T>(f, n1, n2, nxr)) return f;
   return kFormSplit;
 }
@@ -1100,7 +1115,7 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
     geo->nhmax = std::max(geo->nhmax, nh);
   }
   const bool mixed = o->precision == PW_MIXED;
-  PW_CHECK(o->plane_mode >= 0 && o->plane_mode <= 3, PW_EINVAL, "plane_mode must be 0, 1, 2 or 3");
+  PW_CHECK(o->plane_mode >= 0 && o->plane_mode <= 4, PW_EINVAL, "plane_mode must be 0..4");
   PW_CHECK(o->nl_overlap >= 0 && o->nl_overlap <= 2, PW_EINVAL, "nl_overlap must be 0, 1 or 2");
   geo->form64 = plane_form_for<double>(o->plane_mode, geo->n1, geo->n2, geo->nxr);
   geo->form32 = mixed ? plane_form_for<float>(o->plane_mode, geo->n1, geo->n2, geo->nxr) : kFormQuad;
@@ -1547,7 +1562,7 @@ void plane_launch(pw_plan p, const PlaneLaunch<T>& L, cpx<T>* st, const T* vr, c
                                                                                                  tw2);
       break;
     case kFormGroup:
-      L.poct<<<dim3(nbc, p->n3), OCT_THREADS, L.olds, s>>>(m, st, vr, tw1);
+      L.poct<<<dim3(nbc, p->n3), OctCfg<T>::threads, L.olds, s>>>(m, st, vr, tw1);
       break;
     case kFormLds:
       k_plane<T><<<dim3(nbc, p->n3), PTHREADS, L.pl, s>>>(m, st, vr, tw1, tw2, L.cb);

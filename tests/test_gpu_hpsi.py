@@ -295,18 +295,19 @@ def test_band_chunks(ctx, prec, plane_mode):
     assert _rel_err(got, oracle.hpsi(h, p.psi0)) <= (1e-11 if prec == 0 else 2e-6)
 
 
-@pytest.mark.parametrize("prec,plane_mode", [(0, 0), (1, 0), (0, 1), (1, 2)])
+@pytest.mark.parametrize("prec,plane_mode", [(0, 0), (1, 0), (0, 1), (1, 1), (1, 4)])
 def test_config5_largest_cell_sampled_rows(ctx, prec, plane_mode):
     # the largest served cell (a = 41 bohr, 30 Ry, npw 191471, 144^3, 512 atoms,
-    # 2048 projectors) with 16 bands.  By default float64 takes the lane-group
-    # plane kernel (its unpadded 144 x 71 plane fills the 160 KB of LDS) and
-    # float32 the one-plane register kernel; plane_mode 1 forces three kernels,
-    # 2 the lane-group kernel for float32 too.  Rows of the dense H from the oracle.
+    # 2048 projectors) with 16 bands.  By default both precisions take the
+    # lane-group plane kernel (the unpadded float64 144 x 71 plane fills the
+    # 160 KB of LDS; two float32 planes share it); plane_mode 1 forces three
+    # kernels, 4 the one-plane register kernel for float32.  Rows of the dense
+    # H from the oracle.
     p = pwgen.config5_largest(nb=16)
     info = {}
     got = _hpsi(ctx, p, p.psi0, prec=prec, plane_mode=plane_mode, info=info)
-    expect64 = {0: 2, 1: 1, 2: 2}[plane_mode]
-    expect32 = {0: 0, 1: 1, 2: 2}[plane_mode] if prec == 1 else 0
+    expect64 = {0: 2, 1: 1, 4: 2}[plane_mode]
+    expect32 = {0: 2, 1: 1, 4: 0}[plane_mode] if prec == 1 else 0
     assert (info["plane64"], info["plane32"]) == (expect64, expect32)
     rng = np.random.default_rng(5)
     rows = np.sort(rng.choice(p.npw, 64, replace=False))

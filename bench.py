@@ -448,9 +448,6 @@ TRAFFIC_BYTES = {
     # calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant
     # kernel, taken with the kernel as it now stands; an entry is removed
     # whenever that kernel changes, until its counters are taken again.
-    # k_gemm_cn<float, float, double> (three-product form), 8 K chunks:
-    # 55.563 GB read + 0.134 GB written (profiles/hpsi_mixed_512atom_144cubed.md)
-    ("cell512_mixed", "calbec_gemm"): 55.697e9,
 }
 
 

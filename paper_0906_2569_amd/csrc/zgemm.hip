@@ -64,9 +64,21 @@ __device__ __forceinline__ int mcol(int lane) { return lane & 15; }
 // round.  The float64 ones hold three float64 accumulator sets (96
 // registers) and are built for two waves per SIMD, each MFMA there taking
 // twice as many cycles.
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-template <typename T>
-struct GemmWaves { static constexpr int value = sizeof(T) == 8 ? 2 : 3; };
+constexpr int BN = 64, BK = 16, NT = 256;
+// Output tile rows per workgroup (BM) and waves per SIMD the kernels are
+// built for.  The calbec-shaped product (k_gemm_cn) in float32 takes 128 rows
+// (each wave a 64 x 32 block of 4 x 2 MFMA tiles: twice the products per
+// operand byte loaded and per LDS read of a 64 x 64 tile; 22.4 against
+// 23.7 ms at the 512-atom cell) at two waves per SIMD; the add-back
+// (k_gemm_nn) keeps 64 rows, which measured faster there (20.9 against
+// 21.4 ms), at three; float64 takes 64 rows at two waves per SIMD (its three
+// accumulator sets).
+template <typename T, bool CN>
+struct GT {
+  static constexpr int BM = (sizeof(T) == 4 && CN) ? 128 : 64;
+  static constexpr int IM = BM / 32;   // 16-row MFMA tiles per wave (two waves along M)
+  static constexpr int waves = (sizeof(T) == 4 && !CN) ? 3 : 2;
+};
 
 // Workgroups go to the 8 XCDs round-robin in linear launch order.  Each XCD is
 // given one contiguous range of a work order in which tile y (YFAST) or tile x
@@ -90,7 +102,7 @@ __device__ __forceinline__ void xcd_block(int& bx, int& by, int& bz) {
   bz = w / (gx * gy);
 }
 
-template <typename T>
+template <typename T, int BM>
 struct Tile {
   T ar[BK][BM + 1], ai[BK][BM + 1], br[BK][BN + 1], bi[BK][BN + 1];
 };
@@ -100,14 +112,14 @@ struct Tile {
 // four-product form).
 constexpr bool kGauss = true;
 
-template <typename T>
+template <typename T, int IM>
 struct CAcc {
   typedef typename Mma<T>::v4 v4;
   static constexpr bool k3 = kGauss;
-  v4 a[2][2], b[2][2], c[2][2];
+  v4 a[IM][2], b[IM][2], c[IM][2];
   __device__ __forceinline__ void zero() {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) a[i][j] = b[i][j] = c[i][j] = v4{0, 0, 0, 0};
   }
@@ -121,28 +133,34 @@ struct CAcc {
   }
 };
 
-// One BK slice of a 64x64 tile product held in LDS; each of the 4 waves owns a
-// 32x32 quadrant (2x2 blocks of 16x16).
-template <typename T>
-__device__ __forceinline__ void tile_mma(const Tile<T>& t, CAcc<T>& acc, int wm, int wn, int lane) {
+// One BK slice of a BM x 64 tile product held in LDS; each of the 4 waves
+// owns a (BM / 2) x 32 block (IM x 2 MFMA tiles of 16 x 16).
+template <typename T, int BM>
+__device__ __forceinline__ void tile_mma(const Tile<T, BM>& t, CAcc<T, BM / 32>& acc, int wm, int wn, int lane) {
+  constexpr int IM = BM / 32, WM = BM / 2;
   const int r = lane & 15, kq = lane >> 4;
 #pragma unroll
   for (int k4 = 0; k4 < BK; k4 += 4) {
     const int kk = k4 + kq;
-    T ar[2], ai[2], br[2], bi[2];
+    T ar[IM], ai[IM], br[2], bi[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      ar[i] = t.ar[kk][wm * 32 + i * 16 + r];
-      ai[i] = t.ai[kk][wm * 32 + i * 16 + r];
-      br[i] = t.br[kk][wn * 32 + i * 16 + r];
-      bi[i] = t.bi[kk][wn * 32 + i * 16 + r];
+    for (int i = 0; i < IM; ++i) {
+      ar[i] = t.ar[kk][wm * WM + i * 16 + r];
+      ai[i] = t.ai[kk][wm * WM + i * 16 + r];
     }
-    if constexpr (CAcc<T>::k3) {
-      T sa[2], sb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) { sa[i] = ar[i] + ai[i]; sb[i] = br[i] + bi[i]; }
+    for (int j = 0; j < 2; ++j) {
+      br[j] = t.br[kk][wn * 32 + j * 16 + r];
+      bi[j] = t.bi[kk][wn * 32 + j * 16 + r];
+    }
+    if constexpr (CAcc<T, IM>::k3) {
+      T sa[IM], sb[2];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i) sa[i] = ar[i] + ai[i];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) sb[j] = br[j] + bi[j];
+#pragma unroll
+      for (int i = 0; i < IM; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc.a[i][j] = Mma<T>::run(ar[i], br[j], acc.a[i][j]);
@@ -151,7 +169,7 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, CAcc<T>& acc, int wm,
         }
     } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
           acc.a[i][j] = Mma<T>::run(ar[i], br[j], acc.a[i][j]);
@@ -167,10 +185,11 @@ __device__ __forceinline__ void tile_mma(const Tile<T>& t, CAcc<T>& acc, int wm,
 // gridDim.z = 2 nsplit for two products of one launch: z >= nsplit takes B1
 // and writes the partials after those of the first product
 template <typename T, typename TA, typename TB>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GT<T, true>::waves)))
 k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict__ A, int lda,
           const cpx<TB>* __restrict__ B0, const cpx<TB>* __restrict__ B1, int ldb, cpx<T>* __restrict__ P) {
-  __shared__ Tile<T> t;
+  constexpr int BM = GT<T, true>::BM, IM = GT<T, true>::IM;
+  __shared__ Tile<T, BM> t;
   int bx, by, bz;
   xcd_block<false>(bx, by, bz);   // the output tiles of one K chunk share an XCD
   const int m0 = bx * BM, n0 = by * BN;
@@ -179,49 +198,59 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
   const int kbeg = zs * kchunk, kend = min(K, kbeg + kchunk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  CAcc<T> acc;
+  CAcc<T, IM> acc;
   acc.zero();
 
   // the next K slice is loaded into registers while the current one is
   // multiplied out of LDS
-  constexpr int PER = BM * BK / NT;
-  cpx<TA> ra[PER];
-  cpx<TB> rb[PER];
+  constexpr int PA = BM * BK / NT, PB = BN * BK / NT;
+  cpx<TA> ra[PA];
+  cpx<TB> rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
+    for (int it = 0; it < PA; ++it) {
       const int idx = threadIdx.x + it * NT;
       const int kk = idx % BK, mi = idx / BK;
-      const int k = k0 + kk;
-      const int m = m0 + mi, n = n0 + mi;
+      const int k = k0 + kk, m = m0 + mi;
       ra[it] = (m < M && k < kend) ? A[(size_t)m * lda + k] : cpx<TA>{TA(0), TA(0)};
+    }
+#pragma unroll
+    for (int it = 0; it < PB; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, ni = idx / BK;
+      const int k = k0 + kk, n = n0 + ni;
       rb[it] = (n < N && k < kend) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
     }
   };
   if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
+    for (int it = 0; it < PA; ++it) {
       const int idx = threadIdx.x + it * NT;
       const int kk = idx % BK, mi = idx / BK;
       t.ar[kk][mi] = (T)ra[it].x;
       t.ai[kk][mi] = -(T)ra[it].y;  // conj(A)
-      t.br[kk][mi] = (T)rb[it].x;
-      t.bi[kk][mi] = (T)rb[it].y;
+    }
+#pragma unroll
+    for (int it = 0; it < PB; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, ni = idx / BK;
+      t.br[kk][ni] = (T)rb[it].x;
+      t.bi[kk][ni] = (T)rb[it].y;
     }
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);
-    tile_mma<T>(t, acc, wm, wn, lane);
+    tile_mma<T, BM>(t, acc, wm, wn, lane);
     __syncthreads();
   }
   cpx<T>* out = P + (size_t)bz * M * N;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+        const int m = m0 + wm * (BM / 2) + i * 16 + mrow<T>(lane, q);
         const int n = n0 + wn * 32 + j * 16 + mcol(lane);
         if (m < M && n < N) out[(size_t)n * M + m] = acc.get(i, j, q);
       }
@@ -233,7 +262,7 @@ k_gemm_cn(int M, int N, int K, int kchunk, int nsplit, const cpx<TA>* __restrict
 // SPLIT: the z index is instead the K chunk [z kchunk, (z + 1) kchunk) of the one
 // product (A0), whose partial tile goes to P[z][n][m] unscaled, for k_reduce.
 template <typename T, typename TA, typename TB, bool SPLIT = false>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GemmWaves<T>::value)))
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GT<T, false>::waves)))
 k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, const cpx<TA>* __restrict__ A1,
           int lda, const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C0,
           c128* __restrict__ C1, int ldc, const int* __restrict__ guard, int kchunk = 0,
@@ -245,74 +274,75 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
   c128* __restrict__ C = (!SPLIT && bz) ? C1 : C0;
   const int kbeg = SPLIT ? bz * kchunk : 0;
   const int kend = SPLIT ? min(K, kbeg + kchunk) : K;
-  __shared__ Tile<T> t;
+  constexpr int BM = GT<T, false>::BM, IM = GT<T, false>::IM;
+  __shared__ Tile<T, BM> t;
   const int m0 = bx * BM, n0 = by * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  CAcc<T> acc;
+  CAcc<T, IM> acc;
   acc.zero();
 
-  constexpr int PER = BM * BK / NT;
-  cpx<TA> ra[PER];
-  cpx<TB> rb[PER];
+  constexpr int PA = BM * BK / NT, PB = BN * BK / NT;
+  cpx<TA> ra[PA];
+  cpx<TB> rb[PB];
   auto load = [&](int k0) {
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
+    for (int it = 0; it < PA; ++it) {
       const int idx = threadIdx.x + it * NT;
-      {
-        const int mi = idx % BM, kk = idx / BM;
-        const int m = m0 + mi, k = k0 + kk;
-        ra[it] = (m < M && k < kend) ? A[(size_t)k * lda + m] : cpx<TA>{TA(0), TA(0)};
-      }
-      {
-        const int kk = idx % BK, ni = idx / BK;
-        const int n = n0 + ni, k = k0 + kk;
-        rb[it] = (n < N && k < kend) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
-      }
+      const int mi = idx % BM, kk = idx / BM;
+      const int m = m0 + mi, k = k0 + kk;
+      ra[it] = (m < M && k < kend) ? A[(size_t)k * lda + m] : cpx<TA>{TA(0), TA(0)};
+    }
+#pragma unroll
+    for (int it = 0; it < PB; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, ni = idx / BK;
+      const int n = n0 + ni, k = k0 + kk;
+      rb[it] = (n < N && k < kend) ? B[(size_t)n * ldb + k] : cpx<TB>{TB(0), TB(0)};
     }
   };
   if (kbeg < kend) load(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
+    for (int it = 0; it < PA; ++it) {
       const int idx = threadIdx.x + it * NT;
-      {
-        const int mi = idx % BM, kk = idx / BM;
-        t.ar[kk][mi] = (T)ra[it].x;
-        t.ai[kk][mi] = (T)ra[it].y;
-      }
-      {
-        const int kk = idx % BK, ni = idx / BK;
-        t.br[kk][ni] = (T)rb[it].x;
-        t.bi[kk][ni] = (T)rb[it].y;
-      }
+      const int mi = idx % BM, kk = idx / BM;
+      t.ar[kk][mi] = (T)ra[it].x;
+      t.ai[kk][mi] = (T)ra[it].y;
+    }
+#pragma unroll
+    for (int it = 0; it < PB; ++it) {
+      const int idx = threadIdx.x + it * NT;
+      const int kk = idx % BK, ni = idx / BK;
+      t.br[kk][ni] = (T)rb[it].x;
+      t.bi[kk][ni] = (T)rb[it].y;
     }
     __syncthreads();
     if (k0 + BK < kend) load(k0 + BK);
-    tile_mma<T>(t, acc, wm, wn, lane);
+    tile_mma<T, BM>(t, acc, wm, wn, lane);
     __syncthreads();
   }
   if constexpr (SPLIT) {
     cpx<T>* out = P + (size_t)bz * M * N;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < IM; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+          const int m = m0 + wm * (BM / 2) + i * 16 + mrow<T>(lane, q);
           const int n = n0 + wn * 32 + j * 16 + mcol(lane);
           if (m < M && n < N) out[(size_t)n * M + m] = acc.get(i, j, q);
         }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int m = m0 + wm * 32 + i * 16 + mrow<T>(lane, q);
+        const int m = m0 + wm * (BM / 2) + i * 16 + mrow<T>(lane, q);
         const int n = n0 + wn * 32 + j * 16 + mcol(lane);
         if (m < M && n < N) {
           c128* c = C + (size_t)n * ldc + m;
@@ -430,7 +460,7 @@ struct Split {
   int nsplit, kchunk;
 };
 
-Split choose_split(int M, int N, int K) {
+Split choose_split(int M, int N, int K, int BM) {
   const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
   const int target = 512;
   int nsplit = std::max(1, ceil_div(target, tiles));
@@ -451,8 +481,12 @@ Split choose_split(int M, int N, int K) {
 size_t pw::splitk_part_bytes(int M, int N, int K, int elem_bytes) {
   // Upper bound over every M' <= M, N' <= N: nsplit <= 512/tiles + 1, so
   // nsplit M' N' <= 512 BM BN + M N; a long K adds the 8-chunk minimum.
+  // Complex64 partials come from the 128-row tiles, complex128 ones from the
+  // 64-row tiles; a complex128-sized bound covers the complex64 partials of
+  // the same product (512 x 128 x 64 x 8 B = 512 x 64 x 64 x 16 B).
   const size_t mn = (size_t)std::max(M, 1) * std::max(N, 1);
-  size_t e = (size_t)512 * BM * BN + mn;
+  const size_t bm = elem_bytes <= 8 ? (size_t)GT<float, true>::BM : (size_t)GT<double, true>::BM;
+  size_t e = (size_t)512 * bm * BN + mn;
   if (K >= 8 * 256 * BK) e = std::max(e, 8 * mn);
   return e * elem_bytes + 256;
 }
@@ -462,7 +496,7 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
                        c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s, double alpha,
                        double beta, const c128* Cin, int ldcin) {
   if (M <= 0 || N <= 0) return PW_OK;
-  const Split sp = choose_split(M, N, K);
+  const Split sp = choose_split(M, N, K, GT<T, true>::BM);
   const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
   PW_CHECK(need <= part_bytes, PW_ENOMEM, "split-K workspace too small");
   cpx<T>* P = static_cast<cpx<T>*>(part);
@@ -475,7 +509,7 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
   }
   {
     pw::ProfScope ps(pw::PK_GEMM_CN, s, 8.0 * M * N * K);
-    k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+    k_gemm_cn<T, TA, TB><<<dim3(ceil_div(M, GT<T, true>::BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
         M, N, K, sp.kchunk, sp.nsplit, A, lda, B, B, ldb, P);
   }
   {
@@ -490,7 +524,7 @@ pw_status pw::zgemm_cn(int M, int N, int K, const cpx<TA>* A, int lda, const cpx
 pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c128* B0, const c128* B1,
                             int ldb, c128* C0, c128* C1, int ldc, void* part, size_t part_bytes, hipStream_t s) {
   if (M <= 0 || N <= 0) return PW_OK;
-  Split sp = choose_split(M, N, K);
+  Split sp = choose_split(M, N, K, GT<double, true>::BM);
   // half the splits per product: the two products together fill the device
   const int ns = std::max(1, sp.nsplit / 2);
   const int kchunk = std::max(BK, ceil_div(ceil_div(K, ns), BK) * BK);
@@ -503,7 +537,7 @@ pw_status pw::zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c
   c128* P = static_cast<c128*>(part);
   {
     pw::ProfScope ps(pw::PK_GEMM_CN, s, 16.0 * M * N * K);
-    k_gemm_cn<double, double, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 2 * nsplit), NT, 0, s>>>(
+    k_gemm_cn<double, double, double><<<dim3(ceil_div(M, GT<double, true>::BM), ceil_div(N, BN), 2 * nsplit), NT, 0, s>>>(
         M, N, K, kchunk, nsplit, A, lda, B0, B1, ldb, P);
   }
   {
@@ -519,7 +553,7 @@ template <typename T>
 pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* out, hipStream_t s,
                        const cpx<T>* rows) {
   const int M = p->nbeta, N = nb, K = p->npw;
-  const Split sp = choose_split(M, N, K);
+  const Split sp = choose_split(M, N, K, GT<T, true>::BM);
   const size_t need = (size_t)sp.nsplit * M * N * sizeof(cpx<T>);
   PW_CHECK(need <= p->part_bytes, PW_ENOMEM, "split-K workspace too small");
   cpx<T>* P = static_cast<cpx<T>*>(p->part);
@@ -527,7 +561,7 @@ pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* ou
   const cpx<T>* drow = rows ? rows : (sizeof(T) == 8 ? (const cpx<T>*)p->drow64 : (const cpx<T>*)p->drow32);
   {
     pw::ProfScope ps(pw::PK_CALBEC, s, 8.0 * M * N * K);
-    k_gemm_cn<T, T, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
+    k_gemm_cn<T, T, double><<<dim3(ceil_div(M, GT<T, true>::BM), ceil_div(N, BN), sp.nsplit), NT, 0, s>>>(
         M, N, K, sp.kchunk, sp.nsplit, beta, p->ldb, psi, psi, ldpsi, P);
   }
   {
@@ -545,7 +579,7 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
                        const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
-  k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 1), NT, 0, s>>>(
+  k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, GT<T, false>::BM), ceil_div(N, BN), 1), NT, 0, s>>>(
       M, N, K, alpha, A, A, lda, B, ldb, beta, C, C, ldc, guard);
   PW_HIP(hipGetLastError());
   return PW_OK;
@@ -554,7 +588,7 @@ pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int 
 pw_status pw::zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int lda, const c128* B, int ldb,
                           double beta, c128* C, int ldc, void* part, size_t part_bytes, hipStream_t s) {
   if (M <= 0 || N <= 0) return PW_OK;
-  const int tiles = ceil_div(M, BM) * ceil_div(N, BN);
+  const int tiles = ceil_div(M, GT<double, false>::BM) * ceil_div(N, BN);
   // chunks of at least two K slices, up to about 512 workgroups in all
   const int ns = std::min(ceil_div(512, tiles), ceil_div(K, 2 * BK));
   const int kchunk = std::max(BK, ceil_div(ceil_div(K, std::max(ns, 1)), BK) * BK);
@@ -565,7 +599,7 @@ pw_status pw::zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int 
   c128* P = static_cast<c128*>(part);
   {
     pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
-    k_gemm_nn<double, double, double, true><<<dim3(ceil_div(M, BM), ceil_div(N, BN), nsplit), NT, 0, s>>>(
+    k_gemm_nn<double, double, double, true><<<dim3(ceil_div(M, GT<double, false>::BM), ceil_div(N, BN), nsplit), NT, 0, s>>>(
         M, N, K, 1.0, A, A, lda, B, ldb, 0.0, nullptr, nullptr, ldc, nullptr, kchunk, P);
   }
   {
@@ -581,7 +615,7 @@ pw_status pw::zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1,
                             int ldb, c128* C0, c128* C1, int ldc, hipStream_t s, const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 16.0 * M * N * K);
-  k_gemm_nn<double, double, double><<<dim3(ceil_div(M, BM), ceil_div(N, BN), 2), NT, 0, s>>>(
+  k_gemm_nn<double, double, double><<<dim3(ceil_div(M, GT<double, false>::BM), ceil_div(N, BN), 2), NT, 0, s>>>(
       M, N, K, 1.0, A0, A1, lda, B, ldb, 0.0, C0, C1, ldc, guard);
   PW_HIP(hipGetLastError());
   return PW_OK;

@@ -580,10 +580,13 @@ k_zfwd(SphereMap m, const cpx<T>* __restrict__ sticks,
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int g = m.ent_g[e];
     const cpx<T> v = X[(m.ent_s[e] - s0) * n3 + m.ent_z[e]];
-    const c128 p = pb[g];
-    const double t = m.kin[g];
-    c128 r = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
-    if (accumulate) {   // the projector term is already in hpsi
+    c128 r = c128{(double)v.x * inv_n, (double)v.y * inv_n};
+    if (!(accumulate & 2)) {   // kinetic term (not yet in hpsi)
+      const c128 p = pb[g];
+      const double t = m.kin[g];
+      r = c128{r.x + t * p.x, r.y + t * p.y};
+    }
+    if (accumulate & 1) {   // the projector term is already in hpsi
       const c128 o = hb[g];
       r = c128{r.x + o.x, r.y + o.y};
     }
@@ -661,10 +664,13 @@ k_zfwd_reg(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restric
   for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int g = m.ent_g[e];
     const cpx<T> v = X[(m.ent_s[e] - s0) * XS + m.ent_z[e]];
-    const c128 p = pb[g];
-    const double t = m.kin[g];
-    c128 r = c128{t * p.x + (double)v.x * inv_n, t * p.y + (double)v.y * inv_n};
-    if (accumulate) {   // the projector term is already in hpsi
+    c128 r = c128{(double)v.x * inv_n, (double)v.y * inv_n};
+    if (!(accumulate & 2)) {   // kinetic term (not yet in hpsi)
+      const c128 p = pb[g];
+      const double t = m.kin[g];
+      r = c128{r.x + t * p.x, r.y + t * p.y};
+    }
+    if (accumulate & 1) {   // the projector term is already in hpsi
       const c128 o = hb[g];
       r = c128{r.x + o.x, r.y + o.y};
     }
@@ -1704,16 +1710,19 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
       continue;
     }
     if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));
+    // with projectors, hpsi already holds the projector and kinetic terms
+    // (flags 3: add to hpsi, no kinetic term here); else the pass adds the
+    // kinetic term itself (flags 0)
     {
       pw::ProfScope ps(pw::PK_ZFWD, s, nbc * (sphere_b + stick_b));
       if (zr.fwd)
         zr.fwd<<<zrgrid, ZRTHREADS, 0, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
                                             hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
-                                            1.0 / (double)p->N, accumulate ? 1 : 0, gzr, nbc);
+                                            1.0 / (double)p->N, accumulate ? 3 : 0, gzr, nbc);
       else
         k_zfwd<T><<<zgrid, ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
                                                hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
-                                               1.0 / (double)p->N, accumulate ? 1 : 0, gz, nbc);
+                                               1.0 / (double)p->N, accumulate ? 3 : 0, gz, nbc);
     }
   }
   PW_HIP(hipGetLastError());
@@ -1788,7 +1797,10 @@ pw_status nonlocal_side(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hps
   const cpx<T>* beta = sizeof(T) == 8 ? (const cpx<T>*)p->beta64 : (const cpx<T>*)p->beta32;
   PW_TRY(pw::calbec_d<T>(p, nb, psi, ldpsi, bd, side));
   pw::ProfScope ps(pw::PK_ADDNL, side, 8.0 * p->npw * nb * p->nbeta);
-  PW_TRY((pw::zgemm_nn<T, T, T>(p->npw, nb, p->nbeta, 1.0, beta, p->ldb, bd, p->nbeta, 0.0, hpsi, ldhpsi, side)));
+  // hpsi = beta becp' + 1/2 |k+G|^2 psi: the kinetic term rides on the
+  // add-back's coalesced epilogue, so the forward z pass need not gather psi
+  PW_TRY((pw::zgemm_nn<T, T, T>(p->npw, nb, p->nbeta, 1.0, beta, p->ldb, bd, p->nbeta, 0.0, hpsi, ldhpsi, side,
+                                nullptr, p->kin, psi, ldpsi)));
   return PW_OK;
 }
 

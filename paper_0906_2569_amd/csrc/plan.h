@@ -188,10 +188,13 @@ pw_status spsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int
 // C[m, n] = alpha sum_k A[m, k] B[k, n] + beta C[m, n];  A M-contiguous (A[k*lda + m]),
 // B K-contiguous (B[n*ldb + k]), C M-contiguous complex128 (C[n*ldc + m]).
 // `guard (device int, optional): when nonzero at run time the product is skipped.
+// `kin` (device, optional, M entries) adds kin[m] X[n*ldx + m] to C (the
+// kinetic term of H.psi, fused into the projector add-back).
 template <typename T, typename TA, typename TB>
 pw_status zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
                    const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t stream,
-                   const int* guard = nullptr);
+                   const int* guard = nullptr, const double* kin = nullptr, const c128* X = nullptr,
+                   int ldx = 0);
 
 // zgemm_nn in float64 for products with few output tiles: K is split over
 // workgroups and the partials summed in a fixed order (part: workspace of

@@ -266,7 +266,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(GT<T, f
 k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, const cpx<TA>* __restrict__ A1,
           int lda, const cpx<TB>* __restrict__ B, int ldb, double beta, c128* __restrict__ C0,
           c128* __restrict__ C1, int ldc, const int* __restrict__ guard, int kchunk = 0,
-          cpx<T>* __restrict__ P = nullptr) {
+          cpx<T>* __restrict__ P = nullptr, const double* __restrict__ kin = nullptr,
+          const c128* __restrict__ X = nullptr, int ldx = 0) {
   if (guard != nullptr && *guard != 0) return;
   int bx, by, bz;
   xcd_block<true>(bx, by, bz);    // the column tiles of one row strip of A share an XCD
@@ -352,6 +353,11 @@ k_gemm_nn(int M, int N, int K, double alpha, const cpx<TA>* __restrict__ A0, con
             const c128 old = *c;
             re += beta * old.x;
             im += beta * old.y;
+          }
+          if (kin != nullptr) {   // + diag(kin) X (kinetic term of H.psi)
+            const c128 x = X[(size_t)n * ldx + m];
+            re += kin[m] * x.x;
+            im += kin[m] * x.y;
           }
           *c = c128{re, im};
         }
@@ -576,11 +582,11 @@ pw_status pw::calbec_d(pw_plan p, int nb, const c128* psi, int ldpsi, cpx<T>* ou
 template <typename T, typename TA, typename TB>
 pw_status pw::zgemm_nn(int M, int N, int K, double alpha, const cpx<TA>* A, int lda,
                        const cpx<TB>* B, int ldb, double beta, c128* C, int ldc, hipStream_t s,
-                       const int* guard) {
+                       const int* guard, const double* kin, const c128* X, int ldx) {
   if (M <= 0 || N <= 0) return PW_OK;
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 8.0 * M * N * K);
   k_gemm_nn<T, TA, TB><<<dim3(ceil_div(M, GT<T, false>::BM), ceil_div(N, BN), 1), NT, 0, s>>>(
-      M, N, K, alpha, A, A, lda, B, ldb, beta, C, C, ldc, guard);
+      M, N, K, alpha, A, A, lda, B, ldb, beta, C, C, ldc, guard, 0, nullptr, kin, X, ldx);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -631,10 +637,13 @@ template pw_status pw::calbec_d<double>(pw_plan, int, const c128*, int, c128*, h
 template pw_status pw::calbec_d<float>(pw_plan, int, const c128*, int, c64*, hipStream_t, const c64*);
 template pw_status pw::zgemm_nn<double, double, double>(int, int, int, double, const c128*, int,
                                                         const c128*, int, double, c128*, int,
-                                                        hipStream_t, const int*);
+                                                        hipStream_t, const int*, const double*, const c128*,
+                                                        int);
 template pw_status pw::zgemm_nn<float, float, float>(int, int, int, double, const c64*, int,
                                                      const c64*, int, double, c128*, int,
-                                                     hipStream_t, const int*);
+                                                     hipStream_t, const int*, const double*, const c128*,
+                                                     int);
 template pw_status pw::zgemm_nn<float, double, double>(int, int, int, double, const c128*, int,
                                                        const c128*, int, double, c128*, int,
-                                                        hipStream_t, const int*);
+                                                        hipStream_t, const int*, const double*, const c128*,
+                                                        int);

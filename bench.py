@@ -448,6 +448,10 @@ TRAFFIC_BYTES = {
     # calibrated FETCH_SIZE + WRITE_SIZE bytes per launch of the dominant
     # kernel, taken with the kernel as it now stands; an entry is removed
     # whenever that kernel changes, until its counters are taken again.
+    # k_gemm_cn<float, float, double> (three-product form, 128 x 64 tiles),
+    # 8 K chunks: 56.673 GB read + 0.134 GB written
+    # (profiles/hpsi_mixed_512atom_144cubed.md)
+    ("cell512_mixed", "calbec_gemm"): 56.807e9,
 }
 
 
@@ -842,6 +846,13 @@ def main():
         "hpsi_stages": stages,
         "hpsi_graph": graphs,
         "kernel_ms": {k: round(v[1], 3) for k, v in sorted(prof_all.items(), key=lambda kv: -kv[1][1]) if v[0]},
+        # matrix-core products of the solve (subspace projections, Ritz
+        # rotations, reduced products, projector terms): conventional
+        # 8 M N K flops over their time, against the peak of the precision
+        "gemm_rates_fp64": ({k: {"TFLOP_per_s": v[2] / (v[1] * 1e-3) / 1e12,
+                                 "frac_of_fp64_peak": v[2] / (v[1] * 1e-3) / 1e12 / FP64_PEAK_TF}
+                             for k, v in prof_all.items() if k in MFMA_KERNELS and v[1] > 0 and v[2] > 0}
+                            if prec == pwdft.PW_FP64 else None),
         "kernel_ms_from": ("the warm-up steps, every kernel class timed" if args.warmup > 0
                            else "the timed steps"),
     }

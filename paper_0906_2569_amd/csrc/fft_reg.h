@@ -251,18 +251,12 @@ __device__ __forceinline__ void fwd_dif(cpx<T> (&x)[LS], int q, const QuadLane<T
 // radix-2 stages (DPP exchanges with lanes g ^ 8, g ^ 4, g ^ 2, g ^ 1).
 // ---------------------------------------------------------------------------
 
-// value of lane g ^ 4: 7 - i within each half row (row_half_mirror), then
-// 3 - i within each quad: (g ^ 7) ^ 3 = g ^ 4
-__device__ __forceinline__ int lx4_b32(int v) {
-  const int a = __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);
-  return __builtin_amdgcn_mov_dpp(a, 0x1B, 0xF, 0xF, true);
-}
-// value of lane g ^ 8: 15 - i within each row (row_mirror), then 7 - i
-// within each half row: (g ^ 15) ^ 7 = g ^ 8
-__device__ __forceinline__ int lx8_b32(int v) {
-  const int a = __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);
-  return __builtin_amdgcn_mov_dpp(a, 0x141, 0xF, 0xF, true);
-}
+// value of lane g ^ 4 and of lane g ^ 8: one ds_swizzle each in its
+// bit-mask mode (and 0x1F, or 0, xor 4 resp. 8 within groups of 32 lanes),
+// through the LDS crossbar without touching LDS memory; two DPP row
+// permutations would each take a vector ALU slot
+__device__ __forceinline__ int lx4_b32(int v) { return __builtin_amdgcn_ds_swizzle(v, (4 << 10) | 0x1F); }
+__device__ __forceinline__ int lx8_b32(int v) { return __builtin_amdgcn_ds_swizzle(v, (8 << 10) | 0x1F); }
 template <int D>
 __device__ __forceinline__ int lx_b32(int v) {
   if constexpr (D == 8) return lx8_b32(v);

@@ -258,14 +258,14 @@ k_plane_reg(SphereMap m, cpx<T>* __restrict__ sticks, const T* __restrict__ vr,
 // plane is the kernel's only LDS.
 // ---------------------------------------------------------------------------
 constexpr int OCT_G = 16;          // lanes per 1D transform
-// float64: 576 threads (36 groups: a 144^2 plane's 71 columns in two passes,
-// its rows in four), one workgroup per CU (the plane fills the LDS);
-// float32: 512 threads and at most 128 registers, so that two workgroups
-// (two 82 KB planes) share a CU
+// 512 threads (32 groups of 16 lanes).  float64: one workgroup per CU (the
+// plane fills the LDS), two waves per SIMD with up to 256 registers;
+// float32: at most 128 registers, so that two workgroups (two 82 KB planes)
+// share a CU.
 template <typename T>
 struct OctCfg {
-  static constexpr int threads = sizeof(T) == 8 ? 576 : 512;
-  static constexpr int waves = sizeof(T) == 8 ? 3 : 4;
+  static constexpr int threads = 512;
+  static constexpr int waves = sizeof(T) == 8 ? 2 : 4;
 };
 
 // LDS position of (x column c, y): y ^ 2 sigma(c mod 8), sigma rotating the

@@ -679,6 +679,104 @@ k_zfwd_reg(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restric
 }
 
 // ---------------------------------------------------------------------------
+// z passes on 16-lane groups for n3 = 16 LS (float64 columns too long for a
+// quad of lanes to hold in registers, e.g. n3 = 144): one group of 16 lanes
+// per stick, LS points per lane, the same transform as the lane-group plane
+// kernel; twiddles from global memory.
+// ---------------------------------------------------------------------------
+constexpr int ZGTHREADS = 256;
+constexpr int ZGSTICKS = ZGTHREADS / 16;   // sticks per workgroup
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZGTHREADS)
+k_zinv_grp(SphereMap m, const c128* __restrict__ psi, int ldpsi, cpx<T>* __restrict__ sticks,
+           const cpx<T>* __restrict__ tw, int gz, int nb) {
+  constexpr int G = 16, N3 = G * LS;
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  const int s = chunk * ZGSTICKS + (threadIdx.x >> 4);
+  if (s >= m.nst) return;   // the whole group of the stick leaves together
+  const int g = threadIdx.x & (G - 1), nst = m.nst;
+  const c128* pb = psi + (size_t)band * ldpsi;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int j = 0; j < LS; ++j) {
+    const int e = m.zidx[(size_t)(g + G * j) * nst + s];
+    x[j] = e >= 0 ? to_t<T>(pb[e]) : cpx<T>{T(0), T(0)};
+  }
+  const regfft::GLane<T> gl = regfft::glane<T>(g);
+  regfft::ginv<G, LS, T>(x, g, gl, tw);
+  const int blk = regfft::g_block<G>(g);
+  cpx<T>* out = sticks + (size_t)band * N3 * m.ldst + s;
+#pragma unroll
+  for (int k = 0; k < LS; ++k) out[(size_t)(k + LS * blk) * m.ldst] = x[k];
+}
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZGTHREADS)
+k_zfwd_grp(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restrict__ psi, int ldpsi,
+           c128* __restrict__ hpsi, int ldhpsi, const cpx<T>* __restrict__ tw, double inv_n,
+           int accumulate, int gz, int nb) {
+  constexpr int G = 16, N3 = G * LS, XS = N3 + 1;   // padded stick stride of the LDS copy
+  __shared__ cpx<T> X[ZGSTICKS * XS];
+  int chunk, band;
+  if (!z_tile(gz, nb, chunk, band)) return;
+  const int s0 = chunk * ZGSTICKS, sl = threadIdx.x >> 4, s = s0 + sl;
+  const int g = threadIdx.x & (G - 1);
+  if (s < m.nst) {
+    const int blk = regfft::g_block<G>(g);
+    const cpx<T>* in = sticks + (size_t)band * N3 * m.ldst + s;
+    cpx<T> x[LS];
+#pragma unroll
+    for (int k = 0; k < LS; ++k) x[k] = in[(size_t)(k + LS * blk) * m.ldst];
+    const regfft::GLane<T> gl = regfft::glane<T>(g);
+    regfft::gfwd<G, LS, T>(x, g, gl, tw);
+#pragma unroll
+    for (int j = 0; j < LS; ++j) X[sl * XS + g + G * j] = x[j];
+  }
+  __syncthreads();
+  // the chunk's sphere entries in stick order: coalesced index reads
+  const c128* pb = psi + (size_t)band * ldpsi;
+  c128* hb = hpsi + (size_t)band * ldhpsi;
+  const int e0 = m.st_ptr[s0], e1 = m.st_ptr[min(s0 + ZGSTICKS, m.nst)];
+  for (int e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int gi = m.ent_g[e];
+    const cpx<T> v = X[(m.ent_s[e] - s0) * XS + m.ent_z[e]];
+    c128 r = c128{(double)v.x * inv_n, (double)v.y * inv_n};
+    if (!(accumulate & 2)) {   // kinetic term (not yet in hpsi)
+      const c128 p = pb[gi];
+      const double t = m.kin[gi];
+      r = c128{r.x + t * p.x, r.y + t * p.y};
+    }
+    if (accumulate & 1) {   // the projector and kinetic terms are already in hpsi
+      const c128 o = hb[gi];
+      r = c128{r.x + o.x, r.y + o.y};
+    }
+    hb[gi] = r;
+  }
+}
+
+template <typename T>
+struct ZGrpFns {
+  void (*inv)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int) = nullptr;
+  void (*fwd)(SphereMap, const cpx<T>*, const c128*, int, c128*, int, const cpx<T>*, double, int, int, int) = nullptr;
+};
+
+// 16-lane-group z passes for n3 = 16 LS, or none
+template <typename T>
+ZGrpFns<T> zgrp_kernels(int n3) {
+  ZGrpFns<T> f;
+  switch (n3) {
+    case 80: f.inv = k_zinv_grp<T, 5>; f.fwd = k_zfwd_grp<T, 5>; break;
+    case 96: f.inv = k_zinv_grp<T, 6>; f.fwd = k_zfwd_grp<T, 6>; break;
+    case 128: f.inv = k_zinv_grp<T, 8>; f.fwd = k_zfwd_grp<T, 8>; break;
+    case 144: f.inv = k_zinv_grp<T, 9>; f.fwd = k_zfwd_grp<T, 9>; break;
+    default: break;
+  }
+  return f;
+}
+
+// ---------------------------------------------------------------------------
 // Gamma point (real wavefunctions on the half sphere): bands a = 2t and
 // b = 2t + 1 share transform t.  The inverse z pass packs a + i b onto the
 // sticks of the whole sphere (conj(a) + i conj(b) at the mirror -G), so the
@@ -1668,6 +1766,9 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
   const int gz = ceil_div(p->nst, ZSB);
   const ZRegFns<T> zr = p->use_reg_plane ? zreg_kernels<T>(p->n3) : ZRegFns<T>{};
   const int gzr = ceil_div(p->nst, ZRSTICKS);
+  // 16-lane-group z passes where no quad form exists (the complex path)
+  const ZGrpFns<T> zg = (p->use_reg_plane && zr.inv == nullptr) ? zgrp_kernels<T>(p->n3) : ZGrpFns<T>{};
+  const int gzg = ceil_div(p->nst, ZGSTICKS);
   // algorithmic bytes per band: sphere in/out (complex128) and one write plus
   // one read of the stick columns per transform direction; V(r) once per pass
   const double sphere_b = 16.0 * p->npw, stick_b = (double)sizeof(cpx<T>) * p->n3 * p->nst;
@@ -1690,6 +1791,8 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
       pw::ProfScope ps(pw::PK_ZINV, s, nbc * (sphere_b + stick_b));
       if (zr.inv)
         zr.inv<<<zrgrid, ZRTHREADS, 0, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gzr, nbc);
+      else if (zg.inv)
+        zg.inv<<<gzg * nbc8, ZGTHREADS, 0, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gzg, nbc);
       else
         k_zinv<T><<<zgrid, ZTHREADS, zl, s>>>(m, psi + (size_t)c0 * ldpsi, ldpsi, st, tw3, gz, nbc);
     }
@@ -1719,6 +1822,10 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
         zr.fwd<<<zrgrid, ZRTHREADS, 0, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
                                             hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
                                             1.0 / (double)p->N, accumulate ? 3 : 0, gzr, nbc);
+      else if (zg.fwd)
+        zg.fwd<<<gzg * nbc8, ZGTHREADS, 0, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
+                                               hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,
+                                               1.0 / (double)p->N, accumulate ? 3 : 0, gzg, nbc);
       else
         k_zfwd<T><<<zgrid, ZTHREADS, zl, s>>>(m, st, psi + (size_t)c0 * ldpsi, ldpsi,
                                                hpsi + (size_t)c0 * ldhpsi, ldhpsi, tw3,

@@ -365,3 +365,15 @@ def test_plane_form_tuning(ctx, n, n3, ecut, expect_forms):
         assert err <= (1e-11 if prec == 0 else 2e-6), err
     assert forms[1] == forms[2]   # cached per shape
     assert forms[0][0] == forms[1][0]
+
+
+@pytest.mark.parametrize("n3", [80, 96, 128, 144])
+def test_group_z_passes_float64(ctx, n3):
+    # float64 columns of n3 = 16 LS points beyond the quad form (LS > 18)
+    # take the 16-lane-group z passes; odd in-plane grid sizes keep the
+    # plane pass on its other forms
+    p = pwgen.tiny_cell(600 + n3, a=7.0, ecut_ry=9.0, natoms=2, nb=5, kfrac=(0.25, -0.25, 0.0), nr=(30, 27, n3))
+    assert max(pwgen.min_grid(p.miller)) <= 27
+    got = _hpsi(ctx, p, p.psi0, prec=0)
+    ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
+    assert _rel_err(got, ref) <= 1e-11

@@ -756,26 +756,6 @@ k_zfwd_grp(SphereMap m, const cpx<T>* __restrict__ sticks, const c128* __restric
   }
 }
 
-template <typename T>
-struct ZGrpFns {
-  void (*inv)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int) = nullptr;
-  void (*fwd)(SphereMap, const cpx<T>*, const c128*, int, c128*, int, const cpx<T>*, double, int, int, int) = nullptr;
-};
-
-// 16-lane-group z passes for n3 = 16 LS, or none
-template <typename T>
-ZGrpFns<T> zgrp_kernels(int n3) {
-  ZGrpFns<T> f;
-  switch (n3) {
-    case 80: f.inv = k_zinv_grp<T, 5>; f.fwd = k_zfwd_grp<T, 5>; break;
-    case 96: f.inv = k_zinv_grp<T, 6>; f.fwd = k_zfwd_grp<T, 6>; break;
-    case 128: f.inv = k_zinv_grp<T, 8>; f.fwd = k_zfwd_grp<T, 8>; break;
-    case 144: f.inv = k_zinv_grp<T, 9>; f.fwd = k_zfwd_grp<T, 9>; break;
-    default: break;
-  }
-  return f;
-}
-
 // ---------------------------------------------------------------------------
 // Gamma point (real wavefunctions on the half sphere): bands a = 2t and
 // b = 2t + 1 share transform t.  The inverse z pass packs a + i b onto the
@@ -927,6 +907,82 @@ k_gamma_gather(int npw, const int* __restrict__ gpos_p, const int* __restrict__ 
     c128* o = hpsi + (size_t)band * ldhpsi + g;
     if (accumulate) r = c128{r.x + o->x, r.y + o->y};
     *o = r;
+  }
+}
+
+// Gamma z passes on 16-lane groups (n3 = 16 LS, float64 beyond the quad form)
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZGTHREADS)
+k_zinv_grp_g(SphereMap m, const c128* __restrict__ psi, int ldpsi, cpx<T>* __restrict__ sticks,
+             const cpx<T>* __restrict__ tw, int gz, int npair, int nbands) {
+  constexpr int G = 16, N3 = G * LS;
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  const int s = chunk * ZGSTICKS + (threadIdx.x >> 4);
+  if (s >= m.nst) return;
+  const int g = threadIdx.x & (G - 1), nst = m.nst;
+  const c128* pa = psi + (size_t)(2 * pair) * ldpsi;
+  const c128* pb = 2 * pair + 1 < nbands ? pa + ldpsi : nullptr;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int j = 0; j < LS; ++j) {
+    const int enc = m.zidx[(size_t)(g + G * j) * nst + s];
+    x[j] = enc >= 0 ? to_t<T>(gamma_pack(pa, pb, enc)) : cpx<T>{T(0), T(0)};
+  }
+  const regfft::GLane<T> gl = regfft::glane<T>(g);
+  regfft::ginv<G, LS, T>(x, g, gl, tw);
+  const int blk = regfft::g_block<G>(g);
+  cpx<T>* out = sticks + (size_t)pair * N3 * m.ldst + s;
+#pragma unroll
+  for (int k = 0; k < LS; ++k) out[(size_t)(k + LS * blk) * m.ldst] = x[k];
+}
+
+template <typename T, int LS>
+__global__ void __launch_bounds__(ZGTHREADS)
+k_zfwd_grp_g(SphereMap m, cpx<T>* __restrict__ sticks, const cpx<T>* __restrict__ tw, int gz, int npair) {
+  constexpr int G = 16, N3 = G * LS;
+  int chunk, pair;
+  if (!z_tile(gz, npair, chunk, pair)) return;
+  const int s = chunk * ZGSTICKS + (threadIdx.x >> 4);
+  if (s >= m.nst) return;
+  const int g = threadIdx.x & (G - 1);
+  const int blk = regfft::g_block<G>(g);
+  cpx<T>* io = sticks + (size_t)pair * N3 * m.ldst + s;
+  cpx<T> x[LS];
+#pragma unroll
+  for (int k = 0; k < LS; ++k) x[k] = io[(size_t)(k + LS * blk) * m.ldst];
+  const regfft::GLane<T> gl = regfft::glane<T>(g);
+  regfft::gfwd<G, LS, T>(x, g, gl, tw);
+#pragma unroll
+  for (int j = 0; j < LS; ++j) io[(size_t)(g + G * j) * m.ldst] = x[j];
+}
+
+template <typename T>
+struct ZGrpFns {
+  void (*inv)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int) = nullptr;
+  void (*fwd)(SphereMap, const cpx<T>*, const c128*, int, c128*, int, const cpx<T>*, double, int, int, int) = nullptr;
+  void (*inv_g)(SphereMap, const c128*, int, cpx<T>*, const cpx<T>*, int, int, int) = nullptr;
+  void (*fwd_g)(SphereMap, cpx<T>*, const cpx<T>*, int, int) = nullptr;
+};
+template <typename T, int LS>
+ZGrpFns<T> zgrp_set() {
+  ZGrpFns<T> f;
+  f.inv = k_zinv_grp<T, LS>;
+  f.fwd = k_zfwd_grp<T, LS>;
+  f.inv_g = k_zinv_grp_g<T, LS>;
+  f.fwd_g = k_zfwd_grp_g<T, LS>;
+  return f;
+}
+
+// 16-lane-group z passes for n3 = 16 LS, or none
+template <typename T>
+ZGrpFns<T> zgrp_kernels(int n3) {
+  switch (n3) {
+    case 80: return zgrp_set<T, 5>();
+    case 96: return zgrp_set<T, 6>();
+    case 128: return zgrp_set<T, 8>();
+    case 144: return zgrp_set<T, 9>();
+    default: return ZGrpFns<T>{};
   }
 }
 
@@ -1785,6 +1841,8 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
       pw::ProfScope ps(pw::PK_ZINV, s, nbb * sphere_b + nbc * stick_b);
       if (zr.inv_g)
         zr.inv_g<<<zrgrid, ZRTHREADS, 0, s>>>(m, psi + (size_t)b0 * ldpsi, ldpsi, st, tw3, gzr, nbc, nbb);
+      else if (zg.inv_g)
+        zg.inv_g<<<gzg * nbc8, ZGTHREADS, 0, s>>>(m, psi + (size_t)b0 * ldpsi, ldpsi, st, tw3, gzg, nbc, nbb);
       else
         k_zinv_g<T><<<zgrid, ZTHREADS, zl, s>>>(m, psi + (size_t)b0 * ldpsi, ldpsi, st, tw3, gz, nbc, nbb);
     } else {
@@ -1804,6 +1862,8 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
       pw::ProfScope ps(pw::PK_ZFWD, s, nbb * sphere_b + nbc * stick_b);
       if (zr.fwd_g)
         zr.fwd_g<<<zrgrid, ZRTHREADS, 0, s>>>(m, st, tw3, gzr, nbc);
+      else if (zg.fwd_g)
+        zg.fwd_g<<<gzg * nbc8, ZGTHREADS, 0, s>>>(m, st, tw3, gzg, nbc);
       else
         k_zfwd_g<T><<<zgrid, ZTHREADS, zl, s>>>(m, st, tw3, gz, nbc);
       if (join != nullptr && c0 == 0) PW_HIP(hipStreamWaitEvent(s, join, 0));

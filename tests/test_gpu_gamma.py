@@ -128,3 +128,15 @@ def test_gamma_config2_solve_against_golden(ctx):
     print("gamma config-2 solve", stats, "max err", np.abs(eig - w).max())
     assert st == 0
     np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+
+
+@pytest.mark.parametrize("n3", [80, 144])
+def test_gamma_group_z_passes_float64(ctx, n3):
+    # float64 Gamma columns of n3 = 16 LS points beyond the quad form take the
+    # 16-lane-group z passes (band pairs packed as a + i b)
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 15, 23, nr=(30, 30, n3))
+    h = oracle.dense_h_of(g.full)
+    got, _ = _hpsi(ctx, g, g.psi0)
+    ref = oracle.hpsi(h, g.expand(g.psi0))[:, g.half]
+    assert _rel(got, ref) <= 1e-11
+    assert np.abs(got[:, 0].imag).max() == 0.0

@@ -140,6 +140,15 @@ typedef struct {
                                 already converged are locked: kept fixed, projected out of every
                                 later correction and left out of the reduced problems, which then
                                 only hold the unconverged bands; 0: every band stays in the basis */
+  int32_t sub32;             /* mixed only.  2: while H.psi is float32, the Ritz rotations (phi c,
+                                (H phi) c) run in float32 arithmetic on the complex128 basis, and at
+                                each collapse the overlap of the rotated block is formed (float32
+                                products) instead of taken as the identity; the projections
+                                phi^H H phi and phi^H phi, the Cholesky factor, the reduced
+                                eigenproblem and the residual norms stay float64, and so does every
+                                product of the float64 stage.  1 (default): as 2 for blocks whose
+                                rotation is long (16 npw nb^2 >= 1e11 flops), else as 0.
+                                0: float64 rotations                                              */
 } pw_david_opts;
 
 typedef struct {

@@ -50,4 +50,5 @@ extern "C" void pw_david_opts_default(pw_david_opts* o) {
   o->ladder_switch = 3e-4;
   o->history = nullptr;
   o->lock = 1;
+  o->sub32 = 1;
 }

@@ -424,6 +424,8 @@ constexpr double kMaxAmp32 = 1e2;
 // floor lies above ladder_switch)
 constexpr double kStallZone = 100.0;
 constexpr int kStall32 = 12;
+// rotation work (16 npw nb^2 flops) from which sub32 = 1 takes float32 rotations
+constexpr double kSub32MinFlops = 1e11;
 
 struct Solver {
   pw_plan p;
@@ -432,6 +434,20 @@ struct Solver {
   pw_david_stats& stats;
   int nfact = 0;   // leading basis size whose overlap factor is current
   int nl = 0;      // locked bands: psi[0:nl), hpsi[0:nl), eps[0:nl) stay fixed
+  bool sub32 = false;   // Ritz rotations in float32 arithmetic (float32 stage)
+
+  // The projections stay float64 in every stage: an overlap matrix from
+  // float32 products (entry errors of about 5e-7 at npw 191k) breaks the
+  // dependence test of the incremental Cholesky, whose inverse factor
+  // multiplies those errors along K-long columns (a pivot of -4e-3 where a
+  // tiny positive one belonged, at the 512-atom cell).  Only the collapsed
+  // block's overlap, a near-identity, is formed from float32 products (see
+  // collapse); its errors then enter the pivots unamplified, and a direction
+  // counts as dependent below a relative pivot of 1e-5 instead of 1e-10.
+  void set_sub32(bool on) {
+    sub32 = on;
+    W.hw.drop_tol = on ? 1e-5 : 1e-10;
+  }
 
   // H x and, for ultrasoft plans, S x (columns at the same offsets in sphi)
   pw_status hpsi(pw_precision prec, int n, const c128* x, c128* hx, c128* sx = nullptr) {
@@ -485,22 +501,22 @@ struct Solver {
       k_real_part<<<std::min(1024, ceil_div(nbase * nact, 256)), 256, 0, st>>>(nbase, nact, W.cvec, ldm, W.creal);
       PW_HIP(hipGetLastError());
       const long l2 = 2L * W.ld;
-      PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, nact, nbase, 1.0,
-                                                   reinterpret_cast<const double*>(W.phi), l2, W.creal, ldm, 0.0,
-                                                   reinterpret_cast<double*>(W.psi + (size_t)nl * W.ld), l2, st,
-                                                   W.hw.info)));
-      PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, nact, nbase, 1.0,
-                                                   reinterpret_cast<const double*>(W.hphi), l2, W.creal, ldm, 0.0,
-                                                   reinterpret_cast<double*>(W.hpsi + (size_t)nl * W.ld), l2, st,
-                                                   W.hw.info)));
+      auto nn = sub32 ? pw::dgemm_nn<float, double, double> : pw::dgemm_nn<double, double, double>;
+      PW_TRY(nn(2 * p->npw, nact, nbase, 1.0, reinterpret_cast<const double*>(W.phi), l2, W.creal, ldm, 0.0,
+                reinterpret_cast<double*>(W.psi + (size_t)nl * W.ld), l2, st, W.hw.info, -1));
+      PW_TRY(nn(2 * p->npw, nact, nbase, 1.0, reinterpret_cast<const double*>(W.hphi), l2, W.creal, ldm, 0.0,
+                reinterpret_cast<double*>(W.hpsi + (size_t)nl * W.ld), l2, st, W.hw.info, -1));
       return PW_OK;
     }
     // psi = phi c and hpsi = (H phi) c in one launch
-    PW_TRY(pw::zgemm_nn_pair(p->npw, nact, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi + (size_t)nl * W.ld,
-                             W.hpsi + (size_t)nl * W.ld, W.ld, st, W.hw.info));
-    if (p->us)   // S psi = (S phi) c
-      PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, nact, nbase, 1.0, W.sphi, W.ld, W.cvec, ldm, 0.0,
-                                                   W.spsi + (size_t)nl * W.ld, W.ld, st, W.hw.info)));
+    auto nn = sub32 ? pw::zgemm_nn_pair<float> : pw::zgemm_nn_pair<double>;
+    PW_TRY(nn(p->npw, nact, nbase, W.phi, W.hphi, W.ld, W.cvec, ldm, W.psi + (size_t)nl * W.ld,
+              W.hpsi + (size_t)nl * W.ld, W.ld, st, W.hw.info));
+    if (p->us) {   // S psi = (S phi) c
+      auto sn = sub32 ? pw::zgemm_nn<float, double, double> : pw::zgemm_nn<double, double, double>;
+      PW_TRY(sn(p->npw, nact, nbase, 1.0, W.sphi, W.ld, W.cvec, ldm, 0.0, W.spsi + (size_t)nl * W.ld, W.ld, st,
+                W.hw.info, nullptr, nullptr, 0));
+    }
     return PW_OK;
   }
 
@@ -519,6 +535,29 @@ struct Solver {
     PW_HIP(hipGetLastError());
     PW_TRY(pw::heig_reset(W.hw, nact, st));
     nfact = nact;
+    if (sub32) {
+      // Ritz vectors rotated with float32 products are orthonormal only to
+      // about 1e-6, and that error would add up over collapses if the block
+      // were taken as orthonormal: its overlap is formed explicitly instead
+      // (H stays diag(eps): its error is of the order of the float32 stage's
+      // own) and factored afresh
+      const int ldm = W.nbasis;
+      const c128* sb = p->us ? W.sphi : W.phi;
+      if (p->gamma) {
+        const long l2 = 2L * W.ld;
+        PW_TRY((pw::dgemm_tn<float, double, double>(nact, nact, 2 * p->npw, reinterpret_cast<const double*>(W.phi),
+                                                    l2, reinterpret_cast<const double*>(sb), l2, 1.0, 1.0, 0.0,
+                                                    reinterpret_cast<double*>(W.sred), ldm, true, W.part,
+                                                    W.part_bytes, st)));
+      } else {
+        PW_TRY((pw::zgemm_cn<float, double, double>(nact, nact, p->npw, W.phi, W.ld, sb, W.ld, W.sred, ldm, W.part,
+                                                    W.part_bytes, st)));
+      }
+      const int blocks = std::min(1024, ceil_div((size_t)nact * nact, 256));
+      k_herm_fill<<<dim3(blocks, 2), 256, 0, st>>>(0, nact, W.hred, W.sred, ldm);
+      PW_HIP(hipGetLastError());
+      nfact = 0;
+    }
     return PW_OK;
   }
 
@@ -645,6 +684,11 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, psi, sizeof(c128) * ldpsi, sizeof(c128) * npw, nb,
                           hipMemcpyDeviceToDevice, st));
   if (p->gamma) k_zero_im0<<<1, 256, 0, st>>>(nb, W.phi, W.ld);
+  // float32 rotations pay where a rotation takes milliseconds; on small blocks
+  // the overlap formed at each collapse and its fresh factorization cost more
+  // than they save (64-atom cell: 141 against 135 ms per mixed solve)
+  const bool long_rot = 16.0 * npw * (double)nb * nb >= kSub32MinFlops;
+  S.set_sub32(prec == PW_MIXED && (o.sub32 == 2 || (o.sub32 == 1 && long_rot)));
   PW_TRY(S.start_block(prec, nb));
   k_fill<<<1, 256, 0, st>>>(nb, INFINITY, W.eps_prev);
   int nbase = nb;
@@ -690,7 +734,9 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
     }
     if (fp32_stage && (f.n_new == 0 || stall32 >= kStall32)) {
       // precision ladder: continue from the Ritz vectors with float64 H.psi
+      // and float64 subspace products
       prec = PW_FP64;
+      S.set_sub32(false);
       S.nl = 0;
       PW_HIP(hipMemcpy2DAsync(W.phi, sizeof(c128) * W.ld, W.psi, sizeof(c128) * W.ld, sizeof(c128) * npw, nb,
                               hipMemcpyDeviceToDevice, st));

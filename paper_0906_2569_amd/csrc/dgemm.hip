@@ -300,3 +300,9 @@ template pw_status pw::dgemm_nn<double, double, double>(int, int, int, double, c
                                                         long, double, double*, long, hipStream_t, const int*, int);
 template pw_status pw::dgemm_nn<float, float, float>(int, int, int, double, const float*, long, const float*, long,
                                                      double, double*, long, hipStream_t, const int*, int);
+// float32 arithmetic on float64 operands (subspace products of the float32 stage)
+template pw_status pw::dgemm_tn<float, double, double>(int, int, int, const double*, long, const double*, long,
+                                                       double, double, double, double*, int, bool, void*, size_t,
+                                                       hipStream_t, int);
+template pw_status pw::dgemm_nn<float, double, double>(int, int, int, double, const double*, long, const double*,
+                                                       long, double, double*, long, hipStream_t, const int*, int);

@@ -24,6 +24,10 @@ struct HeigWork {
   bool coop_wide = false;  // cooperative tridiagonalization with 16 rows per workgroup at every
                            // size (half the workgroups of the 8-row form used up to 512 rows):
                            // the form for solves that run concurrently
+  double drop_tol = 1e-10; // Cholesky pivot, relative to the original diagonal entry, below which
+                           // a basis direction counts as dependent (lies, to the accuracy of S,
+                           // in the span of the earlier ones); callers whose S comes from float32
+                           // products raise it above that accuracy
 };
 
 size_t heig_work_bytes(int nmax);

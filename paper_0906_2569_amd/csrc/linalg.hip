@@ -23,8 +23,6 @@
 namespace {
 
 constexpr int NTL = 1024;  // threads of the single-workgroup factorizations
-// relative pivot below which a basis direction counts as dependent
-constexpr double kDropTol = 1e-10;
 
 __device__ __forceinline__ c128 cconj(c128 a) { return c128{a.x, -a.y}; }
 
@@ -1587,16 +1585,16 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   {
     pw::ProfScope ps(pw::PK_CHOL, st, 4.0 / 3.0 * m * m * (double)m);
     if (m <= kChRegN) {
-      k_chol_reg<<<1, 1024, 0, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info, hw.drop, n, nev);
+      k_chol_reg<<<1, 1024, 0, st>>>(m, 0, hw.drop_tol, L22, ldw, hw.drop + n0, hw.info, hw.drop, n, nev);
     } else if (m < kChBlockedMinN) {
-      k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, kDropTol, L22, ldw, hw.drop + n0, hw.info);
+      k_chol<<<1, NTL, (sizeof(c128) + sizeof(double)) * m, st>>>(m, 0, hw.drop_tol, L22, ldw, hw.drop + n0, hw.info);
     } else {
       double* diag0 = hw.scratch;   // free until the eigenvector step
       c128* PT = hw.Y;              // free until X12 is formed
       k_chol_init<<<std::min(64, ceil_div(m, 256)), 256, 0, st>>>(m, L22, ldw, diag0, hw.cflags);
       for (int j0 = 0; j0 < m; j0 += kChPanel) {
         const int bb = std::min(kChPanel, m - j0);
-        k_chol_panel<<<1, NTL, sizeof(c128) * m, st>>>(m, j0, bb, kDropTol, L22, ldw, diag0, hw.drop + n0,
+        k_chol_panel<<<1, NTL, sizeof(c128) * m, st>>>(m, j0, bb, hw.drop_tol, L22, ldw, diag0, hw.drop + n0,
                                                       hw.cflags, PT);
         const int mt = m - j0 - bb;
         if (mt > 0) {

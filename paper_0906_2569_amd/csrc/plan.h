@@ -207,7 +207,10 @@ pw_status zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int lda,
 pw_status zgemm_cn_pair(int M, int N, int K, const c128* A, int lda, const c128* B0, const c128* B1, int ldb,
                         c128* C0, c128* C1, int ldc, void* part, size_t part_bytes, hipStream_t stream);
 
-// C0 = A0 B and C1 = A1 B (float64, same shapes and leading dimensions) in one launch
+// C0 = A0 B and C1 = A1 B (same shapes and leading dimensions) in one launch.  T is the
+// arithmetic: double, or float (complex128 operands rounded to float32 as they are
+// staged into LDS, float32 products and sums, complex128 result)
+template <typename T = double>
 pw_status zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1, int lda, const c128* B, int ldb,
                         c128* C0, c128* C1, int ldc, hipStream_t stream, const int* guard = nullptr);
 

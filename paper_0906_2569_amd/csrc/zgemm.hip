@@ -617,16 +617,21 @@ pw_status pw::zgemm_nn_sk(int M, int N, int K, double alpha, const c128* A, int 
   return PW_OK;
 }
 
+template <typename T>
 pw_status pw::zgemm_nn_pair(int M, int N, int K, const c128* A0, const c128* A1, int lda, const c128* B,
                             int ldb, c128* C0, c128* C1, int ldc, hipStream_t s, const int* guard) {
   if (M <= 0 || N <= 0) return PW_OK;
   pw::ProfScope ps(pw::PK_GEMM_NN, s, 16.0 * M * N * K);
-  k_gemm_nn<double, double, double><<<dim3(ceil_div(M, GT<double, false>::BM), ceil_div(N, BN), 2), NT, 0, s>>>(
+  k_gemm_nn<T, double, double><<<dim3(ceil_div(M, GT<T, false>::BM), ceil_div(N, BN), 2), NT, 0, s>>>(
       M, N, K, 1.0, A0, A1, lda, B, ldb, 0.0, C0, C1, ldc, guard);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
 
+template pw_status pw::zgemm_nn_pair<double>(int, int, int, const c128*, const c128*, int, const c128*, int, c128*,
+                                             c128*, int, hipStream_t, const int*);
+template pw_status pw::zgemm_nn_pair<float>(int, int, int, const c128*, const c128*, int, const c128*, int, c128*,
+                                            c128*, int, hipStream_t, const int*);
 template pw_status pw::zgemm_cn<double, double, double>(int, int, int, const c128*, int, const c128*,
                                                         int, c128*, int, void*, size_t, hipStream_t,
                                                         double, double, const c128*, int);

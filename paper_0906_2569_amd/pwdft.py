@@ -52,7 +52,8 @@ class PlanOpts(C.Structure):
 class DavOpts(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("max_iter", C.c_int32), ("tol_resid", C.c_double),
                 ("tol_deig", C.c_double), ("precond_floor", C.c_double),
-                ("ladder_switch", C.c_double), ("history", C.POINTER(C.c_double)), ("lock", C.c_int32)]
+                ("ladder_switch", C.c_double), ("history", C.POINTER(C.c_double)), ("lock", C.c_int32),
+                ("sub32", C.c_int32)]
 
 
 class CgOpts(C.Structure):

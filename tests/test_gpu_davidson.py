@@ -90,10 +90,12 @@ def test_tiny_cells(ctx, seed, a, ecut, kfrac, nr, natoms, nb):
     np.testing.assert_allclose(eig, w, atol=TOL_EIG)
 
 
-def test_mixed_precision_ladder(ctx):
+@pytest.mark.parametrize("sub32", [2, 0])
+def test_mixed_precision_ladder(ctx, sub32):
+    # sub32 = 2: the float32 stage rotates in float32 arithmetic (forced at this size)
     p = pwgen.config1()
     w, _ = oracle.eigh_lowest(oracle.dense_h_of(p), p.nb)
-    st, eig, resid, psi, stats = _solve(ctx, p, precision=1, ndim=4)
+    st, eig, resid, psi, stats = _solve(ctx, p, precision=1, ndim=4, sub32=sub32)
     print("mixed stats", stats, "max |err|", np.abs(eig - w).max())
     assert st == 0
     assert stats["n_hpsi_fp32"] > 0 and stats["n_hpsi_fp64"] > 0
@@ -150,15 +152,16 @@ def _golden_config2():
     return np.loadtxt(path)
 
 
-@pytest.mark.parametrize("precision,ndim", [(0, 3), (1, 2)])
-def test_config2_config3_solve_against_dense_oracle(ctx, precision, ndim):
+@pytest.mark.parametrize("precision,ndim,sub32", [(0, 3, 1), (1, 2, 1), (1, 2, 2)])
+def test_config2_config3_solve_against_dense_oracle(ctx, precision, ndim, sub32):
     # the timed 64-atom solves at the benchmark's settings (float64: basis 3 nb;
-    # mixed: basis 2 nb with the precision ladder; locking on) against the
-    # lowest 128 eigenvalues of the oracle's dense 18277^2 Hamiltonian
+    # mixed: basis 2 nb with the precision ladder, float64 rotations (the
+    # default at this size) or float32 ones in its float32 stage; locking on) against the lowest 128 eigenvalues
+    # of the oracle's dense 18277^2 Hamiltonian
     p = pwgen.config2()
     w = _golden_config2()
     assert w.shape == (p.nb,)
-    st, eig, resid, psi, stats = _solve(ctx, p, precision=precision, ndim=ndim, max_iter=400)
+    st, eig, resid, psi, stats = _solve(ctx, p, precision=precision, ndim=ndim, max_iter=400, sub32=sub32)
     err = np.abs(eig - w)
     print("precision", precision, "stats", stats, "max |eps - eps_oracle|", err.max(), "Ha; band of max",
           int(err.argmax()))

@@ -103,12 +103,13 @@ def _solve(ctx, g, precision=0, ndim=4, **kw):
         plan.close()
 
 
-@pytest.mark.parametrize("precision,ndim,lock", [(0, 4, 1), (0, 2, 1), (1, 4, 1), (0, 3, 0)])
-def test_gamma_davidson_against_dense(ctx, precision, ndim, lock):
+@pytest.mark.parametrize("precision,ndim,lock,sub32", [(0, 4, 1, 1), (0, 2, 1, 1), (1, 4, 1, 1), (1, 4, 1, 2),
+                                                       (0, 3, 0, 1)])
+def test_gamma_davidson_against_dense(ctx, precision, ndim, lock, sub32):
     g = pwgen.gamma_cell(10.0, 15.0, 8, 16, 25, nr=(30, 30, 30))
     h = oracle.dense_h_of(g.full)
     w, _ = oracle.eigh_lowest(h, g.nb)
-    st, eig, resid, psi, stats = _solve(ctx, g, precision, ndim, lock=lock)
+    st, eig, resid, psi, stats = _solve(ctx, g, precision, ndim, lock=lock, sub32=sub32)
     print("gamma Davidson", precision, ndim, lock, stats, "max err", np.abs(eig - w).max())
     assert st == 0
     np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
@@ -118,13 +119,15 @@ def test_gamma_davidson_against_dense(ctx, precision, ndim, lock):
     np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)
 
 
-def test_gamma_config2_solve_against_golden(ctx):
+@pytest.mark.parametrize("precision,ndim", [(0, 3), (1, 2)])
+def test_gamma_config2_solve_against_golden(ctx, precision, ndim):
     # the 64-atom cell at Gamma (diagonal D: the -i of the p projectors leaves
-    # H unchanged) against the golden dense-oracle eigenvalues
+    # H unchanged) against the golden dense-oracle eigenvalues; mixed: the
+    # float32 stage with float32 real Ritz rotations
     import os
     g = pwgen.gamma_cell(20.5, 25.0, 64, 128, pwgen.SEED_BASE + 2, nr=(72, 72, 72))
     w = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_eigenvalues.txt"))
-    st, eig, resid, psi, stats = _solve(ctx, g, 0, 3)
+    st, eig, resid, psi, stats = _solve(ctx, g, precision, ndim, sub32=2)
     print("gamma config-2 solve", stats, "max err", np.abs(eig - w).max())
     assert st == 0
     np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)

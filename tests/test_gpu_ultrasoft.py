@@ -61,8 +61,10 @@ def test_spsi_is_identity_without_q(ctx):
         plan.close()
 
 
-@pytest.mark.parametrize("precision,ndim", [(0, 2), (0, 4), (1, 4)])
-def test_generalized_davidson_against_dense(ctx, precision, ndim):
+@pytest.mark.parametrize("precision,ndim,sub32", [(0, 2, 1), (0, 4, 1), (1, 4, 1), (1, 4, 2)])
+def test_generalized_davidson_against_dense(ctx, precision, ndim, sub32):
+    # sub32 = 2: float32 rotations of phi, H phi and S phi in the float32 stage,
+    # the collapsed block's S-overlap formed from float32 products
     from paper_0906_2569_amd import pwdft
     p = _us(pwgen.config1(), 42)
     h, s = oracle.dense_h_of(p), oracle.dense_s_of(p)
@@ -70,7 +72,7 @@ def test_generalized_davidson_against_dense(ctx, precision, ndim):
     plan = pwdft.Plan(ctx, p, precision=precision, nb_max=p.nb, ndim_max=max(ndim, 2))
     try:
         x = torch.from_numpy(p.psi0).cuda()
-        st, eig, resid, stats = plan.davidson(x, opts=pwdft.default_opts(ndim=ndim, max_iter=400))
+        st, eig, resid, stats = plan.davidson(x, opts=pwdft.default_opts(ndim=ndim, max_iter=400, sub32=sub32))
         torch.cuda.synchronize()
         eig, resid, psi = eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy()
     finally:

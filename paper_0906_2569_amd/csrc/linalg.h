@@ -24,6 +24,7 @@ struct HeigWork {
   bool coop_wide = false;  // cooperative tridiagonalization with 16 rows per workgroup at every
                            // size (half the workgroups of the 8-row form used up to 512 rows):
                            // the form for solves that run concurrently
+  int cus = 0;             // compute units of the device (set by heig_setup)
   double drop_tol = 1e-10; // Cholesky pivot, relative to the original diagonal entry, below which
                            // a basis direction counts as dependent (lies, to the accuracy of S,
                            // in the span of the earlier ones); callers whose S comes from float32

@@ -705,16 +705,19 @@ __global__ void k_tridiag_last(int n, const c128* __restrict__ A, int ld, double
 
 // ---------------------------------------------------------------------------
 // Cooperative Householder tridiagonalization for 64 <= n <= 2048: P =
-// ceil(n / CR) workgroups, workgroup q holding CR rows of the
-// Hermitian matrix B (row r = conj of column r of A) in registers.  Rows are
-// dealt cyclically (row r to workgroup r mod P), so every workgroup keeps
-// about (n - k) / P live rows at step k; thread t holds columns t mod 256 and
-// t mod 256 + 256 of half of its workgroup's rows (two waves per SIMD).
+// ceil(n / CRT) workgroups (CRT = 8 or 16 rows each), workgroup q holding CRT
+// rows of the Hermitian matrix B (row r = conj of column r of A) in
+// registers.  Rows are dealt cyclically (row r to workgroup r mod P), so every
+// workgroup keeps about (n - k) / P live rows at step k; thread t holds
+// columns t mod CBW + CBW c (c < NC) of a 512 / CBW-th of its workgroup's
+// rows (two waves per SIMD; CBW = 256 or 512 columns per pass).
 //
 // Step k (the reflector v_k, tau_k is known in every workgroup, and every
 // workgroup holds y = B v_k for its rows):
-//   1. p_r = tau_k y_r and the partial sum of conj(p_r) v_r are published;
-//      the owner of row k+1 also publishes that row (updated through k-1);
+//   1. p_r = tau_k y_r and the partial sum of conj(p_r) v_r are published,
+//      and with them B[r][k+1] (updated through k-1) for the own rows r:
+//      together they are row k+1, by symmetry (no single workgroup holds
+//      the row and publishes it alone);
 //   2. one barrier across the workgroups;
 //   3. every workgroup reads all of p and forms w = p - 1/2 tau_k (p^H v) v,
 //      applies the rank-2 update to its copy of row k+1 and derives the
@@ -730,7 +733,7 @@ constexpr int CR = 16;      // rows per workgroup
 constexpr int CT = 512;     // threads per workgroup (two waves per SIMD)
 constexpr int CB = 256;     // columns covered by one pass of the threads
 constexpr int kCoopMinN = 64, kCoopMaxN = 2048;
-constexpr int kCoopMaxP = kCoopMaxN / CR;
+constexpr int kCoopMaxP = kCoopMaxN / 8;   // 8 rows per workgroup at the most workgroups
 constexpr long kCoopSpin = 1l << 22;   // polls of a barrier before giving up
 constexpr int kCoopSmallN = 2 * CB;     // up to here, 8 rows per workgroup
 
@@ -742,21 +745,17 @@ struct CoopBuf {
   unsigned* fail;  // set when a barrier timed out
 };
 
-// The exchanged values are written and read with agent-scope atomic 64-bit
-// accesses: they bypass caches that are not coherent across the XCDs, so a
-// value written by a workgroup on one XCD is never read stale from another
-// XCD's L2 (the counter's release/acquire orders them).
+// The exchanged values are written with agent-scope atomic 64-bit stores,
+// which bypass caches that are not coherent across the XCDs, and each
+// workgroup's release fence before its barrier arrival makes them visible.
+// Readers load them with plain loads after the barrier: wave 0's agent-scope
+// acquire fence (which invalidates the non-coherent cache lines) followed by
+// the workgroup barrier orders every wave's loads after the publications.
 __device__ __forceinline__ void xstore(c128* p, c128 v) {
   unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
   __hip_atomic_store(q, (unsigned long long)__double_as_longlong(v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(q + 1, (unsigned long long)__double_as_longlong(v.y), __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ c128 xload(const c128* p) {
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<c128*>(p));
-  const unsigned long long lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const unsigned long long hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return c128{__longlong_as_double((long long)lo), __longlong_as_double((long long)hi)};
 }
 
 // Cross-lane moves of a double through DPP (no LDS traffic).  The four row
@@ -863,16 +862,16 @@ __device__ __forceinline__ Refl householder(c128 al, double xn2) {
   return r;
 }
 
-template <int NC, int CRT>
+template <int NC, int CRT, int CBW = CB>
 __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A, int ld, double* __restrict__ d,
                                                      double* __restrict__ e, c128* __restrict__ tau,
                                                      int* __restrict__ info, CoopBuf cb) {
   constexpr int NW = CT / 64;             // waves
-  constexpr int NH = CT / CB;             // row halves (threads t and t + CB share columns)
+  constexpr int NH = CT / CBW;            // row groups (threads t and t + CBW share columns)
   constexpr int RH = CRT / NH;            // rows per thread
-  constexpr int WH = CB / 64;             // waves per half
+  constexpr int WH = CBW / 64;            // waves per row group
   if (*info != 0) return;
-  __shared__ c128 s_rowbuf[kCoopMaxN];    // owned row k+1 (for publication)
+  __shared__ c128 s_colk[CRT];            // B[r][k+1] of the own rows r (row k+1 by symmetry)
   __shared__ double s_red[NW][2 * RH];    // per-wave row sums of B v (re, then im)
   __shared__ c128 s_rv[2][CRT], s_rw[CRT];  // v_k (by step parity) and w on the own rows
   __shared__ double s_xn2[NW];
@@ -881,7 +880,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 
   const int P = gridDim.x, q = blockIdx.x, tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
-  const int half = tid / CB;
+  const int half = tid / CBW;
   // own rows: row(i) = q + P i (cyclic, so that every workgroup keeps about
   // the same number of live rows as the reduction proceeds)
   auto row_of = [&](int i) { return q + P * i; };
@@ -890,7 +889,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
   int jc[NC];
   bool ok[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) { jc[c] = (tid % CB) + CB * c; ok[c] = jc[c] < n; }
+  for (int c = 0; c < NC; ++c) { jc[c] = (tid % CBW) + CBW * c; ok[c] = jc[c] < n; }
 
   // rows of B: a[c][i] = B[row(half RH + i)][j_c] = conj(A[row * ld + j_c])
   c128 a[NC][RH];
@@ -900,7 +899,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     for (int i = 0; i < RH; ++i) {
       const int R = row_of(half * RH + i);
       a[c][i] = (ok[c] && R < n) ? cconj(A[(size_t)R * ld + jc[c]]) : c128{0.0, 0.0};
-      if (R == 1 && ok[c]) s_rowbuf[jc[c]] = a[c][i];   // row 1 is published at step 0
+      if (jc[c] == 1 && R < n) s_colk[half * RH + i] = a[c][i];   // column 1: row 1, published at step 0
     }
   if (tid == 0) s_fail = 0;
   // own rows past the end of the matrix are never written: start from zeros
@@ -970,7 +969,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
   for (int k = 0; k <= n - 2; ++k) {
     const int par = k & 1;
     // 1. wave 0: finish y on the own rows, publish p_r = tau_k y_r, the
-    //    partial sum of conj(p_r) v_r, and (owner) row k+1; then the barrier
+    //    partial sum of conj(p_r) v_r, and the own entries of row k+1; then the barrier
     if (wid == 0) {
       c128 p{0.0, 0.0};
       const int R = (lane < CRT) ? row_of(lane) : n;
@@ -986,8 +985,8 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
       const double sre = wave_sum(t.x), sim = wave_sum(t.y);
       if (lane < CRT && R < n) xstore(&cb.p[par * kCoopMaxN + R], p);
       if (lane == 0) xstore(&cb.s[par * kCoopMaxP + q], c128{sre, sim});
-      if ((k + 1) % P == q)
-        for (int c = k + 1 + lane; c < n; c += 64) xstore(&cb.row[par * kCoopMaxN + c], s_rowbuf[c]);
+      // row k+1 = conj(column k+1): every workgroup publishes its own entries
+      if (lane < CRT && R >= k + 1 && R < n) xstore(&cb.row[par * kCoopMaxN + R], cconj(s_colk[lane]));
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       if (lane == 0) {
         __hip_atomic_fetch_add(cb.count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1020,13 +1019,13 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       const bool live = ok[c] && jc[c] >= k + 1;
-      pj[c] = live ? xload(&cb.p[par * kCoopMaxN + jc[c]]) : c128{0.0, 0.0};
-      rowj[c] = live ? xload(&cb.row[par * kCoopMaxN + jc[c]]) : c128{0.0, 0.0};
+      pj[c] = live ? cb.p[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
+      rowj[c] = live ? cb.row[par * kCoopMaxN + jc[c]] : c128{0.0, 0.0};
     }
-    const c128 pk1 = xload(&cb.p[par * kCoopMaxN + k + 1]);
+    const c128 pk1 = cb.p[par * kCoopMaxN + k + 1];
     c128 sl{0.0, 0.0};   // partial sums of workgroups lane, lane + 64, ... (fixed order)
     for (int w = lane; w < P; w += 64) {
-      const c128 t = xload(&cb.s[par * kCoopMaxP + w]);
+      const c128 t = cb.s[par * kCoopMaxP + w];
       sl.x += t.x;
       sl.y += t.y;
     }
@@ -1079,15 +1078,15 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
     // buffer: no barrier here
     put_own(s_rv[par ^ 1], vk1);
     // 5. B -= v w^H + w v^H on rows and columns >= k+2, and y = B v_{k+1};
-    //    the owner of row k+2 keeps it for the next publication
+    //    the threads of column k+2 keep its entries for the next publication
     {
       c128 acc[RH];
 #pragma unroll
       for (int i = 0; i < RH; ++i) acc[i] = c128{0.0, 0.0};
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        // columns of this wave: [64 (wid % WH) + CB c, + 64)
-        const int cbase = 64 * (wid % WH) + CB * c;
+        // columns of this wave: [64 (wid % WH) + CBW c, + 64)
+        const int cbase = 64 * (wid % WH) + CBW * c;
         if (cbase + 63 < k + 2 || cbase >= n) continue;
         if (!(ok[c] && jc[c] >= k + 2)) continue;
         const c128 cw = cconj(wj[c]), cv = cconj(vk[c]);
@@ -1099,7 +1098,7 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
             const c128 u1 = cmul(s_rv[par][li], cw), u2 = cmul(s_rw[li], cv);
             a[c][i] = c128{a[c][i].x - u1.x - u2.x, a[c][i].y - u1.y - u2.y};
             acc[i] = acc[i] + cmul(a[c][i], vk1[c]);
-            if (R == k + 2) s_rowbuf[jc[c]] = a[c][i];
+            if (jc[c] == k + 2) s_colk[li] = a[c][i];
           }
         }
       }
@@ -1524,6 +1523,16 @@ size_t pw::heig_work_bytes(int nmax) {
 
 pw_status pw::heig_setup(HeigWork& hw, void* base, int nmax) {
   const size_t n = (size_t)std::max(nmax, 1);
+  {
+    // 0 if the query fails: the large 8-row form is then not taken
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+      hw.cus = cus;
+    else
+      hw.cus = 0;
+    (void)hipGetLastError();
+  }
   char* p = static_cast<char*>(base);
   auto take = [&](size_t bytes) {
     char* q = p;
@@ -1635,10 +1644,20 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     if (coop_tri) {
       const CoopBuf cb = coop_buf(hw);   // counter and flag cleared by k_isolate
       const bool wide = hw.coop_wide;
-      const int P = pw::coop_workgroups(n, wide);
+      // beyond 512 rows a solve that runs alone keeps 8 rows per workgroup,
+      // in passes of 512 columns (up to one workgroup per CU at 2048 rows):
+      // 16 rows per workgroup do not fit the registers there (at 2048 rows
+      // they spilled 885 registers a thread, and the update ran from scratch
+      // memory)
+      const bool big8 = !wide && n > 2 * CB && hw.cus >= ceil_div(n, 8);
+      const int P = big8 ? ceil_div(n, 8) : pw::coop_workgroups(n, wide);
       // up to 512 rows: 8 rows per workgroup (twice the workgroups, half the
       // update work per step on each) unless the wide form is asked for; beyond, 16
-      if (n <= CB && !wide) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      if (big8 && n <= 4 * CB)
+        k_tridiag_coop<2, 8, 2 * CB><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (big8)
+        k_tridiag_coop<4, 8, 2 * CB><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
+      else if (n <= CB && !wide) k_tridiag_coop<1, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
       else if (n <= CB) k_tridiag_coop<1, CR><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);
       else if (n <= 2 * CB && !wide)
         k_tridiag_coop<2, 8><<<P, CT, 0, st>>>(n, hw.A, ldw, hw.d, hw.e, hw.tau, hw.info, cb);

@@ -14,7 +14,8 @@ and the CPU baselines (dense oracle rows, and the CPU FFT method), whose
 sampled rows also give the GPU products' parity on this cell.
 
 Other workloads: cell64 (a step is one Davidson solve of the 64-atom cell),
-batch (32 cells x 4 k-points), serve (Poisson request trace, p50/p99).
+batch (32 cells x 4 k-points), serve (Poisson request trace, p50/p99),
+solve512 (a step is one Davidson solve of the 512-atom cell).
 Inputs are synthetic and resident in HBM before timing starts.
 """
 from __future__ import annotations
@@ -56,11 +57,12 @@ def parse():
     ap.add_argument("--no-gamma", action="store_true", help="cell512: skip the Gamma-point path rates")
     ap.add_argument("--no-stages", action="store_true",
                     help="skip the per-stage H.psi measurement (keeps kernel profiles to the timed steps)")
-    ap.add_argument("--workload", choices=["cell512", "cell64", "batch", "serve"], default="cell512",
+    ap.add_argument("--workload", choices=["cell512", "cell64", "batch", "serve", "solve512"], default="cell512",
                     help="cell512: mixed H.psi of the 512-atom 144^3 cell vs plain float64 (default line); "
                          "cell64: Davidson solves of the 64-atom cell; batch: 32 cells x 4 k-points solved "
                          "concurrently vs one at a time in FP64; serve: Poisson request trace through the "
-                         "serving loop (p50/p99 latency)")
+                         "serving loop (p50/p99 latency); solve512: Davidson solves of the 512-atom cell "
+                         "(mixed: and one float64 solve beside it)")
     ap.add_argument("--nbands", type=int, default=1024, help="cell512: bands of the H.psi block")
     ap.add_argument("--solves", type=int, default=3,
                     help="cell512: Davidson solves of the 64-atom cell per precision (0: skip)")
@@ -84,11 +86,11 @@ def parse():
                          "128-band block (for kernel profiles of H.psi alone)")
     args = ap.parse_args()
     if args.precision is None:
-        args.precision = "mixed" if args.workload in ("batch", "serve") else "fp64"
+        args.precision = "mixed" if args.workload in ("batch", "serve", "solve512") else "fp64"
     if args.steps is None:
-        args.steps = 20 if args.workload == "cell512" else 3
+        args.steps = {"cell512": 20, "solve512": 1}.get(args.workload, 3)
     if args.warmup is None:
-        args.warmup = 3 if args.workload == "cell512" else 1
+        args.warmup = {"cell512": 3, "solve512": 0}.get(args.workload, 1)
     if args.ndim is None:
         args.ndim = 3 if (args.workload == "cell64" and args.precision == "fp64") else 2
     return args
@@ -624,6 +626,61 @@ def gamma_rates(ctx, p, reps, mixed_complex, fp64_complex):
         plan.close()
 
 
+def bench_solve512(args):
+    """Davidson solves of the 512-atom cell (npw 191,471, 144^3 grid, 2048
+    projectors, 1024 bands; basis 2 nb, locking, residuals to 1e-6 Ha) in the
+    chosen precision, timed one solve per step.  A mixed run also solves in
+    float64 once, for the ratio and the largest eigenvalue difference."""
+    import torch
+    from paper_0906_2569_amd import pwdft, pwgen
+    dev = torch.device("cuda", 0)
+    t0 = time.perf_counter()
+    p = pwgen.config5_largest(nb=1024)
+    print(f"bench: cell generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    ctx = pwdft.Context(0)
+    opts = pwdft.default_opts(ndim=args.ndim, max_iter=400)
+    psi0 = torch.from_numpy(p.psi0).to(dev)
+
+    def solves(prec, nsteps, nwarm):
+        plan = pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=args.ndim)
+        try:
+            psi = torch.empty_like(psi0)
+            eig = torch.empty(p.nb, dtype=torch.float64, device=dev)
+            resid = torch.empty_like(eig)
+            out = []
+            for i in range(nwarm + nsteps):
+                psi.copy_(psi0)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st, _, _, stats = plan.davidson(psi, eig, resid, opts=opts)
+                torch.cuda.synchronize()
+                if i >= nwarm:
+                    out.append((time.perf_counter() - t, st, stats.asdict()))
+            return out, eig.cpu().numpy(), resid.cpu().numpy()
+        finally:
+            plan.close()
+
+    prec = pwdft.PW_MIXED if args.precision == "mixed" else pwdft.PW_FP64
+    runs, e, r = solves(prec, args.steps, args.warmup)
+    secs = [t for t, _, _ in runs]
+    sec = sum(secs) / len(secs)
+    line = {"metric": "solves/s", "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+            "config": {"workload": "Davidson solve of the 512-atom cell (npw 191,471, 144^3, 2048 projectors, "
+                                   "1024 bands)", "ndim": args.ndim, "precision": args.precision},
+            "status": [st for _, st, _ in runs], "solve_stats": runs[-1][2],
+            "eig_range_ha": [float(e[0]), float(e[-1])], "max_resid_ha": float(r.max())}
+    if args.precision == "mixed":
+        runs64, e64, _ = solves(pwdft.PW_FP64, 1, 0)
+        line["fp64_seconds"] = runs64[0][0]
+        line["fp64_status"] = runs64[0][1]
+        line["mixed_over_fp64"] = runs64[0][0] / sec
+        line["max_abs_eig_diff_vs_fp64_ha"] = float(np.abs(e - e64).max())
+    print(json.dumps(line), flush=True)
+    return 0 if all(st == 0 for _, st, _ in runs) else 1
+
+
 def bench_cell512(args):
     """Mixed-precision H.psi of the 1024-band block of the 512-atom 144^3 cell,
     against the same product in plain float64."""
@@ -745,6 +802,8 @@ def main():
         return bench_serve(args)
     if args.workload == "cell512":
         return bench_cell512(args)
+    if args.workload == "solve512":
+        return bench_solve512(args)
     import torch
     from paper_0906_2569_amd import pwdft, pwgen
 

@@ -1522,6 +1522,101 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
   }
 }
 
+// The same product for columns of up to 512 rows with the reflectors staged
+// through LDS: the four waves of a workgroup (four columns) share chunks of C
+// reflectors, double-buffered; the loads of the next chunk are issued before
+// the current chunk's C steps and written to LDS after them, so a step waits
+// on LDS, not on memory (the one-step register prefetch above waited on
+// every load).  The dot product keeps two partial sums per complex part.
+template <int NPL>
+__global__ void __launch_bounds__(256) k_backtr_lds(int n, const c128* __restrict__ A, int lda,
+                                                    const c128* __restrict__ tau, const double* __restrict__ Z,
+                                                    int ldz, int nev, c128* __restrict__ Y, int ldy,
+                                                    const int* __restrict__ info) {
+  constexpr int R = 64 * NPL;            // rows of a staged reflector (padded)
+  constexpr int C = NPL >= 8 ? 4 : 8;    // reflectors per chunk: 2 C R x 16 B <= 64 KB
+  constexpr int PER = C * R / 256;       // chunk entries each thread stages
+  __shared__ c128 buf[2][C * R];
+  __shared__ c128 s_tau[2][C];
+  if (*info != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int col = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const bool active = col < nev;   // every wave stays for the barriers
+  c128 y[NPL];
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int r = lane + 64 * t;
+    y[t] = c128{(active && r < n) ? Z[(size_t)col * ldz + r] : 0.0, 0.0};
+  }
+  // reflector k = n - 2 - (c C + j) is entry j of chunk c; v_k holds rows k+1 .. n-1
+  c128 reg[PER], rtau = c128{0.0, 0.0};
+  auto stage = [&](int c) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int idx = threadIdx.x + 256 * e;
+      const int j = idx / R, r = idx % R;
+      const int k = n - 2 - c * C - j;
+      reg[e] = (k >= 0 && r > k && r < n) ? A[(size_t)k * lda + r] : c128{0.0, 0.0};
+    }
+    if (threadIdx.x < C) {
+      const int k = n - 2 - c * C - (int)threadIdx.x;
+      rtau = k >= 0 ? tau[k] : c128{0.0, 0.0};
+    }
+  };
+  auto commit = [&](int b) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) buf[b][threadIdx.x + 256 * e] = reg[e];
+    if (threadIdx.x < C) s_tau[b][threadIdx.x] = rtau;
+  };
+  const int nchunks = (n - 1 + C - 1) / C;
+  if (nchunks > 0) {
+    stage(0);
+    commit(0);
+  }
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int cur = c & 1;
+    if (c + 1 < nchunks) stage(c + 1);
+    if (active) {
+      for (int j = 0; j < C; ++j) {
+        if (n - 2 - c * C - j < 0) break;
+        const c128 tk = s_tau[cur][j];
+        if (tk.x == 0.0 && tk.y == 0.0) continue;
+        const c128* v = &buf[cur][j * R];
+        c128 vv[NPL];
+#pragma unroll
+        for (int t = 0; t < NPL; ++t) vv[t] = v[lane + 64 * t];
+        double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < NPL; t += 2) {
+          const c128 u = cmulc(vv[t], y[t]);   // conj(v_r) y_r
+          sr0 += u.x;
+          si0 += u.y;
+          if (t + 1 < NPL) {
+            const c128 u1 = cmulc(vv[t + 1], y[t + 1]);
+            sr1 += u1.x;
+            si1 += u1.y;
+          }
+        }
+        const c128 sc = cmul(tk, c128{wave_sum(sr0 + sr1), wave_sum(si0 + si1)});
+#pragma unroll
+        for (int t = 0; t < NPL; ++t) {
+          const c128 u = cmul(vv[t], sc);
+          y[t] = c128{y[t].x - u.x, y[t].y - u.y};
+        }
+      }
+    }
+    if (c + 1 < nchunks) commit(cur ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int t = 0; t < NPL; ++t) {
+    const int r = lane + 64 * t;
+    if (r < n) Y[(size_t)col * ldy + r] = y[t];
+  }
+}
+
 }  // namespace
 
 int pw::coop_workgroups(int n, bool wide) { return ceil_div(n, (n <= kCoopSmallN && !wide) ? 8 : CR); }
@@ -1732,9 +1827,9 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     pw::ProfScope ps(pw::PK_BACKTR, st, 8.0 * n * n * (double)nev);
     const dim3 g(ceil_div(nev, 4)), b(256);
     const int npl = ceil_div(n, 64);
-    if (npl <= 2) k_backtr<2><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
-    else if (npl <= 4) k_backtr<4><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
-    else if (npl <= 8) k_backtr<8><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    if (npl <= 2) k_backtr_lds<2><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 4) k_backtr_lds<4><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 8) k_backtr_lds<8><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 16) k_backtr<16><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 32) k_backtr<32><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 64) k_backtr<64><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);

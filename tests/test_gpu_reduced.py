@@ -94,9 +94,11 @@ def test_already_tridiagonal_and_diagonal(ctx, n):
         assert np.linalg.norm(h @ c - c * w, axis=0).max() <= 1e-11 * n
 
 
-def test_cooperative_degenerate_clusters(ctx):
+# 160 rows: 20 workgroups polling the barrier counter; 700 rows: 88 workgroups
+# of 8 rows in 512-column passes, released through the barrier's flags
+@pytest.mark.parametrize("n", [160, 700])
+def test_cooperative_degenerate_clusters(ctx, n):
     rng = np.random.default_rng(8)
-    n = 160
     q, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
     lam = np.concatenate([[0.0] * 4, [1.0] * 20, [2.0] * 40, np.linspace(3, 5, n - 64)])
     h = (q * lam) @ q.conj().T

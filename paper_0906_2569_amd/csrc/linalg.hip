@@ -1137,9 +1137,9 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 }
 
 // ---------------------------------------------------------------------------
-// Lowest nev eigenvalues of the real symmetric tridiagonal (d, e): one wave
-// per eigenvalue, 64 shifts per round (Sturm counts), interval narrowed to
-// the two shifts around the k-th eigenvalue.
+// Lowest nev eigenvalues of the real symmetric tridiagonal (d, e): one
+// workgroup of four waves per eigenvalue, 512 shifts per round (Sturm
+// counts), interval narrowed to the two shifts around the k-th eigenvalue.
 // ---------------------------------------------------------------------------
 // 1/q to a few units in the last place: the hardware reciprocal refined by
 // one Newton step (a shorter dependent chain than an IEEE division; a Sturm
@@ -1174,9 +1174,10 @@ __device__ __forceinline__ void sturm_counts(int n, const double* d, const doubl
   }
 }
 
-// One wave per wanted eigenvalue k: each round evaluates the Sturm count at
-// 64 x CH equally spaced shifts and keeps the interval between the two shifts
-// that bracket the k-th eigenvalue.
+// One workgroup per wanted eigenvalue k (launched with 256 threads: four
+// waves, one per SIMD): each round evaluates the Sturm count at 4 x 64 x CH
+// equally spaced shifts and keeps the interval between the two shifts that
+// bracket the k-th eigenvalue.
 constexpr int kBisectChains = 2;
 __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict__ dg,
                                                 const double* __restrict__ eg, int nev,
@@ -1215,18 +1216,24 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
     }
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int k = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (k >= nev) return;
+  // the workgroup's NW waves share eigenvalue k = blockIdx.x: each round
+  // evaluates NW x 64 x CH equally spaced shifts (wave v the v-th block of
+  // them), one wave per SIMD, and keeps the interval between the two shifts
+  // around the k-th eigenvalue
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, NW = blockDim.x >> 6;
+  const int k = blockIdx.x;
+  __shared__ int s_first[16];
+  const int NT = NS * NW;   // shifts per round
   double lo = s_lo, hi = s_hi;
   const double pivmin = s_piv;
   for (int round = 0; round < 64; ++round) {
+    // the same decision in every thread (lo and hi are uniform)
     if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
-    const double step = (hi - lo) / (double)(NS + 1);
+    const double step = (hi - lo) / (double)(NT + 1);
     double x[CH];
     int c[CH];
 #pragma unroll
-    for (int j = 0; j < CH; ++j) x[j] = lo + step * (CH * lane + j + 1);
+    for (int j = 0; j < CH; ++j) x[j] = lo + step * (NS * wv + CH * lane + j + 1);
     sturm_counts<CH>(n, d, e2, x, pivmin, c);
     // first shift (in increasing order) with more than k eigenvalues below it
     int jf = CH;
@@ -1234,18 +1241,23 @@ __global__ void __launch_bounds__(256) k_bisect(int n, const double* __restrict_
     for (int j = CH - 1; j >= 0; --j)
       if (c[j] > k) jf = j;
     const unsigned long long mask = __ballot(jf < CH);
-    if (mask == 0ull) {
-      lo = lo + step * NS;
+    const int f = mask != 0ull ? __ffsll((long long)mask) - 1 : 0;
+    const int jsel = __shfl(jf, f, 64);   // every lane takes part
+    if (lane == 0) s_first[wv] = mask != 0ull ? NS * wv + CH * f + jsel : NT;   // NT: none in this block
+    __syncthreads();
+    int s0 = NT;
+    for (int v = 0; v < NW; ++v) s0 = min(s0, s_first[v]);
+    __syncthreads();   // s_first is rewritten next round
+    if (s0 == NT) {
+      lo = lo + step * NT;
     } else {
-      const int f = __ffsll((long long)mask) - 1;
-      const int s = CH * f + __shfl(jf, f, 64);   // 0-based shift index
-      const double xf = lo + step * (s + 1);
-      const double xp = (s > 0) ? lo + step * s : lo;
+      const double xf = lo + step * (s0 + 1);
+      const double xp = (s0 > 0) ? lo + step * s0 : lo;
       hi = xf;
       lo = xp;
     }
   }
-  if (lane == 0) w[k] = 0.5 * (lo + hi);
+  if (threadIdx.x == 0) w[k] = 0.5 * (lo + hi);
 }
 
 // ---------------------------------------------------------------------------
@@ -1809,7 +1821,7 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_BISECT, st);
-    k_bisect<<<nev, 64, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
+    k_bisect<<<nev, 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
   }
   {
     pw::ProfScope ps(pw::PK_INVIT, st);

@@ -1138,8 +1138,9 @@ __global__ void __launch_bounds__(CT) k_tridiag_coop(int n, c128* __restrict__ A
 
 // ---------------------------------------------------------------------------
 // Lowest nev eigenvalues of the real symmetric tridiagonal (d, e): one
-// workgroup of four waves per eigenvalue, 512 shifts per round (Sturm
-// counts), interval narrowed to the two shifts around the k-th eigenvalue.
+// workgroup of one or four waves per eigenvalue, 128 or 512 shifts per round
+// (Sturm counts), interval narrowed to the two shifts around the k-th
+// eigenvalue.
 // ---------------------------------------------------------------------------
 // 1/q to a few units in the last place: the hardware reciprocal refined by
 // one Newton step (a shorter dependent chain than an IEEE division; a Sturm
@@ -1174,8 +1175,8 @@ __device__ __forceinline__ void sturm_counts(int n, const double* d, const doubl
   }
 }
 
-// One workgroup per wanted eigenvalue k (launched with 256 threads: four
-// waves, one per SIMD): each round evaluates the Sturm count at 4 x 64 x CH
+// One workgroup per wanted eigenvalue k (of 64 or 256 threads: one or four
+// waves, one per SIMD): each round evaluates the Sturm count at NW x 64 x CH
 // equally spaced shifts and keeps the interval between the two shifts that
 // bracket the k-th eigenvalue.
 constexpr int kBisectChains = 2;
@@ -1821,7 +1822,10 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
   }
   {
     pw::ProfScope ps(pw::PK_BISECT, st);
-    k_bisect<<<nev, 256, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
+    // four waves per eigenvalue while they find a SIMD each (up to 256
+    // eigenvalues); beyond, one wave each (more waves would share SIMDs and
+    // the Sturm steps are issue-bound there)
+    k_bisect<<<nev, nev <= 256 ? 256 : 64, sizeof(double) * 2 * n, st>>>(n, hw.d, hw.e, nev, w, hw.info);
   }
   {
     pw::ProfScope ps(pw::PK_INVIT, st);

@@ -80,3 +80,18 @@ def test_host_side_validation_without_gpu(lib):
     s.ld_beta = p.npw
     s.nr[0] = 49          # 7^2: not a 2,3,5-smooth FFT length
     assert lib.pw_footprint_bytes(ctypes.byref(s), ctypes.byref(o)) == 0
+
+
+def test_davidson_option_defaults_and_layout(lib):
+    # the C defaults land in the binding's fields one for one: a field order
+    # or padding that differed between include/pwdft.h and the binding would
+    # put them in the wrong places
+    from paper_0906_2569_amd import pwdft
+    pwdft.load(LIB)
+    o = pwdft.DavOpts()
+    ctypes.memset(ctypes.byref(o), 0x7F, ctypes.sizeof(o))
+    lib.pw_david_opts_default(ctypes.byref(o))
+    assert ctypes.sizeof(o) == 56
+    assert (o.ndim, o.max_iter, o.lock, o.sub32) == (2, 200, 1, 1)
+    assert (o.tol_resid, o.tol_deig, o.precond_floor, o.ladder_switch) == (1e-6, 5e-9, 0.2, 3e-4)
+    assert not o.history

@@ -95,3 +95,18 @@ def test_davidson_option_defaults_and_layout(lib):
     assert (o.ndim, o.max_iter, o.lock, o.sub32) == (2, 200, 1, 1)
     assert (o.tol_resid, o.tol_deig, o.precond_floor, o.ladder_switch) == (1e-6, 5e-9, 0.2, 3e-4)
     assert not o.history
+
+
+def test_cg_and_server_option_defaults_and_layout(lib):
+    from paper_0906_2569_amd import pwdft
+    pwdft.load(LIB)
+    c = pwdft.CgOpts()
+    ctypes.memset(ctypes.byref(c), 0x7F, ctypes.sizeof(c))
+    lib.pw_cg_opts_default(ctypes.byref(c))
+    assert ctypes.sizeof(c) == 32
+    assert (c.max_iter, c.tol_resid, c.tol_deig, c.precond_floor) == (400, 1e-6, 5e-9, 0.2)
+    s = pwdft.ServerOpts()
+    ctypes.memset(ctypes.byref(s), 0x7F, ctypes.sizeof(s))
+    lib.pw_server_opts_default(ctypes.byref(s))
+    assert ctypes.sizeof(s) == 24
+    assert (s.nworkers, s.mem_budget, s.precision) == (4, 0, pwdft.PW_MIXED)

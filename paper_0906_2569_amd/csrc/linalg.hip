@@ -1535,7 +1535,7 @@ __global__ void __launch_bounds__(256) k_backtr(int n, const c128* __restrict__ 
   }
 }
 
-// The same product for columns of up to 512 rows with the reflectors staged
+// The same product for columns of up to 2048 rows with the reflectors staged
 // through LDS: the four waves of a workgroup (four columns) share chunks of C
 // reflectors, double-buffered; the loads of the next chunk are issued before
 // the current chunk's C steps and written to LDS after them, so a step waits
@@ -1547,7 +1547,7 @@ __global__ void __launch_bounds__(256) k_backtr_lds(int n, const c128* __restric
                                                     int ldz, int nev, c128* __restrict__ Y, int ldy,
                                                     const int* __restrict__ info) {
   constexpr int R = 64 * NPL;            // rows of a staged reflector (padded)
-  constexpr int C = NPL >= 8 ? 4 : 8;    // reflectors per chunk: 2 C R x 16 B <= 64 KB
+  constexpr int C = NPL >= 32 ? 1 : (NPL >= 16 ? 2 : (NPL >= 8 ? 4 : 8));   // 2 C R x 16 B <= 64 KB
   constexpr int PER = C * R / 256;       // chunk entries each thread stages
   __shared__ c128 buf[2][C * R];
   __shared__ c128 s_tau[2][C];
@@ -1596,17 +1596,26 @@ __global__ void __launch_bounds__(256) k_backtr_lds(int n, const c128* __restric
         const c128 tk = s_tau[cur][j];
         if (tk.x == 0.0 && tk.y == 0.0) continue;
         const c128* v = &buf[cur][j * R];
-        c128 vv[NPL];
+        // up to 8 rows a lane the reflector is held in registers for both
+        // passes; beyond, it is read from LDS twice (registers hold y)
+        constexpr int NV = NPL <= 8 ? NPL : 1;
+        c128 vv[NV];
+        if constexpr (NPL <= 8) {
 #pragma unroll
-        for (int t = 0; t < NPL; ++t) vv[t] = v[lane + 64 * t];
+          for (int t = 0; t < NPL; ++t) vv[t] = v[lane + 64 * t];
+        }
+        auto vat = [&](int t) -> c128 {
+          if constexpr (NPL <= 8) return vv[t];
+          else return v[lane + 64 * t];
+        };
         double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
 #pragma unroll
         for (int t = 0; t < NPL; t += 2) {
-          const c128 u = cmulc(vv[t], y[t]);   // conj(v_r) y_r
+          const c128 u = cmulc(vat(t), y[t]);   // conj(v_r) y_r
           sr0 += u.x;
           si0 += u.y;
           if (t + 1 < NPL) {
-            const c128 u1 = cmulc(vv[t + 1], y[t + 1]);
+            const c128 u1 = cmulc(vat(t + 1), y[t + 1]);
             sr1 += u1.x;
             si1 += u1.y;
           }
@@ -1614,7 +1623,7 @@ __global__ void __launch_bounds__(256) k_backtr_lds(int n, const c128* __restric
         const c128 sc = cmul(tk, c128{wave_sum(sr0 + sr1), wave_sum(si0 + si1)});
 #pragma unroll
         for (int t = 0; t < NPL; ++t) {
-          const c128 u = cmul(vv[t], sc);
+          const c128 u = cmul(vat(t), sc);
           y[t] = c128{y[t].x - u.x, y[t].y - u.y};
         }
       }
@@ -1846,8 +1855,8 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
     if (npl <= 2) k_backtr_lds<2><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 4) k_backtr_lds<4><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 8) k_backtr_lds<8><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
-    else if (npl <= 16) k_backtr<16><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
-    else if (npl <= 32) k_backtr<32><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 16) k_backtr_lds<16><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
+    else if (npl <= 32) k_backtr_lds<32><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else if (npl <= 64) k_backtr<64><<<g, b, 0, st>>>(n, hw.A, ldw, hw.tau, hw.Z, ldw, nev, hw.Y, ldw, hw.info);
     else return pw::fail(PW_EINVAL, "reduced problem larger than 4096");
   }

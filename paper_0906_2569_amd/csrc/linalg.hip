@@ -269,10 +269,11 @@ __global__ void __launch_bounds__(1024) k_chol_reg(int n, int nev, double drop_t
     }
 }
 
-// Blocked form of the same factorization for large n (right-looking): a
-// workgroup factors a panel of kChPanel columns with the rule above (only
-// the panel's own columns are updated), the trailing matrix then receives
-// the panel's rank-kChPanel update as one MFMA product
+// Blocked form of the same factorization for large n (right-looking): each
+// panel of kChPanel columns is factored with the rule above (k_chol_diag,
+// k_chol_trsm below: only the panel's own columns are updated), the
+// trailing matrix then receives the panel's rank-kChPanel update as one MFMA
+// product
 //   L22 -= L21 L21^H   (zgemm with the conjugate transpose PT of L21),
 // and a last kernel sets info and clears the strict upper triangle.
 // flags[0] = not positive definite (also the guard that skips the products).
@@ -286,66 +287,104 @@ __global__ void k_chol_init(int n, const c128* __restrict__ L, int ld, double* _
   if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 0;
 }
 
-__global__ void __launch_bounds__(NTL) k_chol_panel(int n, int j0, int bb, double drop_tol, c128* __restrict__ L,
-                                                    int ld, const double* __restrict__ diag0,
-                                                    int* __restrict__ drop, int* __restrict__ flags,
-                                                    c128* __restrict__ PT) {
+// A panel in two kernels: its bb x bb diagonal block factored in LDS by one
+// workgroup (the drop rule above), then the rows below solved against it,
+// L21 = A21 L11^-H, one row per thread over as many workgroups as there are
+// rows (57 us a panel at 1000-2000 rows, against 180 us for one workgroup
+// updating the whole panel through memory column by column).
+__global__ void __launch_bounds__(256) k_chol_diag(int j0, int bb, double drop_tol, c128* __restrict__ L, int ld,
+                                                   const double* __restrict__ diag0, int* __restrict__ drop,
+                                                   int* __restrict__ flags) {
   if (flags[0] != 0) return;
-  extern __shared__ __align__(16) char smem_raw[];
-  c128* col = reinterpret_cast<c128*>(smem_raw);   // [n]
+  __shared__ c128 a[kChPanel][kChPanel + 1];   // a[r][c]: row r, column c of the block (lower triangle)
   __shared__ double s_r;
   __shared__ int s_keep, s_bad;
-  if (threadIdx.x == 0) s_bad = 0;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < bb * bb; idx += blockDim.x) {
+    const int r = idx % bb, c = idx / bb;
+    if (r >= c) a[r][c] = L[(size_t)(j0 + c) * ld + j0 + r];
+  }
+  if (tid == 0) s_bad = 0;
   __syncthreads();
-  const int jend = j0 + bb;
-  for (int j = j0; j < jend; ++j) {
-    if (threadIdx.x == 0) {
-      const double d = L[(size_t)j * ld + j].x;
-      if (!isfinite(d) || !(diag0[j] >= 0.0) || d < -drop_tol * diag0[j]) s_bad = 1;
-      s_keep = (d > drop_tol * diag0[j]) ? 1 : 0;
-      if (s_keep) {
-        s_r = sqrt(d);
-        L[(size_t)j * ld + j] = c128{s_r, 0.0};
-      } else {
-        L[(size_t)j * ld + j] = c128{1.0, 0.0};
-      }
-      drop[j] = 1 - s_keep;
+  for (int j = 0; j < bb; ++j) {
+    if (tid == 0) {
+      const double d = a[j][j].x, d0 = diag0[j0 + j];
+      if (!isfinite(d) || !(d0 >= 0.0) || d < -drop_tol * d0) s_bad = 1;
+      s_keep = (d > drop_tol * d0) ? 1 : 0;
+      s_r = s_keep ? sqrt(d) : 1.0;
+      a[j][j] = c128{s_r, 0.0};
+      drop[j0 + j] = 1 - s_keep;
       if (s_bad) flags[0] = 1;
     }
     __syncthreads();
     if (s_bad) return;
-    const int m = n - j - 1;
-    if (!s_keep) {
-      for (int i = threadIdx.x; i < m; i += blockDim.x) L[(size_t)j * ld + j + 1 + i] = c128{0.0, 0.0};
-      __syncthreads();
-      continue;
-    }
-    const double inv = 1.0 / s_r;
-    for (int i = threadIdx.x; i < m; i += blockDim.x) {
-      c128 v = L[(size_t)j * ld + j + 1 + i];
-      v = c128{v.x * inv, v.y * inv};
-      L[(size_t)j * ld + j + 1 + i] = v;
-      col[i] = v;
-    }
+    // column j below the diagonal: scaled, or zero for a dropped direction
+    const double inv = s_keep ? 1.0 / s_r : 0.0;
+    for (int i = j + 1 + tid; i < bb; i += blockDim.x) a[i][j] = c128{a[i][j].x * inv, a[i][j].y * inv};
     __syncthreads();
-    // rank-1 update of the panel's remaining columns j+1 .. jend-1 (rows >= column)
-    const int pc = jend - j - 1;
-    for (int idx = threadIdx.x; idx < m * pc; idx += blockDim.x) {
-      const int ii = idx % m, kk = idx / m;
-      if (ii >= kk) {
-        c128* a = L + (size_t)(j + 1 + kk) * ld + j + 1 + ii;
-        const c128 u = cmulc(col[kk], col[ii]);   // col[ii] conj(col[kk])
-        *a = c128{a->x - u.x, a->y - u.y};
+    if (s_keep) {
+      const int w = bb - j - 1;
+      for (int idx = tid; idx < w * w; idx += blockDim.x) {
+        const int ii = j + 1 + idx % w, kk = j + 1 + idx / w;
+        if (ii >= kk) {
+          const c128 u = cmulc(a[kk][j], a[ii][j]);   // L[ii][j] conj(L[kk][j])
+          a[ii][kk] = c128{a[ii][kk].x - u.x, a[ii][kk].y - u.y};
+        }
       }
     }
     __syncthreads();
   }
-  // PT[r * kChPanel + t] = conj(L[jend + r][j0 + t]): the panel below its diagonal block
-  const int mt = n - jend;
-  for (int idx = threadIdx.x; idx < mt * bb; idx += blockDim.x) {
-    const int r = idx % mt, t = idx / mt;
-    PT[(size_t)r * kChPanel + t] = cconj(L[(size_t)(j0 + t) * ld + jend + r]);
+  for (int idx = tid; idx < bb * bb; idx += blockDim.x) {
+    const int r = idx % bb, c = idx / bb;
+    if (r >= c) L[(size_t)(j0 + c) * ld + j0 + r] = a[r][c];
   }
+}
+
+// rows jend .. n-1 of the panel: x L11^H = a, column c of x zero where
+// direction c was dropped; also PT[r * kChPanel + c] = conj(x_c) for the
+// trailing product
+__global__ void __launch_bounds__(256) k_chol_trsm(int n, int j0, int bb, c128* __restrict__ L, int ld,
+                                                   const int* __restrict__ drop, const int* __restrict__ flags,
+                                                   c128* __restrict__ PT) {
+  if (flags[0] != 0) return;
+  __shared__ c128 l11[kChPanel][kChPanel + 1];
+  __shared__ int s_drop[kChPanel];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < bb * bb; idx += blockDim.x) {
+    const int r = idx % bb, c = idx / bb;
+    l11[r][c] = (r >= c) ? L[(size_t)(j0 + c) * ld + j0 + r] : c128{0.0, 0.0};
+  }
+  if (tid < bb) s_drop[tid] = drop[j0 + tid];
+  __syncthreads();
+  const int jend = j0 + bb, mt = n - jend;
+  const int r = blockIdx.x * blockDim.x + tid;
+  if (r >= mt) return;
+  c128 x[kChPanel];
+#pragma unroll
+  for (int c = 0; c < kChPanel; ++c) x[c] = c < bb ? L[(size_t)(j0 + c) * ld + jend + r] : c128{0.0, 0.0};
+#pragma unroll
+  for (int c = 0; c < kChPanel; ++c) {
+    if (c < bb) {
+      if (s_drop[c]) {
+        x[c] = c128{0.0, 0.0};
+      } else {
+        c128 v = x[c];
+#pragma unroll
+        for (int t = 0; t < c; ++t) {
+          const c128 u = cmulc(l11[c][t], x[t]);   // x_t conj(L11[c][t])
+          v = c128{v.x - u.x, v.y - u.y};
+        }
+        const double inv = 1.0 / l11[c][c].x;
+        x[c] = c128{v.x * inv, v.y * inv};
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kChPanel; ++c)
+    if (c < bb) {
+      L[(size_t)(j0 + c) * ld + jend + r] = x[c];
+      PT[(size_t)r * kChPanel + c] = cconj(x[c]);
+    }
 }
 
 __global__ void k_chol_finish(int n, c128* __restrict__ L, int ld, const int* __restrict__ flags,
@@ -1746,9 +1785,9 @@ pw_status pw::heig_solve(HeigWork& hw, int n0, int n, int nev, const c128* H, co
       k_chol_init<<<std::min(64, ceil_div(m, 256)), 256, 0, st>>>(m, L22, ldw, diag0, hw.cflags);
       for (int j0 = 0; j0 < m; j0 += kChPanel) {
         const int bb = std::min(kChPanel, m - j0);
-        k_chol_panel<<<1, NTL, sizeof(c128) * m, st>>>(m, j0, bb, hw.drop_tol, L22, ldw, diag0, hw.drop + n0,
-                                                      hw.cflags, PT);
         const int mt = m - j0 - bb;
+        k_chol_diag<<<1, 256, 0, st>>>(j0, bb, hw.drop_tol, L22, ldw, diag0, hw.drop + n0, hw.cflags);
+        if (mt > 0) k_chol_trsm<<<ceil_div(mt, 256), 256, 0, st>>>(m, j0, bb, L22, ldw, hw.drop + n0, hw.cflags, PT);
         if (mt > 0) {
           // trailing L22 -= L21 L21^H (full square; the upper triangle is cleared at the end)
           c128* L21 = L22 + (size_t)j0 * ldw + j0 + bb;

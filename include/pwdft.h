@@ -242,15 +242,20 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
 
 /*
  * Band-by-band preconditioned conjugate gradient for the nb lowest
- * eigenpairs (the iterative-diagonalization appendix, "Conjugate-Gradient"):
- * band i minimizes the Rayleigh quotient under orthogonality to bands
- * 0..i-1, along Polak-Ribiere conjugate directions of the preconditioned
- * gradient, with the exact line minimization psi cos(theta) + n sin(theta);
- * kinetic-only preconditioner P^2(G) = 1 / smax(T_G, precond_floor),
- * smax as in pw_david_opts.  One single-band float64 H.psi per iteration.
- * Same arguments and outputs as davidson_solve (psi [dev] in: trial vectors,
- * out: orthonormal eigenvectors; eig, resid [dev] from a final float64
- * H.psi); needs a plan with ndim_max >= 2 (its workspace).  Returns PW_OK,
+ * eigenpairs of H psi = eps S psi (the iterative-diagonalization appendix,
+ * "Conjugate-Gradient"): band i minimizes the Rayleigh quotient
+ * <psi|H|psi> / <psi|S|psi> under S-orthogonality to bands 0..i-1, along
+ * Polak-Ribiere conjugate directions of the preconditioned gradient, with the
+ * exact line minimization psi cos(theta) + n sin(theta), n S-normalized and
+ * S-orthogonal to psi; kinetic-only preconditioner
+ * P^2(G) = 1 / smax(T_G, precond_floor), smax as in pw_david_opts.  S = 1
+ * unless the plan carries ultrasoft q blocks.  One single-band float64 H.psi
+ * per iteration (with q blocks also two single-band S.psi).  Full-sphere
+ * plans only (PW_EINVAL for Gamma plans).  Same arguments and outputs as
+ * davidson_solve (psi [dev] in: trial vectors, out: S-orthonormal
+ * eigenvectors; eig, resid [dev] from a final float64 H.psi and S.psi,
+ * resid_i = ||H psi_i - eps_i S psi_i||_2); needs a plan with
+ * ndim_max >= 2 (its workspace).  Returns PW_OK,
  * PW_ENOTCONV (a band reached max_iter; outputs valid), PW_ENAN, PW_EINVAL,
  * PW_EDEVICE.  The host reads one small result per iteration.
  */

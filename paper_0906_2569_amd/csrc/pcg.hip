@@ -1,25 +1,26 @@
 // Band-by-band preconditioned conjugate gradient for the nb lowest
 // eigenpairs (the iterative-diagonalization appendix, "Conjugate-Gradient"),
-// S = 1, float64.
+// float64, for S = 1 and for the ultrasoft overlap S = 1 + sum beta q beta^H.
 //
 // Band i minimizes <y|H~|y> - lambda (<y|S~|y> - 1), H~ = PHP, S~ = PSP,
-// y = P^-1 psi, subject to orthogonality to the bands already found.  The
+// y = P^-1 psi, subject to S-orthogonality to the bands already found.  The
 // vectors kept are the appendix's P g and P h, in the psi variables:
 //
-//   lambda = Re <psi|P^2|H psi> / <psi|P^2|psi>       (makes P g orthogonal to psi)
-//   G = P g = P^2 (H psi - lambda psi), then made orthogonal to psi_j, j < i
+//   lambda = Re <S psi|P^2|H psi> / <S psi|P^2|S psi>   (makes P g S-orthogonal to psi)
+//   G = P g = P^2 (H psi - lambda S psi), then made S-orthogonal to psi_j, j < i
 //   D = P h = G + gamma D_prev,  gamma = Re <G - G_prev|G> / <G_prev|G_prev>
-//       (Polak-Ribiere), then made orthogonal to psi;  N = D / ||D||
-//   psi <- psi cos(theta) + N sin(theta),  H psi <- H psi cos(theta) + H N sin(theta)
+//       (Polak-Ribiere), then made S-orthogonal to psi;  N = D / <D|S|D>^(1/2)
+//   psi <- psi cos(theta) + N sin(theta), and H psi, S psi likewise
 //   theta = (1/2) atan(a / (eps - b)), a = 2 Re <psi|H N>, b = <N|H N>,
 //       eps = <psi|H psi>; of the two stationary angles theta, theta + pi/2
 //       the one with the lower energy
 //
 // with the kinetic-only preconditioner P^2(G) = 1 / smax(T_G, tau).  One H.psi
-// of a single band per iteration.  The vector steps run in single 1024-thread
-// workgroups (fixed-order reductions: reproducible); the host reads one small
-// flag block per iteration.  A final float64 H.psi of the whole block gives
-// the returned eigenvalues and residual norms.
+// of a single band per iteration (and, with S != 1, one S.psi of N and one of
+// G for its projection on the bands found).  The vector steps run in single
+// 1024-thread workgroups (fixed-order reductions: reproducible); the host
+// reads one small flag block per iteration.  A final float64 H.psi (and S.psi)
+// of the whole block gives the returned eigenvalues and residual norms.
 #include <cmath>
 
 #include "plan.h"
@@ -73,30 +74,34 @@ __global__ void __launch_bounds__(CT) k_cg_start(int npw, const c128* __restrict
   }
 }
 
-// G = P^2 (H psi - lambda psi), lambda = Re <psi|P^2 H psi> / <psi|P^2 psi>
-__global__ void __launch_bounds__(CT) k_cg_grad(int npw, const c128* __restrict__ psi,
+// G = P^2 (H psi - lambda S psi), lambda = Re <S psi|P^2 H psi> / <S psi|P^2 S psi>;
+// spsi is S psi (psi itself when S = 1)
+__global__ void __launch_bounds__(CT) k_cg_grad(int npw, const c128* __restrict__ spsi,
                                               const c128* __restrict__ hpsi, const double* __restrict__ kin,
                                               double tau, c128* __restrict__ G, CgScalars* __restrict__ sc) {
   __shared__ double red[2 * 16];
   double v[2] = {0.0, 0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const double p2 = p2_of(kin[g], tau);
-    v[0] += p2 * (psi[g].x * hpsi[g].x + psi[g].y * hpsi[g].y);
-    v[1] += p2 * (psi[g].x * psi[g].x + psi[g].y * psi[g].y);
+    v[0] += p2 * (spsi[g].x * hpsi[g].x + spsi[g].y * hpsi[g].y);
+    v[1] += p2 * (spsi[g].x * spsi[g].x + spsi[g].y * spsi[g].y);
   }
   block_sums<2>(v, red);
   const double lam = v[0] / v[1];
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const double p2 = p2_of(kin[g], tau);
-    G[g] = c128{p2 * (hpsi[g].x - lam * psi[g].x), p2 * (hpsi[g].y - lam * psi[g].y)};
+    G[g] = c128{p2 * (hpsi[g].x - lam * spsi[g].x), p2 * (hpsi[g].y - lam * spsi[g].y)};
   }
   if (threadIdx.x == 0) sc->lambda = lam;
 }
 
-// D = G + gamma D (gamma = 0 on the first iteration), D -= psi <psi|D>,
-// N = D / ||D||, Gp = G, gg_prev = <G|G>
-__global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__ psi, const c128* __restrict__ G,
-                                             c128* __restrict__ Gp, c128* __restrict__ D, c128* __restrict__ N,
+// D = G + gamma D (gamma = 0 on the first iteration), D -= psi <S psi|D>,
+// Gp = G, gg_prev = <G|G>; N = D / ||D|| when S = 1 (US false: spsi is psi),
+// N = D otherwise (normalized in the S metric once S N is known)
+template <bool US>
+__global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__ psi, const c128* __restrict__ spsi,
+                                             const c128* __restrict__ G, c128* __restrict__ Gp,
+                                             c128* __restrict__ D, c128* __restrict__ N,
                                              CgScalars* __restrict__ sc) {
   __shared__ double red[2 * 16];
   double v[2] = {0.0, 0.0};
@@ -113,8 +118,8 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
     const c128 d = c128{G[g].x + gamma * dprev.x, G[g].y + gamma * dprev.y};
     D[g] = d;
     Gp[g] = G[g];
-    w[0] += psi[g].x * d.x + psi[g].y * d.y;                     // Re <psi|D>
-    w[1] += psi[g].x * d.y - psi[g].y * d.x;                     // Im <psi|D>
+    w[0] += spsi[g].x * d.x + spsi[g].y * d.y;                   // Re <S psi|D>
+    w[1] += spsi[g].x * d.y - spsi[g].y * d.x;                   // Im <S psi|D>
   }
   block_sums<2>(w, red);
   double u[1] = {0.0};
@@ -124,18 +129,25 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
     D[g] = d;
     u[0] += d.x * d.x + d.y * d.y;
   }
-  block_sums<1>(u, red);
-  const double inv = u[0] > 0.0 ? 1.0 / sqrt(u[0]) : 0.0;
-  for (int g = threadIdx.x; g < npw; g += blockDim.x) N[g] = c128{D[g].x * inv, D[g].y * inv};
+  if (US) {
+    for (int g = threadIdx.x; g < npw; g += blockDim.x) N[g] = D[g];
+  } else {
+    block_sums<1>(u, red);
+    const double inv = u[0] > 0.0 ? 1.0 / sqrt(u[0]) : 0.0;
+    for (int g = threadIdx.x; g < npw; g += blockDim.x) N[g] = c128{D[g].x * inv, D[g].y * inv};
+  }
   if (threadIdx.x == 0) {
     sc->gg_prev = v[0];
     sc->first = 0;
   }
 }
 
-// line minimization along N, update of psi and H psi, new eps and residual
+// line minimization along N, update of psi, H psi (and S psi when US), new
+// eps = <psi|H psi> / <psi|S psi> and residual ||H psi - eps S psi||
+template <bool US>
 __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ psi, c128* __restrict__ hpsi,
-                                                const c128* __restrict__ N, const c128* __restrict__ HN,
+                                                c128* __restrict__ spsi, const c128* __restrict__ N,
+                                                const c128* __restrict__ HN, const c128* __restrict__ SN,
                                                 double tol_r, double tol_e, CgScalars* __restrict__ sc) {
   __shared__ double red[2 * 16];
   __shared__ double cs[2];
@@ -164,14 +176,20 @@ __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ ps
     const c128 hx = c128{hpsi[g].x * c + HN[g].x * s, hpsi[g].y * c + HN[g].y * s};
     psi[g] = x;
     hpsi[g] = hx;
+    c128 sx = x;
+    if (US) {
+      sx = c128{spsi[g].x * c + SN[g].x * s, spsi[g].y * c + SN[g].y * s};
+      spsi[g] = sx;
+    }
     w[0] += x.x * hx.x + x.y * hx.y;
-    w[1] += x.x * x.x + x.y * x.y;
+    w[1] += x.x * sx.x + x.y * sx.y;
   }
   block_sums<2>(w, red);
   const double e = w[0] / w[1];
   double r[1] = {0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double re = hpsi[g].x - e * psi[g].x, im = hpsi[g].y - e * psi[g].y;
+    const c128 sx = US ? spsi[g] : psi[g];
+    const double re = hpsi[g].x - e * sx.x, im = hpsi[g].y - e * sx.y;
     r[0] += re * re + im * im;
   }
   block_sums<1>(r, red);
@@ -195,11 +213,25 @@ __global__ void __launch_bounds__(CT) k_cg_normalize(int npw, c128* __restrict__
   for (int g = threadIdx.x; g < npw; g += blockDim.x) x[g] = c128{x[g].x * inv, x[g].y * inv};
 }
 
+// x <- x / <x|S x>^(1/2) and S x likewise
+__global__ void __launch_bounds__(CT) k_cg_snormalize(int npw, c128* __restrict__ x, c128* __restrict__ sx) {
+  __shared__ double red[16];
+  double v[1] = {0.0};
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) v[0] += x[g].x * sx[g].x + x[g].y * sx[g].y;
+  block_sums<1>(v, red);
+  const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    x[g] = c128{x[g].x * inv, x[g].y * inv};
+    sx[g] = c128{sx[g].x * inv, sx[g].y * inv};
+  }
+}
+
 }  // namespace
 
 struct CgWork {
   int ld = 0;
   c128 *psi = nullptr, *hpsi = nullptr, *G = nullptr, *Gp = nullptr, *D = nullptr, *N = nullptr, *HN = nullptr;
+  c128 *spsi = nullptr, *SN = nullptr, *SX = nullptr;   // S psi, S N, S x of a projection (S != 1 only)
   c128* coef = nullptr;          // [nb_max] projections on the bands already found
   CgScalars* sc = nullptr;       // device
   CgScalars* hsc = nullptr;      // pinned host
@@ -210,7 +242,7 @@ struct CgWork {
 
 size_t pw::cg_bytes(int npw, int nb_max) {
   const size_t ld = ((size_t)npw + 15) / 16 * 16;
-  return 7 * ld * sizeof(c128) + (size_t)nb_max * sizeof(c128) + 4096 +
+  return 10 * ld * sizeof(c128) + (size_t)nb_max * sizeof(c128) + 4096 +
          pw::splitk_part_bytes(nb_max, 1, npw, sizeof(c128));
 }
 
@@ -224,7 +256,8 @@ pw_status pw::cg_alloc(pw_plan p) {
     return PW_OK;
   };
   const size_t vb = (size_t)W->ld * sizeof(c128);
-  for (c128** v : {&W->psi, &W->hpsi, &W->G, &W->Gp, &W->D, &W->N, &W->HN}) PW_TRY(get(vb, (void**)v));
+  for (c128** v : {&W->psi, &W->hpsi, &W->G, &W->Gp, &W->D, &W->N, &W->HN, &W->spsi, &W->SN, &W->SX})
+    PW_TRY(get(vb, (void**)v));
   PW_TRY(get((size_t)p->opts.nb_max * sizeof(c128), (void**)&W->coef));
   PW_TRY(get(sizeof(CgScalars), (void**)&W->sc));
   W->part_bytes = pw::splitk_part_bytes(p->opts.nb_max, 1, p->npw, sizeof(c128));
@@ -253,12 +286,29 @@ extern "C" void pw_cg_opts_default(pw_cg_opts* o) {
 }
 
 namespace {
-// x -= Psi (Psi^H x) for the i bands in Psi (column-major, ldq)
+// x -= Psi (Psi^H S x) for the i S-orthonormal bands in Psi (column-major, ldq)
 pw_status orth_lower(pw_plan p, CgWork& W, int i, const c128* Psi, int ldq, c128* x, hipStream_t st) {
   if (i == 0) return PW_OK;
-  PW_TRY((pw::zgemm_cn<double, double, double>(i, 1, p->npw, Psi, ldq, x, W.ld, W.coef, i, W.part, W.part_bytes,
+  const c128* sx = x;
+  if (p->us) {
+    PW_TRY(pw::spsi_launch(p, PW_FP64, 1, x, W.ld, W.SX, W.ld, st));
+    sx = W.SX;
+  }
+  PW_TRY((pw::zgemm_cn<double, double, double>(i, 1, p->npw, Psi, ldq, sx, W.ld, W.coef, i, W.part, W.part_bytes,
                                                st)));
   PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, 1, i, -1.0, Psi, ldq, W.coef, i, 1.0, x, W.ld, st)));
+  return PW_OK;
+}
+
+// psi normalized in the S metric; S psi in W.spsi when S != 1
+pw_status normalize(pw_plan p, CgWork& W, hipStream_t st) {
+  if (p->us) {
+    PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.psi, W.ld, W.spsi, W.ld, st));
+    k_cg_snormalize<<<1, CT, 0, st>>>(p->npw, W.psi, W.spsi);
+  } else {
+    k_cg_normalize<<<1, CT, 0, st>>>(p->npw, W.psi);
+  }
+  PW_HIP(hipGetLastError());
   return PW_OK;
 }
 }  // namespace
@@ -267,7 +317,6 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
                                const pw_cg_opts* o_, pw_cg_stats* stats_out, void* stream) {
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
   PW_CHECK(p->cg != nullptr, PW_EINVAL, "plan was created without solver workspace (ndim_max = 0)");
-  PW_CHECK(!p->us, PW_EINVAL, "the conjugate-gradient solver handles S = 1 (norm-conserving) problems only");
   PW_CHECK(!p->gamma, PW_EINVAL, "the conjugate-gradient solver works on the full sphere (no Gamma plans)");
   pw_cg_opts o;
   if (o_) o = *o_; else pw_cg_opts_default(&o);
@@ -282,6 +331,7 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
   CgWork& W = *p->cg;
   c128* out = reinterpret_cast<c128*>(psi_u);
   const int npw = p->npw;
+  const bool us = p->us;
   const size_t pitch = sizeof(c128) * npw;
   pw_cg_stats stats{};
   pw_status result = PW_OK;
@@ -290,18 +340,29 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
     PW_HIP(hipMemcpyAsync(W.psi, out + (size_t)i * ldpsi, pitch, hipMemcpyDeviceToDevice, st));
     PW_TRY(orth_lower(p, W, i, out, ldpsi, W.psi, st));
     PW_TRY(orth_lower(p, W, i, out, ldpsi, W.psi, st));
-    k_cg_normalize<<<1, CT, 0, st>>>(npw, W.psi);
+    PW_TRY(normalize(p, W, st));
     PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.psi, W.ld, W.hpsi, W.ld, st));
     k_cg_start<<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.sc);
     PW_HIP(hipGetLastError());
     int it = 0;
     bool conv = false;
     for (; it < o.max_iter; ) {
-      k_cg_grad<<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, p->kin, o.precond_floor, W.G, W.sc);
+      k_cg_grad<<<1, CT, 0, st>>>(npw, us ? W.spsi : W.psi, W.hpsi, p->kin, o.precond_floor, W.G, W.sc);
       PW_TRY(orth_lower(p, W, i, out, ldpsi, W.G, st));
-      k_cg_dir<<<1, CT, 0, st>>>(npw, W.psi, W.G, W.Gp, W.D, W.N, W.sc);
+      if (us) {
+        k_cg_dir<true><<<1, CT, 0, st>>>(npw, W.psi, W.spsi, W.G, W.Gp, W.D, W.N, W.sc);
+        PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.N, W.ld, W.SN, W.ld, st));
+        k_cg_snormalize<<<1, CT, 0, st>>>(npw, W.N, W.SN);
+      } else {
+        k_cg_dir<false><<<1, CT, 0, st>>>(npw, W.psi, W.psi, W.G, W.Gp, W.D, W.N, W.sc);
+      }
       PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.N, W.ld, W.HN, W.ld, st));
-      k_cg_rotate<<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.N, W.HN, o.tol_resid, o.tol_deig, W.sc);
+      if (us)
+        k_cg_rotate<true><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.spsi, W.N, W.HN, W.SN, o.tol_resid, o.tol_deig,
+                                            W.sc);
+      else
+        k_cg_rotate<false><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, nullptr, W.N, W.HN, nullptr, o.tol_resid,
+                                             o.tol_deig, W.sc);
       PW_HIP(hipGetLastError());
       ++it;
       PW_HIP(hipMemcpyAsync(W.hsc, W.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
@@ -317,9 +378,9 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
       }
     }
     if (result != PW_OK) break;
-    // the band joins the found ones, orthogonal to them and normalized
+    // the band joins the found ones, S-orthogonal to them and S-normalized
     PW_TRY(orth_lower(p, W, i, out, ldpsi, W.psi, st));
-    k_cg_normalize<<<1, CT, 0, st>>>(npw, W.psi);
+    PW_TRY(normalize(p, W, st));
     PW_HIP(hipMemcpyAsync(out + (size_t)i * ldpsi, W.psi, pitch, hipMemcpyDeviceToDevice, st));
     stats.iters += it;
     stats.max_band_iters = std::max(stats.max_band_iters, it);

@@ -106,13 +106,30 @@ def test_generalized_davidson_tiny_cell_k_point(ctx):
     np.testing.assert_allclose(eig.cpu().numpy(), w, atol=TOL_EIG, rtol=0)
 
 
-def test_pcg_rejects_ultrasoft(ctx):
+@pytest.mark.parametrize("cell,general", [("config1", False), ("tiny", True)])
+def test_generalized_pcg_against_dense(ctx, cell, general):
+    # band-by-band CG in the S metric: the lowest generalized eigenvalues, an
+    # S-orthonormal block, and residuals ||H psi - eps S psi|| of that problem
     from paper_0906_2569_amd import pwdft
-    p = _us(pwgen.config1(), 44)
+    if cell == "config1":
+        p = _us(pwgen.config1(), 44, general)
+    else:
+        p = _us(pwgen.tiny_cell(45, a=7.0, ecut_ry=9.0, natoms=4, nb=8, kfrac=(0.1, -0.2, 0.3), nr=(36, 30, 40)),
+                45, general)
+    h, s = oracle.dense_h_of(p), oracle.dense_s_of(p)
+    w, _ = oracle.eigh_lowest_gen(h, s, p.nb)
     plan = pwdft.Plan(ctx, p, precision=0, nb_max=p.nb, ndim_max=2)
     try:
-        with pytest.raises(pwdft.PwError) as ei:
-            plan.pcg(torch.from_numpy(p.psi0).cuda())
-        assert ei.value.status == pwdft.PW_EINVAL
+        x = torch.from_numpy(np.ascontiguousarray(p.psi0)).cuda()
+        st, eig, resid, stats = plan.pcg(x)
+        torch.cuda.synchronize()
+        eig, resid, psi = eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy()
     finally:
         plan.close()
+    print("generalized CG", cell, "stats", stats.asdict(), "max err", np.abs(eig - w).max())
+    assert st == 0 and stats.nconv == p.nb
+    np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+    np.testing.assert_allclose(np.conj(psi) @ s @ psi.T, np.eye(p.nb), atol=1e-10)
+    r = np.linalg.norm(psi @ h.T - eig[:, None] * (psi @ s.T), axis=1)
+    np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)
+    assert resid.max() <= 1e-6

@@ -118,7 +118,7 @@ typedef struct {
                                 psi(0) real; the imaginary part of psi(0) is ignored).  H.psi packs two
                                 bands into one complex transform, and the projector and subspace
                                 products are real products over the interleaved half sphere.
-                                Norm-conserving only; pw_density and pcg_solve are not available. */
+                                Norm-conserving only; pcg_solve is not available.                 */
 } pw_plan_opts;
 
 typedef struct {
@@ -279,7 +279,9 @@ pw_status pcg_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, doubl
  * Output charge density of a block of bands (the rho_out equation of the
  * self-consistency appendix, with occupation weights):
  *   rho(r_j) = (1/omega) sum_b w_b |psi_b(r_j)|^2,   psi_b(r_j) = sum_G psi_b(G) exp(+i G.r_j),
- * on the plan's FFT grid r_j (x fastest).  psi [dev] [nb][ldpsi] complex128;
+ * on the plan's FFT grid r_j (x fastest).  psi [dev] [nb][ldpsi] complex128
+ * (at Gamma the half-sphere coefficients, psi(-G) = conj psi(G); two bands
+ * share one complex transform);
  * w [dev] double[nb]; omega = cell volume in bohr^3; rho [dev]
  * double[n3][n2][n1], overwritten (accumulate = 0) or added to (accumulate = 1).
  * The grid holds the density without aliasing when n_d >= 4 max|m_d| + 1

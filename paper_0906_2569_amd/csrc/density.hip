@@ -29,11 +29,14 @@ size_t dens_lds_bytes(int n1, int n2, int n3) {
   return 2 * sizeof(c128) * (size_t)DCB * lmax + sizeof(double) * (size_t)DCB * n1 + sizeof(int) * (size_t)n1;
 }
 
-// rows [r0, r0+DCB) of plane z: for each band, inverse x of the row (its x
-// columns scattered to their grid positions), then acc += w_b |psi_b(r)|^2
+// rows [r0, r0+DCB) of plane z: for each transform t, inverse x of the row
+// (its x columns scattered to their grid positions), then
+// acc += w_t |psi_t(r)|^2, or at Gamma (gamma = 1: transform t holds
+// psi_2t(r) + i psi_2t+1(r), both real) acc += w_2t Re^2 + w_2t+1 Im^2
 __global__ void __launch_bounds__(DTHREADS)
-k_density_x(SphereMap m, const c128* __restrict__ rows, int nb, const double* __restrict__ w,
-            const c128* __restrict__ tw1, double inv_omega, int add, double* __restrict__ rho) {
+k_density_x(SphereMap m, const c128* __restrict__ rows, int nt, int nbands, int gamma,
+            const double* __restrict__ w, const c128* __restrict__ tw1, double inv_omega, int add,
+            double* __restrict__ rho) {
   extern __shared__ __align__(16) char smem_raw[];
   const int n1 = m.n1, n2 = m.n2, nxr = m.nxr;
   const int lmax = max(n1, max(n2, m.n3));
@@ -46,9 +49,10 @@ k_density_x(SphereMap m, const c128* __restrict__ rows, int nb, const double* __
   for (int i = threadIdx.x; i < n1; i += blockDim.x) hx_of[i] = m.i1_hx[i];
   for (int i = threadIdx.x; i < DCB * n1; i += blockDim.x) acc[i] = 0.0;
   __syncthreads();
-  for (int b = 0; b < nb; ++b) {
+  for (int b = 0; b < nt; ++b) {
     const c128* rw = rows + (((size_t)b * m.n3 + z) * n2 + r0) * nxr;
-    const double wb = w[b];
+    const double wa = gamma ? w[2 * b] : w[b];
+    const double wi = gamma ? (2 * b + 1 < nbands ? w[2 * b + 1] : 0.0) : wa;
     fft_run<double>(
         m.f1, nr, 1.0, tw1, A, B, lmax, false, false,
         [&](int r, int i) {
@@ -56,7 +60,7 @@ k_density_x(SphereMap m, const c128* __restrict__ rows, int nb, const double* __
           return hx >= 0 ? rw[(size_t)r * nxr + hx] : c128{0.0, 0.0};
         },
         // every (r, i) is stored by exactly one thread per transform
-        [&](int r, int i, c128 v) { acc[r * n1 + i] += wb * (v.x * v.x + v.y * v.y); });
+        [&](int r, int i, c128 v) { acc[r * n1 + i] += wa * (v.x * v.x) + wi * (v.y * v.y); });
   }
   double* out = rho + ((size_t)z * n2 + r0) * n1;
   for (int e = threadIdx.x; e < nr * n1; e += blockDim.x) {
@@ -180,7 +184,6 @@ extern "C" pw_status pw_density(pw_plan p, int32_t nb, const pw_c128* psi, int32
                                 double omega, int32_t accumulate, double* rho, void* stream) {
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
   PW_CHECK(p->dgrid != nullptr, PW_EINVAL, "plan was created without density workspace (opts.density = 0)");
-  PW_CHECK(!p->gamma, PW_EINVAL, "pw_density works on full-sphere plans (no Gamma plans)");
   PW_CHECK(nb >= 0 && nb <= p->opts.nb_max, PW_EINVAL, "nb out of range [0, nb_max]");
   PW_CHECK(ldpsi >= p->npw, PW_EINVAL, "ldpsi < npw");
   PW_CHECK(omega > 0.0 && std::isfinite(omega), PW_EINVAL, "omega must be positive");
@@ -197,12 +200,17 @@ extern "C" pw_status pw_density(pw_plan p, int32_t nb, const pw_c128* psi, int32
     return PW_OK;
   }
   pw::ProfScope ps(pw::PK_DENSITY, s, (double)nb * (16.0 * p->npw) + 8.0 * (double)p->N);
-  for (int c0 = 0; c0 < nb; c0 += p->band_chunk) {
-    const int nbc = std::min(p->band_chunk, nb - c0);
-    PW_TRY(pw::psi_to_rows(p, nbc, psi_c + (size_t)c0 * ldpsi, ldpsi, s));
+  // transforms: one per band, or one per pair of bands at Gamma
+  const bool gam = p->gamma;
+  const int nt = gam ? ceil_div(nb, 2) : nb;
+  for (int c0 = 0; c0 < nt; c0 += p->band_chunk) {
+    const int ntc = std::min(p->band_chunk, nt - c0);
+    const int b0 = gam ? 2 * c0 : c0;
+    const int nbb = gam ? std::min(nb - b0, 2 * ntc) : ntc;
+    PW_TRY(pw::psi_to_rows(p, ntc, nbb, psi_c + (size_t)b0 * ldpsi, ldpsi, s));
     k_density_x<<<dim3(p->n3, ceil_div(p->n2, DCB)), DTHREADS, lds, s>>>(
-        m, static_cast<const c128*>(p->rows), nbc, w + c0, p->tw64_1, 1.0 / omega, (accumulate || c0 > 0) ? 1 : 0,
-        rho);
+        m, static_cast<const c128*>(p->rows), ntc, nbb, gam ? 1 : 0, w + b0, p->tw64_1, 1.0 / omega,
+        (accumulate || c0 > 0) ? 1 : 0, rho);
     PW_HIP(hipGetLastError());
   }
   return PW_OK;

@@ -1897,24 +1897,31 @@ pw_status hpsi_fft(pw_plan p, int nb, const c128* psi, int ldpsi, c128* hpsi, in
 }
 }  // namespace
 
-pw_status pw::psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStream_t s) {
+pw_status pw::psi_to_rows(pw_plan p, int nt, int nbands, const c128* psi, int ldpsi, hipStream_t s) {
   PW_CHECK(p->rows != nullptr, PW_EINVAL, "plan has no plane-copy workspace (create it with opts.density = 1)");
-  PW_CHECK(nb >= 0 && nb <= p->band_chunk, PW_EINVAL, "more bands than one transform chunk");
-  if (nb == 0) return PW_OK;
+  PW_CHECK(nt >= 0 && nt <= p->band_chunk, PW_EINVAL, "more transforms than one chunk");
+  PW_CHECK(p->gamma ? (nbands <= 2 * nt && nbands >= 2 * nt - 1) || (nt == 0 && nbands == 0) : nbands == nt,
+           PW_EINVAL, "band count does not match the transform count");
+  if (nt == 0) return PW_OK;
   const SphereMap m = p->map();
   const cpx<double>* tw2 = (const cpx<double>*)p->tw64_2;
   const cpx<double>* tw3 = (const cpx<double>*)p->tw64_3;
   cpx<double>* st = static_cast<cpx<double>*>(p->sticks);
   const ZRegFns<double> zr = p->use_reg_plane ? zreg_kernels<double>(p->n3) : ZRegFns<double>{};
-  const int nb8 = ceil_div(nb, 8) * 8;
-  if (zr.inv) {
-    const int gzr = ceil_div(p->nst, ZRSTICKS);
-    zr.inv<<<gzr * nb8, ZRTHREADS, 0, s>>>(m, psi, ldpsi, st, tw3, gzr, nb);
+  const int nt8 = ceil_div(nt, 8) * 8;
+  const int gzr = ceil_div(p->nst, ZRSTICKS), gz = ceil_div(p->nst, ZSB);
+  const size_t zl = z_lds_bytes<double>(p->n3);
+  if (p->gamma) {
+    if (zr.inv_g)
+      zr.inv_g<<<gzr * nt8, ZRTHREADS, 0, s>>>(m, psi, ldpsi, st, tw3, gzr, nt, nbands);
+    else
+      k_zinv_g<double><<<gz * nt8, ZTHREADS, zl, s>>>(m, psi, ldpsi, st, tw3, gz, nt, nbands);
+  } else if (zr.inv) {
+    zr.inv<<<gzr * nt8, ZRTHREADS, 0, s>>>(m, psi, ldpsi, st, tw3, gzr, nt);
   } else {
-    const int gz = ceil_div(p->nst, ZSB);
-    k_zinv<double><<<gz * nb8, ZTHREADS, z_lds_bytes<double>(p->n3), s>>>(m, psi, ldpsi, st, tw3, gz, nb);
+    k_zinv<double><<<gz * nt8, ZTHREADS, zl, s>>>(m, psi, ldpsi, st, tw3, gz, nt);
   }
-  k_plane_yinv<double><<<dim3(p->n3, nb, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS,
+  k_plane_yinv<double><<<dim3(p->n3, nt, ceil_div(p->nxr, SPLIT_CB)), SPLIT_THREADS,
                          split_lds_bytes<double>(p->n1, p->n2), s>>>(m, st, static_cast<cpx<double>*>(p->rows), tw2);
   PW_HIP(hipGetLastError());
   return PW_OK;

@@ -161,9 +161,11 @@ pw_status plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* o, M
                       hipStream_t stream, pw_plan* out);
 void plan_destroy(pw_plan p);
 
-// sphere -> sticks -> rows for nb <= band_chunk bands in float64: inverse z
-// and inverse y transforms into p->rows ([band][z][y][x column])
-pw_status psi_to_rows(pw_plan p, int nb, const c128* psi, int ldpsi, hipStream_t stream);
+// sphere -> sticks -> rows for nt <= band_chunk transforms in float64: inverse
+// z and inverse y transforms into p->rows ([transform][z][y][x column]).  One
+// transform per band (nt = nbands), or at Gamma one per pair of bands
+// (nt = ceil(nbands / 2), psi_2t + i psi_2t+1)
+pw_status psi_to_rows(pw_plan p, int nt, int nbands, const c128* psi, int ldpsi, hipStream_t stream);
 // H.psi for nb bands (nb <= opts.nb_max) on `stream`.
 pw_status hpsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi,
                       c128* hpsi, int ldhpsi, hipStream_t stream);

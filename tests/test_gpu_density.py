@@ -125,3 +125,32 @@ def test_scf_norm_of_two_densities(ctx):
     ref = oracle.scf_norm2(oracle.density(p.miller, p.nr, p.psi0, w, omega) -
                            oracle.density(p.miller, p.nr, psi2, w, omega), bvec, omega)
     assert abs(got - ref) <= 1e-11 * ref
+
+
+@pytest.mark.parametrize("nb,chunked", [(8, False), (7, False), (7, True)])
+def test_gamma_density_against_oracle(ctx, nb, chunked):
+    # Gamma plans: half-sphere bands, two real bands per complex transform
+    # (psi_2t(r) + i psi_2t+1(r)); an odd count leaves the last one alone, and
+    # a small workspace splits the 4 transforms into chunks of 2
+    g = pwgen.gamma_cell(7.0, 9.0, 3, nb, 86, nr=(36, 30, 40))
+    w = np.linspace(2.0, 0.5, nb)
+    omega = g.a ** 3
+    ref = oracle.density(g.full.miller, g.nr, g.expand(g.psi0), w, omega)
+    kw = {}
+    if chunked:
+        probe = _plan(ctx, g, nb, gamma=1)
+        info = probe.info()
+        probe.close()
+        per_t = 16 * g.nr[2] * ((info["nsticks"] + 3) // 4 * 4) + 16 * g.nr[2] * g.nr[1] * info["ncols"]
+        kw["fft_ws_bytes"] = 2 * per_t + 100
+    plan = _plan(ctx, g, nb, gamma=1, **kw)
+    try:
+        if chunked:
+            assert plan.info()["band_chunk"] == 2
+        x = torch.from_numpy(np.ascontiguousarray(g.psi0)).cuda()
+        got = plan.density(x, w, omega).cpu().numpy()
+    finally:
+        plan.close()
+    np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max(), rtol=0)
+    charge = got.sum() * omega / np.prod(g.nr)
+    assert abs(charge - w.sum()) <= 1e-12 * w.sum()

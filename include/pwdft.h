@@ -118,7 +118,7 @@ typedef struct {
                                 psi(0) real; the imaginary part of psi(0) is ignored).  H.psi packs two
                                 bands into one complex transform, and the projector and subspace
                                 products are real products over the interleaved half sphere.
-                                Norm-conserving only; pcg_solve is not available.                 */
+                                Norm-conserving only.                                             */
 } pw_plan_opts;
 
 typedef struct {
@@ -250,8 +250,9 @@ pw_status davidson_solve(pw_plan plan, int32_t nb, pw_c128* psi, int32_t ldpsi, 
  * S-orthogonal to psi; kinetic-only preconditioner
  * P^2(G) = 1 / smax(T_G, precond_floor), smax as in pw_david_opts.  S = 1
  * unless the plan carries ultrasoft q blocks.  One single-band float64 H.psi
- * per iteration (with q blocks also two single-band S.psi).  Full-sphere
- * plans only (PW_EINVAL for Gamma plans).  Same arguments and outputs as
+ * per iteration (with q blocks also two single-band S.psi).  On Gamma plans
+ * the bands are half-sphere real functions and every inner product is the
+ * whole-sphere real one.  Same arguments and outputs as
  * davidson_solve (psi [dev] in: trial vectors, out: S-orthonormal
  * eigenvectors; eig, resid [dev] from a final float64 H.psi and S.psi,
  * resid_i = ||H psi_i - eps_i S psi_i||_2); needs a plan with

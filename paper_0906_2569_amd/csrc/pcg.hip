@@ -1,6 +1,7 @@
 // Band-by-band preconditioned conjugate gradient for the nb lowest
 // eigenpairs (the iterative-diagonalization appendix, "Conjugate-Gradient"),
-// float64, for S = 1 and for the ultrasoft overlap S = 1 + sum beta q beta^H.
+// float64, for S = 1 and for the ultrasoft overlap S = 1 + sum beta q beta^H,
+// on the full sphere or, at Gamma, on the half sphere of real functions.
 //
 // Band i minimizes <y|H~|y> - lambda (<y|S~|y> - 1), H~ = PHP, S~ = PSP,
 // y = P^-1 psi, subject to S-orthogonality to the bands already found.  The
@@ -59,12 +60,21 @@ __device__ __forceinline__ double p2_of(double t, double tau) {
   return 1.0 / (0.5 * (t + tau + sqrt((t - tau) * (t - tau) + tau * tau)));
 }
 
+// Weight of entry g in a real inner product over the whole sphere.  At Gamma
+// (GAM) the vectors hold the half sphere of real functions: every entry but
+// G = 0 (index 0, real) stands for G and -G, so Re <a|b> = 2 sum - a(0) b(0);
+// the imaginary part of such a product is zero.
+template <bool GAM>
+__device__ __forceinline__ double wt(int g) { return GAM ? (g == 0 ? 1.0 : 2.0) : 1.0; }
+
 // eps = <psi|H psi> (psi normalized before), first iteration flag
+template <bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_start(int npw, const c128* __restrict__ psi,
                                                const c128* __restrict__ hpsi, CgScalars* __restrict__ sc) {
   __shared__ double red[16];
   double v[1] = {0.0};
-  for (int g = threadIdx.x; g < npw; g += blockDim.x) v[0] += psi[g].x * hpsi[g].x + psi[g].y * hpsi[g].y;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x)
+    v[0] += wt<GAM>(g) * (psi[g].x * hpsi[g].x + psi[g].y * hpsi[g].y);
   block_sums<1>(v, red);
   if (threadIdx.x == 0) {
     sc->eps = v[0];
@@ -76,13 +86,14 @@ __global__ void __launch_bounds__(CT) k_cg_start(int npw, const c128* __restrict
 
 // G = P^2 (H psi - lambda S psi), lambda = Re <S psi|P^2 H psi> / <S psi|P^2 S psi>;
 // spsi is S psi (psi itself when S = 1)
+template <bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_grad(int npw, const c128* __restrict__ spsi,
                                               const c128* __restrict__ hpsi, const double* __restrict__ kin,
                                               double tau, c128* __restrict__ G, CgScalars* __restrict__ sc) {
   __shared__ double red[2 * 16];
   double v[2] = {0.0, 0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    const double p2 = p2_of(kin[g], tau);
+    const double p2 = wt<GAM>(g) * p2_of(kin[g], tau);
     v[0] += p2 * (spsi[g].x * hpsi[g].x + spsi[g].y * hpsi[g].y);
     v[1] += p2 * (spsi[g].x * spsi[g].x + spsi[g].y * spsi[g].y);
   }
@@ -98,7 +109,7 @@ __global__ void __launch_bounds__(CT) k_cg_grad(int npw, const c128* __restrict_
 // D = G + gamma D (gamma = 0 on the first iteration), D -= psi <S psi|D>,
 // Gp = G, gg_prev = <G|G>; N = D / ||D|| when S = 1 (US false: spsi is psi),
 // N = D otherwise (normalized in the S metric once S N is known)
-template <bool US>
+template <bool US, bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__ psi, const c128* __restrict__ spsi,
                                              const c128* __restrict__ G, c128* __restrict__ Gp,
                                              c128* __restrict__ D, c128* __restrict__ N,
@@ -106,8 +117,8 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
   __shared__ double red[2 * 16];
   double v[2] = {0.0, 0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    v[0] += G[g].x * G[g].x + G[g].y * G[g].y;                   // <G|G>
-    v[1] += Gp[g].x * G[g].x + Gp[g].y * G[g].y;                 // Re <Gp|G>
+    v[0] += wt<GAM>(g) * (G[g].x * G[g].x + G[g].y * G[g].y);    // <G|G>
+    v[1] += wt<GAM>(g) * (Gp[g].x * G[g].x + Gp[g].y * G[g].y);  // Re <Gp|G>
   }
   block_sums<2>(v, red);
   const bool first = sc->first != 0;
@@ -118,16 +129,17 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
     const c128 d = c128{G[g].x + gamma * dprev.x, G[g].y + gamma * dprev.y};
     D[g] = d;
     Gp[g] = G[g];
-    w[0] += spsi[g].x * d.x + spsi[g].y * d.y;                   // Re <S psi|D>
+    w[0] += wt<GAM>(g) * (spsi[g].x * d.x + spsi[g].y * d.y);    // Re <S psi|D>
     w[1] += spsi[g].x * d.y - spsi[g].y * d.x;                   // Im <S psi|D>
   }
   block_sums<2>(w, red);
+  if (GAM) w[1] = 0.0;
   double u[1] = {0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const c128 p = psi[g];
     const c128 d = c128{D[g].x - (p.x * w[0] - p.y * w[1]), D[g].y - (p.x * w[1] + p.y * w[0])};
     D[g] = d;
-    u[0] += d.x * d.x + d.y * d.y;
+    u[0] += wt<GAM>(g) * (d.x * d.x + d.y * d.y);
   }
   if (US) {
     for (int g = threadIdx.x; g < npw; g += blockDim.x) N[g] = D[g];
@@ -144,7 +156,7 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
 
 // line minimization along N, update of psi, H psi (and S psi when US), new
 // eps = <psi|H psi> / <psi|S psi> and residual ||H psi - eps S psi||
-template <bool US>
+template <bool US, bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ psi, c128* __restrict__ hpsi,
                                                 c128* __restrict__ spsi, const c128* __restrict__ N,
                                                 const c128* __restrict__ HN, const c128* __restrict__ SN,
@@ -153,8 +165,8 @@ __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ ps
   __shared__ double cs[2];
   double v[2] = {0.0, 0.0};
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
-    v[0] += psi[g].x * HN[g].x + psi[g].y * HN[g].y;             // Re <psi|H N>
-    v[1] += N[g].x * HN[g].x + N[g].y * HN[g].y;                 // <N|H N>
+    v[0] += wt<GAM>(g) * (psi[g].x * HN[g].x + psi[g].y * HN[g].y);   // Re <psi|H N>
+    v[1] += wt<GAM>(g) * (N[g].x * HN[g].x + N[g].y * HN[g].y);       // <N|H N>
   }
   block_sums<2>(v, red);
   if (threadIdx.x == 0) {
@@ -181,8 +193,8 @@ __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ ps
       sx = c128{spsi[g].x * c + SN[g].x * s, spsi[g].y * c + SN[g].y * s};
       spsi[g] = sx;
     }
-    w[0] += x.x * hx.x + x.y * hx.y;
-    w[1] += x.x * sx.x + x.y * sx.y;
+    w[0] += wt<GAM>(g) * (x.x * hx.x + x.y * hx.y);
+    w[1] += wt<GAM>(g) * (x.x * sx.x + x.y * sx.y);
   }
   block_sums<2>(w, red);
   const double e = w[0] / w[1];
@@ -190,7 +202,7 @@ __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ ps
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
     const c128 sx = US ? spsi[g] : psi[g];
     const double re = hpsi[g].x - e * sx.x, im = hpsi[g].y - e * sx.y;
-    r[0] += re * re + im * im;
+    r[0] += wt<GAM>(g) * (re * re + im * im);
   }
   block_sums<1>(r, red);
   if (threadIdx.x == 0) {
@@ -203,11 +215,15 @@ __global__ void __launch_bounds__(CT) k_cg_rotate(int npw, c128* __restrict__ ps
   }
 }
 
-// x <- x / ||x||
+// x <- x / ||x||; at Gamma the imaginary part of x(G = 0) is set to zero first
+template <bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_normalize(int npw, c128* __restrict__ x) {
   __shared__ double red[16];
   double v[1] = {0.0};
-  for (int g = threadIdx.x; g < npw; g += blockDim.x) v[0] += x[g].x * x[g].x + x[g].y * x[g].y;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) {
+    if (GAM && g == 0) x[0].y = 0.0;   // the thread that owns g = 0 reads it back below
+    v[0] += wt<GAM>(g) * (x[g].x * x[g].x + x[g].y * x[g].y);
+  }
   block_sums<1>(v, red);
   const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) x[g] = c128{x[g].x * inv, x[g].y * inv};
@@ -243,7 +259,7 @@ struct CgWork {
 size_t pw::cg_bytes(int npw, int nb_max) {
   const size_t ld = ((size_t)npw + 15) / 16 * 16;
   return 10 * ld * sizeof(c128) + (size_t)nb_max * sizeof(c128) + 4096 +
-         pw::splitk_part_bytes(nb_max, 1, npw, sizeof(c128));
+         std::max(pw::splitk_part_bytes(nb_max, 1, npw, sizeof(c128)), pw::dgemm_part_bytes(nb_max, 1));
 }
 
 pw_status pw::cg_alloc(pw_plan p) {
@@ -260,7 +276,8 @@ pw_status pw::cg_alloc(pw_plan p) {
     PW_TRY(get(vb, (void**)v));
   PW_TRY(get((size_t)p->opts.nb_max * sizeof(c128), (void**)&W->coef));
   PW_TRY(get(sizeof(CgScalars), (void**)&W->sc));
-  W->part_bytes = pw::splitk_part_bytes(p->opts.nb_max, 1, p->npw, sizeof(c128));
+  W->part_bytes = std::max(pw::splitk_part_bytes(p->opts.nb_max, 1, p->npw, sizeof(c128)),
+                           pw::dgemm_part_bytes(p->opts.nb_max, 1));
   PW_TRY(get(W->part_bytes, &W->part));
   void* h = nullptr;
   PW_TRY(pw::host_alloc(p, sizeof(CgScalars), &h));
@@ -286,7 +303,8 @@ extern "C" void pw_cg_opts_default(pw_cg_opts* o) {
 }
 
 namespace {
-// x -= Psi (Psi^H S x) for the i S-orthonormal bands in Psi (column-major, ldq)
+// x -= Psi (Psi^H S x) for the i S-orthonormal bands in Psi (column-major, ldq);
+// at Gamma the projections are the real whole-sphere products 2 sum - (G = 0 term)
 pw_status orth_lower(pw_plan p, CgWork& W, int i, const c128* Psi, int ldq, c128* x, hipStream_t st) {
   if (i == 0) return PW_OK;
   const c128* sx = x;
@@ -294,8 +312,14 @@ pw_status orth_lower(pw_plan p, CgWork& W, int i, const c128* Psi, int ldq, c128
     PW_TRY(pw::spsi_launch(p, PW_FP64, 1, x, W.ld, W.SX, W.ld, st));
     sx = W.SX;
   }
-  PW_TRY((pw::zgemm_cn<double, double, double>(i, 1, p->npw, Psi, ldq, sx, W.ld, W.coef, i, W.part, W.part_bytes,
-                                               st)));
+  if (p->gamma)
+    PW_TRY((pw::dgemm_tn<double, double, double>(i, 1, 2 * p->npw, reinterpret_cast<const double*>(Psi), 2L * ldq,
+                                                 reinterpret_cast<const double*>(sx), 2L * W.ld, 1.0, 1.0, 0.0,
+                                                 reinterpret_cast<double*>(W.coef), i, true, W.part, W.part_bytes,
+                                                 st)));
+  else
+    PW_TRY((pw::zgemm_cn<double, double, double>(i, 1, p->npw, Psi, ldq, sx, W.ld, W.coef, i, W.part,
+                                                 W.part_bytes, st)));
   PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, 1, i, -1.0, Psi, ldq, W.coef, i, 1.0, x, W.ld, st)));
   return PW_OK;
 }
@@ -305,9 +329,30 @@ pw_status normalize(pw_plan p, CgWork& W, hipStream_t st) {
   if (p->us) {
     PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.psi, W.ld, W.spsi, W.ld, st));
     k_cg_snormalize<<<1, CT, 0, st>>>(p->npw, W.psi, W.spsi);
+  } else if (p->gamma) {
+    k_cg_normalize<true><<<1, CT, 0, st>>>(p->npw, W.psi);
   } else {
-    k_cg_normalize<<<1, CT, 0, st>>>(p->npw, W.psi);
+    k_cg_normalize<false><<<1, CT, 0, st>>>(p->npw, W.psi);
   }
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
+// one CG step of band i: gradient, its projection on the bands found, the
+// conjugate direction, H N (and S N), the line minimization
+template <bool US, bool GAM>
+pw_status cg_step(pw_plan p, CgWork& W, int i, const c128* out, int ldpsi, const pw_cg_opts& o, hipStream_t st) {
+  const int npw = p->npw;
+  k_cg_grad<GAM><<<1, CT, 0, st>>>(npw, US ? W.spsi : W.psi, W.hpsi, p->kin, o.precond_floor, W.G, W.sc);
+  PW_TRY(orth_lower(p, W, i, out, ldpsi, W.G, st));
+  k_cg_dir<US, GAM><<<1, CT, 0, st>>>(npw, W.psi, US ? W.spsi : W.psi, W.G, W.Gp, W.D, W.N, W.sc);
+  if (US) {
+    PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.N, W.ld, W.SN, W.ld, st));
+    k_cg_snormalize<<<1, CT, 0, st>>>(npw, W.N, W.SN);
+  }
+  PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.N, W.ld, W.HN, W.ld, st));
+  k_cg_rotate<US, GAM><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, US ? W.spsi : nullptr, W.N, W.HN,
+                                         US ? W.SN : nullptr, o.tol_resid, o.tol_deig, W.sc);
   PW_HIP(hipGetLastError());
   return PW_OK;
 }
@@ -317,7 +362,6 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
                                const pw_cg_opts* o_, pw_cg_stats* stats_out, void* stream) {
   PW_CHECK(p != nullptr, PW_EINVAL, "NULL plan");
   PW_CHECK(p->cg != nullptr, PW_EINVAL, "plan was created without solver workspace (ndim_max = 0)");
-  PW_CHECK(!p->gamma, PW_EINVAL, "the conjugate-gradient solver works on the full sphere (no Gamma plans)");
   pw_cg_opts o;
   if (o_) o = *o_; else pw_cg_opts_default(&o);
   PW_CHECK(nb >= 1 && nb <= p->opts.nb_max, PW_EINVAL, "nb out of range [1, nb_max]");
@@ -331,7 +375,7 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
   CgWork& W = *p->cg;
   c128* out = reinterpret_cast<c128*>(psi_u);
   const int npw = p->npw;
-  const bool us = p->us;
+  const bool us = p->us, gam = p->gamma;   // Gamma plans are norm-conserving: never both
   const size_t pitch = sizeof(c128) * npw;
   pw_cg_stats stats{};
   pw_status result = PW_OK;
@@ -342,28 +386,16 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
     PW_TRY(orth_lower(p, W, i, out, ldpsi, W.psi, st));
     PW_TRY(normalize(p, W, st));
     PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.psi, W.ld, W.hpsi, W.ld, st));
-    k_cg_start<<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.sc);
+    if (gam)
+      k_cg_start<true><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.sc);
+    else
+      k_cg_start<false><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.sc);
     PW_HIP(hipGetLastError());
     int it = 0;
     bool conv = false;
     for (; it < o.max_iter; ) {
-      k_cg_grad<<<1, CT, 0, st>>>(npw, us ? W.spsi : W.psi, W.hpsi, p->kin, o.precond_floor, W.G, W.sc);
-      PW_TRY(orth_lower(p, W, i, out, ldpsi, W.G, st));
-      if (us) {
-        k_cg_dir<true><<<1, CT, 0, st>>>(npw, W.psi, W.spsi, W.G, W.Gp, W.D, W.N, W.sc);
-        PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.N, W.ld, W.SN, W.ld, st));
-        k_cg_snormalize<<<1, CT, 0, st>>>(npw, W.N, W.SN);
-      } else {
-        k_cg_dir<false><<<1, CT, 0, st>>>(npw, W.psi, W.psi, W.G, W.Gp, W.D, W.N, W.sc);
-      }
-      PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.N, W.ld, W.HN, W.ld, st));
-      if (us)
-        k_cg_rotate<true><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, W.spsi, W.N, W.HN, W.SN, o.tol_resid, o.tol_deig,
-                                            W.sc);
-      else
-        k_cg_rotate<false><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, nullptr, W.N, W.HN, nullptr, o.tol_resid,
-                                             o.tol_deig, W.sc);
-      PW_HIP(hipGetLastError());
+      auto step = us ? cg_step<true, false> : gam ? cg_step<false, true> : cg_step<false, false>;
+      PW_TRY(step(p, W, i, out, ldpsi, o, st));
       ++it;
       PW_HIP(hipMemcpyAsync(W.hsc, W.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));
       PW_HIP(hipStreamSynchronize(st));

@@ -143,3 +143,29 @@ def test_gamma_group_z_passes_float64(ctx, n3):
     ref = oracle.hpsi(h, g.expand(g.psi0))[:, g.half]
     assert _rel(got, ref) <= 1e-11
     assert np.abs(got[:, 0].imag).max() == 0.0
+
+
+@pytest.mark.parametrize("nb", [16, 7])
+def test_gamma_pcg_against_dense(ctx, nb):
+    # band-by-band CG on the half sphere: real whole-sphere inner products
+    # (2 sum - G = 0 term) in every step and in the projections on the bands found
+    from paper_0906_2569_amd import pwdft
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 16, 26, nr=(30, 30, 30))
+    h = oracle.dense_h_of(g.full)
+    w, _ = oracle.eigh_lowest(h, nb)
+    plan = pwdft.Plan(ctx, g, precision=0, nb_max=nb, ndim_max=2, gamma=1)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(g.psi0[:nb])).cuda()
+        st, eig, resid, stats = plan.pcg(x)
+        torch.cuda.synchronize()
+        eig, resid, psi = eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy()
+    finally:
+        plan.close()
+    print("gamma CG", nb, stats.asdict(), "max err", np.abs(eig - w).max())
+    assert st == 0 and stats.nconv == nb
+    np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+    np.testing.assert_allclose(_gdot(psi, psi), np.eye(nb), atol=1e-10)
+    assert np.abs(psi[:, 0].imag).max() == 0.0
+    full = g.expand(psi)
+    r = np.linalg.norm(oracle.hpsi(h, full) - eig[:, None] * full, axis=1)
+    np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)

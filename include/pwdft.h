@@ -223,7 +223,8 @@ pw_status spsi_apply(pw_plan plan, pw_precision prec, int32_t nb, const pw_c128*
  * With an ultrasoft problem (qmat) the generalized problem H psi = eps S psi
  * is solved: residuals (H - eps_i S) psi_i, reduced overlap phi^H S phi, the
  * preconditioner's diagonal h_diag(G) - eps_i s_diag(G), and S phi carried
- * through every Ritz rotation; opts->lock is ignored (no locking).
+ * through every Ritz rotation; locked bands (opts->lock) keep S psi, and later
+ * corrections are made S-orthogonal to them.
  *   eig   [dev] double[nb], ascending Rayleigh quotients of the output psi.
  *   resid [dev] double[nb], ||H psi_i - eps_i psi_i||_2 of the output psi.
  * Both are recomputed by a final float64 H.psi.  opts may be NULL (defaults);

@@ -582,11 +582,15 @@ struct Solver {
     const dim3 g(std::min(64, ceil_div(npw, 256)), std::min(nact, 1024));
     k_gather_cols<<<g, 256, 0, st>>>(npw, nact, W.perm, W.psi, W.ld, W.phi, W.ld);
     k_gather_cols<<<g, 256, 0, st>>>(npw, nact, W.perm, W.hpsi, W.ld, W.hphi, W.ld);
+    if (p->us) k_gather_cols<<<g, 256, 0, st>>>(npw, nact, W.perm, W.spsi, W.ld, W.sphi, W.ld);
     PW_HIP(hipGetLastError());
     PW_HIP(hipMemcpy2DAsync(W.psi + (size_t)nl * W.ld, pitch, W.phi, pitch, sizeof(c128) * npw, nact,
                             hipMemcpyDeviceToDevice, st));
     PW_HIP(hipMemcpy2DAsync(W.hpsi + (size_t)nl * W.ld, pitch, W.hphi, pitch, sizeof(c128) * npw, nact,
                             hipMemcpyDeviceToDevice, st));
+    if (p->us)
+      PW_HIP(hipMemcpy2DAsync(W.spsi + (size_t)nl * W.ld, pitch, W.sphi, pitch, sizeof(c128) * npw, nact,
+                              hipMemcpyDeviceToDevice, st));
     nl += nc;
     return PW_OK;
   }
@@ -597,10 +601,26 @@ struct Solver {
   // along it): no locked direction re-enters the basis
   // x -= Psi_l (Psi_l^H x) over `passes` passes (classical Gram-Schmidt
   // repeated: the second pass removes what rounding left after the first; it
-  // needs no normalization in between), then unit columns if `normalize`
-  pw_status project_out_locked(int c0, int n, int passes = 2, bool normalize = true) {
+  // needs no normalization in between), then unit columns if `normalize`.
+  // With S != 1 the projector is 1 - Psi_l (S Psi_l)^H, which leaves x
+  // S-orthogonal to the locked bands, or for a residual (`dual`, a vector of
+  // the form (H - eps S) psi) its adjoint 1 - (S Psi_l) Psi_l^H
+  pw_status project_out_locked(int c0, int n, int passes = 2, bool normalize = true, bool dual = false) {
     if (nl == 0 || n == 0) return PW_OK;
     c128* x = W.phi + (size_t)c0 * W.ld;
+    if (p->us) {   // no Gamma plans with S != 1
+      const c128* cl = dual ? W.psi : W.spsi;   // the columns the coefficients take
+      const c128* ul = dual ? W.spsi : W.psi;   // the columns the update takes
+      for (int pass = 0; pass < passes; ++pass) {
+        PW_TRY((pw::zgemm_cn<double, double, double>(nl, n, p->npw, cl, W.ld, x, W.ld, W.lockc, nl, W.part,
+                                                     W.part_bytes, st)));
+        PW_TRY((pw::zgemm_nn<double, double, double>(p->npw, n, nl, -1.0, ul, W.ld, W.lockc, nl, 1.0, x, W.ld,
+                                                     st)));
+      }
+      if (normalize) k_normalize<<<n, kVecThreads, 0, st>>>(p->npw, x, W.ld, 0);
+      PW_HIP(hipGetLastError());
+      return PW_OK;
+    }
     for (int pass = 0; pass < passes; ++pass) {
       if (p->gamma) {
         const long l2 = 2L * W.ld;
@@ -636,7 +656,7 @@ struct Solver {
       return PW_OK;
     }
     k_residvec<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, spsi_or_psi(), W.hpsi, W.ld, W.eps, x, W.ld);
-    PW_TRY(project_out_locked(c0, n, 1, false));
+    PW_TRY(project_out_locked(c0, n, 1, false, true));
     k_precond<<<n, kVecThreads, 0, st>>>(p->npw, W.idx, W.eps, p->hdiag, p->sdiag, floor_, x, W.ld, p->gamma ? 1 : 0);
     PW_HIP(hipGetLastError());
     return project_out_locked(c0, n);
@@ -664,7 +684,6 @@ extern "C" pw_status davidson_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32
   PW_CHECK(p->dav != nullptr, PW_EINVAL, "plan was created without Davidson workspace (ndim_max = 0)");
   pw_david_opts o;
   if (o_) o = *o_; else pw_david_opts_default(&o);
-  if (p->us) o.lock = 0;   // locked bands would need S-orthogonal projections: not done
   DavWork& W = *p->dav;
   PW_CHECK(nb >= 1 && nb <= W.nbmax, PW_EINVAL, "nb out of range [1, nb_max]");
   PW_CHECK(nb <= p->npw, PW_EINVAL, "nb > npw");

@@ -61,10 +61,13 @@ def test_spsi_is_identity_without_q(ctx):
         plan.close()
 
 
-@pytest.mark.parametrize("precision,ndim,sub32", [(0, 2, 1), (0, 4, 1), (1, 4, 1), (1, 4, 2)])
-def test_generalized_davidson_against_dense(ctx, precision, ndim, sub32):
+@pytest.mark.parametrize("precision,ndim,sub32,lock", [(0, 2, 1, 1), (0, 2, 1, 0), (0, 4, 1, 1), (1, 4, 1, 1),
+                                                       (1, 4, 2, 1), (1, 2, 1, 1)])
+def test_generalized_davidson_against_dense(ctx, precision, ndim, sub32, lock):
     # sub32 = 2: float32 rotations of phi, H phi and S phi in the float32 stage,
-    # the collapsed block's S-overlap formed from float32 products
+    # the collapsed block's S-overlap formed from float32 products; lock = 1:
+    # converged bands locked in the float64 stage, later corrections made
+    # S-orthogonal to them
     from paper_0906_2569_amd import pwdft
     p = _us(pwgen.config1(), 42)
     h, s = oracle.dense_h_of(p), oracle.dense_s_of(p)
@@ -72,13 +75,18 @@ def test_generalized_davidson_against_dense(ctx, precision, ndim, sub32):
     plan = pwdft.Plan(ctx, p, precision=precision, nb_max=p.nb, ndim_max=max(ndim, 2))
     try:
         x = torch.from_numpy(p.psi0).cuda()
-        st, eig, resid, stats = plan.davidson(x, opts=pwdft.default_opts(ndim=ndim, max_iter=400, sub32=sub32))
+        st, eig, resid, stats = plan.davidson(x, opts=pwdft.default_opts(ndim=ndim, max_iter=400, sub32=sub32,
+                                                                         lock=lock))
         torch.cuda.synchronize()
         eig, resid, psi = eig.cpu().numpy(), resid.cpu().numpy(), x.cpu().numpy()
     finally:
         plan.close()
     print("generalized Davidson, precision", precision, "stats", stats.asdict(), "max err", np.abs(eig - w).max())
-    assert st == 0 and stats.nlocked == 0
+    assert st == 0
+    if lock == 0:
+        assert stats.nlocked == 0
+    elif ndim == 2:
+        assert stats.nlocked > 0     # frequent collapses: some bands lock
     np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
     # S-orthonormal output and residuals of the generalized problem
     np.testing.assert_allclose(np.conj(psi) @ s @ psi.T, np.eye(p.nb), atol=1e-10)

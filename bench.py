@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device to device once (reference kernel "
                          "for the FETCH_SIZE / WRITE_SIZE counter scale)")
+    ap.add_argument("--class-profile", action="store_true",
+                    help="solve512: after the timed solves, one more float64 solve with every kernel class "
+                         "timed (HIP events around each class's launches); reports each class's time and "
+                         "rate, the subspace products' fraction of the FP64 MFMA peak among them")
     ap.add_argument("--mode", choices=["solve", "hpsi"], default="solve",
                     help="solve: a step is one Davidson solve; hpsi: a step is one hpsi_apply of the "
                          "128-band block (for kernel profiles of H.psi alone)")
@@ -641,7 +645,9 @@ def bench_solve512(args):
     opts = pwdft.default_opts(ndim=args.ndim, max_iter=400)
     psi0 = torch.from_numpy(p.psi0).to(dev)
 
-    def solves(prec, nsteps, nwarm):
+    prof_out = {}
+
+    def solves(prec, nsteps, nwarm, profile=False):
         plan = pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=args.ndim)
         try:
             psi = torch.empty_like(psi0)
@@ -651,6 +657,8 @@ def bench_solve512(args):
             for i in range(nwarm + nsteps):
                 psi.copy_(psi0)
                 torch.cuda.synchronize()
+                if profile:
+                    pwdft.profile_enable(True)
                 t = time.perf_counter()
                 st, _, _, stats = plan.davidson(psi, eig, resid, opts=opts)
                 torch.cuda.synchronize()
@@ -658,6 +666,9 @@ def bench_solve512(args):
                     out.append((time.perf_counter() - t, st, stats.asdict()))
             return out, eig.cpu().numpy(), resid.cpu().numpy()
         finally:
+            if profile:
+                prof_out.update({k: v for k, v in pwdft.profile_read().items() if v[0] > 0})
+                pwdft.profile_enable(False)
             plan.close()
 
     prec = pwdft.PW_MIXED if args.precision == "mixed" else pwdft.PW_FP64
@@ -677,6 +688,29 @@ def bench_solve512(args):
         line["fp64_status"] = runs64[0][1]
         line["mixed_over_fp64"] = runs64[0][0] / sec
         line["max_abs_eig_diff_vs_fp64_ha"] = float(np.abs(e - e64).max())
+    if args.class_profile:
+        # every class timed with events in one more float64 solve (kept out of
+        # the figures above); flops for the products and factorizations, bytes
+        # for the transform passes and vector kernels
+        runs_p, _, _ = solves(pwdft.PW_FP64, 1, 0, profile=True)
+        flop_classes = {"calbec_gemm", "add_nl_gemm", "zgemm_cn", "zgemm_nn", "k_chol", "k_trinv", "k_tridiag",
+                        "k_backtr"}
+        cls = {}
+        for k, (n, ms, units) in sorted(prof_out.items(), key=lambda kv: -kv[1][1]):
+            rec = {"launches": n, "ms": round(ms, 2)}
+            if units > 0 and ms > 0:
+                if k in flop_classes:
+                    rec["tflops"] = round(units / ms * 1e-9, 2)
+                else:
+                    rec["gbs"] = round(units / ms * 1e-6, 1)
+            cls[k] = rec
+        line["fp64_solve_profiled_seconds"] = runs_p[0][0]
+        line["fp64_solve_classes"] = cls
+        line["fp64_solve_classes_note"] = ("one float64 solve with events around every kernel class; zgemm_cn: "
+                                           "the projections phi^H H phi, phi^H phi and the locked-band "
+                                           "projections; zgemm_nn: Ritz rotations, locked-band updates and the "
+                                           "Cholesky trailing updates (also inside k_chol); peak FP64 MFMA "
+                                           f"{FP64_PEAK_TF} TFLOP/s")
     print(json.dumps(line), flush=True)
     return 0 if all(st == 0 for _, st, _ in runs) else 1
 

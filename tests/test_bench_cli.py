@@ -32,6 +32,11 @@ def test_workload_defaults():
             assert (a.workload, a.precision, a.steps, a.warmup) == want
         sys.argv = ["bench.py", "--workload", "cell64"]
         assert bench.parse().ndim == 3
+        # the per-class profile of the 512-atom solve is opt-in
+        sys.argv = ["bench.py", "--workload", "solve512"]
+        assert bench.parse().class_profile is False
+        sys.argv = ["bench.py", "--workload", "solve512", "--class-profile"]
+        assert bench.parse().class_profile is True
     finally:
         sys.argv = argv
         sys.path.remove(ROOT)

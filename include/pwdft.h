@@ -197,6 +197,22 @@ pw_status pw_plan_destroy(pw_plan plan);
 pw_status pw_plan_info(pw_plan plan, int64_t out[8]);
 
 /*
+ * Replace the plan's local potential (one step of the self-consistency loop
+ * of the self-consistency appendix: V_in changes, the cell does not).
+ * vloc_r [dev] double[n3][n2][n1] real V_loc(r_j) in Ha, x fastest, as in
+ * pw_problem; read during the call (the caller may free it afterwards).  The
+ * plan's float64 copy, its float32 copy (PW_MIXED plans) and the diagonal of
+ * H used by the preconditioner (which holds the mean of V) are updated on
+ * `stream`; maps, projectors, D and q blocks and all workspace stay.  The new
+ * values are read back and checked first (one synchronization of `stream`):
+ * on PW_ENAN (a non-finite value) or PW_EDEVICE the plan is unchanged.  Work
+ * of this plan on other streams must not overlap the call; H.psi graphs of
+ * the plan replay with the new potential.  Errors: PW_EINVAL (NULL),
+ * PW_ENAN, PW_EDEVICE.
+ */
+pw_status pw_plan_set_potential(pw_plan plan, const double* vloc_r, void* stream);
+
+/*
  * hpsi = H psi for nb bands (overwrite).  psi and hpsi are [dev] blocks
  * [nb][ld] of pw_c128, ldpsi/ldhpsi >= npw, and must not overlap.  `prec`
  * selects float64 or float32 arithmetic for the FFT and projector steps (the

@@ -1657,6 +1657,31 @@ extern "C" pw_status pw_plan_info(pw_plan p, int64_t out[8]) {
   return PW_OK;
 }
 
+// New local potential for an existing plan (the self-consistency loop: the
+// geometry, sphere, projectors and workspace stay).  The new V(r) is read back
+// and checked on the host before anything of the plan changes.
+extern "C" pw_status pw_plan_set_potential(pw_plan p, const double* vloc_r, void* stream) {
+  PW_CHECK(p != nullptr && vloc_r != nullptr, PW_EINVAL, "NULL plan or vloc_r");
+  PW_HIP(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<double> hv(p->N);
+  PW_CHECK(hipMemcpyAsync(hv.data(), vloc_r, sizeof(double) * p->N, hipMemcpyDeviceToHost, st) == hipSuccess &&
+               hipStreamSynchronize(st) == hipSuccess,
+           PW_EDEVICE, "readback of vloc_r failed (is it a device pointer?)");
+  long double acc = 0.0L;
+  for (long i = 0; i < p->N; ++i) {
+    PW_CHECK(std::isfinite(hv[i]), PW_ENAN, "non-finite value in vloc_r");
+    acc += hv[i];
+  }
+  const double v0 = (double)(acc / (long double)p->N);
+  PW_HIP(hipMemcpyAsync(p->vr64, vloc_r, sizeof(double) * p->N, hipMemcpyDeviceToDevice, st));
+  if (p->vr32) k_f64_to_f32<<<1024, 256, 0, st>>>(p->vr64, p->vr32, (size_t)p->N);
+  k_hdiag<<<ceil_div(p->npw, 256), 256, 0, st>>>(p->npw, p->nbeta, p->beta64, p->ldb, p->dstart, p->dlen,
+                                               p->drow64, std::max(p->nhmax, 1), p->kin, v0, p->hdiag);
+  PW_HIP(hipGetLastError());
+  return PW_OK;
+}
+
 namespace {
 // The kernels and LDS sizes of one plane pass form, resolved once per call.
 template <typename T>

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "PW_OK", 1: "PW_ENOTCONV", -1: "PW_EINVAL", -2: "PW_ENOMEM", 
 # every symbol include/pwdft.h declares
 EXPORTS = ["pw_last_error", "pw_ctx_create", "pw_ctx_destroy", "pw_david_opts_default",
            "pw_footprint_bytes", "pw_plan_create", "pw_plan_destroy", "pw_plan_info",
-           "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
+           "pw_plan_set_potential", "hpsi_apply", "davidson_solve", "hpsi_apply_batched", "davidson_solve_batched",
            "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve", "pw_cg_opts_default", "spsi_apply", "pw_cancel", "pw_hpsi_graph_create",
            "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "pw_profile_enable", "pw_server_opts_default", "pw_server_create",
            "pw_server_submit", "pw_server_wait", "pw_server_poll", "pw_server_clock", "pw_server_destroy",
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.pw_plan_create.argtypes = [C.c_void_p, C.POINTER(Problem), C.POINTER(PlanOpts), C.POINTER(C.c_void_p)]
     lib.pw_plan_destroy.argtypes = [C.c_void_p]
     lib.pw_plan_info.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+    lib.pw_plan_set_potential.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
     lib.hpsi_apply.argtypes = [C.c_void_p, C.c_int, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p,
                                C.c_int32, C.c_void_p]
     lib.spsi_apply.argtypes = lib.hpsi_apply.argtypes
@@ -150,7 +151,8 @@ def load(path: str = LIB_PATH):
     lib.pw_profile_name.restype = C.c_char_p
     lib.pw_profile_read.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double), C.POINTER(C.c_double)]
     for name in ("pw_ctx_create", "pw_ctx_destroy", "pw_plan_create", "pw_plan_destroy",
-                 "pw_plan_info", "hpsi_apply", "spsi_apply", "davidson_solve", "pw_cancel",
+                 "pw_plan_info", "pw_plan_set_potential", "hpsi_apply", "spsi_apply", "davidson_solve",
+                 "pw_cancel",
                  "pw_hpsi_graph_create", "pw_graph_launch", "pw_graph_destroy", "pw_server_cancel", "hpsi_apply_batched", "davidson_solve_batched",
                  "pw_reduced_eigh", "pw_reduced_eigh_noalloc", "pw_density", "pw_scf_norm", "pcg_solve",
                  "pw_profile_enable", "pw_profile_only", "pw_profile_read", "pw_server_create",
@@ -354,6 +356,12 @@ class Plan:
         d["split_plane64"] = int(d["plane64"] == 1)
         d["split_plane32"] = int(d["plane32"] == 1)
         return d
+
+    def set_potential(self, vloc_r, stream=None):
+        """Replace V_loc(r) (float64 [n3][n2][n1] on the device) for the next H.psi and solves."""
+        assert vloc_r.dtype.is_floating_point and vloc_r.element_size() == 8 and vloc_r.is_contiguous()
+        assert vloc_r.numel() == self.nr[0] * self.nr[1] * self.nr[2]
+        _check(self.lib.pw_plan_set_potential(self.h, C.c_void_p(vloc_r.data_ptr()), _stream_ptr(stream)))
 
     def hpsi(self, psi, out=None, prec=PW_FP64, stream=None):
         """out = H psi for psi [nb][>=npw] complex128 on the device."""

@@ -377,3 +377,44 @@ def test_group_z_passes_float64(ctx, n3):
     got = _hpsi(ctx, p, p.psi0, prec=0)
     ref = oracle.hpsi(oracle.dense_h_of(p), p.psi0)
     assert _rel_err(got, ref) <= 1e-11
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_set_potential_matches_fresh_plan(ctx, precision):
+    # one self-consistency step: the plan takes a new V(r).  Its H.psi and its
+    # Davidson solve then equal those of a plan created with that V (same
+    # kernels on the same data: bit for bit), and H.psi matches the oracle's
+    # dense H built with it; a non-finite V is refused and leaves the plan as it was
+    import dataclasses
+    from paper_0906_2569_amd import pwdft
+    p = pwgen.config1()
+    rng = np.random.default_rng(91)
+    v2 = np.ascontiguousarray(p.vloc_r + 0.05 * rng.standard_normal(p.vloc_r.shape))
+    p2 = dataclasses.replace(p, vloc_r=v2)
+    x = _dev(p.psi0)
+    plan = pwdft.Plan(ctx, p, precision=precision, nb_max=p.nb, ndim_max=2)
+    fresh = pwdft.Plan(ctx, p2, precision=precision, nb_max=p.nb, ndim_max=2)
+    try:
+        before = plan.hpsi(x).cpu().numpy()
+        plan.set_potential(_dev(v2))
+        got = {}
+        for prec in ([0, 1] if precision else [0]):
+            got[prec] = plan.hpsi(x, prec=prec).cpu().numpy()
+            np.testing.assert_array_equal(got[prec], fresh.hpsi(x, prec=prec).cpu().numpy())
+        assert not np.array_equal(before, got[0])
+        assert _rel_err(got[0], oracle.hpsi(oracle.dense_h_of(p2), p.psi0)) <= 1e-11
+        ya, yb = x.clone(), x.clone()
+        sta, ea, _, _ = plan.davidson(ya)
+        stb, eb, _, _ = fresh.davidson(yb)
+        torch.cuda.synchronize()
+        assert sta == 0 and stb == 0
+        np.testing.assert_array_equal(ea.cpu().numpy(), eb.cpu().numpy())
+        bad = v2.copy()
+        bad[1, 2, 3] = np.inf
+        with pytest.raises(pwdft.PwError) as ei:
+            plan.set_potential(_dev(bad))
+        assert ei.value.status == pwdft.PW_ENAN
+        np.testing.assert_array_equal(plan.hpsi(x).cpu().numpy(), got[0])
+    finally:
+        plan.close()
+        fresh.close()

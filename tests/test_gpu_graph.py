@@ -72,3 +72,44 @@ def test_graph_of_gamma_and_mixed_plans(ctx):
         graph.close()
     finally:
         plan.close()
+
+
+@pytest.mark.parametrize("gamma", [0, 1])
+def test_graph_replays_after_set_potential(ctx, gamma):
+    # a captured H.psi reads the plan's potential buffers: after
+    # pw_plan_set_potential its replays give the product with the new V(r),
+    # equal to the eager call (full sphere and Gamma plans)
+    import dataclasses
+    from paper_0906_2569_amd import pwdft
+    if gamma:
+        g = pwgen.gamma_cell(10.0, 15.0, 8, 16, 27, nr=(30, 30, 30))
+        p, x0, full = g, g.psi0, g.full
+    else:
+        p = pwgen.config1()
+        x0, full = p.psi0, p
+    v2 = np.ascontiguousarray(full.vloc_r * 0.5 + 0.02)
+    plan = pwdft.Plan(ctx, p, precision=0, nb_max=p.nb, ndim_max=0, gamma=gamma)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(x0)).cuda()
+        y = torch.empty_like(x)
+        gr = plan.hpsi_graph(x, y, prec=0)
+        gr.replay()
+        torch.cuda.synchronize()
+        old = y.clone()
+        plan.set_potential(torch.from_numpy(v2).cuda())
+        for _ in range(2):
+            ref = plan.hpsi(x.clone(), prec=0)
+            torch.cuda.synchronize()
+            gr.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref)
+        assert not torch.equal(y, old)
+        h2 = oracle.dense_h_of(dataclasses.replace(full, vloc_r=v2))
+        want = oracle.hpsi(h2, full.psi0)
+        got = y.cpu().numpy()
+        if gamma:
+            want = want[:, g.half]
+        err = np.linalg.norm(got - want, axis=1) / np.linalg.norm(want, axis=1)
+        assert err.max() <= 1e-11
+    finally:
+        plan.close()

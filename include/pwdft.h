@@ -118,7 +118,8 @@ typedef struct {
                                 psi(0) real; the imaginary part of psi(0) is ignored).  H.psi packs two
                                 bands into one complex transform, and the projector and subspace
                                 products are real products over the interleaved half sphere.
-                                Norm-conserving only.                                             */
+                                q blocks (ultrasoft S) must be real as D is; S.psi is then a real
+                                product over the half sphere as well.                             */
 } pw_plan_opts;
 
 typedef struct {

@@ -506,6 +506,9 @@ struct Solver {
                 reinterpret_cast<double*>(W.psi + (size_t)nl * W.ld), l2, st, W.hw.info, -1));
       PW_TRY(nn(2 * p->npw, nact, nbase, 1.0, reinterpret_cast<const double*>(W.hphi), l2, W.creal, ldm, 0.0,
                 reinterpret_cast<double*>(W.hpsi + (size_t)nl * W.ld), l2, st, W.hw.info, -1));
+      if (p->us)   // S psi = (S phi) c
+        PW_TRY(nn(2 * p->npw, nact, nbase, 1.0, reinterpret_cast<const double*>(W.sphi), l2, W.creal, ldm, 0.0,
+                  reinterpret_cast<double*>(W.spsi + (size_t)nl * W.ld), l2, st, W.hw.info, -1));
       return PW_OK;
     }
     // psi = phi c and hpsi = (H phi) c in one launch
@@ -608,7 +611,7 @@ struct Solver {
   pw_status project_out_locked(int c0, int n, int passes = 2, bool normalize = true, bool dual = false) {
     if (nl == 0 || n == 0) return PW_OK;
     c128* x = W.phi + (size_t)c0 * W.ld;
-    if (p->us) {   // no Gamma plans with S != 1
+    if (p->us && !p->gamma) {
       const c128* cl = dual ? W.psi : W.spsi;   // the columns the coefficients take
       const c128* ul = dual ? W.spsi : W.psi;   // the columns the update takes
       for (int pass = 0; pass < passes; ++pass) {
@@ -622,13 +625,15 @@ struct Solver {
       return PW_OK;
     }
     for (int pass = 0; pass < passes; ++pass) {
-      if (p->gamma) {
+      if (p->gamma) {   // real products, S Psi_l in the same roles as above when S != 1
         const long l2 = 2L * W.ld;
         double* lc = reinterpret_cast<double*>(W.lockc);
-        PW_TRY((pw::dgemm_tn<double, double, double>(nl, n, 2 * p->npw, reinterpret_cast<const double*>(W.psi), l2,
+        const c128* cl = p->us && !dual ? W.spsi : W.psi;
+        const c128* ul = p->us && dual ? W.spsi : W.psi;
+        PW_TRY((pw::dgemm_tn<double, double, double>(nl, n, 2 * p->npw, reinterpret_cast<const double*>(cl), l2,
                                                      reinterpret_cast<const double*>(x), l2, 1.0, 1.0, 0.0, lc, nl,
                                                      false, W.part, W.part_bytes, st)));
-        PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, n, nl, -1.0, reinterpret_cast<const double*>(W.psi),
+        PW_TRY((pw::dgemm_nn<double, double, double>(2 * p->npw, n, nl, -1.0, reinterpret_cast<const double*>(ul),
                                                      l2, lc, nl, 1.0, reinterpret_cast<double*>(x), l2, st)));
         continue;
       }

@@ -1237,8 +1237,6 @@ pw_status check_problem(const pw_problem* pr, const pw_plan_opts* o, Geometry* g
   }
   PW_CHECK(o->gamma == 0 || o->gamma == 1, PW_EINVAL, "gamma must be 0 or 1");
   geo->gamma = o->gamma == 1;
-  if (geo->gamma) PW_CHECK(pr->qmat == nullptr || pr->nbeta == 0, PW_EINVAL,
-                           "the Gamma-point path handles norm-conserving (S = 1) problems only");
   PW_TRY(full_sphere(pr, geo->gamma, geo));
   const int nfull = (int)geo->enc.size();
   const int* mf = geo->mfull.data();
@@ -1383,6 +1381,8 @@ pw_status pw::plan_create(pw_ctx ctx, const pw_problem* pr, const pw_plan_opts* 
           PW_CHECK(std::isfinite(qij.re) && std::isfinite(qij.im), PW_ENAN, "non-finite q block entry");
           PW_CHECK(std::abs(qij.re - qji.re) <= 1e-12 * scale && std::abs(qij.im + qji.im) <= 1e-12 * scale,
                    PW_EINVAL, "q block " + std::to_string(b) + " is not Hermitian");
+          PW_CHECK(!geo.gamma || std::abs(qij.im) <= 1e-12 * scale, PW_EINVAL,
+                   "a Gamma-point problem needs real q blocks (real-space-real projectors)");
           qrow[(size_t)(o0 + i) * geo.nhmax + j] = c128{qij.re, qij.im};
         }
       pos += (size_t)nh * nh;
@@ -2070,6 +2070,29 @@ extern "C" pw_status hpsi_apply(pw_plan p, pw_precision prec, int32_t nb, const 
                          reinterpret_cast<c128*>(hpsi), ldhpsi, static_cast<hipStream_t>(stream));
 }
 
+namespace {
+// Gamma: S psi = psi + beta (q <beta|psi>) with the real projections of the
+// half sphere (2 sum - G = 0 term) and a real add-back over 2 npw rows;
+// spsi already holds psi
+template <typename T>
+pw_status spsi_gamma(pw_plan p, int nb, const c128* psi, int ldpsi, c128* spsi, int ldspsi, hipStream_t s) {
+  const T* beta = sizeof(T) == 8 ? (const T*)p->beta64 : (const T*)p->beta32;
+  // the real projections, then q applied to them, both in the q workspace
+  // (16 bytes per band and projector)
+  double* becp = static_cast<double*>(p->becpq);
+  T* becpq = reinterpret_cast<T*>(becp + (size_t)nb * p->nbeta);
+  const int K = 2 * p->npw;
+  PW_TRY((pw::dgemm_tn<T, T, double>(p->nbeta, nb, K, beta, 2L * p->ldb, reinterpret_cast<const double*>(psi),
+                                     2L * ldpsi, 1.0, 1.0, 0.0, becp, p->nbeta, false, p->part, p->part_bytes, s,
+                                     pw::PK_CALBEC)));
+  k_dapply_real<T><<<nb, 256, 0, s>>>(p->nbeta, nb, becp, p->dstart, p->dlen, p->qrow64, p->nhmax, becpq);
+  PW_HIP(hipGetLastError());
+  PW_TRY((pw::dgemm_nn<T, T, T>(K, nb, p->nbeta, 1.0, beta, 2L * p->ldb, becpq, p->nbeta, 1.0,
+                                reinterpret_cast<double*>(spsi), 2L * ldspsi, s, nullptr, pw::PK_ADDNL)));
+  return PW_OK;
+}
+}  // namespace
+
 pw_status pw::spsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi, int ldpsi, c128* spsi,
                           int ldspsi, hipStream_t s) {
   if (nb == 0) return PW_OK;
@@ -2078,6 +2101,8 @@ pw_status pw::spsi_launch(pw_plan p, pw_precision prec, int nb, const c128* psi,
   PW_HIP(hipMemcpy2DAsync(spsi, sizeof(c128) * ldspsi, psi, sizeof(c128) * ldpsi, sizeof(c128) * p->npw, nb,
                           hipMemcpyDeviceToDevice, s));
   if (!p->us) return PW_OK;
+  if (p->gamma) return f64 ? spsi_gamma<double>(p, nb, psi, ldpsi, spsi, ldspsi, s)
+                           : spsi_gamma<float>(p, nb, psi, ldpsi, spsi, ldspsi, s);
   if (f64) {
     c128* bq = static_cast<c128*>(p->becpq);
     PW_TRY(pw::calbec_d<double>(p, nb, psi, ldpsi, bq, s, p->qrow64));

@@ -229,11 +229,13 @@ __global__ void __launch_bounds__(CT) k_cg_normalize(int npw, c128* __restrict__
   for (int g = threadIdx.x; g < npw; g += blockDim.x) x[g] = c128{x[g].x * inv, x[g].y * inv};
 }
 
-// x <- x / <x|S x>^(1/2) and S x likewise
+// x <- x / <x|S x>^(1/2) and S x likewise (at Gamma the whole-sphere product;
+// x(G = 0) and S x(G = 0) are real there)
+template <bool GAM>
 __global__ void __launch_bounds__(CT) k_cg_snormalize(int npw, c128* __restrict__ x, c128* __restrict__ sx) {
   __shared__ double red[16];
   double v[1] = {0.0};
-  for (int g = threadIdx.x; g < npw; g += blockDim.x) v[0] += x[g].x * sx[g].x + x[g].y * sx[g].y;
+  for (int g = threadIdx.x; g < npw; g += blockDim.x) v[0] += wt<GAM>(g) * (x[g].x * sx[g].x + x[g].y * sx[g].y);
   block_sums<1>(v, red);
   const double inv = v[0] > 0.0 ? 1.0 / sqrt(v[0]) : 0.0;
   for (int g = threadIdx.x; g < npw; g += blockDim.x) {
@@ -327,8 +329,12 @@ pw_status orth_lower(pw_plan p, CgWork& W, int i, const c128* Psi, int ldq, c128
 // psi normalized in the S metric; S psi in W.spsi when S != 1
 pw_status normalize(pw_plan p, CgWork& W, hipStream_t st) {
   if (p->us) {
+    if (p->gamma) k_cg_normalize<true><<<1, CT, 0, st>>>(p->npw, W.psi);   // real psi(0) before S psi
     PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.psi, W.ld, W.spsi, W.ld, st));
-    k_cg_snormalize<<<1, CT, 0, st>>>(p->npw, W.psi, W.spsi);
+    if (p->gamma)
+      k_cg_snormalize<true><<<1, CT, 0, st>>>(p->npw, W.psi, W.spsi);
+    else
+      k_cg_snormalize<false><<<1, CT, 0, st>>>(p->npw, W.psi, W.spsi);
   } else if (p->gamma) {
     k_cg_normalize<true><<<1, CT, 0, st>>>(p->npw, W.psi);
   } else {
@@ -348,7 +354,7 @@ pw_status cg_step(pw_plan p, CgWork& W, int i, const c128* out, int ldpsi, const
   k_cg_dir<US, GAM><<<1, CT, 0, st>>>(npw, W.psi, US ? W.spsi : W.psi, W.G, W.Gp, W.D, W.N, W.sc);
   if (US) {
     PW_TRY(pw::spsi_launch(p, PW_FP64, 1, W.N, W.ld, W.SN, W.ld, st));
-    k_cg_snormalize<<<1, CT, 0, st>>>(npw, W.N, W.SN);
+    k_cg_snormalize<GAM><<<1, CT, 0, st>>>(npw, W.N, W.SN);
   }
   PW_TRY(pw::hpsi_launch(p, PW_FP64, 1, W.N, W.ld, W.HN, W.ld, st));
   k_cg_rotate<US, GAM><<<1, CT, 0, st>>>(npw, W.psi, W.hpsi, US ? W.spsi : nullptr, W.N, W.HN,
@@ -375,7 +381,7 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
   CgWork& W = *p->cg;
   c128* out = reinterpret_cast<c128*>(psi_u);
   const int npw = p->npw;
-  const bool us = p->us, gam = p->gamma;   // Gamma plans are norm-conserving: never both
+  const bool us = p->us, gam = p->gamma;
   const size_t pitch = sizeof(c128) * npw;
   pw_cg_stats stats{};
   pw_status result = PW_OK;
@@ -394,7 +400,8 @@ extern "C" pw_status pcg_solve(pw_plan p, int32_t nb, pw_c128* psi_u, int32_t ld
     int it = 0;
     bool conv = false;
     for (; it < o.max_iter; ) {
-      auto step = us ? cg_step<true, false> : gam ? cg_step<false, true> : cg_step<false, false>;
+      auto step = us ? (gam ? cg_step<true, true> : cg_step<true, false>)
+                     : (gam ? cg_step<false, true> : cg_step<false, false>);
       PW_TRY(step(p, W, i, out, ldpsi, o, st));
       ++it;
       PW_HIP(hipMemcpyAsync(W.hsc, W.sc, sizeof(CgScalars), hipMemcpyDeviceToHost, st));

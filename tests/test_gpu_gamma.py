@@ -169,3 +169,66 @@ def test_gamma_pcg_against_dense(ctx, nb):
     full = g.expand(psi)
     r = np.linalg.norm(oracle.hpsi(h, full) - eig[:, None] * full, axis=1)
     np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)
+
+
+def _gamma_us(seed, general=False):
+    # a Gamma cell with ultrasoft q blocks: diagonal ones, or small real
+    # symmetric ones (real-space-real projectors need real q at Gamma)
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 16, seed, nr=(30, 30, 30))
+    if general:
+        q = pwgen.hermitian_blocks(np.random.default_rng(seed), g.full.blk_off, scale=0.1)
+        g.full.qmat = np.ascontiguousarray(q.real.astype(np.complex128))
+    else:
+        g.full.qmat = pwgen.ultrasoft_q(g.full, seed)
+    return g
+
+
+@pytest.mark.parametrize("prec,general", [(0, False), (0, True), (1, True)])
+def test_gamma_spsi_against_dense(ctx, prec, general):
+    from paper_0906_2569_amd import pwdft
+    g = _gamma_us(28, general)
+    s = oracle.dense_s_of(g.full)
+    plan = pwdft.Plan(ctx, g, precision=prec, nb_max=g.nb, ndim_max=0, gamma=1)
+    try:
+        got = plan.spsi(torch.from_numpy(np.ascontiguousarray(g.psi0)).cuda(), prec=prec).cpu().numpy()
+    finally:
+        plan.close()
+    ref = (g.expand(g.psi0) @ s.T)[:, g.half]
+    assert _rel(got, ref) <= (1e-11 if prec == 0 else 2e-6)
+    assert np.abs(got[:, 0].imag).max() == 0.0
+
+
+@pytest.mark.parametrize("precision,lock,general", [(0, 1, False), (0, 0, True), (1, 1, True)])
+def test_gamma_generalized_davidson_against_dense(ctx, precision, lock, general):
+    g = _gamma_us(29, general)
+    h, s = oracle.dense_h_of(g.full), oracle.dense_s_of(g.full)
+    w, _ = oracle.eigh_lowest_gen(h, s, g.nb)
+    st, eig, resid, psi, stats = _solve(ctx, g, precision, 2, lock=lock, sub32=1)
+    print("gamma generalized Davidson", precision, lock, general, stats, "max err", np.abs(eig - w).max())
+    assert st == 0
+    np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+    full = g.expand(psi)
+    np.testing.assert_allclose(np.real(np.conj(full) @ s @ full.T), np.eye(g.nb), atol=1e-10)
+    r = np.linalg.norm(full @ h.T - eig[:, None] * (full @ s.T), axis=1)
+    np.testing.assert_allclose(resid, r, rtol=1e-6, atol=1e-12)
+
+
+def test_gamma_generalized_pcg_against_dense(ctx):
+    from paper_0906_2569_amd import pwdft
+    g = _gamma_us(30, True)
+    h, s = oracle.dense_h_of(g.full), oracle.dense_s_of(g.full)
+    nb = 8
+    w, _ = oracle.eigh_lowest_gen(h, s, nb)
+    plan = pwdft.Plan(ctx, g, precision=0, nb_max=nb, ndim_max=2, gamma=1)
+    try:
+        x = torch.from_numpy(np.ascontiguousarray(g.psi0[:nb])).cuda()
+        st, eig, resid, stats = plan.pcg(x)
+        torch.cuda.synchronize()
+        eig, psi = eig.cpu().numpy(), x.cpu().numpy()
+    finally:
+        plan.close()
+    print("gamma generalized CG", stats.asdict(), "max err", np.abs(eig - w).max())
+    assert st == 0
+    np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
+    full = g.expand(psi)
+    np.testing.assert_allclose(np.real(np.conj(full) @ s @ full.T), np.eye(nb), atol=1e-10)

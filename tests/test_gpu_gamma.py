@@ -232,3 +232,16 @@ def test_gamma_generalized_pcg_against_dense(ctx):
     np.testing.assert_allclose(eig, w, atol=TOL_EIG, rtol=0)
     full = g.expand(psi)
     np.testing.assert_allclose(np.real(np.conj(full) @ s @ full.T), np.eye(nb), atol=1e-10)
+
+
+def test_gamma_refuses_complex_q(ctx):
+    # q blocks with an imaginary part cannot belong to real-space-real
+    # projectors: the Gamma plan is refused, as for complex D
+    from paper_0906_2569_amd import pwdft
+    g = _gamma_us(31, True)
+    q = pwgen.hermitian_blocks(np.random.default_rng(31), g.full.blk_off, scale=0.1)
+    assert np.abs(q.imag).max() > 1e-3
+    g.full.qmat = q
+    with pytest.raises(pwdft.PwError) as ei:
+        pwdft.Plan(ctx, g, precision=0, nb_max=g.nb, ndim_max=0, gamma=1)
+    assert ei.value.status == pwdft.PW_EINVAL

@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(CT) k_cg_dir(int npw, const c128* __restrict__
     const c128 p = psi[g];
     const c128 d = c128{D[g].x - (p.x * w[0] - p.y * w[1]), D[g].y - (p.x * w[1] + p.y * w[0])};
     D[g] = d;
-    u[0] += wt<GAM>(g) * (d.x * d.x + d.y * d.y);
+    if (!US) u[0] += wt<GAM>(g) * (d.x * d.x + d.y * d.y);
   }
   if (US) {
     for (int g = threadIdx.x; g < npw; g += blockDim.x) N[g] = D[g];

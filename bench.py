@@ -81,6 +81,9 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after the timed region, copy 1 GiB device to device once (reference kernel "
                          "for the FETCH_SIZE / WRITE_SIZE counter scale)")
+    ap.add_argument("--gamma", action="store_true",
+                    help="solve512: the same cell at Gamma on the half sphere with real wavefunctions "
+                         "(two bands per transform, real products)")
     ap.add_argument("--class-profile", action="store_true",
                     help="solve512: after the timed solves, one more float64 solve with every kernel class "
                          "timed (HIP events around each class's launches); reports each class's time and "
@@ -639,16 +642,21 @@ def bench_solve512(args):
     from paper_0906_2569_amd import pwdft, pwgen
     dev = torch.device("cuda", 0)
     t0 = time.perf_counter()
-    p = pwgen.config5_largest(nb=1024)
+    if args.gamma:
+        # the same cell (a = 41 bohr, 30 Ry, 512 atoms, seed of the full-sphere form) at Gamma
+        p = pwgen.gamma_cell(41.0, 30.0, 512, 1024, pwgen.SEED_BASE + 5, name="cfg5_gamma")
+    else:
+        p = pwgen.config5_largest(nb=1024)
     print(f"bench: cell generated in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     ctx = pwdft.Context(0)
     opts = pwdft.default_opts(ndim=args.ndim, max_iter=400)
-    psi0 = torch.from_numpy(p.psi0).to(dev)
+    psi0 = torch.from_numpy(np.ascontiguousarray(p.psi0)).to(dev)
+    gam = 1 if args.gamma else 0
 
     prof_out = {}
 
     def solves(prec, nsteps, nwarm, profile=False):
-        plan = pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=args.ndim)
+        plan = pwdft.Plan(ctx, p, precision=prec, nb_max=p.nb, ndim_max=args.ndim, gamma=gam)
         try:
             psi = torch.empty_like(psi0)
             eig = torch.empty(p.nb, dtype=torch.float64, device=dev)
@@ -678,8 +686,10 @@ def bench_solve512(args):
     line = {"metric": "solves/s", "value": 1.0 / sec, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1e3 * sec, "higher_is_better": True, "scaling": "weak",
             "vs_baseline": None, "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
-            "config": {"workload": "Davidson solve of the 512-atom cell (npw 191,471, 144^3, 2048 projectors, "
-                                   "1024 bands)", "ndim": args.ndim, "precision": args.precision},
+            "config": {"workload": ("Davidson solve of the 512-atom cell (npw 191,471, 144^3, 2048 projectors, "
+                                    "1024 bands)" + (" at Gamma: half sphere of " + f"{p.npw:,}" +
+                                                     " coefficients, real wavefunctions" if gam else "")),
+                       "ndim": args.ndim, "precision": args.precision, "gamma": bool(gam)},
             "status": [st for _, st, _ in runs], "solve_stats": runs[-1][2],
             "eig_range_ha": [float(e[0]), float(e[-1])], "max_resid_ha": float(r.max())}
     if args.precision == "mixed":

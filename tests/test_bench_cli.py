@@ -37,6 +37,11 @@ def test_workload_defaults():
         assert bench.parse().class_profile is False
         sys.argv = ["bench.py", "--workload", "solve512", "--class-profile"]
         assert bench.parse().class_profile is True
+        # the whole sphere unless the Gamma form is asked for
+        sys.argv = ["bench.py", "--workload", "solve512"]
+        assert bench.parse().gamma is False
+        sys.argv = ["bench.py", "--workload", "solve512", "--gamma"]
+        assert bench.parse().gamma is True
     finally:
         sys.argv = argv
         sys.path.remove(ROOT)

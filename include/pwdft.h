@@ -414,6 +414,8 @@ typedef struct {
   int32_t      nworkers;     /* concurrent requests, 1..64                                          */
   size_t       mem_budget;   /* device bytes the running requests' plans may hold (0: 60% of free)  */
   pw_precision precision;    /* precision of the requests' plans                                    */
+  int32_t      gamma;        /* 1: every request is a Gamma-point problem on the half sphere (plans
+                                with pw_plan_opts.gamma = 1); 0 (default): whole-sphere problems   */
 } pw_server_opts;
 void      pw_server_opts_default(pw_server_opts* opts);
 pw_status pw_server_create(pw_ctx ctx, const pw_server_opts* opts, pw_server* out);

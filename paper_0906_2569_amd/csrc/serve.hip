@@ -74,6 +74,7 @@ struct pw_server_s {
         r->t_start = now();
       }
       pw_plan_opts po{opts.precision, r->nb, r->dopts.ndim};
+      po.gamma = opts.gamma;
       pw_plan plan = nullptr;
       pw_status st = pw::plan_create(ctx, &r->prob, &po, &pool, streams[w], &plan);
       if (st == PW_OK) {
@@ -139,6 +140,7 @@ extern "C" void pw_server_opts_default(pw_server_opts* o) {
   o->nworkers = 4;
   o->mem_budget = 0;
   o->precision = PW_MIXED;
+  o->gamma = 0;
 }
 
 extern "C" pw_status pw_server_create(pw_ctx ctx, const pw_server_opts* opts, pw_server* out) {
@@ -148,6 +150,7 @@ extern "C" pw_status pw_server_create(pw_ctx ctx, const pw_server_opts* opts, pw
   if (opts) o = *opts; else pw_server_opts_default(&o);
   PW_CHECK(o.nworkers >= 1 && o.nworkers <= 64, PW_EINVAL, "nworkers out of range [1, 64]");
   PW_CHECK(o.precision == PW_FP64 || o.precision == PW_MIXED, PW_EINVAL, "bad precision");
+  PW_CHECK(o.gamma == 0 || o.gamma == 1, PW_EINVAL, "gamma must be 0 or 1");
   PW_HIP(hipSetDevice(ctx->device));
   if (o.mem_budget == 0) {
     size_t fr = 0, tot = 0;
@@ -195,6 +198,7 @@ extern "C" pw_status pw_server_submit(pw_server s, const pw_problem* problem, in
   PW_CHECK(o.history == nullptr, PW_EINVAL, "history is not supported for served requests");
   PW_CHECK(nb >= 1 && nb <= problem->npw && ldpsi >= problem->npw, PW_EINVAL, "bad nb or ldpsi");
   pw_plan_opts po{s->opts.precision, nb, o.ndim};
+  po.gamma = s->opts.gamma;
   const size_t bytes = pw_footprint_bytes(problem, &po);
   PW_CHECK(bytes > 0, PW_EINVAL, std::string("invalid problem: ") + pw_last_error());
   PW_CHECK(bytes <= s->opts.mem_budget, PW_ENOMEM, "request needs more device memory than the budget");

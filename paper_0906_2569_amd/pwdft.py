@@ -70,7 +70,7 @@ class CgStats(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("nworkers", C.c_int32), ("mem_budget", C.c_size_t), ("precision", C.c_int)]
+    _fields_ = [("nworkers", C.c_int32), ("mem_budget", C.c_size_t), ("precision", C.c_int), ("gamma", C.c_int32)]
 
 
 class DavStats(C.Structure):
@@ -501,11 +501,12 @@ class HpsiGraph:
 class Server:
     """Serving loop of the library (see pw_server_* in include/pwdft.h)."""
 
-    def __init__(self, ctx: Context, nworkers=4, mem_budget=0, precision=PW_MIXED):
+    def __init__(self, ctx: Context, nworkers=4, mem_budget=0, precision=PW_MIXED, gamma=0):
         self.ctx, self.lib = ctx, ctx.lib
         o = ServerOpts()
         self.lib.pw_server_opts_default(C.byref(o))
         o.nworkers, o.mem_budget, o.precision = int(nworkers), int(mem_budget), int(precision)
+        o.gamma = int(gamma)
         self.h = C.c_void_p()
         self._keep = {}
         _check(self.lib.pw_server_create(ctx.h, C.byref(o), C.byref(self.h)))

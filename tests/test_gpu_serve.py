@@ -85,3 +85,29 @@ def test_memory_budget_and_errors(ctx):
     e0 = subs[0][1].cpu().numpy()
     for _, e, _ in subs[1:]:
         np.testing.assert_array_equal(e.cpu().numpy(), e0)
+
+
+def test_gamma_server(ctx):
+    # a server for Gamma-point requests: half-sphere problems of different
+    # sizes served concurrently, each against the dense oracle of its whole
+    # sphere; a whole-sphere request to it fails its plan creation (the half
+    # sphere is checked there), which its wait reports
+    from paper_0906_2569_amd import pwdft
+    cells = [pwgen.gamma_cell(a, 12.0, nat, nb, seed, nr=(30, 30, 30))
+             for a, nat, nb, seed in [(8.0, 4, 8, 61), (9.0, 6, 12, 62), (10.0, 8, 16, 63)]]
+    opts = pwdft.default_opts(ndim=2)
+    srv = pwdft.Server(ctx, nworkers=2, precision=pwdft.PW_MIXED, gamma=1)
+    try:
+        tickets = [srv.submit(g, torch.from_numpy(np.ascontiguousarray(g.psi0)).cuda(), opts=opts) for g in cells]
+        results = [srv.wait(t) for t, _, _ in tickets]
+        whole = pwgen.config1()
+        bad, _, _ = srv.submit(whole, torch.from_numpy(whole.psi0).cuda(), opts=opts)
+        with pytest.raises(pwdft.PwError) as ei:
+            srv.wait(bad)
+        assert ei.value.status == pwdft.PW_EINVAL
+    finally:
+        srv.close()
+    for g, (t, e, r), (st, stats, times) in zip(cells, tickets, results):
+        assert st == 0 and stats["max_resid"] <= 1e-6
+        w, _ = oracle.eigh_lowest(oracle.dense_h_of(g.full), g.nb)
+        np.testing.assert_allclose(e.cpu().numpy(), w, atol=TOL_EIG, rtol=0)

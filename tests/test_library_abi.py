@@ -109,4 +109,4 @@ def test_cg_and_server_option_defaults_and_layout(lib):
     ctypes.memset(ctypes.byref(s), 0x7F, ctypes.sizeof(s))
     lib.pw_server_opts_default(ctypes.byref(s))
     assert ctypes.sizeof(s) == 24
-    assert (s.nworkers, s.mem_budget, s.precision) == (4, 0, pwdft.PW_MIXED)
+    assert (s.nworkers, s.mem_budget, s.precision, s.gamma) == (4, 0, pwdft.PW_MIXED, 0)

@@ -436,3 +436,20 @@ def test_gamma_cell_is_real_in_real_space():
     hp = oracle.hpsi(h, g.full.psi0)
     np.testing.assert_allclose(hp[:, mir], np.conj(hp), atol=1e-14)
     assert len(g.half) == (g.full.npw + 1) // 2 and g.half[0] == np.nonzero((g.full.miller == 0).all(1))[0][0]
+
+
+def test_gamma_ultrasoft_overlap_needs_real_q():
+    # at Gamma S = 1 + beta q beta^H maps real-space-real functions to real
+    # ones, S(-G, -G') = conj(S(G, G')), exactly when the q blocks are real:
+    # the half sphere then carries S psi too.  A q block with an imaginary
+    # part breaks the symmetry (the Gamma plan refuses such blocks).
+    g = pwgen.gamma_cell(10.0, 15.0, 8, 4, 32, nr=(30, 30, 30))
+    mir = pwgen.mirror_index(g.full.miller)
+    q = pwgen.hermitian_blocks(np.random.default_rng(32), g.full.blk_off, scale=0.1)
+    assert np.abs(q.imag).max() > 1e-3
+    s_real = oracle.dense_s(g.full.npw, g.full.beta, g.full.blk_off, np.ascontiguousarray(q.real + 0j))
+    np.testing.assert_allclose(s_real[np.ix_(mir, mir)], np.conj(s_real), atol=1e-14)
+    sp = g.full.psi0 @ s_real.T
+    np.testing.assert_allclose(sp[:, mir], np.conj(sp), atol=1e-14)
+    s_cplx = oracle.dense_s(g.full.npw, g.full.beta, g.full.blk_off, q)
+    assert np.abs(s_cplx[np.ix_(mir, mir)] - np.conj(s_cplx)).max() > 1e-4
